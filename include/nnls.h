@@ -1,0 +1,193 @@
+/*
+ * nnls.h -- C ABI of the MI355X (gfx950) block principal pivoting NNLS library.
+ *
+ * Solves  min 1/2 ||A x - b||_2^2  subject to  x >= 0  (Cantarella & Piatek, "tsnnls",
+ * arXiv cs/0408029, Eq. 1) for A of size m x n, m >= n, full column rank, and returns the
+ * solution x together with the dual vector y = A^T A x - A^T b of the complementarity form
+ * (Eq. 3): x >= 0, y >= 0, x_i y_i = 0.
+ *
+ * Method: the block principal pivoting loop of the paper's Sec. 2 algorithm box.  Each
+ * pivot iteration solves the unconstrained least-squares problem on the free columns F
+ * (Eq. 4) through the normal equations with a Cholesky factor of the F-principal block of
+ * the cached Gram matrix A^T A (Sec. 2.1, Sec. 3), forms y_G = A_G^T (A_F x_F - b) (Eq. 5),
+ * zeroes tested entries within tau of zero, counts the negative ones and exchanges them
+ * between F and G (all at once; after p_max non-improving block exchanges, only the one
+ * with the largest index).  Every step runs in HIP kernels on the device.
+ *
+ * Conventions shared by every call:
+ *   - Array arguments are DEVICE pointers unless the comment says "host".  They are
+ *     borrowed for the duration of the call and owned by the caller.
+ *   - Matrices: CSC with int32 colptr[n+1], int32 rowidx[nnz] (0-based, strictly
+ *     increasing within each column) and double val[nnz]; or dense column-major double
+ *     with leading dimension lda >= m.
+ *   - Indices are 0-based; "largest index" is the largest column number.
+ *   - Calls are stream-ordered on the handle's stream and return after the result is on
+ *     the device (the call synchronises that stream).  A handle must not be used from two
+ *     threads at once; separate handles are independent.
+ *   - Return value: an nnls_status.  No exception or abort crosses the ABI.  When a solve
+ *     fails, x and y hold the last iterate (unspecified after INVALID_* errors) and
+ *     info->status / info->failed_index say why.
+ */
+#ifndef NNLS_H_
+#define NNLS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NNLS_OK = 0,
+  NNLS_ERR_INVALID_ARG = -1,   /* bad size, null pointer, malformed CSC structure       */
+  NNLS_ERR_INVALID_VALUE = -2, /* NaN or Inf in A or b                                   */
+  NNLS_ERR_NOT_PD = -3,        /* Cholesky breakdown: the F-block is not numerically
+                                  positive definite (A_F rank deficient, or kappa^2 eps
+                                  >= 1 as Sec. 2.1 warns); failed_index names the column */
+  NNLS_ERR_MAXITER = -4,       /* iteration cap reached before a feasible split          */
+  NNLS_ERR_NO_MEMORY = -5,     /* device or pinned host allocation failed                */
+  NNLS_ERR_DEVICE = -6,        /* HIP runtime error, or a device-side wait exceeded its
+                                  bound                                                  */
+  NNLS_ERR_REFINE = -7         /* mixed precision: refinement did not reach its target   */
+} nnls_status;
+
+typedef enum {
+  NNLS_FP64 = 0,     /* factor and every vector in float64                               */
+  NNLS_FP32_IR = 1   /* F-block factor in float32, float64 iterative refinement of the
+                        normal equations; residual, y_G and sign tests in float64        */
+} nnls_precision;
+
+/* flags */
+#define NNLS_FLAG_PROFILE 1u   /* time kernel classes with HIP events (nnls_get_profile) */
+
+typedef struct {
+  double tau;           /* zeroing threshold; paper: 1e-12 (Sec. 2)                      */
+  int32_t p_max;        /* non-improving block exchanges allowed; paper: 3 (Sec. 2 box)  */
+  int32_t max_iter;     /* pivot iteration cap; <= 0 means 5 n + 100 (paper gives none)  */
+  int32_t precision;    /* nnls_precision                                                */
+  int32_t ir_max_steps; /* NNLS_FP32_IR: refinement steps per pivot iteration            */
+  double ir_rtol;       /* NNLS_FP32_IR: target ||A_F^T r||_inf / ||A_F^T b||_inf        */
+  uint32_t flags;       /* NNLS_FLAG_*                                                   */
+  uint32_t reserved;
+} nnls_options;
+
+typedef struct {
+  int32_t status;       /* nnls_status of the solve                                      */
+  int32_t iterations;   /* pivot iterations (exchange + solve passes)                    */
+  int32_t n_free;       /* |F| of the returned split                                     */
+  int32_t last_ninf;    /* infeasible count at exit (0 on success)                       */
+  int32_t failed_index; /* NOT_PD: column of the first non-positive pivot; else -1       */
+  int32_t ir_steps;     /* NNLS_FP32_IR: total refinement steps                          */
+  double min_margin;    /* smallest |v| over the final sign tests that were not zeroed   */
+  double setup_ms;      /* host wall time of validation + Gram formation                 */
+  double solve_ms;      /* host wall time of the whole call                              */
+} nnls_info;
+
+/* One row of the per-iteration trace recorded by the last solve on a handle. */
+typedef struct {
+  int32_t k;        /* infeasible count after zeroing                                    */
+  int32_t branch;   /* 0: k < N, block exchange; 1: budget block exchange; 2: single     */
+  int32_t N;        /* best count after the rule                                         */
+  int32_t p;        /* remaining budget after the rule                                   */
+  int32_t n_free;   /* |F| after the exchange                                            */
+  int32_t reserved;
+} nnls_trace_row;
+
+typedef struct nnls_handle nnls_handle;
+
+/* Human-readable name of a status code (static storage). */
+const char* nnls_status_string(int status);
+
+/* Paper defaults: tau 1e-12, p_max 3 (Sec. 2); max_iter 0 (= 5n+100); FP64. */
+void nnls_default_options(nnls_options* opts);
+
+/* Create a handle on HIP device `device`, issuing work on `stream` (a hipStream_t, or
+ * NULL for the default stream).  The handle owns a growable device workspace and a small
+ * pinned host buffer; both are released by nnls_destroy. */
+int nnls_create(nnls_handle** out, int device, void* stream);
+int nnls_destroy(nnls_handle* h);
+
+/* Solve Eq. 1 for sparse A in CSC (device arrays).  b: double[m].  Outputs x, y:
+ * double[n] device, written with x_G = 0 and y_F = 0 exactly.  opts may be NULL
+ * (defaults).  info is a host struct and may be NULL.
+ * Errors: INVALID_ARG for sizes (m < n, n < 1, nnz < 0), null pointers, colptr not
+ * starting at 0 / not non-decreasing / not ending at nnz, or a row index out of [0, m) or
+ * not strictly increasing in its column; INVALID_VALUE for non-finite A or b. */
+int nnls_solve_csc(nnls_handle* h, int32_t m, int32_t n, int64_t nnz, const int32_t* colptr,
+                   const int32_t* rowidx, const double* val, const double* b, double* x,
+                   double* y, const nnls_options* opts, nnls_info* info);
+
+/* Solve Eq. 1 for dense column-major A (device, lda >= m).  Same outputs and errors. */
+int nnls_solve_dense(nnls_handle* h, int32_t m, int32_t n, const double* A, int32_t lda,
+                     const double* b, double* x, double* y, const nnls_options* opts,
+                     nnls_info* info);
+
+/* Copy up to `cap` trace rows of the last solve on this handle into `rows` (host).
+ * Returns the number of rows the solve recorded (which may exceed cap). */
+int nnls_get_trace(nnls_handle* h, nnls_trace_row* rows, int cap);
+
+/* Kernel-class timings of the solves run with NNLS_FLAG_PROFILE since the last reset.
+ * For class c (see nnls_profile_class), launches[c] and total_ms[c] are written (host
+ * arrays of length NNLS_PROFILE_CLASSES), and flops[c] the algorithmic work of those
+ * launches (floating-point operations; bytes for the memory-bound classes). */
+#define NNLS_PROFILE_CLASSES 8
+typedef enum {
+  NNLS_PROF_GRAM = 0,      /* A^T A and A^T b (bytes)                                   */
+  NNLS_PROF_CONTROL = 1,   /* classify, count, exchange, rebuild F (bytes)              */
+  NNLS_PROF_CHOLESKY = 2,  /* gather + tiled Cholesky of the F-block (flops |F|^3/3)    */
+  NNLS_PROF_TRSV = 3,      /* two triangular solves (bytes of L read)                   */
+  NNLS_PROF_RESIDUAL = 4,  /* r = A x - b and y_G = A_G^T r (bytes)                     */
+  NNLS_PROF_REFINE = 5     /* mixed precision refinement (bytes)                        */
+} nnls_profile_class;
+int nnls_get_profile(nnls_handle* h, int64_t* launches, double* total_ms, double* work);
+int nnls_reset_profile(nnls_handle* h);
+
+/* ---------------------------------------------------------------------------------
+ * Step entry points.  Each runs one step of the pivot iteration on its own, with the
+ * same kernels the solver uses, so that every step can be checked in isolation.
+ * --------------------------------------------------------------------------------- */
+
+/* Gram matrix and right-hand side (Sec. 3: A^T A from column dot products, cached once;
+ * Sec. 2.1: A^T b).  Writes the full symmetric H = A^T A as a dense n x n column-major
+ * double array (device, ldh >= n) and c = A^T b (device double[n]). */
+int nnls_gram_csc(nnls_handle* h, int32_t m, int32_t n, int64_t nnz, const int32_t* colptr,
+                  const int32_t* rowidx, const double* val, const double* b, double* H,
+                  int32_t ldh, double* c);
+
+/* Cholesky factor of the symmetric positive definite n x n matrix S (device, column-major,
+ * lower triangle read) into L (device, column-major, ldl >= n; the strict upper triangle
+ * is written as zero).  This is the factor of Sec. 2.1, run by the tiled MFMA kernel the
+ * solver uses on its F-block.  precision: NNLS_FP64 or NNLS_FP32_IR (float32 factor,
+ * returned widened to double).  *failed (host) is -1, or the first column whose pivot was
+ * non-positive or non-finite (then the status is NNLS_ERR_NOT_PD). */
+int nnls_cholesky(nnls_handle* h, int32_t n, const double* S, int32_t lds, double* L,
+                  int32_t ldl, int32_t precision, int32_t* failed);
+
+/* Solve S x = rhs for the SPD matrix S (device, column-major, lower triangle read) by the
+ * solver's factor and its two triangular solves (normal equations of Sec. 2.1). */
+int nnls_spd_solve(nnls_handle* h, int32_t n, const double* S, int32_t lds, const double* rhs,
+                   double* x, int32_t* failed);
+
+/* Eq. 5 on a given split: r = A x - b (x is used as given: callers pass x_G = 0) and
+ * y_i = a_i^T r for i in G (free[i] == 0), y_i = 0 for i in F.  free: uint8[n] device.
+ * r may be NULL. */
+int nnls_dual_csc(nnls_handle* h, int32_t m, int32_t n, int64_t nnz, const int32_t* colptr,
+                  const int32_t* rowidx, const double* val, const double* b,
+                  const uint8_t* free_flags, const double* x, double* r, double* y);
+
+/* One classify-and-exchange step (Sec. 2 box): zero tested entries with |v| < tau (v = x_i
+ * on F, y_i on G), count the negative ones (k), apply the counter rule to (N, p) and flip
+ * the membership of the exchanged variables.  x, y, free_flags are device arrays updated
+ * in place (x is additionally zeroed on the new G and y on the new F).  state (host,
+ * int32[3]) holds {N, p, reserved} in and out; N < 0 stands for infinity.  out (host,
+ * int32[4]) receives {k, branch (-1 when k == 0), largest infeasible index, new |F|
+ * (-1 when k == 0: nothing is exchanged)}. */
+int nnls_pivot_step(nnls_handle* h, int32_t n, double* x, double* y, uint8_t* free_flags,
+                    double tau, int32_t p_max, int32_t* state, int32_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NNLS_H_ */

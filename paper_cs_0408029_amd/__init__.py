@@ -1,0 +1,186 @@
+"""MI355X (gfx950) block principal pivoting NNLS.
+
+Thin Python layer over the C ABI of lib/libnnls.so (include/nnls.h).  The functions below
+carry the C names and only marshal arguments: they take torch device tensors, check
+dtype / device / layout, and pass raw device pointers and the handle's HIP stream.
+PyTorch supplies device memory and streams; every step of the method runs in the
+library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import List, Optional, Tuple
+
+from ._lib import (LIB_PATH, NNLS_ERR_DEVICE, NNLS_ERR_INVALID_ARG, NNLS_ERR_INVALID_VALUE,  # noqa: F401
+                   NNLS_ERR_MAXITER, NNLS_ERR_NO_MEMORY, NNLS_ERR_NOT_PD, NNLS_ERR_REFINE,
+                   NNLS_FLAG_PROFILE, NNLS_FP32_IR, NNLS_FP64, NNLS_OK, NNLS_PROFILE_CLASSES,
+                   PROFILE_CLASS_NAMES, default_options, load, nnls_info, nnls_options,
+                   nnls_trace_row, status_string)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t, dtype, name, numel=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: expected a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous tensor")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name}: needs at least {numel} elements, has {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Handle:
+    """Owns an nnls_handle bound to a device and a HIP stream (torch's current stream of
+    that device unless one is given)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        self.lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        self.device = device
+        h = C.c_void_p()
+        st = self.lib.nnls_create(C.byref(h), device, C.c_void_p(stream.cuda_stream))
+        if st != NNLS_OK:
+            raise RuntimeError(f"nnls_create failed: {status_string(st)}")
+        self._h = h
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            self.lib.nnls_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def nnls_solve_csc(h: Handle, m: int, n: int, colptr, rowidx, val, b, x, y,
+                   opts: Optional[nnls_options] = None) -> Tuple[int, nnls_info]:
+    torch = _torch()
+    nnz = int(rowidx.numel())
+    info = nnls_info()
+    st = h.lib.nnls_solve_csc(h.ptr, m, n, nnz, _ptr(colptr, torch.int32, "colptr", n + 1),
+                              _ptr(rowidx, torch.int32, "rowidx"), _ptr(val, torch.float64, "val", nnz),
+                              _ptr(b, torch.float64, "b", m), _ptr(x, torch.float64, "x", n),
+                              _ptr(y, torch.float64, "y", n), C.byref(opts) if opts else None,
+                              C.byref(info))
+    return st, info
+
+
+def nnls_solve_dense(h: Handle, A, b, x, y, opts: Optional[nnls_options] = None) -> Tuple[int, nnls_info]:
+    """A: float64 device tensor of shape (m, n) in column-major layout (A.stride(0) == 1),
+    e.g. the transpose of a contiguous (n, m) tensor."""
+    torch = _torch()
+    m, n = A.shape
+    if A.dtype != torch.float64 or not A.is_cuda or A.stride(0) != 1:
+        raise ValueError("A: expected a column-major float64 device tensor")
+    lda = A.stride(1) if n > 1 else m
+    info = nnls_info()
+    st = h.lib.nnls_solve_dense(h.ptr, m, n, C.c_void_p(A.data_ptr()), lda, _ptr(b, torch.float64, "b", m),
+                                _ptr(x, torch.float64, "x", n), _ptr(y, torch.float64, "y", n),
+                                C.byref(opts) if opts else None, C.byref(info))
+    return st, info
+
+
+def nnls_get_trace(h: Handle) -> List[Tuple[int, int, int, int, int]]:
+    cnt = h.lib.nnls_get_trace(h.ptr, None, 0)
+    rows = (nnls_trace_row * max(cnt, 1))()
+    h.lib.nnls_get_trace(h.ptr, rows, cnt)
+    return [(r.k, r.branch, r.N, r.p, r.n_free) for r in rows[:cnt]]
+
+
+def nnls_get_profile(h: Handle) -> dict:
+    la = (C.c_int64 * NNLS_PROFILE_CLASSES)()
+    ms = (C.c_double * NNLS_PROFILE_CLASSES)()
+    wk = (C.c_double * NNLS_PROFILE_CLASSES)()
+    h.lib.nnls_get_profile(h.ptr, la, ms, wk)
+    return {PROFILE_CLASS_NAMES[c]: {"launches": la[c], "ms": ms[c], "work": wk[c]}
+            for c in range(NNLS_PROFILE_CLASSES)}
+
+
+def nnls_reset_profile(h: Handle) -> int:
+    return h.lib.nnls_reset_profile(h.ptr)
+
+
+def nnls_gram_csc(h: Handle, m: int, n: int, colptr, rowidx, val, b, H, c) -> int:
+    torch = _torch()
+    nnz = int(rowidx.numel())
+    if H.dtype != torch.float64 or not H.is_cuda or H.stride(0) != 1 or H.shape != (n, n):
+        raise ValueError("H: expected an (n, n) column-major float64 device tensor")
+    return h.lib.nnls_gram_csc(h.ptr, m, n, nnz, _ptr(colptr, torch.int32, "colptr", n + 1),
+                               _ptr(rowidx, torch.int32, "rowidx"), _ptr(val, torch.float64, "val", nnz),
+                               _ptr(b, torch.float64, "b", m), C.c_void_p(H.data_ptr()),
+                               H.stride(1) if n > 1 else n, _ptr(c, torch.float64, "c", n))
+
+
+def _colmajor(M, name):
+    torch = _torch()
+    if M.dtype != torch.float64 or not M.is_cuda or M.stride(0) != 1 or M.dim() != 2:
+        raise ValueError(f"{name}: expected a column-major float64 device matrix")
+    return C.c_void_p(M.data_ptr()), (M.stride(1) if M.shape[1] > 1 else M.shape[0])
+
+
+def nnls_cholesky(h: Handle, S, L, precision: int = NNLS_FP64) -> Tuple[int, int]:
+    n = S.shape[0]
+    sp, lds = _colmajor(S, "S")
+    lp, ldl = _colmajor(L, "L")
+    failed = C.c_int32(-1)
+    st = h.lib.nnls_cholesky(h.ptr, n, sp, lds, lp, ldl, precision, C.byref(failed))
+    return st, failed.value
+
+
+def nnls_spd_solve(h: Handle, S, rhs, x) -> Tuple[int, int]:
+    torch = _torch()
+    n = S.shape[0]
+    sp, lds = _colmajor(S, "S")
+    failed = C.c_int32(-1)
+    st = h.lib.nnls_spd_solve(h.ptr, n, sp, lds, _ptr(rhs, torch.float64, "rhs", n),
+                              _ptr(x, torch.float64, "x", n), C.byref(failed))
+    return st, failed.value
+
+
+def nnls_dual_csc(h: Handle, m: int, n: int, colptr, rowidx, val, b, free_flags, x, r, y) -> int:
+    torch = _torch()
+    nnz = int(rowidx.numel())
+    return h.lib.nnls_dual_csc(h.ptr, m, n, nnz, _ptr(colptr, torch.int32, "colptr", n + 1),
+                               _ptr(rowidx, torch.int32, "rowidx"), _ptr(val, torch.float64, "val", nnz),
+                               _ptr(b, torch.float64, "b", m), _ptr(free_flags, torch.uint8, "free", n),
+                               _ptr(x, torch.float64, "x", n),
+                               _ptr(r, torch.float64, "r", m) if r is not None else None,
+                               _ptr(y, torch.float64, "y", n))
+
+
+def nnls_pivot_step(h: Handle, x, y, free_flags, tau: float, p_max: int, state: List[int]):
+    """state: [N, p] (N < 0 = infinity), updated in place.  Returns (status, [k, branch,
+    largest infeasible index, new |F| or -1])."""
+    torch = _torch()
+    n = x.numel()
+    st_arr = (C.c_int32 * 3)(state[0], state[1], 0)
+    out = (C.c_int32 * 4)()
+    st = h.lib.nnls_pivot_step(h.ptr, n, _ptr(x, torch.float64, "x", n), _ptr(y, torch.float64, "y", n),
+                               _ptr(free_flags, torch.uint8, "free", n), tau, p_max, st_arr, out)
+    state[0], state[1] = st_arr[0], st_arr[1]
+    return st, list(out)

@@ -1,0 +1,657 @@
+// Host side of the C ABI: handle, device workspace, and the driver of the block principal
+// pivoting loop (Sec. 2 algorithm box of the tsnnls paper).  Every arithmetic step runs
+// in the kernels of k_setup / k_pivot / k_chol / k_spmv; the host only sizes launches
+// and reads the device control block once per pivot iteration.
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "nnls_internal.h"
+
+using namespace nnls;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct PendingEvent {
+  int cls;
+  hipEvent_t a, b;
+  double work;
+};
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct nnls_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  uint64_t wait_ticks = 0;
+  // workspace
+  DevBuf err, ctrl, rowcnt, rowptr, colidx, valr, hptr, hcnt, hrow, hval, c, r, flags, Flist, pos;
+  DevBuf Lt, Dinv, tflags, z, xF, zflags, xflags, Hd;
+  Ctrl* h_ctrl = nullptr;     // pinned
+  int64_t* h_scalar = nullptr;  // pinned scratch for small reads
+  int epoch = 0;
+  std::vector<nnls_trace_row> trace;
+  // profiling
+  bool profiling = false;
+  int64_t prof_launches[NNLS_PROFILE_CLASSES] = {};
+  double prof_ms[NNLS_PROFILE_CLASSES] = {};
+  double prof_work[NNLS_PROFILE_CLASSES] = {};
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<PendingEvent> pending;
+};
+
+namespace {
+
+int set_info_status(nnls_info* info, int st) {
+  if (info) info->status = st;
+  return st;
+}
+
+// Grow a device buffer to at least `bytes`.  Flag buffers are zero-filled when they grow.
+int ensure(nnls_handle* h, DevBuf& b, size_t bytes, bool zero_i32 = false) {
+  if (bytes == 0) bytes = 8;
+  if (b.bytes >= bytes) return NNLS_OK;
+  if (b.p) {
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return NNLS_ERR_DEVICE;
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  if (hipMalloc(&b.p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return NNLS_ERR_NO_MEMORY;
+  }
+  b.bytes = bytes;
+  if (zero_i32) launch_fill_i32(h->stream, (int32_t*)b.p, (int64_t)(bytes / 4), 0);
+  return NNLS_OK;
+}
+
+#define TRY(expr)                  \
+  do {                             \
+    const int st_ = (expr);        \
+    if (st_ != NNLS_OK) return st_; \
+  } while (0)
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    if ((expr) != hipSuccess) {                         \
+      (void)hipGetLastError();                          \
+      return NNLS_ERR_DEVICE;                           \
+    }                                                   \
+  } while (0)
+
+int prof_begin(nnls_handle* h, int cls) {
+  if (!h->profiling) return -1;
+  PendingEvent pe;
+  pe.cls = cls;
+  pe.work = 0.0;
+  for (hipEvent_t* e : {&pe.a, &pe.b}) {
+    if (!h->ev_pool.empty()) {
+      *e = h->ev_pool.back();
+      h->ev_pool.pop_back();
+    } else if (hipEventCreate(e) != hipSuccess) {
+      return -1;
+    }
+  }
+  (void)hipEventRecord(pe.a, h->stream);
+  h->pending.push_back(pe);
+  return (int)h->pending.size() - 1;
+}
+
+void prof_end(nnls_handle* h, int idx, double work) {
+  if (idx < 0) return;
+  (void)hipEventRecord(h->pending[idx].b, h->stream);
+  h->pending[idx].work = work;
+}
+
+// Call only after the stream has been synchronised.
+void prof_flush(nnls_handle* h) {
+  for (PendingEvent& pe : h->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) {
+      h->prof_launches[pe.cls] += 1;
+      h->prof_ms[pe.cls] += ms;
+      h->prof_work[pe.cls] += pe.work;
+    }
+    h->ev_pool.push_back(pe.a);
+    h->ev_pool.push_back(pe.b);
+  }
+  h->pending.clear();
+}
+
+int sync_read(nnls_handle* h, void* dst, const void* src, size_t bytes) {
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  prof_flush(h);
+  return NNLS_OK;
+}
+
+int check_options(const nnls_options& o) {
+  if (!(o.tau >= 0.0) || !std::isfinite(o.tau)) return NNLS_ERR_INVALID_ARG;
+  if (o.p_max < 0) return NNLS_ERR_INVALID_ARG;
+  if (o.precision != NNLS_FP64 && o.precision != NNLS_FP32_IR) return NNLS_ERR_INVALID_ARG;
+  return NNLS_OK;
+}
+
+// Problem description shared by the sparse and dense drivers.
+struct Problem {
+  bool sparse;
+  int m, n;
+  int64_t nnz;
+  const int32_t* colptr;
+  const int32_t* rowidx;
+  const double* val;
+  const double* A;
+  int lda;
+  const double* b;
+};
+
+int validate_device(nnls_handle* h, const Problem& P) {
+  TRY(ensure(h, h->err, 16));
+  launch_fill_i32(h->stream, (int32_t*)h->err.p, 4, 0);
+  if (P.sparse)
+    launch_validate_csc(h->stream, P.m, P.n, P.nnz, P.colptr, P.rowidx, P.val, P.b, (int32_t*)h->err.p);
+  else
+    launch_validate_dense(h->stream, P.m, P.n, P.A, P.lda, P.b, (int32_t*)h->err.p);
+  int32_t e[4];
+  TRY(sync_read(h, e, h->err.p, sizeof(e)));
+  if (e[0]) return NNLS_ERR_INVALID_ARG;
+  if (e[1]) return NNLS_ERR_INVALID_VALUE;
+  return NNLS_OK;
+}
+
+int build_csr(nnls_handle* h, const Problem& P) {
+  TRY(ensure(h, h->rowcnt, sizeof(int32_t) * (size_t)P.m));
+  TRY(ensure(h, h->rowptr, sizeof(int32_t) * ((size_t)P.m + 1)));
+  TRY(ensure(h, h->colidx, sizeof(int32_t) * (size_t)P.nnz));
+  TRY(ensure(h, h->valr, sizeof(double) * (size_t)P.nnz));
+  launch_build_csr(h->stream, P.m, P.n, P.nnz, P.colptr, P.rowidx, P.val, (int32_t*)h->rowcnt.p,
+                   (int32_t*)h->rowptr.p, (int32_t*)h->colidx.p, (double*)h->valr.p);
+  return NNLS_OK;
+}
+
+// Gram matrix (lower, padded CSC) and c = A^T b for a validated CSC problem.
+int build_gram_sparse(nnls_handle* h, const Problem& P) {
+  TRY(build_csr(h, P));
+  TRY(ensure(h, h->hptr, sizeof(int64_t) * ((size_t)P.n + 1)));
+  launch_gram_bound(h->stream, P.n, P.colptr, P.rowidx, (const int32_t*)h->rowptr.p, (int64_t*)h->hptr.p);
+  int64_t ub = 0;
+  TRY(sync_read(h, &ub, (int64_t*)h->hptr.p + P.n, sizeof(int64_t)));
+  TRY(ensure(h, h->hcnt, sizeof(int32_t) * (size_t)P.n));
+  TRY(ensure(h, h->hrow, sizeof(int32_t) * (size_t)ub));
+  TRY(ensure(h, h->hval, sizeof(double) * (size_t)ub));
+  launch_gram_lower(h->stream, P.n, P.colptr, P.rowidx, P.val, (const int32_t*)h->rowptr.p,
+                    (const int32_t*)h->colidx.p, (const double*)h->valr.p, (const int64_t*)h->hptr.p,
+                    (int32_t*)h->hcnt.p, (int32_t*)h->hrow.p, (double*)h->hval.p);
+  TRY(ensure(h, h->c, sizeof(double) * (size_t)P.n));
+  launch_spmvT_csc(h->stream, P.n, P.colptr, P.rowidx, P.val, P.b, (double*)h->c.p, 1.0);
+  return NNLS_OK;
+}
+
+int build_gram_dense(nnls_handle* h, const Problem& P) {
+  TRY(ensure(h, h->Hd, sizeof(double) * (size_t)P.n * (size_t)P.n));
+  launch_gram_dense(h->stream, P.m, P.n, P.A, P.lda, (double*)h->Hd.p, P.n);
+  TRY(ensure(h, h->c, sizeof(double) * (size_t)P.n));
+  launch_gemvT_dense(h->stream, P.m, P.n, P.A, P.lda, P.b, (double*)h->c.p, 1.0);
+  return NNLS_OK;
+}
+
+GramLower gram_view(nnls_handle* h) {
+  GramLower g;
+  g.hptr = (const int64_t*)h->hptr.p;
+  g.hcnt = (const int32_t*)h->hcnt.p;
+  g.hrow = (const int32_t*)h->hrow.p;
+  g.hval = (const double*)h->hval.p;
+  return g;
+}
+
+// Factor-and-solve workspace for an F-block of order nF.
+int ensure_factor(nnls_handle* h, int nF, bool fp32) {
+  const int nb = (nF + TILE - 1) / TILE;
+  const size_t w = fp32 ? sizeof(float) : sizeof(double);
+  const size_t ntiles = (size_t)tile_count(nb);
+  TRY(ensure(h, h->Lt, ntiles * TILE_ELEMS * w));
+  TRY(ensure(h, h->Dinv, (size_t)nb * TILE_ELEMS * w));
+  TRY(ensure(h, h->tflags, ntiles * sizeof(int32_t), true));
+  TRY(ensure(h, h->z, (size_t)nb * TILE * sizeof(double)));
+  TRY(ensure(h, h->xF, (size_t)nb * TILE * sizeof(double)));
+  TRY(ensure(h, h->zflags, (size_t)nb * sizeof(int32_t), true));
+  TRY(ensure(h, h->xflags, (size_t)nb * sizeof(int32_t), true));
+  return NNLS_OK;
+}
+
+FactorArgs factor_args(nnls_handle* h, int nF, const int32_t* Flist, const int32_t* pos,
+                       const double* dense, int64_t ldd, bool sparse) {
+  FactorArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.nF = nF;
+  a.nb = (nF + TILE - 1) / TILE;
+  a.Flist = Flist;
+  a.pos = pos;
+  if (sparse) a.lower = gram_view(h);
+  a.dense = dense;
+  a.ldd = ldd;
+  a.Ltiles = h->Lt.p;
+  a.Dinv = h->Dinv.p;
+  a.tile_flags = (int32_t*)h->tflags.p;
+  a.epoch = h->epoch;
+  a.ctrl = (Ctrl*)h->ctrl.p;
+  a.wait_ticks = h->wait_ticks;
+  return a;
+}
+
+SolveArgs solve_args(nnls_handle* h, int nF, const int32_t* Flist, const double* rhs, double* out) {
+  SolveArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.nF = nF;
+  a.nb = (nF + TILE - 1) / TILE;
+  a.Flist = Flist;
+  a.Ltiles = h->Lt.p;
+  a.Dinv = h->Dinv.p;
+  a.rhs_full = rhs;
+  a.rhs_dense = nullptr;
+  a.z = (double*)h->z.p;
+  a.xF = (double*)h->xF.p;
+  a.out = out;
+  a.zflags = (int32_t*)h->zflags.p;
+  a.xflags = (int32_t*)h->xflags.p;
+  a.epoch = h->epoch;
+  a.ctrl = (Ctrl*)h->ctrl.p;
+  a.wait_ticks = h->wait_ticks;
+  return a;
+}
+
+double chol_flops(double nF) { return nF * nF * nF / 3.0; }
+
+// The pivot loop on a problem whose Gram matrix and c are built.
+int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnls_options& o,
+               nnls_info* info) {
+  const int n = P.n, m = P.m;
+  const bool fp32 = false;
+  TRY(ensure(h, h->flags, (size_t)n));
+  TRY(ensure(h, h->Flist, sizeof(int32_t) * (size_t)n));
+  TRY(ensure(h, h->pos, sizeof(int32_t) * (size_t)n));
+  TRY(ensure(h, h->r, sizeof(double) * (size_t)m));
+  TRY(ensure(h, h->ctrl, sizeof(Ctrl)));
+  const int max_iter = o.max_iter > 0 ? o.max_iter : 5 * n + 100;
+  uint8_t* flags = (uint8_t*)h->flags.p;
+  int32_t* Flist = (int32_t*)h->Flist.p;
+  int32_t* pos = (int32_t*)h->pos.p;
+  double* r = (double*)h->r.p;
+  Ctrl* ctrl = (Ctrl*)h->ctrl.p;
+  launch_pivot_init(h->stream, n, (const double*)h->c.p, x, y, flags, ctrl, o.p_max);
+
+  // bytes moved by the classify / exchange sweep and by the residual + dual sweep
+  const double ctrl_bytes = 2.0 * 17.0 * n;
+  const double spmv_bytes = P.sparse ? (2.0 * 12.0 * (double)P.nnz + 32.0 * m + 24.0 * n)
+                                     : (2.0 * 8.0 * (double)m * n + 32.0 * m + 24.0 * n);
+  for (;;) {
+    int pe = prof_begin(h, NNLS_PROF_CONTROL);
+    launch_pivot_control(h->stream, n, x, y, flags, Flist, pos, ctrl, o.tau, o.p_max, max_iter);
+    prof_end(h, pe, ctrl_bytes);
+    TRY(sync_read(h, h->h_ctrl, ctrl, sizeof(Ctrl)));
+    const Ctrl c = *h->h_ctrl;
+    if (c.status != 0 || c.done) break;
+    nnls_trace_row row;
+    row.k = c.k;
+    row.branch = c.branch;
+    row.N = c.N;
+    row.p = c.p;
+    row.n_free = c.n_free;
+    row.reserved = 0;
+    h->trace.push_back(row);
+    const int nF = c.n_free;
+    if (nF > 0) {
+      TRY(ensure_factor(h, nF, fp32));
+      h->epoch += 1;
+      FactorArgs fa = factor_args(h, nF, Flist, pos, P.sparse ? nullptr : (const double*)h->Hd.p,
+                                  P.sparse ? 0 : n, P.sparse);
+      pe = prof_begin(h, NNLS_PROF_CHOLESKY);
+      launch_cholesky(h->stream, fa, fp32);
+      prof_end(h, pe, chol_flops(nF));
+      SolveArgs sa = solve_args(h, nF, Flist, (const double*)h->c.p, x);
+      const int nb = fa.nb;
+      pe = prof_begin(h, NNLS_PROF_TRSV);
+      launch_trsv(h->stream, sa, fp32);
+      prof_end(h, pe, 2.0 * 8.0 * (double)tile_count(nb) * TILE_ELEMS);
+    }
+    pe = prof_begin(h, NNLS_PROF_RESIDUAL);
+    if (P.sparse) {
+      launch_residual_csr(h->stream, m, (const int32_t*)h->rowptr.p, (const int32_t*)h->colidx.p,
+                          (const double*)h->valr.p, x, P.b, r);
+      launch_dual_csc(h->stream, n, P.colptr, P.rowidx, P.val, r, flags, y);
+    } else {
+      launch_residual_dense(h->stream, m, n, P.A, P.lda, x, P.b, r);
+      launch_dual_dense(h->stream, m, n, P.A, P.lda, r, flags, y);
+    }
+    prof_end(h, pe, spmv_bytes);
+    if (hipGetLastError() != hipSuccess) return NNLS_ERR_DEVICE;
+  }
+  const Ctrl c = *h->h_ctrl;
+  if (info) {
+    info->iterations = c.iter;
+    info->n_free = c.n_free;
+    info->last_ninf = c.k;
+    info->min_margin = c.min_margin;
+    info->failed_index = -1;
+  }
+  if (c.status == NNLS_ERR_NOT_PD) {
+    int32_t col = -1;
+    if (c.failed_pos >= 0 && c.failed_pos < n)
+      TRY(sync_read(h, &col, Flist + c.failed_pos, sizeof(int32_t)));
+    if (info) info->failed_index = col;
+  }
+  return c.status;
+}
+
+int solve_common(nnls_handle* h, const Problem& P, double* x, double* y, const nnls_options* opts,
+                 nnls_info* info) {
+  const double t0 = now_ms();
+  nnls_options o;
+  nnls_default_options(&o);
+  if (opts) o = *opts;
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->failed_index = -1;
+  }
+  if (!h) return set_info_status(info, NNLS_ERR_INVALID_ARG);
+  h->trace.clear();
+  if (check_options(o) != NNLS_OK) return set_info_status(info, NNLS_ERR_INVALID_ARG);
+  if (o.precision != NNLS_FP64) return set_info_status(info, NNLS_ERR_INVALID_ARG);
+  if (P.n < 1 || P.m < P.n || !P.b || !x || !y) return set_info_status(info, NNLS_ERR_INVALID_ARG);
+  if (P.sparse) {
+    if (P.nnz < 0 || P.nnz > INT32_MAX || !P.colptr || (P.nnz > 0 && (!P.rowidx || !P.val)))
+      return set_info_status(info, NNLS_ERR_INVALID_ARG);
+  } else {
+    if (!P.A || P.lda < P.m) return set_info_status(info, NNLS_ERR_INVALID_ARG);
+  }
+  if (hipSetDevice(h->device) != hipSuccess) return set_info_status(info, NNLS_ERR_DEVICE);
+  h->profiling = (o.flags & NNLS_FLAG_PROFILE) != 0;
+  int st = validate_device(h, P);
+  if (st != NNLS_OK) return set_info_status(info, st);
+  const int pe = prof_begin(h, NNLS_PROF_GRAM);
+  st = P.sparse ? build_gram_sparse(h, P) : build_gram_dense(h, P);
+  if (st != NNLS_OK) return set_info_status(info, st);
+  prof_end(h, pe, P.sparse ? 12.0 * (double)P.nnz * 3.0 : 8.0 * (double)P.m * P.n);
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return set_info_status(info, NNLS_ERR_DEVICE);
+  prof_flush(h);
+  if (info) info->setup_ms = now_ms() - t0;
+  st = pivot_loop(h, P, x, y, o, info);
+  if (info) info->solve_ms = now_ms() - t0;
+  h->profiling = false;
+  return set_info_status(info, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nnls_status_string(int status) {
+  switch (status) {
+    case NNLS_OK: return "NNLS_OK";
+    case NNLS_ERR_INVALID_ARG: return "NNLS_ERR_INVALID_ARG";
+    case NNLS_ERR_INVALID_VALUE: return "NNLS_ERR_INVALID_VALUE";
+    case NNLS_ERR_NOT_PD: return "NNLS_ERR_NOT_PD";
+    case NNLS_ERR_MAXITER: return "NNLS_ERR_MAXITER";
+    case NNLS_ERR_NO_MEMORY: return "NNLS_ERR_NO_MEMORY";
+    case NNLS_ERR_DEVICE: return "NNLS_ERR_DEVICE";
+    case NNLS_ERR_REFINE: return "NNLS_ERR_REFINE";
+    default: return "NNLS_ERR_UNKNOWN";
+  }
+}
+
+void nnls_default_options(nnls_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tau = 1e-12;
+  o->p_max = 3;
+  o->max_iter = 0;
+  o->precision = NNLS_FP64;
+  o->ir_max_steps = 10;
+  o->ir_rtol = 1e-13;
+  o->flags = 0;
+}
+
+int nnls_create(nnls_handle** out, int device, void* stream) {
+  if (!out) return NNLS_ERR_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+    (void)hipGetLastError();
+    return NNLS_ERR_DEVICE;
+  }
+  if (hipSetDevice(device) != hipSuccess) return NNLS_ERR_DEVICE;
+  nnls_handle* h = new (std::nothrow) nnls_handle();
+  if (!h) return NNLS_ERR_NO_MEMORY;
+  h->device = device;
+  h->stream = (hipStream_t)stream;
+  int rate_khz = 0;
+  if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || rate_khz <= 0)
+    rate_khz = 100000;
+  h->wait_ticks = (uint64_t)rate_khz * 1000ull * 20ull;   // 20 s
+  if (hipHostMalloc((void**)&h->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_scalar, 64, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    nnls_destroy(h);
+    return NNLS_ERR_NO_MEMORY;
+  }
+  std::memset(h->h_ctrl, 0, sizeof(Ctrl));
+  *out = h;
+  return NNLS_OK;
+}
+
+int nnls_destroy(nnls_handle* h) {
+  if (!h) return NNLS_ERR_INVALID_ARG;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  DevBuf* bufs[] = {&h->err, &h->ctrl, &h->rowcnt, &h->rowptr, &h->colidx, &h->valr, &h->hptr,
+                    &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
+                    &h->Lt, &h->Dinv, &h->tflags, &h->z, &h->xF, &h->zflags, &h->xflags, &h->Hd};
+  for (DevBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  for (PendingEvent& pe : h->pending) {
+    (void)hipEventDestroy(pe.a);
+    (void)hipEventDestroy(pe.b);
+  }
+  if (h->h_ctrl) (void)hipHostFree(h->h_ctrl);
+  if (h->h_scalar) (void)hipHostFree(h->h_scalar);
+  delete h;
+  return NNLS_OK;
+}
+
+int nnls_solve_csc(nnls_handle* h, int32_t m, int32_t n, int64_t nnz, const int32_t* colptr,
+                   const int32_t* rowidx, const double* val, const double* b, double* x, double* y,
+                   const nnls_options* opts, nnls_info* info) {
+  Problem P;
+  std::memset(&P, 0, sizeof(P));
+  P.sparse = true;
+  P.m = m;
+  P.n = n;
+  P.nnz = nnz;
+  P.colptr = colptr;
+  P.rowidx = rowidx;
+  P.val = val;
+  P.b = b;
+  return solve_common(h, P, x, y, opts, info);
+}
+
+int nnls_solve_dense(nnls_handle* h, int32_t m, int32_t n, const double* A, int32_t lda,
+                     const double* b, double* x, double* y, const nnls_options* opts, nnls_info* info) {
+  Problem P;
+  std::memset(&P, 0, sizeof(P));
+  P.sparse = false;
+  P.m = m;
+  P.n = n;
+  P.A = A;
+  P.lda = lda;
+  P.b = b;
+  return solve_common(h, P, x, y, opts, info);
+}
+
+int nnls_get_trace(nnls_handle* h, nnls_trace_row* rows, int cap) {
+  if (!h) return NNLS_ERR_INVALID_ARG;
+  const int cnt = (int)h->trace.size();
+  if (rows && cap > 0) std::memcpy(rows, h->trace.data(), sizeof(nnls_trace_row) * (size_t)std::min(cap, cnt));
+  return cnt;
+}
+
+int nnls_get_profile(nnls_handle* h, int64_t* launches, double* total_ms, double* work) {
+  if (!h) return NNLS_ERR_INVALID_ARG;
+  for (int c = 0; c < NNLS_PROFILE_CLASSES; ++c) {
+    if (launches) launches[c] = h->prof_launches[c];
+    if (total_ms) total_ms[c] = h->prof_ms[c];
+    if (work) work[c] = h->prof_work[c];
+  }
+  return NNLS_OK;
+}
+
+int nnls_reset_profile(nnls_handle* h) {
+  if (!h) return NNLS_ERR_INVALID_ARG;
+  for (int c = 0; c < NNLS_PROFILE_CLASSES; ++c) {
+    h->prof_launches[c] = 0;
+    h->prof_ms[c] = 0.0;
+    h->prof_work[c] = 0.0;
+  }
+  return NNLS_OK;
+}
+
+int nnls_gram_csc(nnls_handle* h, int32_t m, int32_t n, int64_t nnz, const int32_t* colptr,
+                  const int32_t* rowidx, const double* val, const double* b, double* H, int32_t ldh,
+                  double* c) {
+  if (!h || n < 1 || m < 1 || nnz < 0 || nnz > INT32_MAX || !colptr || !b || !H || !c || ldh < n ||
+      (nnz > 0 && (!rowidx || !val)))
+    return NNLS_ERR_INVALID_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return NNLS_ERR_DEVICE;
+  Problem P;
+  std::memset(&P, 0, sizeof(P));
+  P.sparse = true;
+  P.m = m;
+  P.n = n;
+  P.nnz = nnz;
+  P.colptr = colptr;
+  P.rowidx = rowidx;
+  P.val = val;
+  P.b = b;
+  TRY(validate_device(h, P));
+  TRY(build_gram_sparse(h, P));
+  launch_fill_2d(h->stream, n, n, H, ldh, 0.0);
+  launch_lower_to_dense(h->stream, n, gram_view(h), H, ldh);
+  HIP_TRY(hipMemcpyAsync(c, h->c.p, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return NNLS_OK;
+}
+
+int nnls_cholesky(nnls_handle* h, int32_t n, const double* S, int32_t lds, double* L, int32_t ldl,
+                  int32_t precision, int32_t* failed) {
+  if (failed) *failed = -1;
+  if (!h || n < 1 || !S || !L || lds < n || ldl < n ||
+      (precision != NNLS_FP64 && precision != NNLS_FP32_IR))
+    return NNLS_ERR_INVALID_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return NNLS_ERR_DEVICE;
+  const bool fp32 = precision == NNLS_FP32_IR;
+  TRY(ensure(h, h->ctrl, sizeof(Ctrl)));
+  TRY(ensure_factor(h, n, fp32));
+  launch_ctrl_set_state(h->stream, (Ctrl*)h->ctrl.p, INT32_MAX, 0, 0, 0);
+  h->epoch += 1;
+  FactorArgs fa = factor_args(h, n, nullptr, nullptr, S, lds, false);
+  launch_cholesky(h->stream, fa, fp32);
+  launch_tiles_to_dense(h->stream, n, fa.nb, h->Lt.p, fp32, L, ldl);
+  TRY(sync_read(h, h->h_ctrl, h->ctrl.p, sizeof(Ctrl)));
+  const Ctrl c = *h->h_ctrl;
+  if (c.status == NNLS_ERR_NOT_PD) {
+    if (failed) *failed = c.failed_pos;
+    return NNLS_ERR_NOT_PD;
+  }
+  return c.status;
+}
+
+int nnls_spd_solve(nnls_handle* h, int32_t n, const double* S, int32_t lds, const double* rhs, double* x,
+                   int32_t* failed) {
+  if (failed) *failed = -1;
+  if (!h || n < 1 || !S || !rhs || !x || lds < n) return NNLS_ERR_INVALID_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return NNLS_ERR_DEVICE;
+  TRY(ensure(h, h->ctrl, sizeof(Ctrl)));
+  TRY(ensure_factor(h, n, false));
+  launch_ctrl_set_state(h->stream, (Ctrl*)h->ctrl.p, INT32_MAX, 0, 0, 0);
+  h->epoch += 1;
+  FactorArgs fa = factor_args(h, n, nullptr, nullptr, S, lds, false);
+  launch_cholesky(h->stream, fa, false);
+  SolveArgs sa = solve_args(h, n, nullptr, rhs, x);
+  launch_trsv(h->stream, sa, false);
+  TRY(sync_read(h, h->h_ctrl, h->ctrl.p, sizeof(Ctrl)));
+  const Ctrl c = *h->h_ctrl;
+  if (c.status == NNLS_ERR_NOT_PD && failed) *failed = c.failed_pos;
+  return c.status;
+}
+
+int nnls_dual_csc(nnls_handle* h, int32_t m, int32_t n, int64_t nnz, const int32_t* colptr,
+                  const int32_t* rowidx, const double* val, const double* b, const uint8_t* free_flags,
+                  const double* x, double* r, double* y) {
+  if (!h || n < 1 || m < 1 || nnz < 0 || nnz > INT32_MAX || !colptr || !b || !free_flags || !x || !y ||
+      (nnz > 0 && (!rowidx || !val)))
+    return NNLS_ERR_INVALID_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return NNLS_ERR_DEVICE;
+  Problem P;
+  std::memset(&P, 0, sizeof(P));
+  P.sparse = true;
+  P.m = m;
+  P.n = n;
+  P.nnz = nnz;
+  P.colptr = colptr;
+  P.rowidx = rowidx;
+  P.val = val;
+  P.b = b;
+  TRY(validate_device(h, P));
+  TRY(build_csr(h, P));
+  double* rr = r;
+  if (!rr) {
+    TRY(ensure(h, h->r, sizeof(double) * (size_t)m));
+    rr = (double*)h->r.p;
+  }
+  launch_residual_csr(h->stream, m, (const int32_t*)h->rowptr.p, (const int32_t*)h->colidx.p,
+                      (const double*)h->valr.p, x, b, rr);
+  launch_dual_csc(h->stream, n, colptr, rowidx, val, rr, free_flags, y);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return NNLS_OK;
+}
+
+int nnls_pivot_step(nnls_handle* h, int32_t n, double* x, double* y, uint8_t* free_flags, double tau,
+                    int32_t p_max, int32_t* state, int32_t* out) {
+  if (!h || n < 1 || !x || !y || !free_flags || !state || !out || !(tau >= 0.0) || p_max < 0)
+    return NNLS_ERR_INVALID_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return NNLS_ERR_DEVICE;
+  TRY(ensure(h, h->ctrl, sizeof(Ctrl)));
+  TRY(ensure(h, h->Flist, sizeof(int32_t) * (size_t)n));
+  TRY(ensure(h, h->pos, sizeof(int32_t) * (size_t)n));
+  const int N = state[0] < 0 ? INT32_MAX : state[0];
+  launch_ctrl_set_state(h->stream, (Ctrl*)h->ctrl.p, N, state[1], 0, 0);
+  launch_pivot_control(h->stream, n, x, y, free_flags, (int32_t*)h->Flist.p, (int32_t*)h->pos.p,
+                       (Ctrl*)h->ctrl.p, tau, p_max, INT32_MAX);
+  TRY(sync_read(h, h->h_ctrl, h->ctrl.p, sizeof(Ctrl)));
+  const Ctrl c = *h->h_ctrl;
+  state[0] = c.N == INT32_MAX ? -1 : c.N;
+  state[1] = c.p;
+  out[0] = c.k;
+  out[1] = c.branch;
+  out[2] = c.rmax;
+  out[3] = c.done ? -1 : c.n_free;
+  return c.status;
+}
+
+}  // extern "C"

@@ -1,0 +1,362 @@
+// Setup kernels, run once per problem: input validation, a row-major (CSR) copy of A,
+// the cached Gram matrix H = A^T A from column dot products (Sec. 3 of the tsnnls paper)
+// and the right-hand side c = A^T b of the normal equations (Sec. 2.1).
+//
+// H is kept as its lower triangle in a padded CSC layout: column j holds the rows i >= j
+// with a structurally nonzero a_i^T a_j, ascending.  The pivot loop only ever gathers
+// lower tiles of the F-principal block from it, so the upper half is never needed.
+#include "nnls_internal.h"
+
+namespace nnls {
+
+namespace {
+
+constexpr int GRAM_CHUNK = 2048;   // dense accumulator span per wave (doubles)
+
+__global__ void k_validate_csc(int m, int n, int64_t nnz, const int32_t* __restrict__ colptr,
+                               const int32_t* __restrict__ rowidx, const double* __restrict__ val,
+                               const double* __restrict__ b, int32_t* err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+    const int64_t c0 = colptr[j], c1 = colptr[j + 1];
+    if (j == 0 && c0 != 0) atomicOr(&err[0], 1);
+    if (j == n - 1 && c1 != nnz) atomicOr(&err[0], 1);
+    if (c0 < 0 || c1 < c0 || c1 > nnz) {
+      atomicOr(&err[0], 1);
+      continue;
+    }
+    int prev = -1;
+    for (int64_t e = c0; e < c1; ++e) {
+      const int r = rowidx[e];
+      if (r <= prev || r >= m) {
+        atomicOr(&err[0], 2);
+        break;
+      }
+      prev = r;
+      if (!isfinite(val[e])) atomicOr(&err[1], 1);
+    }
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride)
+    if (!isfinite(b[i])) atomicOr(&err[1], 2);
+}
+
+__global__ void k_validate_dense(int m, int n, const double* __restrict__ A, int lda,
+                                 const double* __restrict__ b, int32_t* err) {
+  const int64_t total = (int64_t)m * n;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t j = e / m, i = e - j * m;
+    if (!isfinite(A[i + j * lda])) atomicOr(&err[1], 1);
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride)
+    if (!isfinite(b[i])) atomicOr(&err[1], 2);
+}
+
+__global__ void k_fill_f64(double* p, int64_t count, double v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
+}
+
+__global__ void k_fill_2d(int rows, int cols, double* p, int ld, double v) {
+  const int64_t total = (int64_t)rows * cols;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t c = e / rows, r = e - c * rows;
+    p[r + c * ld] = v;
+  }
+}
+
+__global__ void k_row_count(int64_t nnz, const int32_t* __restrict__ rowidx, int32_t* rowcnt) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride)
+    atomicAdd(&rowcnt[rowidx[e]], 1);
+}
+
+// Exclusive scan of count[0..n) into out[0..n], out[n] = total.  One workgroup of 1024
+// threads; each thread scans a contiguous segment.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(1024) void k_scan_single(int64_t n, const Tin* count,
+                                                      Tout* out) {
+  __shared__ Tout s_wave[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t seg = (n + 1023) / 1024;
+  const int64_t s0 = min(n, (int64_t)tid * seg), s1 = min(n, s0 + seg);
+  Tout local = 0;
+  for (int64_t i = s0; i < s1; ++i) local += (Tout)count[i];
+  // inclusive scan inside the wave
+  Tout v = local;
+  for (int d = 1; d < 64; d <<= 1) {
+    Tout o = __shfl_up(v, d, 64);
+    if (lane >= d) v += o;
+  }
+  if (lane == 63) s_wave[w] = v;
+  __syncthreads();
+  if (tid == 0) {
+    Tout run = 0;
+    for (int q = 0; q < 16; ++q) {
+      Tout t = s_wave[q];
+      s_wave[q] = run;
+      run += t;
+    }
+  }
+  __syncthreads();
+  Tout off = s_wave[w] + v - local;
+  for (int64_t i = s0; i < s1; ++i) {   // read before write: count may alias out
+    const Tout c = (Tout)count[i];
+    out[i] = off;
+    off += c;
+  }
+  if (tid == 1023) out[n] = off;   // thread 1023 owns the last (possibly empty) segment
+}
+
+__global__ void k_csr_fill(int n, const int32_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
+                           const double* __restrict__ val, const int32_t* __restrict__ rowptr,
+                           int32_t* fill, int32_t* colidx, double* valr) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  for (int e = colptr[j]; e < colptr[j + 1]; ++e) {
+    const int r = rowidx[e];
+    const int slot = rowptr[r] + atomicAdd(&fill[r], 1);
+    colidx[slot] = j;
+    valr[slot] = val[e];
+  }
+}
+
+// Sort each CSR row by column so that every later row sum has a fixed order.
+__global__ void k_csr_sort(int m, const int32_t* __restrict__ rowptr, int32_t* colidx, double* valr) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= m) return;
+  const int s = rowptr[r], e = rowptr[r + 1];
+  for (int i = s + 1; i < e; ++i) {
+    const int c = colidx[i];
+    const double v = valr[i];
+    int k = i - 1;
+    while (k >= s && colidx[k] > c) {
+      colidx[k + 1] = colidx[k];
+      valr[k + 1] = valr[k];
+      --k;
+    }
+    colidx[k + 1] = c;
+    valr[k + 1] = v;
+  }
+}
+
+// Upper bound of the entries of column j of lower(H): sum of the lengths of the rows
+// that column j touches.
+__global__ void k_gram_bound(int n, const int32_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
+                             const int32_t* __restrict__ rowptr, int64_t* ub) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int64_t s = 0;
+  for (int e = colptr[j]; e < colptr[j + 1]; ++e) {
+    const int r = rowidx[e];
+    s += rowptr[r + 1] - rowptr[r];
+  }
+  ub[j] = s;
+}
+
+// H_ij = a_i^T a_j for i >= j.  One wave per column j; a dense accumulator of
+// GRAM_CHUNK doubles in LDS covers rows [base, base + GRAM_CHUNK) per pass.  The rows r
+// of column j are visited in ascending order and, inside row r, each i appears once, so
+// every H_ij is summed in ascending r: a fixed order, independent of the launch.
+__global__ __launch_bounds__(256) void k_gram_lower(
+    int n, const int32_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
+    const double* __restrict__ val, const int32_t* __restrict__ rowptr,
+    const int32_t* __restrict__ colidx, const double* __restrict__ valr,
+    const int64_t* __restrict__ hptr, int32_t* __restrict__ hcnt, int32_t* __restrict__ hrow,
+    double* __restrict__ hval) {
+  __shared__ double s_acc[4][GRAM_CHUNK];
+  __shared__ uint32_t s_mark[4][GRAM_CHUNK / 32];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = blockIdx.x * 4 + w;
+  if (j >= n) return;   // whole wave leaves; no workgroup barrier follows
+  double* acc = s_acc[w];
+  uint32_t* mark = s_mark[w];
+  const int cs = colptr[j], ce = colptr[j + 1];
+  const int64_t out = hptr[j];
+  int count = 0;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int base = j; base < n; base += GRAM_CHUNK) {
+    for (int q = lane; q < GRAM_CHUNK; q += 64) acc[q] = 0.0;
+    for (int q = lane; q < GRAM_CHUNK / 32; q += 64) mark[q] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    for (int e = cs; e < ce; ++e) {
+      const int r = rowidx[e];
+      const double a = val[e];
+      const int rs = rowptr[r], re = rowptr[r + 1];
+      for (int t = rs + lane; t < re; t += 64) {
+        const int i = colidx[t];
+        const int q = i - base;
+        if (q >= 0 && q < GRAM_CHUNK) {
+          acc[q] = fma(a, valr[t], acc[q]);
+          atomicOr(&mark[q >> 5], 1u << (q & 31));
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    for (int q0 = 0; q0 < GRAM_CHUNK && base + q0 < n; q0 += 64) {
+      const int q = q0 + lane;
+      const bool hit = (base + q < n) && ((mark[q >> 5] >> (q & 31)) & 1u);
+      const uint64_t bal = __ballot(hit);
+      if (hit) {
+        const int slot = count + __popcll(bal & lt_mask);
+        hrow[out + slot] = base + q;
+        hval[out + slot] = acc[q];
+      }
+      count += __popcll(bal);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (lane == 0) hcnt[j] = count;
+}
+
+// out_j = scale * sum_r a_rj v_r  (ascending r), one thread per column.
+__global__ void k_spmvT_csc(int n, const int32_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
+                            const double* __restrict__ val, const double* __restrict__ v,
+                            double* __restrict__ out, double scale) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int e = colptr[j]; e < colptr[j + 1]; ++e) s = fma(val[e], v[rowidx[e]], s);
+  out[j] = scale * s;
+}
+
+__global__ void k_lower_to_dense(int n, GramLower g, double* H, int ldh) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t s = g.hptr[j];
+  for (int q = 0; q < g.hcnt[j]; ++q) {
+    const int i = g.hrow[s + q];
+    const double v = g.hval[s + q];
+    H[i + (int64_t)j * ldh] = v;
+    H[j + (int64_t)i * ldh] = v;
+  }
+}
+
+// Dense H = A^T A, 16 x 16 output tile per workgroup, rows of A staged through LDS in
+// slabs of 16; each entry is summed in ascending row order.
+__global__ __launch_bounds__(256) void k_gram_dense(int m, int n, const double* __restrict__ A, int lda,
+                                                    double* __restrict__ H, int ldh) {
+  __shared__ double sa[16][17], sb[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int i = blockIdx.y * 16 + ty, j = blockIdx.x * 16 + tx;
+  const int ci = blockIdx.y * 16 + tx, cj = blockIdx.x * 16 + tx;
+  double s = 0.0;
+  for (int r0 = 0; r0 < m; r0 += 16) {
+    const int r = r0 + ty;
+    sa[ty][tx] = (r < m && ci < n) ? A[r + (int64_t)ci * lda] : 0.0;   // sa[row][col i]
+    sb[ty][tx] = (r < m && cj < n) ? A[r + (int64_t)cj * lda] : 0.0;
+    __syncthreads();
+    for (int q = 0; q < 16; ++q) s = fma(sa[q][ty], sb[q][tx], s);
+    __syncthreads();
+  }
+  if (i < n && j < n) H[i + (int64_t)j * ldh] = s;
+}
+
+// out_j = scale * sum_r A_rj v_r: one wave per column, fixed lane-stride partial sums and
+// a fixed shuffle tree.
+__global__ __launch_bounds__(256) void k_gemvT_dense(int m, int n, const double* __restrict__ A, int lda,
+                                                     const double* __restrict__ v, double* __restrict__ out,
+                                                     double scale) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= n) return;
+  const double* col = A + (int64_t)j * lda;
+  double s = 0.0;
+  for (int r = lane; r < m; r += 64) s = fma(col[r], v[r], s);
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+  if (lane == 0) out[j] = scale * s;
+}
+
+inline int blocks_for(int64_t n, int bs, int cap = 8192) {
+  int64_t b = (n + bs - 1) / bs;
+  if (b < 1) b = 1;
+  return (int)(b > cap ? cap : b);
+}
+
+}  // namespace
+
+void launch_fill(hipStream_t s, double* p, int64_t count, double v) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(count, 256)), dim3(256), 0, s, p, count, v);
+}
+
+void launch_fill_i32(hipStream_t s, int32_t* p, int64_t count, int32_t v) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(count, 256)), dim3(256), 0, s, p, count, v);
+}
+
+void launch_fill_2d(hipStream_t s, int rows, int cols, double* p, int ld, double v) {
+  hipLaunchKernelGGL(k_fill_2d, dim3(blocks_for((int64_t)rows * cols, 256)), dim3(256), 0, s, rows, cols, p, ld, v);
+}
+
+void launch_validate_csc(hipStream_t s, int m, int n, int64_t nnz, const int32_t* colptr,
+                         const int32_t* rowidx, const double* val, const double* b, int32_t* err) {
+  hipLaunchKernelGGL(k_validate_csc, dim3(blocks_for(m > n ? m : n, 256, 2048)), dim3(256), 0, s,
+                     m, n, nnz, colptr, rowidx, val, b, err);
+}
+
+void launch_validate_dense(hipStream_t s, int m, int n, const double* A, int lda, const double* b,
+                           int32_t* err) {
+  hipLaunchKernelGGL(k_validate_dense, dim3(blocks_for((int64_t)m * n, 256, 4096)), dim3(256), 0, s,
+                     m, n, A, lda, b, err);
+}
+
+void launch_build_csr(hipStream_t s, int m, int n, int64_t nnz, const int32_t* colptr,
+                      const int32_t* rowidx, const double* val, int32_t* rowcnt, int32_t* rowptr,
+                      int32_t* colidx, double* valr) {
+  launch_fill_i32(s, rowcnt, m, 0);
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_row_count, dim3(blocks_for(nnz, 256)), dim3(256), 0, s, nnz, rowidx, rowcnt);
+  hipLaunchKernelGGL((k_scan_single<int32_t, int32_t>), dim3(1), dim3(1024), 0, s, (int64_t)m,
+                     (const int32_t*)rowcnt, rowptr);
+  launch_fill_i32(s, rowcnt, m, 0);
+  hipLaunchKernelGGL(k_csr_fill, dim3(blocks_for(n, 256, 1 << 30)), dim3(256), 0, s, n, colptr, rowidx,
+                     val, (const int32_t*)rowptr, rowcnt, colidx, valr);
+  hipLaunchKernelGGL(k_csr_sort, dim3(blocks_for(m, 256, 1 << 30)), dim3(256), 0, s, m,
+                     (const int32_t*)rowptr, colidx, valr);
+}
+
+void launch_gram_bound(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx,
+                       const int32_t* rowptr, int64_t* hptr) {
+  // ub into hptr[0..n), then an in-place exclusive scan into hptr[0..n]
+  hipLaunchKernelGGL(k_gram_bound, dim3(blocks_for(n, 256, 1 << 30)), dim3(256), 0, s, n, colptr,
+                     rowidx, rowptr, hptr);
+  hipLaunchKernelGGL((k_scan_single<int64_t, int64_t>), dim3(1), dim3(1024), 0, s, (int64_t)n,
+                     (const int64_t*)hptr, hptr);
+}
+
+void launch_gram_lower(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx,
+                       const double* val, const int32_t* rowptr, const int32_t* colidx,
+                       const double* valr, const int64_t* hptr, int32_t* hcnt, int32_t* hrow,
+                       double* hval) {
+  hipLaunchKernelGGL(k_gram_lower, dim3((n + 3) / 4), dim3(256), 0, s, n, colptr, rowidx, val, rowptr,
+                     colidx, valr, hptr, hcnt, hrow, hval);
+}
+
+void launch_spmvT_csc(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx,
+                      const double* val, const double* v, double* out, double scale) {
+  hipLaunchKernelGGL(k_spmvT_csc, dim3(blocks_for(n, 256, 1 << 30)), dim3(256), 0, s, n, colptr, rowidx,
+                     val, v, out, scale);
+}
+
+void launch_lower_to_dense(hipStream_t s, int n, GramLower g, double* H, int ldh) {
+  hipLaunchKernelGGL(k_lower_to_dense, dim3(blocks_for(n, 256, 1 << 30)), dim3(256), 0, s, n, g, H, ldh);
+}
+
+void launch_gram_dense(hipStream_t s, int m, int n, const double* A, int lda, double* H, int ldh) {
+  dim3 grid((n + 15) / 16, (n + 15) / 16);
+  hipLaunchKernelGGL(k_gram_dense, grid, dim3(256), 0, s, m, n, A, lda, H, ldh);
+}
+
+void launch_gemvT_dense(hipStream_t s, int m, int n, const double* A, int lda, const double* v,
+                        double* out, double scale) {
+  hipLaunchKernelGGL(k_gemvT_dense, dim3((n + 3) / 4), dim3(256), 0, s, m, n, A, lda, v, out, scale);
+}
+
+}  // namespace nnls

@@ -1,0 +1,104 @@
+// Residual and dual of a complementary basic solution (Eq. 5 of the tsnnls paper):
+//   r   = A_F x_F - b      (x holds x_F on F and exact zeros on G)
+//   y_G = A_G^T r,  y_F = 0
+// Both are FP64 and memory bound.  r is a row sweep over the CSR copy of A (each row sum
+// in ascending column order); y is a column sweep over the CSC input (ascending row
+// order), so both results are independent of the launch configuration.
+#include "nnls_internal.h"
+
+namespace nnls {
+
+namespace {
+
+// One wave handles 64 consecutive rows, one row per lane.
+__global__ __launch_bounds__(256) void k_residual_csr(int m, const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ colidx,
+                                                      const double* __restrict__ valr,
+                                                      const double* __restrict__ x,
+                                                      const double* __restrict__ b,
+                                                      double* __restrict__ r) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double s = 0.0;
+  const int e1 = rowptr[i + 1];
+  for (int e = rowptr[i]; e < e1; ++e) s = fma(valr[e], x[colidx[e]], s);
+  r[i] = s - b[i];
+}
+
+// 16 lanes per column: each lane takes a fixed stride of the column's entries, then a
+// fixed xor tree combines the 16 partial sums.
+__global__ __launch_bounds__(256) void k_dual_csc(int n, const int32_t* __restrict__ colptr,
+                                                  const int32_t* __restrict__ rowidx,
+                                                  const double* __restrict__ val,
+                                                  const double* __restrict__ r,
+                                                  const uint8_t* __restrict__ flags,
+                                                  double* __restrict__ y) {
+  const int sub = threadIdx.x & 15;
+  const int j = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const bool active = j < n;
+  double s = 0.0;
+  const bool free_j = active ? (flags[j] != 0) : true;
+  if (active && !free_j) {
+    const int e1 = colptr[j + 1];
+    for (int e = colptr[j] + sub; e < e1; e += 16) s = fma(val[e], r[rowidx[e]], s);
+  }
+  for (int d = 8; d >= 1; d >>= 1) s += __shfl_xor(s, d, 16);
+  if (active && sub == 0) y[j] = free_j ? 0.0 : s;
+}
+
+// Dense r = A x - b: one thread per row, ascending column order.
+__global__ __launch_bounds__(256) void k_residual_dense(int m, int n, const double* __restrict__ A,
+                                                        int lda, const double* __restrict__ x,
+                                                        const double* __restrict__ b,
+                                                        double* __restrict__ r) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double s = 0.0;
+  for (int j = 0; j < n; ++j) s = fma(A[i + (int64_t)j * lda], x[j], s);
+  r[i] = s - b[i];
+}
+
+// Dense y_j = a_j^T r on G: one wave per column.
+__global__ __launch_bounds__(256) void k_dual_dense(int m, int n, const double* __restrict__ A, int lda,
+                                                    const double* __restrict__ r,
+                                                    const uint8_t* __restrict__ flags,
+                                                    double* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= n) return;
+  if (flags[j]) {
+    if (lane == 0) y[j] = 0.0;
+    return;
+  }
+  const double* col = A + (int64_t)j * lda;
+  double s = 0.0;
+  for (int q = lane; q < m; q += 64) s = fma(col[q], r[q], s);
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+  if (lane == 0) y[j] = s;
+}
+
+}  // namespace
+
+void launch_residual_csr(hipStream_t s, int m, const int32_t* rowptr, const int32_t* colidx,
+                         const double* valr, const double* x, const double* b, double* r) {
+  hipLaunchKernelGGL(k_residual_csr, dim3((m + 255) / 256), dim3(256), 0, s, m, rowptr, colidx, valr, x, b, r);
+}
+
+void launch_dual_csc(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx,
+                     const double* val, const double* r, const uint8_t* flags, double* y) {
+  const int64_t threads = (int64_t)n * 16;
+  hipLaunchKernelGGL(k_dual_csc, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, n, colptr,
+                     rowidx, val, r, flags, y);
+}
+
+void launch_residual_dense(hipStream_t s, int m, int n, const double* A, int lda,
+                           const double* x, const double* b, double* r) {
+  hipLaunchKernelGGL(k_residual_dense, dim3((m + 255) / 256), dim3(256), 0, s, m, n, A, lda, x, b, r);
+}
+
+void launch_dual_dense(hipStream_t s, int m, int n, const double* A, int lda, const double* r,
+                       const uint8_t* flags, double* y) {
+  hipLaunchKernelGGL(k_dual_dense, dim3((n + 3) / 4), dim3(256), 0, s, m, n, A, lda, r, flags, y);
+}
+
+}  // namespace nnls

@@ -1,0 +1,133 @@
+// Internal declarations shared by the HIP translation units of the NNLS library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/nnls.h"
+
+namespace nnls {
+
+constexpr int TILE = 64;          // Cholesky / triangular-solve tile edge
+constexpr int TILE_ELEMS = TILE * TILE;
+
+// Device-resident control block of one solve.  Written by the pivot-control kernel and by
+// the factorisation kernels; read back by the host once per pivot iteration.
+struct Ctrl {
+  int32_t k;           // infeasible count of the last classify step
+  int32_t branch;      // exchange branch taken (-1 when k == 0)
+  int32_t rmax;        // largest infeasible index
+  int32_t N;           // best infeasible count so far (INT32_MAX = infinity)
+  int32_t p;           // remaining non-improving block exchanges
+  int32_t iter;        // pivot iterations done
+  int32_t n_free;      // |F| after the exchange
+  int32_t done;        // 1: feasible split reached, or stop
+  int32_t status;      // nnls_status raised on the device (NOT_PD, DEVICE, MAXITER)
+  int32_t failed_pos;  // first non-positive pivot position in F (INT32_MAX: none)
+  int32_t abort;       // set when a device-side wait exceeds its bound
+  int32_t chol_ticket; // work-queue counters of the dataflow kernels
+  int32_t fwd_ticket;
+  int32_t bwd_ticket;
+  int32_t pad0, pad1;
+  double min_margin;   // smallest |v| over the tested entries that were not zeroed
+};
+
+// Lower-triangle Gram matrix in padded CSC: column j occupies
+// [hptr[j], hptr[j] + hcnt[j]) of hrow / hval, rows ascending and >= j.
+struct GramLower {
+  const int64_t* hptr;
+  const int32_t* hcnt;
+  const int32_t* hrow;
+  const double* hval;
+};
+
+// Tile index of lower tile (I, J), I >= J, in column-major packed order.
+__host__ __device__ inline int64_t tile_index(int I, int J, int nb) {
+  return (int64_t)J * nb - (int64_t)J * (J - 1) / 2 + (I - J);
+}
+__host__ __device__ inline int64_t tile_count(int nb) { return (int64_t)nb * (nb + 1) / 2; }
+
+// ---------------------------------------------------------------- launchers
+// setup (k_setup.hip)
+void launch_validate_csc(hipStream_t s, int m, int n, int64_t nnz, const int32_t* colptr,
+                         const int32_t* rowidx, const double* val, const double* b, int32_t* err);
+void launch_validate_dense(hipStream_t s, int m, int n, const double* A, int lda, const double* b,
+                           int32_t* err);
+void launch_build_csr(hipStream_t s, int m, int n, int64_t nnz, const int32_t* colptr,
+                      const int32_t* rowidx, const double* val, int32_t* rowcnt, int32_t* rowptr,
+                      int32_t* colidx, double* valr);
+void launch_gram_bound(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx,
+                       const int32_t* rowptr, int64_t* hptr);
+void launch_gram_lower(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx,
+                       const double* val, const int32_t* rowptr, const int32_t* colidx,
+                       const double* valr, const int64_t* hptr, int32_t* hcnt, int32_t* hrow,
+                       double* hval);
+void launch_spmvT_csc(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx,
+                      const double* val, const double* v, double* out, double scale);
+void launch_gram_dense(hipStream_t s, int m, int n, const double* A, int lda, double* H, int ldh);
+void launch_gemvT_dense(hipStream_t s, int m, int n, const double* A, int lda, const double* v,
+                        double* out, double scale);
+void launch_lower_to_dense(hipStream_t s, int n, GramLower g, double* H, int ldh);
+void launch_fill(hipStream_t s, double* p, int64_t count, double v);
+void launch_fill_i32(hipStream_t s, int32_t* p, int64_t count, int32_t v);
+void launch_fill_2d(hipStream_t s, int rows, int cols, double* p, int ld, double v);
+
+// pivot control (k_pivot.hip)
+void launch_pivot_init(hipStream_t s, int n, const double* c, double* x, double* y,
+                       uint8_t* flags, Ctrl* ctrl, int p_max);
+void launch_pivot_control(hipStream_t s, int n, double* x, double* y, uint8_t* flags,
+                          int32_t* Flist, int32_t* pos, Ctrl* ctrl, double tau, int p_max,
+                          int max_iter);
+void launch_ctrl_set_state(hipStream_t s, Ctrl* ctrl, int N, int p, int iter, int max_iter_flag);
+
+// residual and dual (k_spmv.hip)
+void launch_residual_csr(hipStream_t s, int m, const int32_t* rowptr, const int32_t* colidx,
+                         const double* valr, const double* x, const double* b, double* r);
+void launch_dual_csc(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx,
+                     const double* val, const double* r, const uint8_t* flags, double* y);
+void launch_residual_dense(hipStream_t s, int m, int n, const double* A, int lda,
+                           const double* x, const double* b, double* r);
+void launch_dual_dense(hipStream_t s, int m, int n, const double* A, int lda, const double* r,
+                       const uint8_t* flags, double* y);
+
+// factorisation and triangular solves (k_chol.hip)
+struct FactorArgs {
+  int nF;                 // order of the F-block
+  int nb;                 // ceil(nF / TILE)
+  const int32_t* Flist;   // F positions -> column numbers (nullptr: identity)
+  const int32_t* pos;     // column number -> F position or -1 (sparse source only)
+  GramLower lower;        // sparse source (used when dense == nullptr)
+  const double* dense;    // dense symmetric source, column-major
+  int64_t ldd;
+  void* Ltiles;           // tile storage, tile_count(nb) tiles of TILE_ELEMS
+  void* Dinv;             // nb inverted diagonal tiles
+  int32_t* tile_flags;    // tile_count(nb) epoch flags
+  int epoch;
+  Ctrl* ctrl;
+  uint64_t wait_ticks;    // bound of one device-side wait, in wall-clock ticks
+};
+void launch_cholesky(hipStream_t s, const FactorArgs& a, bool fp32);
+// z = L^-1 rhs (rhs gathered through Flist when gather != nullptr); x = L^-T z and
+// scatter x through Flist into out (when out != nullptr) and into xF.
+struct SolveArgs {
+  int nF, nb;
+  const int32_t* Flist;
+  const void* Ltiles;
+  const void* Dinv;
+  const double* rhs_full;   // indexed by column number (through Flist) ...
+  const double* rhs_dense;  // ... or by F position (used when rhs_full == nullptr)
+  double* z;                // nb * TILE
+  double* xF;               // nb * TILE
+  double* out;              // optional scatter target, indexed by column number
+  int32_t* zflags;          // nb
+  int32_t* xflags;          // nb
+  int epoch;
+  Ctrl* ctrl;
+  uint64_t wait_ticks;
+};
+void launch_trsv(hipStream_t s, const SolveArgs& a, bool fp32);
+void launch_tiles_to_dense(hipStream_t s, int n, int nb, const void* Ltiles, bool fp32,
+                           double* L, int ldl);
+void launch_reset_tickets(hipStream_t s, Ctrl* ctrl);
+
+}  // namespace nnls

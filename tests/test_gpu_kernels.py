@@ -1,0 +1,159 @@
+"""Parity of each step of the pivot iteration, called through the C ABI on the GPU,
+against the CPU oracle's step functions and textbook bounds."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import classify, dual, exchange_rule, gram
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_cs_0408029_amd as N  # noqa: E402
+from _gpu_util import DEV, colmajor_dev, csc_dev, t  # noqa: E402
+
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def h():
+    with N.Handle(0) as hh:
+        yield hh
+
+
+@pytest.mark.parametrize("m,n,density,seed", [(300, 70, 0.1, 1), (2000, 400, 0.02, 2),
+                                              (5000, 2500, 0.003, 3), (64, 64, 0.5, 4)])
+def test_gram_and_rhs(h, m, n, density, seed):
+    inst = W.sparse_small(seed, m=m, n=n, density=density)
+    A = inst.A
+    colptr, rowidx, val = csc_dev(A)
+    H = colmajor_dev(np.full((n, n), np.nan))
+    c = torch.empty(n, dtype=torch.float64, device=DEV)
+    assert N.nnls_gram_csc(h, m, n, colptr, rowidx, val, t(inst.b), H, c) == N.NNLS_OK
+    H_or, c_or = gram(A, inst.b)
+    H_or = H_or.toarray()
+    absA = abs(A)
+    bound = (absA.T @ absA).toarray() * (m * EPS) + 1e-300
+    Hg = H.cpu().numpy()
+    assert np.all(np.abs(Hg - H_or) <= bound)
+    assert np.array_equal(Hg, Hg.T)
+    assert np.allclose(c.cpu().numpy(), c_or, rtol=1e-13, atol=1e-13 * np.abs(c_or).max())
+
+
+def spd(n, seed, cond=100.0):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    ev = np.geomspace(1.0, 1.0 / cond, n)
+    return (Q * ev) @ Q.T
+
+
+@pytest.mark.parametrize("n", [1, 2, 15, 17, 63, 64, 65, 127, 128, 129, 200, 255, 300, 700])
+def test_cholesky_fp64(h, n):
+    S = spd(n, n)
+    Sd = colmajor_dev(S)
+    L = colmajor_dev(np.full((n, n), np.nan))
+    st, failed = N.nnls_cholesky(h, Sd, L, N.NNLS_FP64)
+    assert st == N.NNLS_OK and failed == -1
+    Lg = L.cpu().numpy()
+    assert np.all(np.triu(Lg, 1) == 0)
+    assert np.linalg.norm(Lg @ Lg.T - S) <= 4 * n * EPS * np.linalg.norm(S)
+    assert np.allclose(Lg, np.linalg.cholesky(S), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [1, 33, 64, 100, 257])
+def test_cholesky_fp32(h, n):
+    S = spd(n, 10 + n)
+    Sd = colmajor_dev(S)
+    L = colmajor_dev(np.zeros((n, n)))
+    st, failed = N.nnls_cholesky(h, Sd, L, N.NNLS_FP32_IR)
+    assert st == N.NNLS_OK
+    Lg = L.cpu().numpy()
+    e32 = np.finfo(np.float32).eps
+    assert np.linalg.norm(Lg @ Lg.T - S) <= 4 * n * e32 * np.linalg.norm(S)
+
+
+@pytest.mark.parametrize("n,k", [(10, 3), (100, 70), (130, 128), (64, 0)])
+def test_cholesky_breakdown_position(h, n, k):
+    """A negative pivot at position k: the factor reports k, as LAPACK's info does."""
+    rng = np.random.default_rng(k)
+    S = np.eye(n) * 4.0 + 0.01 * rng.standard_normal((n, n))
+    S = (S + S.T) / 2
+    S[k, k] = -1.0
+    st, failed = N.nnls_cholesky(h, colmajor_dev(S), colmajor_dev(np.zeros((n, n))), N.NNLS_FP64)
+    assert st == N.NNLS_ERR_NOT_PD and failed == k
+
+
+@pytest.mark.parametrize("n", [1, 5, 64, 65, 190, 513])
+def test_spd_solve(h, n):
+    S = spd(n, 100 + n, cond=1e3)
+    rhs = np.random.default_rng(n).standard_normal(n)
+    x = torch.empty(n, dtype=torch.float64, device=DEV)
+    st, failed = N.nnls_spd_solve(h, colmajor_dev(S), t(rhs), x)
+    assert st == N.NNLS_OK
+    xr = np.linalg.solve(S, rhs)
+    assert np.linalg.norm(x.cpu().numpy() - xr) <= 1e3 * 50 * n * EPS * np.linalg.norm(xr)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_dual_step(h, seed):
+    inst = W.sparse_small(seed, m=1500, n=500, density=0.03)
+    rng = np.random.default_rng(seed)
+    free = rng.random(inst.n) < 0.4
+    x = np.where(free, rng.standard_normal(inst.n), 0.0)
+    colptr, rowidx, val = csc_dev(inst.A)
+    yd = torch.full((inst.n,), np.nan, dtype=torch.float64, device=DEV)
+    rd = torch.empty(inst.m, dtype=torch.float64, device=DEV)
+    st = N.nnls_dual_csc(h, inst.m, inst.n, colptr, rowidx, val, t(inst.b), t(free, np.uint8),
+                         t(x), rd, yd)
+    assert st == N.NNLS_OK
+    idx_f, idx_g = np.flatnonzero(free), np.flatnonzero(~free)
+    y_or = np.zeros(inst.n)
+    y_or[idx_g] = dual(inst.A, inst.b, idx_f, x[idx_f], idx_g)
+    yg = yd.cpu().numpy()
+    assert np.all(yg[free] == 0.0)
+    absA = abs(inst.A)
+    r = inst.A @ x - inst.b
+    bound = (absA.T @ (absA @ np.abs(x) + np.abs(inst.b))) * 4 * inst.m * EPS
+    assert np.all(np.abs(yg - y_or) <= bound + 1e-300)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_pivot_step_matches_rule(h, seed):
+    """Classify, count, counter rule and exchange: bit-exact against the oracle's steps."""
+    rng = np.random.default_rng(seed)
+    n = [7, 64, 1000, 1023, 1025, 5000][seed]
+    free = rng.random(n) < 0.5
+    x = np.where(free, rng.standard_normal(n), 0.0)
+    y = np.where(~free, rng.standard_normal(n), 0.0)
+    # some entries inside the zeroing band, some exactly on its edge
+    for arr in (x, y):
+        k = rng.choice(n, size=max(1, n // 10), replace=False)
+        arr[k] = rng.uniform(-1e-12, 1e-12, size=k.size)
+    x[free & (rng.random(n) < 0.02)] = 1e-12
+    for N_in, p_in in [(-1, 3), (n, 0), (0, 2), (0, 0)]:
+        xo, yo, fo = x.copy(), y.copy(), free.copy()
+        infeasible, _ = classify(xo, yo, fo, 1e-12)
+        k = int(infeasible.sum())
+        xd, yd, fd = t(x), t(y), t(free, np.uint8)
+        state = [N_in, p_in]
+        st, out = N.nnls_pivot_step(h, xd, yd, fd, 1e-12, 3, state)
+        assert st == N.NNLS_OK
+        assert out[0] == k
+        Nprev = np.inf if N_in < 0 else N_in
+        if k == 0:
+            assert out[1] == -1
+            continue
+        N_new, p_new, branch = exchange_rule(k, Nprev, p_in, 3)
+        assert out[1] == branch and state == [N_new, p_new]
+        assert out[2] == int(np.flatnonzero(infeasible).max())
+        if branch == 2:
+            fo[out[2]] = not fo[out[2]]
+        else:
+            fo = fo ^ infeasible
+        assert np.array_equal(fd.cpu().numpy().astype(bool), fo)
+        assert out[3] == int(fo.sum())
+        xg, yg = xd.cpu().numpy(), yd.cpu().numpy()
+        # zeroed on the tested side, and x_G = 0, y_F = 0 on the new split
+        assert np.array_equal(xg[fo], xo[fo]) and np.all(xg[~fo] == 0)
+        assert np.array_equal(yg[~fo], yo[~fo]) and np.all(yg[fo] == 0)

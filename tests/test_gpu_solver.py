@@ -1,0 +1,190 @@
+"""Solver parity: the GPU pivot loop through the C ABI against the CPU oracle on the same
+seeded inputs.  The final free set must be identical; x and y must agree to 1e-10
+relative (FP64 path); the per-iteration trace (k, branch, N, p, |F|) must be identical
+whenever every sign test of the run was certified (no tested value within 1e-8 relative
+of the zeroing threshold)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import bpp_solve, kkt_residuals
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_cs_0408029_amd as N  # noqa: E402
+from _gpu_util import certified, oracle_trace, solve_csc, solve_dense  # noqa: E402
+
+RTOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def h():
+    with N.Handle(0) as hh:
+        yield hh
+
+
+def relerr(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def check_parity(res, st, info, x, y, trace, rtol=RTOL, scale=1.0):
+    assert st == N.NNLS_OK, N.status_string(st)
+    assert res.status == "ok"
+    assert info.iterations == res.iterations
+    assert info.n_free == int(res.free.sum())
+    assert np.array_equal(np.flatnonzero(x != 0), np.flatnonzero(res.x != 0))
+    assert relerr(x, res.x) <= rtol
+    assert np.linalg.norm(y - res.y) <= rtol * max(np.linalg.norm(res.y), 1.0)
+    assert np.all(x >= 0) and np.all(y >= 0) and np.dot(x, y) == 0.0
+    if certified(res, scale):
+        assert trace == oracle_trace(res)
+
+
+@pytest.mark.parametrize("seed", range(1001, 1006))
+def test_sparse_small_full_size(h, seed):
+    """m = 2000, n = 400, 2% Bernoulli N(0,1) plus diagonal, planted, FP64."""
+    inst = W.sparse_small(seed)
+    res = bpp_solve(inst.A, inst.b)
+    st, info, x, y, trace = solve_csc(h, inst.A, inst.b)
+    check_parity(res, st, info, x, y, trace)
+    assert np.array_equal(x > 0, inst.active)
+
+
+@pytest.mark.parametrize("m,n,seed", [(2400, 480, 7), (6000, 1200, 8), (15000, 3000, 9)])
+def test_sparse_large_recipe_reduced(h, m, n, seed):
+    inst = W.sparse_large(seed, m=m, n=n)
+    res = bpp_solve(inst.A, inst.b)
+    st, info, x, y, trace = solve_csc(h, inst.A, inst.b)
+    check_parity(res, st, info, x, y, trace)
+
+
+def test_sparse_large_full_size(h):
+    """m = 60000, n = 12000, 25 N(0,1) per column + band, 30% active, margin 1e-3 -- the
+    benchmark workload, element by element against the oracle and the planted answer."""
+    inst = W.sparse_large(1002)
+    st, info, x, y, trace = solve_csc(h, inst.A, inst.b)
+    assert st == N.NNLS_OK
+    assert np.array_equal(x > 0, inst.active)
+    assert np.abs(x - inst.x_star).max() <= 1e-10
+    assert np.abs(y - inst.y_star).max() <= 1e-10
+    res = bpp_solve(inst.A, inst.b)
+    check_parity(res, st, info, x, y, trace)
+    nx, ny, comp, dres = kkt_residuals(inst.A, inst.b, x, y)
+    assert nx == 0 and ny == 0 and comp == 0 and dres < 1e-9
+
+
+@pytest.mark.parametrize("m,n,seed", [(40, 16, 1), (300, 100, 2), (700, 256, 3), (1100, 520, 4)])
+def test_dense_planted(h, m, n, seed):
+    inst = W.dense_planted(seed, m, n)
+    res = bpp_solve(inst.A, inst.b)
+    st, info, x, y, trace = solve_dense(h, inst.A, inst.b)
+    check_parity(res, st, info, x, y, trace)
+    assert np.array_equal(x > 0, inst.active)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_dense_random_rhs(h, seed):
+    n = 1 + seed * 7
+    A, b = W.random_dense(500 + seed, 2 * n + 1, n)
+    res = bpp_solve(A, b)
+    st, info, x, y, trace = solve_dense(h, A, b)
+    check_parity(res, st, info, x, y, trace)
+
+
+@pytest.mark.parametrize("seed", range(1, 41))
+def test_ill_scaled_all_branches(h, seed):
+    """Small ill-scaled problems that take the budget and single-exchange branches."""
+    A, b = W.tiny_dense(seed)
+    res = bpp_solve(A, b)
+    st, info, x, y, trace = solve_dense(h, A, b)
+    assert st == N.NNLS_OK and res.status == "ok"
+    Hff = (A.T @ A)[np.ix_(res.free, res.free)]
+    kappa = np.linalg.cond(Hff) if res.free.any() else 1.0
+    tol = max(RTOL, 100 * kappa * np.finfo(float).eps)
+    if certified(res, np.abs(A).max() * np.abs(b).max(), rel=1e-6):
+        assert np.array_equal(x != 0, res.x != 0)
+        assert trace == oracle_trace(res)
+    assert relerr(x, res.x) <= tol
+
+
+def test_sparse_path_equals_dense_path(h):
+    inst = W.sparse_small(1001, m=800, n=200, density=0.05)
+    st1, info1, x1, y1, tr1 = solve_csc(h, inst.A, inst.b)
+    st2, info2, x2, y2, tr2 = solve_dense(h, inst.A.toarray(), inst.b)
+    assert st1 == st2 == N.NNLS_OK and tr1 == tr2
+    assert relerr(x1, x2) <= 1e-12
+
+
+def test_rerun_is_bitwise_identical(h):
+    inst = W.sparse_large(1002, m=6000, n=1200)
+    a = solve_csc(h, inst.A, inst.b)
+    b = solve_csc(h, inst.A, inst.b)
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3]) and a[4] == b[4]
+
+
+def test_empty_free_set(h):
+    A = np.array([[1.0, 0.0], [0.0, 1.0], [1.0, 1.0]])
+    b = np.array([-1.0, -2.0, 0.5])
+    st, info, x, y, trace = solve_dense(h, A, b)
+    assert st == N.NNLS_OK and info.iterations == 0 and trace == []
+    assert np.array_equal(x, [0.0, 0.0]) and np.allclose(y, -(A.T @ b))
+
+
+def test_breakdown_reports_column(h):
+    A = np.array([[1.0, 1.0, 0.0], [0.0, 0.0, 1.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    b = np.array([1.0, 1.0, 0.0, 0.0])
+    st, info, *_ = solve_dense(h, A, b)
+    assert st == N.NNLS_ERR_NOT_PD and info.failed_index == 1
+    res = bpp_solve(A, b)
+    assert res.status == "not_pd" and res.failed_index == info.failed_index
+    import scipy.sparse as sp
+    st, info, *_ = solve_csc(h, sp.csc_matrix(A), b)
+    assert st == N.NNLS_ERR_NOT_PD and info.failed_index == 1
+
+
+def test_iteration_cap(h):
+    A, b = W.tiny_dense(1)
+    st, info, *_ = solve_dense(h, A, b, max_iter=2)
+    res = bpp_solve(A, b, max_iter=2)
+    assert st == N.NNLS_ERR_MAXITER and res.status == "maxiter"
+    assert info.iterations == 2 and info.last_ninf == res.last_ninf
+
+
+def test_backup_rule_only(h):
+    """p_max = 0: every non-improving step is a single exchange."""
+    for seed in (1, 3, 5):
+        A, b = W.tiny_dense(seed)
+        res = bpp_solve(A, b, p_max=0)
+        st, info, x, y, trace = solve_dense(h, A, b, p_max=0)
+        assert st == N.NNLS_OK
+        assert np.array_equal(x != 0, res.x != 0)
+
+
+def test_invalid_inputs(h):
+    import scipy.sparse as sp
+    from _gpu_util import DEV, t
+    inst = W.sparse_small(3, m=50, n=20, density=0.2)
+    A = inst.A
+    m, n = A.shape
+    x = torch.empty(n, dtype=torch.float64, device=DEV)
+    y = torch.empty_like(x)
+
+    def run(colptr, rowidx, val, b, mm=m, nn=n):
+        st, _ = N.nnls_solve_csc(h, mm, nn, t(colptr, np.int32), t(rowidx, np.int32), t(val), t(b), x, y)
+        return st
+
+    cp, ri, va = A.indptr.copy(), A.indices.copy(), A.data.copy()
+    assert run(cp, ri, va, inst.b) == N.NNLS_OK
+    bad = cp.copy(); bad[3], bad[4] = bad[4], bad[3]
+    assert run(bad, ri, va, inst.b) == N.NNLS_ERR_INVALID_ARG          # colptr not monotone
+    bad = ri.copy(); bad[5] = m
+    assert run(cp, bad, va, inst.b) == N.NNLS_ERR_INVALID_ARG          # row out of range
+    bad = ri.copy(); s = cp[2]; bad[s], bad[s + 1] = bad[s + 1], bad[s]
+    assert run(cp, bad, va, inst.b) == N.NNLS_ERR_INVALID_ARG          # rows not ascending
+    bad = va.copy(); bad[7] = np.nan
+    assert run(cp, ri, bad, inst.b) == N.NNLS_ERR_INVALID_VALUE
+    bb = inst.b.copy(); bb[0] = np.inf
+    assert run(cp, ri, va, bb) == N.NNLS_ERR_INVALID_VALUE
+    assert run(cp[: n + 1], ri, va, inst.b[: n - 1], mm=n - 1) == N.NNLS_ERR_INVALID_ARG  # m < n
