@@ -1,0 +1,165 @@
+"""Benchmark: NNLS solves/s of the plain FP64 GPU path on one MI355X.
+
+One step = one complete solve (validation, Gram matrix and A^T b, the whole pivot loop)
+of a seeded synthetic instance whose inputs are already resident in device memory.
+Default workload: sparse m = 60000, n = 12000, 25 N(0,1) entries per column at random
+rows plus a three-wide diagonal band, 30% of variables active with margin 1e-3 (seed 1002).
+
+Prints one JSON line with solves/s, p50/p99 latency, the roofline of the dominant kernel
+(the tiled Cholesky, timed with HIP events on the solver's stream during the timed
+steps) and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix) peak
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E peak
+METRIC = "NNLS solves/s + p50/p99 latency vs plain FP64 GPU path at ≤1e-8 rel err"
+
+
+def make_instance(name: str):
+    import workloads as W
+    if name == "sparse_large":
+        return W.sparse_large(1002), ("sparse m=60000 n=12000, 25 N(0,1)/col + band(5,2.5,1.25), "
+                                      "30% active, margin 1e-3, seed 1002")
+    if name == "sparse_small":
+        return W.sparse_small(1001), ("sparse m=2000 n=400, Bernoulli(0.02) N(0,1) + diag, "
+                                      "50% active, margin 0.1, seed 1001")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(inst, budget_s: float):
+    """The oracle as it stands, on this host, over whole solves of the same instance until
+    budget_s of CPU work has been spent (at least one solve)."""
+    from oracle import bpp_solve
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    count = 0
+    while True:
+        res = bpp_solve(inst.A, inst.b)
+        count += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or count >= 5:
+            break
+    return {"value": count / el, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{count} whole solve(s) of the benchmark instance, {el:.1f} s",
+            "status": res.status}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="sparse_large")
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the solver has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_cs_0408029_amd as N
+
+    if not os.path.exists(N.LIB_PATH):
+        from paper_cs_0408029_amd.build import build
+        build()
+    inst, desc = make_instance(args.workload)
+    dev = torch.device("cuda:0")
+    A = inst.A
+    colptr = torch.from_numpy(A.indptr.astype(np.int32)).to(dev)
+    rowidx = torch.from_numpy(A.indices.astype(np.int32)).to(dev)
+    val = torch.from_numpy(A.data).to(dev)
+    b = torch.from_numpy(inst.b).to(dev)
+    x = torch.empty(inst.n, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    h = N.Handle(0)
+    opts = N.default_options()
+    popts = N.default_options(flags=N.NNLS_FLAG_PROFILE)
+
+    def step(o):
+        st, info = N.nnls_solve_csc(h, inst.m, inst.n, colptr, rowidx, val, b, x, y, o)
+        if st != N.NNLS_OK:
+            raise RuntimeError(f"solve failed: {N.status_string(st)}")
+        return info
+
+    for _ in range(args.warmup):
+        step(opts)
+    N.nnls_reset_profile(h)
+    torch.cuda.synchronize()
+    lat = []
+    iters = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        info = step(opts if args.no_profile else popts)
+        lat.append((time.perf_counter() - s0) * 1e3)
+        iters += info.iterations
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    prof = N.nnls_get_profile(h)
+
+    xh, yh = x.cpu().numpy(), y.cpu().numpy()
+    rel = float(np.linalg.norm(xh - inst.x_star) / np.linalg.norm(inst.x_star))
+    fmatch = bool(np.array_equal(xh > 0, inst.active))
+
+    chol = prof["cholesky"]
+    roof = None
+    if chol["launches"] > 0 and chol["ms"] > 0:
+        achieved = chol["work"] / (chol["ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": "k_chol_tiles<double>", "achieved": round(achieved, 3),
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                "traffic": None, "launches": chol["launches"],
+                "avg_launch_ms": round(chol["ms"] / chol["launches"], 4),
+                "work_per_launch": "nF^3/3 flops of the F-block factor"}
+    breakdown = {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in prof.items()
+                 if v["launches"]}
+    out = {
+        "metric": METRIC,
+        "value": round(args.steps / total, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total / args.steps * 1e3, 3),
+        "p50_ms": round(float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "pivot_iters_per_s": round(iters / total, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "path": "plain FP64 GPU path, one problem per call",
+                   "m": inst.m, "n": inst.n, "nnz": int(A.nnz)},
+        "rel_err_vs_planted": rel,
+        "free_set_match": fmatch,
+        "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in breakdown.items()},
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    h.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

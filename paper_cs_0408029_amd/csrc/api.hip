@@ -25,6 +25,8 @@ struct PendingEvent {
   int cls;
   hipEvent_t a, b;
   double work;
+  bool ended;
+  int64_t id;
 };
 
 double now_ms() {
@@ -40,7 +42,7 @@ struct nnls_handle {
   uint64_t wait_ticks = 0;
   // workspace
   DevBuf err, ctrl, rowcnt, rowptr, colidx, valr, hptr, hcnt, hrow, hval, c, r, flags, Flist, pos;
-  DevBuf Lt, Dinv, tflags, z, xF, zflags, xflags, Hd;
+  DevBuf Lt, Dinv, colcnt, dflag, tflag, z, xF, Hd;
   Ctrl* h_ctrl = nullptr;     // pinned
   int64_t* h_scalar = nullptr;  // pinned scratch for small reads
   int epoch = 0;
@@ -52,6 +54,7 @@ struct nnls_handle {
   double prof_work[NNLS_PROFILE_CLASSES] = {};
   std::vector<hipEvent_t> ev_pool;
   std::vector<PendingEvent> pending;
+  int64_t next_event_id = 0;
 };
 
 namespace {
@@ -95,11 +98,12 @@ int ensure(nnls_handle* h, DevBuf& b, size_t bytes, bool zero_i32 = false) {
     }                                                   \
   } while (0)
 
-int prof_begin(nnls_handle* h, int cls) {
+int64_t prof_begin(nnls_handle* h, int cls) {
   if (!h->profiling) return -1;
   PendingEvent pe;
   pe.cls = cls;
   pe.work = 0.0;
+  pe.ended = false;
   for (hipEvent_t* e : {&pe.a, &pe.b}) {
     if (!h->ev_pool.empty()) {
       *e = h->ev_pool.back();
@@ -109,29 +113,44 @@ int prof_begin(nnls_handle* h, int cls) {
     }
   }
   (void)hipEventRecord(pe.a, h->stream);
+  pe.id = h->next_event_id++;
   h->pending.push_back(pe);
-  return (int)h->pending.size() - 1;
+  return pe.id;
 }
 
-void prof_end(nnls_handle* h, int idx, double work) {
-  if (idx < 0) return;
-  (void)hipEventRecord(h->pending[idx].b, h->stream);
-  h->pending[idx].work = work;
-}
-
-// Call only after the stream has been synchronised.
-void prof_flush(nnls_handle* h) {
+void prof_end(nnls_handle* h, int64_t id, double work) {
+  if (id < 0) return;
   for (PendingEvent& pe : h->pending) {
+    if (pe.id != id) continue;
+    (void)hipEventRecord(pe.b, h->stream);
+    pe.work = work;
+    pe.ended = true;
+    return;
+  }
+}
+
+// Call only after the stream has been synchronised.  Pairs whose end is not recorded yet
+// (a phase that itself reads back from the device) stay pending, at their positions.
+void prof_flush(nnls_handle* h) {
+  size_t keep = 0;
+  for (size_t i = 0; i < h->pending.size(); ++i) {
+    PendingEvent& pe = h->pending[i];
+    if (!pe.ended) {
+      h->pending[keep++] = pe;
+      continue;
+    }
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) {
       h->prof_launches[pe.cls] += 1;
       h->prof_ms[pe.cls] += ms;
       h->prof_work[pe.cls] += pe.work;
+    } else {
+      (void)hipGetLastError();
     }
     h->ev_pool.push_back(pe.a);
     h->ev_pool.push_back(pe.b);
   }
-  h->pending.clear();
+  h->pending.resize(keep);
 }
 
 int sync_read(nnls_handle* h, void* dst, const void* src, size_t bytes) {
@@ -227,11 +246,11 @@ int ensure_factor(nnls_handle* h, int nF, bool fp32) {
   const size_t ntiles = (size_t)tile_count(nb);
   TRY(ensure(h, h->Lt, ntiles * TILE_ELEMS * w));
   TRY(ensure(h, h->Dinv, (size_t)nb * TILE_ELEMS * w));
-  TRY(ensure(h, h->tflags, ntiles * sizeof(int32_t), true));
+  TRY(ensure(h, h->colcnt, (size_t)nb * sizeof(int32_t), true));
+  TRY(ensure(h, h->dflag, (size_t)nb * sizeof(int32_t), true));
+  TRY(ensure(h, h->tflag, ntiles * sizeof(int32_t), true));
   TRY(ensure(h, h->z, (size_t)nb * TILE * sizeof(double)));
   TRY(ensure(h, h->xF, (size_t)nb * TILE * sizeof(double)));
-  TRY(ensure(h, h->zflags, (size_t)nb * sizeof(int32_t), true));
-  TRY(ensure(h, h->xflags, (size_t)nb * sizeof(int32_t), true));
   return NNLS_OK;
 }
 
@@ -248,7 +267,9 @@ FactorArgs factor_args(nnls_handle* h, int nF, const int32_t* Flist, const int32
   a.ldd = ldd;
   a.Ltiles = h->Lt.p;
   a.Dinv = h->Dinv.p;
-  a.tile_flags = (int32_t*)h->tflags.p;
+  a.colcnt = (int32_t*)h->colcnt.p;
+  a.dflag = (int32_t*)h->dflag.p;
+  a.tflag = (int32_t*)h->tflag.p;
   a.epoch = h->epoch;
   a.ctrl = (Ctrl*)h->ctrl.p;
   a.wait_ticks = h->wait_ticks;
@@ -268,8 +289,6 @@ SolveArgs solve_args(nnls_handle* h, int nF, const int32_t* Flist, const double*
   a.z = (double*)h->z.p;
   a.xF = (double*)h->xF.p;
   a.out = out;
-  a.zflags = (int32_t*)h->zflags.p;
-  a.xflags = (int32_t*)h->xflags.p;
   a.epoch = h->epoch;
   a.ctrl = (Ctrl*)h->ctrl.p;
   a.wait_ticks = h->wait_ticks;
@@ -288,6 +307,9 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
   TRY(ensure(h, h->pos, sizeof(int32_t) * (size_t)n));
   TRY(ensure(h, h->r, sizeof(double) * (size_t)m));
   TRY(ensure(h, h->ctrl, sizeof(Ctrl)));
+  const int ncol = (n + TILE - 1) / TILE;
+  TRY(ensure(h, h->colcnt, sizeof(int32_t) * (size_t)ncol, true));
+  TRY(ensure(h, h->dflag, sizeof(int32_t) * (size_t)ncol, true));
   const int max_iter = o.max_iter > 0 ? o.max_iter : 5 * n + 100;
   uint8_t* flags = (uint8_t*)h->flags.p;
   int32_t* Flist = (int32_t*)h->Flist.p;
@@ -301,8 +323,9 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
   const double spmv_bytes = P.sparse ? (2.0 * 12.0 * (double)P.nnz + 32.0 * m + 24.0 * n)
                                      : (2.0 * 8.0 * (double)m * n + 32.0 * m + 24.0 * n);
   for (;;) {
-    int pe = prof_begin(h, NNLS_PROF_CONTROL);
-    launch_pivot_control(h->stream, n, x, y, flags, Flist, pos, ctrl, o.tau, o.p_max, max_iter);
+    int64_t pe = prof_begin(h, NNLS_PROF_CONTROL);
+    launch_pivot_control(h->stream, n, x, y, flags, Flist, pos, ctrl, o.tau, o.p_max, max_iter,
+                         (int32_t*)h->colcnt.p, ncol);
     prof_end(h, pe, ctrl_bytes);
     TRY(sync_read(h, h->h_ctrl, ctrl, sizeof(Ctrl)));
     const Ctrl c = *h->h_ctrl;
@@ -384,7 +407,7 @@ int solve_common(nnls_handle* h, const Problem& P, double* x, double* y, const n
   h->profiling = (o.flags & NNLS_FLAG_PROFILE) != 0;
   int st = validate_device(h, P);
   if (st != NNLS_OK) return set_info_status(info, st);
-  const int pe = prof_begin(h, NNLS_PROF_GRAM);
+  const int64_t pe = prof_begin(h, NNLS_PROF_GRAM);
   st = P.sparse ? build_gram_sparse(h, P) : build_gram_dense(h, P);
   if (st != NNLS_OK) return set_info_status(info, st);
   prof_end(h, pe, P.sparse ? 12.0 * (double)P.nnz * 3.0 : 8.0 * (double)P.m * P.n);
@@ -461,7 +484,7 @@ int nnls_destroy(nnls_handle* h) {
   (void)hipStreamSynchronize(h->stream);
   DevBuf* bufs[] = {&h->err, &h->ctrl, &h->rowcnt, &h->rowptr, &h->colidx, &h->valr, &h->hptr,
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
-                    &h->Lt, &h->Dinv, &h->tflags, &h->z, &h->xF, &h->zflags, &h->xflags, &h->Hd};
+                    &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
@@ -568,6 +591,7 @@ int nnls_cholesky(nnls_handle* h, int32_t n, const double* S, int32_t lds, doubl
   TRY(ensure(h, h->ctrl, sizeof(Ctrl)));
   TRY(ensure_factor(h, n, fp32));
   launch_ctrl_set_state(h->stream, (Ctrl*)h->ctrl.p, INT32_MAX, 0, 0, 0);
+  launch_fill_i32(h->stream, (int32_t*)h->colcnt.p, (n + TILE - 1) / TILE, 0);
   h->epoch += 1;
   FactorArgs fa = factor_args(h, n, nullptr, nullptr, S, lds, false);
   launch_cholesky(h->stream, fa, fp32);
@@ -589,6 +613,7 @@ int nnls_spd_solve(nnls_handle* h, int32_t n, const double* S, int32_t lds, cons
   TRY(ensure(h, h->ctrl, sizeof(Ctrl)));
   TRY(ensure_factor(h, n, false));
   launch_ctrl_set_state(h->stream, (Ctrl*)h->ctrl.p, INT32_MAX, 0, 0, 0);
+  launch_fill_i32(h->stream, (int32_t*)h->colcnt.p, (n + TILE - 1) / TILE, 0);
   h->epoch += 1;
   FactorArgs fa = factor_args(h, n, nullptr, nullptr, S, lds, false);
   launch_cholesky(h->stream, fa, false);
@@ -641,8 +666,10 @@ int nnls_pivot_step(nnls_handle* h, int32_t n, double* x, double* y, uint8_t* fr
   TRY(ensure(h, h->pos, sizeof(int32_t) * (size_t)n));
   const int N = state[0] < 0 ? INT32_MAX : state[0];
   launch_ctrl_set_state(h->stream, (Ctrl*)h->ctrl.p, N, state[1], 0, 0);
+  TRY(ensure(h, h->colcnt, sizeof(int32_t) * (size_t)((n + TILE - 1) / TILE), true));
   launch_pivot_control(h->stream, n, x, y, free_flags, (int32_t*)h->Flist.p, (int32_t*)h->pos.p,
-                       (Ctrl*)h->ctrl.p, tau, p_max, INT32_MAX);
+                       (Ctrl*)h->ctrl.p, tau, p_max, INT32_MAX, (int32_t*)h->colcnt.p,
+                       (n + TILE - 1) / TILE);
   TRY(sync_read(h, h->h_ctrl, h->ctrl.p, sizeof(Ctrl)));
   const Ctrl c = *h->h_ctrl;
   state[0] = c.N == INT32_MAX ? -1 : c.N;

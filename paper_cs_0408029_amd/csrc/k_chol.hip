@@ -6,15 +6,20 @@
 // (tickets are handed out in column-major lower-tile order), gathers its tile of H_FF
 // straight from the Gram matrix into LDS, then computes, left-looking,
 //     S_IJ = H_IJ - sum_{k<J} L_Ik L_Jk^T        (MFMA, 16x16x4 blocks)
-// waiting on the per-tile ready flags of L_Ik and L_Jk.  A diagonal tile is factored and
-// inverted in LDS; an off-diagonal tile becomes L_IJ = S_IJ (L_JJ^-1)^T once the diagonal
-// tile (J, J) is ready.  Each finished tile publishes its flag (epoch number of the launch).
-// Every dependency of a tile has a smaller ticket, and a ticket is only taken by a running
-// workgroup, so the waits always end; each wait is also bounded in wall time and raises
-// NNLS_ERR_DEVICE instead of spinning forever.
+// A diagonal tile is then factored and inverted in LDS; an off-diagonal tile becomes
+// L_IJ = S_IJ (L_JJ^-1)^T once the diagonal tile of its column is ready.
 //
-// Triangular solves: the same scheme over 64-row blocks, one workgroup per block,
-// z = L^-1 c_F forward and x_F = L^-T z backward, using the inverted diagonal tiles.
+// Dependencies: colcnt[J] counts the finished tiles of column J (complete at nb - J), and
+// every finished tile also sets its own ready flag.  Every tile of column J+1 needs all of
+// column J, so columns complete in order; each wave caches how many leading columns it
+// knows to be complete and skips all checks below that frontier.  At the frontier it waits
+// only for the two tiles the next step reads (relaxed polls, then one acquire fence).  Every dependency of a tile has a smaller
+// ticket, and tickets are only taken by running workgroups, so every wait ends; each wait
+// is also bounded in wall time and raises NNLS_ERR_DEVICE instead of spinning forever.
+//
+// Triangular solves: one workgroup per 64-row block, z = L^-1 c_F forward and
+// x_F = L^-T z backward with the inverted diagonal tiles; blocks finish in order, so a
+// single frontier counter per direction carries every dependency.
 #include <climits>
 
 #include "nnls_internal.h"
@@ -44,28 +49,65 @@ template <> struct MF<float> {
   static __device__ inline int row(int l, int v) { return 4 * (l >> 4) + v; }
 };
 
-constexpr int LDT = TILE + 1;   // LDS leading dimension of a staged tile
+constexpr int LDT = TILE + 1;    // LDS leading dimension of a column-major staged tile
 
-// Every wave polls the flag itself, so its later loads are ordered after its own acquire.
-__device__ inline bool wait_epoch(const int32_t* flag, int epoch, Ctrl* ctrl, uint64_t wait_ticks) {
-  if (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == epoch) return true;
-  const uint64_t t0 = wall_clock64();
-  while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-    if (__hip_atomic_load(&ctrl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-    if (wall_clock64() - t0 > wait_ticks) {
-      __hip_atomic_store(&ctrl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      atomicCAS(&ctrl->status, 0, (int)NNLS_ERR_DEVICE);
-      return false;
-    }
-    __builtin_amdgcn_s_sleep(2);
-  }
-  return true;
+__device__ inline int32_t ld_relaxed(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+__device__ inline void raise_abort(Ctrl* ctrl) {
+  __hip_atomic_store(&ctrl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  atomicCAS(&ctrl->status, 0, (int)NNLS_ERR_DEVICE);
 }
 
-__device__ inline void publish(int32_t* flag, int epoch) {
+// Spin with relaxed loads until *p >= target (or == target when exact).  No fence: the
+// caller issues one acquire after it has learned all it can from the counters.
+__device__ inline bool spin_until(const int32_t* p, int target, bool exact, Ctrl* ctrl,
+                                  uint64_t wait_ticks) {
+  int32_t v = ld_relaxed(p);
+  if (exact ? v == target : v >= target) return true;
+  const uint64_t t0 = wall_clock64();
+  for (;;) {
+    __builtin_amdgcn_s_sleep(1);
+    v = ld_relaxed(p);
+    if (exact ? v == target : v >= target) return true;
+    if (ld_relaxed(&ctrl->abort)) return false;
+    if (wall_clock64() - t0 > wait_ticks) {
+      raise_abort(ctrl);
+      return false;
+    }
+  }
+}
+
+// Make every thread's global stores visible at agent scope, then let thread 0 bump a
+// counter (add) or set a flag (store).
+__device__ inline void publish_add(int32_t* counter) {
   __threadfence();
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void publish_tile(int32_t* flag, int32_t* counter, int epoch) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+__device__ inline void publish_store(int32_t* flag, int value) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline double bcast_lane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline float bcast_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
 // Stage tile (I, J) of H_FF in LDS (column-major, leading dimension LDT).  Positions at or
@@ -117,65 +159,166 @@ __device__ inline void gather_tile(const FactorArgs& a, int I, int J, T* S) {
   __syncthreads();
 }
 
-// Unblocked right-looking Cholesky of the lower triangle of S in LDS.
+// 16 x 16 block product on MFMA for one wave: acc += sign * A * op(B), where A is the
+// block of P at (pr, pc) and op(B) is the block of Q at (qr, qc), transposed when transB.
+// Both operands are column-major with leading dimension LDT.
 template <typename T>
-__device__ inline void potrf_lds(T* S, T* s_diag, int J, const FactorArgs& a) {
-  const int tid = threadIdx.x;
-  const int i = tid & (TILE - 1), g = tid >> 6;
-  for (int c = 0; c < TILE; ++c) {
-    const T d = S[c + c * LDT];
+__device__ inline typename MF<T>::acc mm16(typename MF<T>::acc acc, T sign, const T* P, int pr, int pc,
+                                         const T* Q, int qr, int qc, bool transB) {
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 16; kk += 4) {
+    const T av = sign * P[(pr + lr) + (pc + kk + lk) * LDT];
+    const T bv = transB ? Q[(qr + lr) + (qc + kk + lk) * LDT] : Q[(qr + kk + lk) + (qc + lr) * LDT];
+    acc = MF<T>::op(av, bv, acc);
+  }
+  return acc;
+}
+
+template <typename T>
+__device__ inline typename MF<T>::acc load16(const T* X, int r0, int c0) {
+  const int lane = threadIdx.x & 63, lr = lane & 15;
+  typename MF<T>::acc v;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) v[e] = X[(r0 + MF<T>::row(lane, e)) + (c0 + lr) * LDT];
+  return v;
+}
+
+template <typename T>
+__device__ inline void store16(T* X, int r0, int c0, typename MF<T>::acc v) {
+  const int lane = threadIdx.x & 63, lr = lane & 15;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) X[(r0 + MF<T>::row(lane, e)) + (c0 + lr) * LDT] = v[e];
+}
+
+__device__ inline double rsqrt_refined(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  y = y * fma(-0.5 * d, y * y, 1.5);
+  y = y * fma(-0.5 * d, y * y, 1.5);
+  return y;
+}
+__device__ inline float rsqrt_refined(float d) {
+  float y = __builtin_amdgcn_rsqf(d);
+  y = y * fmaf(-0.5f * d, y * y, 1.5f);
+  return y;
+}
+
+// Factor and invert the 16 x 16 diagonal block at offset o of S (one wave).  Lane i keeps
+// row i in registers; pivots come from a refined reciprocal square root (no divide); the
+// scaled column of each step is broadcast through LDS (16-byte broadcast reads), and the
+// inverse reuses the pivot reciprocals.  L goes back into S, its inverse into W; the LDS
+// broadcast buffers live in the unused upper blocks of S.
+template <typename T>
+__device__ inline void diag16(T* S, T* W, int o, int J, const FactorArgs& a) {
+  const int lane = threadIdx.x & 63, i = lane & 15;
+  T* colbuf = S + 48 * LDT;          // column buffer: rows 0..15 of column 48 (upper block)
+  T* LR = S + 16 + 48 * LDT;         // rows of L: LR[i * LDT + k], in the upper block (16, 48)
+  T r[16], invd[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) r[j] = S[(o + i) + (o + j) * LDT];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const T d = bcast_lane(r[c], c);
     const bool bad = !(d > (T)0) || !isfinite(d);
-    const T l = bad ? (T)1 : (T)sqrt(d);
-    const T inv = (T)1 / l;
-    if (tid > c && tid < TILE) S[tid + c * LDT] *= inv;
-    if (tid == 0) {
-      s_diag[c] = l;
-      if (bad && J * TILE + c < a.nF) {
-        atomicMin(&a.ctrl->failed_pos, J * TILE + c);
-        atomicCAS(&a.ctrl->status, 0, (int)NNLS_ERR_NOT_PD);
-      }
+    if (bad && lane == 0 && J * TILE + o + c < a.nF) {
+      atomicMin(&a.ctrl->failed_pos, J * TILE + o + c);
+      atomicCAS(&a.ctrl->status, 0, (int)NNLS_ERR_NOT_PD);
+    }
+    const T y = bad ? (T)1 : rsqrt_refined(d);   // 1 / L_cc
+    const T l = bad ? (T)1 : d * y;               // L_cc
+    invd[c] = y;
+    const T lic = (i == c) ? l : r[c] * y;
+    r[c] = lic;
+    if (lane < 16) colbuf[i] = lic;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+#pragma unroll
+    for (int j = c + 1; j < 16; ++j) r[j] -= lic * colbuf[j];
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const T v = (j <= i) ? r[j] : (T)0;
+      S[(o + i) + (o + j) * LDT] = v;
+      LR[i * LDT + j] = v;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  // inverse: lane i runs forward substitution down column i
+  T x[16];
+#pragma unroll
+  for (int ii = 0; ii < 16; ++ii) {
+    const T* row = LR + ii * LDT;
+    T s0 = (T)0, s1 = (T)0;
+#pragma unroll
+    for (int k = 0; k + 1 < ii; k += 2) {
+      s0 += row[k] * x[k];
+      s1 += row[k + 1] * x[k + 1];
+    }
+    if (ii & 1) s0 += row[ii - 1] * x[ii - 1];
+    x[ii] = ((i == ii ? (T)1 : (T)0) - (s0 + s1)) * invd[ii];
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii) W[(o + ii) + (o + i) * LDT] = x[ii];
+  }
+}
+
+// Blocked Cholesky and inverse of the 64 x 64 tile in S (lower triangle) by the whole
+// workgroup: 4 x 4 blocks of 16; diagonal blocks by one wave, the panel and trailing
+// updates on MFMA across the four waves.  Leaves L in the lower triangle of S and L^-1
+// in the lower triangle of W.
+template <typename T>
+__device__ inline void factor_invert_tile(T* S, T* W, int J, const FactorArgs& a) {
+  typedef typename MF<T>::acc Acc;
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (w == 0) diag16<T>(S, W, 16 * q, J, a);
+    __syncthreads();
+    // panel: L_pq = A_pq W_qq^T
+    const int p = q + 1 + w;
+    if (p < 4) {
+      Acc acc = {};
+      acc = mm16<T>(acc, (T)1, S, 16 * p, 16 * q, W, 16 * q, 16 * q, true);
+      store16<T>(S, 16 * p, 16 * q, acc);
     }
     __syncthreads();
-    if (i > c) {
-      const T lic = S[i + c * LDT];
-      for (int j = c + 1 + g; j <= i; j += 4) S[i + j * LDT] -= lic * S[j + c * LDT];
+    // trailing update: A_pr -= L_pq L_rq^T for q < r <= p
+    int idx = 0;
+    for (int rr = q + 1; rr < 4; ++rr)
+      for (int pp = rr; pp < 4; ++pp, ++idx)
+        if ((idx & 3) == w) {
+          Acc acc = load16<T>(S, 16 * pp, 16 * rr);
+          acc = mm16<T>(acc, (T)-1, S, 16 * pp, 16 * q, S, 16 * rr, 16 * q, true);
+          store16<T>(S, 16 * pp, 16 * rr, acc);
+        }
+    __syncthreads();
+  }
+  // off-diagonal blocks of the inverse, by distance from the diagonal:
+  // W_pq = -W_pp sum_{k=q}^{p-1} L_pk W_kq
+  for (int dd = 1; dd < 4; ++dd) {
+    const int p = dd + w, q = w;
+    if (p < 4) {
+      Acc t = {};
+      for (int k = q; k < p; ++k) t = mm16<T>(t, (T)1, S, 16 * p, 16 * k, W, 16 * k, 16 * q, false);
+      // stage t in this wave's free upper block of S, then multiply by -W_pp
+      const int sr = (w == 3) ? 16 : 0, sc = (w == 3) ? 32 : 16 * (w + 1);
+      store16<T>(S, sr, sc, t);
+      Acc u = {};
+      u = mm16<T>(u, (T)-1, W, 16 * p, 16 * p, S, sr, sc, false);
+      store16<T>(W, 16 * p, 16 * q, u);
     }
     __syncthreads();
   }
-  if (tid < TILE) S[tid + tid * LDT] = s_diag[tid];
-  __syncthreads();
-}
-
-// W = L^-1 for the lower-triangular L in S.  Four lanes of one wave own a column j and
-// run forward substitution down it; the column never leaves its wave.
-template <typename T>
-__device__ inline void trtri_lds(const T* S, T* W) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int j = w * 16 + (lane >> 2);
-  const int sub = lane & 3;
-  for (int i = 0; i < TILE; ++i) {
-    T s = (T)0;
-    if (i > j)
-      for (int k = j + sub; k < i; k += 4) s += S[i + k * LDT] * W[k + j * LDT];
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
-    if (sub == 0) {
-      const T dii = S[i + i * LDT];
-      W[i + j * LDT] = (i < j) ? (T)0 : (i == j) ? (T)1 / dii : -s / dii;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-  }
-  __syncthreads();
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_chol_tiles(FactorArgs a, uint64_t wait_ticks) {
+__global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wait_ticks) {
   typedef MF<T> M;
   typedef typename M::acc Acc;
   __shared__ T S[TILE * LDT];
   __shared__ T W[TILE * LDT];
-  __shared__ T s_diag[TILE];
   __shared__ int s_t, s_I, s_J;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int nb = a.nb;
@@ -212,9 +355,19 @@ __global__ __launch_bounds__(256) void k_chol_tiles(FactorArgs a, uint64_t wait_
         acc[bi][bj][v] = S[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT];
 
   const bool skip = (I == J) && (qr < qc);   // upper quadrant of a diagonal tile
+  int known = 0;                             // leading columns this wave knows are complete
   for (int k = 0; k < J; ++k) {
-    wait_epoch(&a.tile_flags[tile_index(I, k, nb)], a.epoch, a.ctrl, wait_ticks);
-    if (I != J) wait_epoch(&a.tile_flags[tile_index(J, k, nb)], a.epoch, a.ctrl, wait_ticks);
+    if (k >= known) {
+      if (ld_relaxed(&a.colcnt[k]) >= nb - k) {
+        known = k + 1;
+        while (known < J && ld_relaxed(&a.colcnt[known]) >= nb - known) ++known;
+      } else {
+        // at the frontier: wait only for the two tiles this step reads
+        spin_until(&a.tflag[tile_index(I, k, nb)], a.epoch, true, a.ctrl, wait_ticks);
+        if (I != J) spin_until(&a.tflag[tile_index(J, k, nb)], a.epoch, true, a.ctrl, wait_ticks);
+      }
+      acquire_agent();
+    }
     if (skip) continue;
     const T* LI = Lt + tile_index(I, k, nb) * TILE_ELEMS;
     const T* LJ = Lt + tile_index(J, k, nb) * TILE_ELEMS;
@@ -241,46 +394,54 @@ __global__ __launch_bounds__(256) void k_chol_tiles(FactorArgs a, uint64_t wait_
 
   T* dst = Lt + (int64_t)t * TILE_ELEMS;
   if (I == J) {
-    potrf_lds<T>(S, s_diag, J, a);
-    trtri_lds<T>(S, W);
+    factor_invert_tile<T>(S, W, J, a);
+    // the inverse first: it is what the rest of the column waits for
     T* dinv = Dv + (int64_t)J * TILE_ELEMS;
     for (int e = tid; e < TILE_ELEMS; e += 256) {
       const int r = e & (TILE - 1), c = e >> 6;
-      dst[e] = (r >= c) ? S[r + c * LDT] : (T)0;
       dinv[e] = (r >= c) ? W[r + c * LDT] : (T)0;
     }
-  } else {
-    wait_epoch(&a.tile_flags[tile_index(J, J, nb)], a.epoch, a.ctrl, wait_ticks);
-    const T* D = Dv + (int64_t)J * TILE_ELEMS;
-    Acc o[2][2];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) o[bi][bj][v] = (T)0;
-#pragma unroll
-    for (int kk = 0; kk < TILE; kk += 4) {
-      const int kc = kk + lk;
-      const T a0 = S[(qr + lr) + kc * LDT], a1 = S[(qr + 16 + lr) + kc * LDT];
-      const T b0 = D[kc * TILE + qc + lr], b1 = D[kc * TILE + qc + 16 + lr];
-      o[0][0] = M::op(a0, b0, o[0][0]);
-      o[0][1] = M::op(a0, b1, o[0][1]);
-      o[1][0] = M::op(a1, b0, o[1][0]);
-      o[1][1] = M::op(a1, b1, o[1][1]);
+    publish_store(&a.dflag[J], a.epoch);
+    for (int e = tid; e < TILE_ELEMS; e += 256) {
+      const int r = e & (TILE - 1), c = e >> 6;
+      dst[e] = (r >= c) ? S[r + c * LDT] : (T)0;
     }
-    __syncthreads();
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          S[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT] = o[bi][bj][v];
-    __syncthreads();
-    for (int e = tid; e < TILE_ELEMS; e += 256) dst[e] = S[(e & (TILE - 1)) + (e >> 6) * LDT];
+    publish_tile(&a.tflag[t], &a.colcnt[J], a.epoch);
+    return;
   }
-  publish(&a.tile_flags[t], a.epoch);
+
+  // off-diagonal: L_IJ = S_IJ (L_JJ^-1)^T once the diagonal tile of column J is ready
+  spin_until(&a.dflag[J], a.epoch, true, a.ctrl, wait_ticks);
+  acquire_agent();
+  const T* D = Dv + (int64_t)J * TILE_ELEMS;
+  Acc o[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) o[bi][bj][v] = (T)0;
+#pragma unroll
+  for (int kk = 0; kk < TILE; kk += 4) {
+    const int kc = kk + lk;
+    const T a0 = S[(qr + lr) + kc * LDT], a1 = S[(qr + 16 + lr) + kc * LDT];
+    const T b0 = D[kc * TILE + qc + lr], b1 = D[kc * TILE + qc + 16 + lr];
+    o[0][0] = M::op(a0, b0, o[0][0]);
+    o[0][1] = M::op(a0, b1, o[0][1]);
+    o[1][0] = M::op(a1, b0, o[1][0]);
+    o[1][1] = M::op(a1, b1, o[1][1]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        S[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT] = o[bi][bj][v];
+  __syncthreads();
+  for (int e = tid; e < TILE_ELEMS; e += 256) dst[e] = S[(e & (TILE - 1)) + (e >> 6) * LDT];
+  publish_tile(&a.tflag[t], &a.colcnt[J], a.epoch);
 }
 
 // z_I = L_II^-1 (rhs_I - sum_{k<I} L_Ik z_k)
@@ -296,9 +457,15 @@ __global__ __launch_bounds__(256) void k_trsv_fwd(SolveArgs a, uint64_t wait_tic
   if (I >= nb) return;
   const T* Lt = (const T*)a.Ltiles;
   const T* Dv = (const T*)a.Dinv;
+  int32_t* done = &a.ctrl->fwd_done;   // blocks 0 .. done-1 of z are final
   double acc = 0.0;
+  int known = 0;
   for (int k = 0; k < I; ++k) {
-    wait_epoch(&a.zflags[k], a.epoch, a.ctrl, wait_ticks);
+    if (k >= known) {
+      spin_until(done, k + 1, false, a.ctrl, wait_ticks);
+      known = ld_relaxed(done);
+      acquire_agent();
+    }
     const T* tl = Lt + tile_index(I, k, nb) * TILE_ELEMS;
     const double* zk = a.z + (int64_t)k * TILE;
 #pragma unroll
@@ -327,7 +494,8 @@ __global__ __launch_bounds__(256) void k_trsv_fwd(SolveArgs a, uint64_t wait_tic
   __syncthreads();
   if (tid < TILE)
     a.z[(int64_t)I * TILE + tid] = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
-  publish(&a.zflags[I], a.epoch);
+  // blocks finish in order (block I needs every earlier block), so done == I here
+  publish_store(done, I + 1);
 }
 
 // x_I = L_II^-T (z_I - sum_{k>I} L_kI^T x_k); scatter x_I through F
@@ -344,11 +512,17 @@ __global__ __launch_bounds__(256) void k_trsv_bwd(SolveArgs a, uint64_t wait_tic
   if (I < 0) return;
   const T* Lt = (const T*)a.Ltiles;
   const T* Dv = (const T*)a.Dinv;
+  int32_t* done = &a.ctrl->bwd_done;   // blocks nb-done .. nb-1 of x are final
   double accl[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) accl[q] = 0.0;
+  int known = 0;
   for (int k = nb - 1; k > I; --k) {
-    wait_epoch(&a.xflags[k], a.epoch, a.ctrl, wait_ticks);
+    if (nb - k > known) {
+      spin_until(done, nb - k, false, a.ctrl, wait_ticks);
+      known = ld_relaxed(done);
+      acquire_agent();
+    }
     const T* tl = Lt + tile_index(k, I, nb) * TILE_ELEMS;
     const double xr = a.xF[(int64_t)k * TILE + r];
 #pragma unroll
@@ -378,7 +552,7 @@ __global__ __launch_bounds__(256) void k_trsv_bwd(SolveArgs a, uint64_t wait_tic
     a.xF[p] = v;
     if (a.out && p < a.nF) a.out[a.Flist ? a.Flist[p] : p] = v;
   }
-  publish(&a.xflags[I], a.epoch);
+  publish_store(done, nb - I);
 }
 
 template <typename T>

@@ -55,7 +55,7 @@ __device__ inline int wave_max(int v) {
 __global__ __launch_bounds__(CTRL_THREADS) void k_pivot_control(
     int n, double* __restrict__ x, double* __restrict__ y, uint8_t* __restrict__ flags,
     int32_t* __restrict__ Flist, int32_t* __restrict__ pos, Ctrl* ctrl, double tau, int p_max,
-    int max_iter) {
+    int max_iter, int32_t* __restrict__ colcnt, int ncol) {
   __shared__ int s_cnt[16], s_max[16];
   __shared__ double s_mar[16];
   __shared__ int s_branch, s_rmax, s_done;
@@ -66,6 +66,9 @@ __global__ __launch_bounds__(CTRL_THREADS) void k_pivot_control(
     if (tid == 0) ctrl->done = 1;
     return;
   }
+
+  // the factorisation and solves of this iteration start from zeroed counters
+  for (int i = tid; i < ncol; i += CTRL_THREADS) colcnt[i] = 0;
 
   // 1. classify + zero + count
   int cnt = 0, rmax = -1;
@@ -134,6 +137,8 @@ __global__ __launch_bounds__(CTRL_THREADS) void k_pivot_control(
     ctrl->chol_ticket = 0;
     ctrl->fwd_ticket = 0;
     ctrl->bwd_ticket = 0;
+    ctrl->fwd_done = 0;
+    ctrl->bwd_done = 0;
     s_branch = branch;
     s_rmax = r;
     s_done = done;
@@ -192,6 +197,8 @@ __global__ void k_reset_tickets(Ctrl* ctrl) {
   ctrl->chol_ticket = 0;
   ctrl->fwd_ticket = 0;
   ctrl->bwd_ticket = 0;
+  ctrl->fwd_done = 0;
+  ctrl->bwd_done = 0;
 }
 
 __global__ void k_ctrl_set_state(Ctrl* ctrl, int N, int p, int iter) {
@@ -218,9 +225,9 @@ void launch_pivot_init(hipStream_t s, int n, const double* c, double* x, double*
 
 void launch_pivot_control(hipStream_t s, int n, double* x, double* y, uint8_t* flags,
                           int32_t* Flist, int32_t* pos, Ctrl* ctrl, double tau, int p_max,
-                          int max_iter) {
+                          int max_iter, int32_t* colcnt, int ncol) {
   hipLaunchKernelGGL(k_pivot_control, dim3(1), dim3(CTRL_THREADS), 0, s, n, x, y, flags, Flist, pos,
-                     ctrl, tau, p_max, max_iter);
+                     ctrl, tau, p_max, max_iter, colcnt, ncol);
 }
 
 void launch_ctrl_set_state(hipStream_t s, Ctrl* ctrl, int N, int p, int iter, int /*unused*/) {

@@ -28,7 +28,8 @@ struct Ctrl {
   int32_t chol_ticket; // work-queue counters of the dataflow kernels
   int32_t fwd_ticket;
   int32_t bwd_ticket;
-  int32_t pad0, pad1;
+  int32_t fwd_done;    // frontier of the forward triangular solve (blocks finished)
+  int32_t bwd_done;    // frontier of the backward triangular solve
   double min_margin;   // smallest |v| over the tested entries that were not zeroed
 };
 
@@ -77,7 +78,7 @@ void launch_pivot_init(hipStream_t s, int n, const double* c, double* x, double*
                        uint8_t* flags, Ctrl* ctrl, int p_max);
 void launch_pivot_control(hipStream_t s, int n, double* x, double* y, uint8_t* flags,
                           int32_t* Flist, int32_t* pos, Ctrl* ctrl, double tau, int p_max,
-                          int max_iter);
+                          int max_iter, int32_t* colcnt, int ncol);
 void launch_ctrl_set_state(hipStream_t s, Ctrl* ctrl, int N, int p, int iter, int max_iter_flag);
 
 // residual and dual (k_spmv.hip)
@@ -101,7 +102,9 @@ struct FactorArgs {
   int64_t ldd;
   void* Ltiles;           // tile storage, tile_count(nb) tiles of TILE_ELEMS
   void* Dinv;             // nb inverted diagonal tiles
-  int32_t* tile_flags;    // tile_count(nb) epoch flags
+  int32_t* colcnt;        // nb counters of finished tiles per column, zero at launch
+  int32_t* tflag;         // tile_count(nb) flags: tile ready when == epoch
+  int32_t* dflag;         // nb flags: diagonal tile of column J ready when == epoch
   int epoch;
   Ctrl* ctrl;
   uint64_t wait_ticks;    // bound of one device-side wait, in wall-clock ticks
@@ -119,8 +122,6 @@ struct SolveArgs {
   double* z;                // nb * TILE
   double* xF;               // nb * TILE
   double* out;              // optional scatter target, indexed by column number
-  int32_t* zflags;          // nb
-  int32_t* xflags;          // nb
   int epoch;
   Ctrl* ctrl;
   uint64_t wait_ticks;
