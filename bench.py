@@ -38,6 +38,21 @@ def make_instance(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def profiled_traffic(kernel_src: str, summary: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or None when the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(os.path.join(ROOT, summary)).read()
+        src = open(os.path.join(ROOT, kernel_src), "rb").read()
+    except OSError:
+        return None
+    fields = dict(l.strip().split(": ", 1) for l in text.splitlines() if ": " in l and l.startswith("    "))
+    if fields.get("source_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(inst, budget_s: float):
     """The oracle as it stands, on this host, over whole solves of the same instance until
     budget_s of CPU work has been spent (at least one solve)."""
@@ -69,6 +84,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path (run with --gpus 1)",
@@ -77,6 +94,16 @@ def main():
 
     import torch
     import paper_cs_0408029_amd as N
+
+    if args.copy_mib:
+        n = args.copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_mib": args.copy_mib, "read_bytes": n * 8, "write_bytes": n * 8}))
+        return
 
     if not os.path.exists(N.LIB_PATH):
         from paper_cs_0408029_amd.build import build
@@ -126,7 +153,10 @@ def main():
         achieved = chol["work"] / (chol["ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "kernel": "k_chol_tiles<double>", "achieved": round(achieved, 3),
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                "traffic": None, "launches": chol["launches"],
+                "traffic": profiled_traffic("paper_cs_0408029_amd/csrc/k_chol.hip",
+                                            "profiles/k_chol_tiles_sparse_large_m60000_n12000.md")
+                if args.workload == "sparse_large" else None,
+                "launches": chol["launches"],
                 "avg_launch_ms": round(chol["ms"] / chol["launches"], 4),
                 "work_per_launch": "nF^3/3 flops of the F-block factor"}
     breakdown = {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in prof.items()

@@ -344,13 +344,15 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
       h->epoch += 1;
       FactorArgs fa = factor_args(h, nF, Flist, pos, P.sparse ? nullptr : (const double*)h->Hd.p,
                                   P.sparse ? 0 : n, P.sparse);
+      fa.rhs = (const double*)h->c.p;
+      fa.z = (double*)h->z.p;
       pe = prof_begin(h, NNLS_PROF_CHOLESKY);
       launch_cholesky(h->stream, fa, fp32);
       prof_end(h, pe, chol_flops(nF));
       SolveArgs sa = solve_args(h, nF, Flist, (const double*)h->c.p, x);
       const int nb = fa.nb;
       pe = prof_begin(h, NNLS_PROF_TRSV);
-      launch_trsv(h->stream, sa, fp32);
+      launch_trsv(h->stream, sa, fp32, false);
       prof_end(h, pe, 2.0 * 8.0 * (double)tile_count(nb) * TILE_ELEMS);
     }
     pe = prof_begin(h, NNLS_PROF_RESIDUAL);
@@ -616,9 +618,11 @@ int nnls_spd_solve(nnls_handle* h, int32_t n, const double* S, int32_t lds, cons
   launch_fill_i32(h->stream, (int32_t*)h->colcnt.p, (n + TILE - 1) / TILE, 0);
   h->epoch += 1;
   FactorArgs fa = factor_args(h, n, nullptr, nullptr, S, lds, false);
+  fa.rhs = rhs;
+  fa.z = (double*)h->z.p;
   launch_cholesky(h->stream, fa, false);
   SolveArgs sa = solve_args(h, n, nullptr, rhs, x);
-  launch_trsv(h->stream, sa, false);
+  launch_trsv(h->stream, sa, false, false);
   TRY(sync_read(h, h->h_ctrl, h->ctrl.p, sizeof(Ctrl)));
   const Ctrl c = *h->h_ctrl;
   if (c.status == NNLS_ERR_NOT_PD && failed) *failed = c.failed_pos;

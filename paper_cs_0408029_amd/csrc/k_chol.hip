@@ -13,13 +13,16 @@
 // every finished tile also sets its own ready flag.  Every tile of column J+1 needs all of
 // column J, so columns complete in order; each wave caches how many leading columns it
 // knows to be complete and skips all checks below that frontier.  At the frontier it waits
-// only for the two tiles the next step reads (relaxed polls, then one acquire fence).  Every dependency of a tile has a smaller
-// ticket, and tickets are only taken by running workgroups, so every wait ends; each wait
-// is also bounded in wall time and raises NNLS_ERR_DEVICE instead of spinning forever.
+// only for the two tiles the next step reads (relaxed polls, then one acquire fence).
+// Every dependency of a tile has a smaller ticket, and tickets are only taken by running
+// workgroups, so every wait ends; each wait is also bounded in wall time and raises
+// NNLS_ERR_DEVICE instead of spinning forever.
 //
-// Triangular solves: one workgroup per 64-row block, z = L^-1 c_F forward and
-// x_F = L^-T z backward with the inverted diagonal tiles; blocks finish in order, so a
-// single frontier counter per direction carries every dependency.
+// Forward solve z = L^-1 c_F: fused into the factorisation (the diagonal tile of column J
+// emits z_J).  A stand-alone forward kernel remains for right-hand sides that arrive
+// after the factor.  Backward solve x_F = L^-T z: one workgroup per 64-row block with
+// the inverted diagonal tiles; blocks finish in order, so one frontier counter carries
+// every dependency.
 #include <climits>
 
 #include "nnls_internal.h"
@@ -216,24 +219,28 @@ __device__ inline void diag16(T* S, T* W, int o, int J, const FactorArgs& a) {
   T r[16], invd[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) r[j] = S[(o + i) + (o + j) * LDT];
+  int firstbad = -1;                 // uniform: pivots are read from one lane
+  T d = bcast_lane(r[0], 0);
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
-    const T d = bcast_lane(r[c], c);
     const bool bad = !(d > (T)0) || !isfinite(d);
-    if (bad && lane == 0 && J * TILE + o + c < a.nF) {
-      atomicMin(&a.ctrl->failed_pos, J * TILE + o + c);
-      atomicCAS(&a.ctrl->status, 0, (int)NNLS_ERR_NOT_PD);
-    }
+    if (bad && firstbad < 0) firstbad = c;
     const T y = bad ? (T)1 : rsqrt_refined(d);   // 1 / L_cc
     const T l = bad ? (T)1 : d * y;               // L_cc
     invd[c] = y;
     const T lic = (i == c) ? l : r[c] * y;
     r[c] = lic;
+    // the next pivot only needs lane c+1's own diagonal update, off the LDS path
+    if (c + 1 < 16) d = bcast_lane(fma(-lic, lic, r[c + 1]), c + 1);
     if (lane < 16) colbuf[i] = lic;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
 #pragma unroll
-    for (int j = c + 1; j < 16; ++j) r[j] -= lic * colbuf[j];
+    for (int j = c + 1; j < 16; ++j) r[j] = fma(-lic, colbuf[j], r[j]);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  if (firstbad >= 0 && lane == 0 && J * TILE + o + firstbad < a.nF) {
+    atomicMin(&a.ctrl->failed_pos, J * TILE + o + firstbad);
+    atomicCAS(&a.ctrl->status, 0, (int)NNLS_ERR_NOT_PD);
   }
   if (lane < 16) {
 #pragma unroll
@@ -244,19 +251,23 @@ __device__ inline void diag16(T* S, T* W, int o, int J, const FactorArgs& a) {
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  // inverse: lane i runs forward substitution down column i
+  // inverse: lane i runs forward substitution down column i; the newest term is added
+  // last so each row waits on one product
   T x[16];
 #pragma unroll
   for (int ii = 0; ii < 16; ++ii) {
     const T* row = LR + ii * LDT;
     T s0 = (T)0, s1 = (T)0;
+    // terms k = 0 .. ii-2 in two chains, then k = ii-1
 #pragma unroll
-    for (int k = 0; k + 1 < ii; k += 2) {
+    for (int k = 0; k + 1 < ii - 1; k += 2) {
       s0 += row[k] * x[k];
       s1 += row[k + 1] * x[k + 1];
     }
-    if (ii & 1) s0 += row[ii - 1] * x[ii - 1];
-    x[ii] = ((i == ii ? (T)1 : (T)0) - (s0 + s1)) * invd[ii];
+    if (ii >= 2 && ((ii - 1) & 1)) s0 += row[ii - 2] * x[ii - 2];
+    T s = s0 + s1;
+    if (ii >= 1) s += row[ii - 1] * x[ii - 1];
+    x[ii] = ((i == ii ? (T)1 : (T)0) - s) * invd[ii];
   }
   if (lane < 16) {
 #pragma unroll
@@ -319,6 +330,8 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wa
   typedef typename M::acc Acc;
   __shared__ T S[TILE * LDT];
   __shared__ T W[TILE * LDT];
+  __shared__ double s_part[4][TILE];   // fused forward solve: partial sums per wave
+  __shared__ double s_rhs[TILE];
   __shared__ int s_t, s_I, s_J;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int nb = a.nb;
@@ -355,6 +368,10 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wa
         acc[bi][bj][v] = S[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT];
 
   const bool skip = (I == J) && (qr < qc);   // upper quadrant of a diagonal tile
+  // The diagonal tile also runs the forward solve L z = c_F for its block: it streams
+  // every L_Jk anyway, and z_k is published before column k completes.
+  const bool fwd = (I == J) && (a.rhs != nullptr);
+  double tacc = 0.0;                         // row `lane`, columns 16 w .. 16 w + 15
   int known = 0;                             // leading columns this wave knows are complete
   for (int k = 0; k < J; ++k) {
     if (k >= known) {
@@ -367,6 +384,15 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wa
         if (I != J) spin_until(&a.tflag[tile_index(J, k, nb)], a.epoch, true, a.ctrl, wait_ticks);
       }
       acquire_agent();
+    }
+    if (fwd) {
+      const T* LJk = Lt + tile_index(J, k, nb) * TILE_ELEMS;
+      const double* zk = a.z + (int64_t)k * TILE;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int cc = w * 16 + q;
+        tacc = fma((double)LJk[cc * TILE + lane], zk[cc], tacc);
+      }
     }
     if (skip) continue;
     const T* LI = Lt + tile_index(I, k, nb) * TILE_ELEMS;
@@ -394,7 +420,27 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wa
 
   T* dst = Lt + (int64_t)t * TILE_ELEMS;
   if (I == J) {
+    if (fwd) s_part[w][lane] = tacc;
     factor_invert_tile<T>(S, W, J, a);
+    if (fwd) {
+      if (tid < TILE) {
+        const int p = J * TILE + tid;
+        double c = 0.0;
+        if (p < a.nF) c = a.rhs[a.Flist ? a.Flist[p] : p];
+        s_rhs[tid] = c - (((s_part[0][tid] + s_part[1][tid]) + s_part[2][tid]) + s_part[3][tid]);
+      }
+      __syncthreads();
+      double zz = 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int c = w * 16 + q;   // W holds L_JJ^-1 in its lower triangle only
+        if (c <= lane) zz = fma((double)W[lane + c * LDT], s_rhs[c], zz);
+      }
+      s_part[w][lane] = zz;
+      __syncthreads();
+      if (tid < TILE)
+        a.z[(int64_t)J * TILE + tid] = ((s_part[0][tid] + s_part[1][tid]) + s_part[2][tid]) + s_part[3][tid];
+    }
     // the inverse first: it is what the rest of the column waits for
     T* dinv = Dv + (int64_t)J * TILE_ELEMS;
     for (int e = tid; e < TILE_ELEMS; e += 256) {
@@ -498,7 +544,9 @@ __global__ __launch_bounds__(256) void k_trsv_fwd(SolveArgs a, uint64_t wait_tic
   publish_store(done, I + 1);
 }
 
-// x_I = L_II^-T (z_I - sum_{k>I} L_kI^T x_k); scatter x_I through F
+// x_I = L_II^-T (z_I - sum_{k>I} L_kI^T x_k); scatter x_I through F.  The tile of the
+// next step and the inverse diagonal block are loaded before waiting on the frontier, so
+// a step on the critical path waits only for x_k itself.
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsv_bwd(SolveArgs a, uint64_t wait_ticks) {
   __shared__ double ssum[TILE];
@@ -511,22 +559,38 @@ __global__ __launch_bounds__(256) void k_trsv_bwd(SolveArgs a, uint64_t wait_tic
   const int I = s_I, nb = a.nb;
   if (I < 0) return;
   const T* Lt = (const T*)a.Ltiles;
-  const T* Dv = (const T*)a.Dinv;
+  const T* D = (const T*)a.Dinv + (int64_t)I * TILE_ELEMS;
   int32_t* done = &a.ctrl->bwd_done;   // blocks nb-done .. nb-1 of x are final
+  T dv[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) dv[q] = D[r * TILE + g * 16 + q];
   double accl[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) accl[q] = 0.0;
   int known = 0;
+  T tv[16];
+  if (I < nb - 1) {
+    const T* tl = Lt + tile_index(nb - 1, I, nb) * TILE_ELEMS;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) tv[q] = tl[(g * 16 + q) * TILE + r];
+  }
   for (int k = nb - 1; k > I; --k) {
     if (nb - k > known) {
       spin_until(done, nb - k, false, a.ctrl, wait_ticks);
       known = ld_relaxed(done);
       acquire_agent();
     }
-    const T* tl = Lt + tile_index(k, I, nb) * TILE_ELEMS;
     const double xr = a.xF[(int64_t)k * TILE + r];
+    T cur[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) accl[q] = fma((double)tl[(g * 16 + q) * TILE + r], xr, accl[q]);
+    for (int q = 0; q < 16; ++q) cur[q] = tv[q];
+    if (k - 1 > I) {
+      const T* tl = Lt + tile_index(k - 1, I, nb) * TILE_ELEMS;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) tv[q] = tl[(g * 16 + q) * TILE + r];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) accl[q] = fma((double)cur[q], xr, accl[q]);
   }
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
@@ -537,13 +601,9 @@ __global__ __launch_bounds__(256) void k_trsv_bwd(SolveArgs a, uint64_t wait_tic
   __syncthreads();
   if (tid < TILE) srhs[tid] = a.z[(int64_t)I * TILE + tid] - ssum[tid];
   __syncthreads();
-  const T* D = Dv + (int64_t)I * TILE_ELEMS;
   double xx = 0.0;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int c = g * 16 + q;
-    xx = fma((double)D[r * TILE + c], srhs[c], xx);
-  }
+  for (int q = 0; q < 16; ++q) xx = fma((double)dv[q], srhs[g * 16 + q], xx);
   part[g][r] = xx;
   __syncthreads();
   if (tid < TILE) {
@@ -578,13 +638,13 @@ void launch_cholesky(hipStream_t s, const FactorArgs& a, bool fp32) {
     hipLaunchKernelGGL(k_chol_tiles<double>, dim3((unsigned)grid), dim3(256), 0, s, a, a.wait_ticks);
 }
 
-void launch_trsv(hipStream_t s, const SolveArgs& a, bool fp32) {
+void launch_trsv(hipStream_t s, const SolveArgs& a, bool fp32, bool forward) {
   if (a.nb <= 0) return;
   if (fp32) {
-    hipLaunchKernelGGL(k_trsv_fwd<float>, dim3(a.nb), dim3(256), 0, s, a, a.wait_ticks);
+    if (forward) hipLaunchKernelGGL(k_trsv_fwd<float>, dim3(a.nb), dim3(256), 0, s, a, a.wait_ticks);
     hipLaunchKernelGGL(k_trsv_bwd<float>, dim3(a.nb), dim3(256), 0, s, a, a.wait_ticks);
   } else {
-    hipLaunchKernelGGL(k_trsv_fwd<double>, dim3(a.nb), dim3(256), 0, s, a, a.wait_ticks);
+    if (forward) hipLaunchKernelGGL(k_trsv_fwd<double>, dim3(a.nb), dim3(256), 0, s, a, a.wait_ticks);
     hipLaunchKernelGGL(k_trsv_bwd<double>, dim3(a.nb), dim3(256), 0, s, a, a.wait_ticks);
   }
 }

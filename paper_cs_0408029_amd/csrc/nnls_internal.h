@@ -108,6 +108,8 @@ struct FactorArgs {
   int epoch;
   Ctrl* ctrl;
   uint64_t wait_ticks;    // bound of one device-side wait, in wall-clock ticks
+  const double* rhs;      // optional: forward-solve L z = rhs_F during the factorisation
+  double* z;              // nb * TILE, written when rhs != nullptr
 };
 void launch_cholesky(hipStream_t s, const FactorArgs& a, bool fp32);
 // z = L^-1 rhs (rhs gathered through Flist when gather != nullptr); x = L^-T z and
@@ -126,7 +128,7 @@ struct SolveArgs {
   Ctrl* ctrl;
   uint64_t wait_ticks;
 };
-void launch_trsv(hipStream_t s, const SolveArgs& a, bool fp32);
+void launch_trsv(hipStream_t s, const SolveArgs& a, bool fp32, bool forward);
 void launch_tiles_to_dense(hipStream_t s, int n, int nb, const void* Ltiles, bool fp32,
                            double* L, int ldl);
 void launch_reset_tickets(hipStream_t s, Ctrl* ctrl);
