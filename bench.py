@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix) peak
+PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 (matrix) peak
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E peak
 METRIC = "NNLS solves/s + p50/p99 latency vs plain FP64 GPU path at ≤1e-8 rel err"
 
@@ -84,6 +85,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--precision", choices=["fp64", "fp32ir"], default="fp64",
+                    help="fp64: the plain FP64 path (the metric's reference); fp32ir: float32 factor "
+                         "with float64 refinement")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -118,8 +122,9 @@ def main():
     x = torch.empty(inst.n, dtype=torch.float64, device=dev)
     y = torch.empty_like(x)
     h = N.Handle(0)
-    opts = N.default_options()
-    popts = N.default_options(flags=N.NNLS_FLAG_PROFILE)
+    prec = N.NNLS_FP64 if args.precision == "fp64" else N.NNLS_FP32_IR
+    opts = N.default_options(precision=prec)
+    popts = N.default_options(precision=prec, flags=N.NNLS_FLAG_PROFILE)
 
     def step(o):
         st, info = N.nnls_solve_csc(h, inst.m, inst.n, colptr, rowidx, val, b, x, y, o)
@@ -133,12 +138,14 @@ def main():
     torch.cuda.synchronize()
     lat = []
     iters = 0
+    ir_steps = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
         s0 = time.perf_counter()
         info = step(opts if args.no_profile else popts)
         lat.append((time.perf_counter() - s0) * 1e3)
         iters += info.iterations
+        ir_steps += info.ir_steps
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     prof = N.nnls_get_profile(h)
@@ -149,13 +156,16 @@ def main():
 
     chol = prof["cholesky"]
     roof = None
+    fp32 = args.precision == "fp32ir"
+    peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
     if chol["launches"] > 0 and chol["ms"] > 0:
         achieved = chol["work"] / (chol["ms"] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "kernel": "k_chol_tiles<double>", "achieved": round(achieved, 3),
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+        roof = {"bound": "mfma", "kernel": "k_chol_tiles<float>" if fp32 else "k_chol_tiles<double>",
+                "achieved": round(achieved, 3),
+                "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": profiled_traffic("paper_cs_0408029_amd/csrc/k_chol.hip",
                                             "profiles/k_chol_tiles_sparse_large_m60000_n12000.md")
-                if args.workload == "sparse_large" else None,
+                if args.workload == "sparse_large" and not fp32 else None,
                 "launches": chol["launches"],
                 "avg_launch_ms": round(chol["ms"] / chol["launches"], 4),
                 "work_per_launch": "nF^3/3 flops of the F-block factor"}
@@ -172,12 +182,15 @@ def main():
         "p50_ms": round(float(np.percentile(lat, 50)), 3),
         "p99_ms": round(float(np.percentile(lat, 99)), 3),
         "pivot_iters_per_s": round(iters / total, 2),
+        "refinement_steps_per_solve": round(ir_steps / args.steps, 2),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if not fp32 else "f32-factor+f64-refinement",
         "data": "synthetic",
-        "config": {"workload": desc, "path": "plain FP64 GPU path, one problem per call",
+        "config": {"workload": desc,
+                   "path": "plain FP64 GPU path, one problem per call" if not fp32 else
+                           "float32 factor, float64 refinement, one problem per call",
                    "m": inst.m, "n": inst.n, "nnz": int(A.nnz)},
         "rel_err_vs_planted": rel,
         "free_set_match": fmatch,

@@ -42,7 +42,7 @@ struct nnls_handle {
   uint64_t wait_ticks = 0;
   // workspace
   DevBuf err, ctrl, rowcnt, rowptr, colidx, valr, hptr, hcnt, hrow, hval, c, r, flags, Flist, pos;
-  DevBuf Lt, Dinv, colcnt, dflag, tflag, z, xF, Hd;
+  DevBuf Lt, Dinv, colcnt, dflag, tflag, z, xF, Hd, gF;
   Ctrl* h_ctrl = nullptr;     // pinned
   int64_t* h_scalar = nullptr;  // pinned scratch for small reads
   int epoch = 0;
@@ -297,11 +297,96 @@ SolveArgs solve_args(nnls_handle* h, int nF, const int32_t* Flist, const double*
 
 double chol_flops(double nF) { return nF * nF * nF / 3.0; }
 
+// Eq. 5: r = A x - b, then y_G = A_G^T r (y_F = 0); with gfree also A_F^T r on F.
+void residual_dual(nnls_handle* h, const Problem& P, const double* x, double* y, double* gfree) {
+  double* r = (double*)h->r.p;
+  const uint8_t* flags = (const uint8_t*)h->flags.p;
+  if (P.sparse) {
+    launch_residual_csr(h->stream, P.m, (const int32_t*)h->rowptr.p, (const int32_t*)h->colidx.p,
+                        (const double*)h->valr.p, x, P.b, r);
+    launch_dual_csc(h->stream, P.n, P.colptr, P.rowidx, P.val, r, flags, y, gfree);
+  } else {
+    launch_residual_dense(h->stream, P.m, P.n, P.A, P.lda, x, P.b, r);
+    launch_dual_dense(h->stream, P.m, P.n, P.A, P.lda, r, flags, y, gfree);
+  }
+}
+
+// x_F for the current split (Eq. 4 by the normal equations, Sec. 2.1): factor H_FF with
+// the forward solve fused, then the backward solve scattered into x.  In NNLS_FP32_IR the
+// factor is float32 and x_F is refined in float64 against the residual from A,
+//   g_F = A_F^T (A x - b),  x_F <- x_F - (L L^T)^-1 g_F,
+// until the correction is below ir_rtol relative to x_F; if it stalls or the step cap is
+// reached, the iteration is redone with a float64 factor.  *y_done is set when the last
+// refinement pass already left y_G for the final x.
+int solve_free(nnls_handle* h, const Problem& P, int nF, double* x, double* y, const nnls_options& o,
+               double spmv_bytes, bool* y_done, nnls_info* info) {
+  const int32_t* Flist = (const int32_t*)h->Flist.p;
+  const int32_t* pos = (const int32_t*)h->pos.p;
+  Ctrl* ctrl = (Ctrl*)h->ctrl.p;
+  bool fp32 = o.precision == NNLS_FP32_IR;
+  *y_done = false;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    TRY(ensure_factor(h, nF, fp32));
+    h->epoch += 1;
+    FactorArgs fa = factor_args(h, nF, Flist, pos, P.sparse ? nullptr : (const double*)h->Hd.p,
+                                P.sparse ? 0 : P.n, P.sparse);
+    fa.rhs = (const double*)h->c.p;
+    fa.z = (double*)h->z.p;
+    int64_t pe = prof_begin(h, NNLS_PROF_CHOLESKY);
+    launch_cholesky(h->stream, fa, fp32);
+    prof_end(h, pe, chol_flops(nF));
+    const double l_bytes = (fp32 ? 4.0 : 8.0) * (double)tile_count(fa.nb) * TILE_ELEMS;
+    SolveArgs sa = solve_args(h, nF, Flist, (const double*)h->c.p, x);
+    pe = prof_begin(h, NNLS_PROF_TRSV);
+    launch_trsv(h->stream, sa, fp32, false);
+    prof_end(h, pe, l_bytes);
+    if (!fp32) return NNLS_OK;
+
+    TRY(ensure(h, h->gF, sizeof(double) * (size_t)P.n));
+    double* gF = (double*)h->gF.p;
+    bool converged = false;
+    double prev = INFINITY;
+    for (int step = 0;; ++step) {
+      pe = prof_begin(h, NNLS_PROF_RESIDUAL);
+      residual_dual(h, P, x, y, gF);
+      prof_end(h, pe, spmv_bytes);
+      if (converged) break;
+      if (step >= o.ir_max_steps) break;
+      pe = prof_begin(h, NNLS_PROF_REFINE);
+      launch_reset_tickets(h->stream, ctrl);
+      SolveArgs ca = solve_args(h, nF, Flist, gF, nullptr);
+      launch_trsv(h->stream, ca, true, true);
+      launch_ir_update(h->stream, nF, Flist, (const double*)h->xF.p, x, ctrl);
+      prof_end(h, pe, 2.0 * l_bytes);
+      TRY(sync_read(h, h->h_ctrl, ctrl, sizeof(Ctrl)));
+      if (h->h_ctrl->status == NNLS_ERR_NOT_PD) {     // float32 breakdown: redo in float64
+        launch_ctrl_clear_breakdown(h->stream, ctrl);
+        break;
+      }
+      if (h->h_ctrl->status != 0) return NNLS_OK;   // reported by the next control step
+      if (info) info->ir_steps += 1;
+      const double dmax = h->h_ctrl->ir_dmax, xmax = h->h_ctrl->ir_xmax;
+      if (!(dmax <= INFINITY) || !(xmax <= INFINITY)) break;
+      if (dmax <= o.ir_rtol * xmax) {
+        converged = true;
+      } else if (dmax > 0.5 * prev) {
+        break;                                      // not contracting: factor in float64
+      }
+      prev = dmax;
+    }
+    if (converged) {
+      *y_done = true;
+      return NNLS_OK;
+    }
+    fp32 = false;
+  }
+  return NNLS_OK;
+}
+
 // The pivot loop on a problem whose Gram matrix and c are built.
 int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnls_options& o,
                nnls_info* info) {
   const int n = P.n, m = P.m;
-  const bool fp32 = false;
   TRY(ensure(h, h->flags, (size_t)n));
   TRY(ensure(h, h->Flist, sizeof(int32_t) * (size_t)n));
   TRY(ensure(h, h->pos, sizeof(int32_t) * (size_t)n));
@@ -314,7 +399,6 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
   uint8_t* flags = (uint8_t*)h->flags.p;
   int32_t* Flist = (int32_t*)h->Flist.p;
   int32_t* pos = (int32_t*)h->pos.p;
-  double* r = (double*)h->r.p;
   Ctrl* ctrl = (Ctrl*)h->ctrl.p;
   launch_pivot_init(h->stream, n, (const double*)h->c.p, x, y, flags, ctrl, o.p_max);
 
@@ -339,32 +423,13 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
     row.reserved = 0;
     h->trace.push_back(row);
     const int nF = c.n_free;
-    if (nF > 0) {
-      TRY(ensure_factor(h, nF, fp32));
-      h->epoch += 1;
-      FactorArgs fa = factor_args(h, nF, Flist, pos, P.sparse ? nullptr : (const double*)h->Hd.p,
-                                  P.sparse ? 0 : n, P.sparse);
-      fa.rhs = (const double*)h->c.p;
-      fa.z = (double*)h->z.p;
-      pe = prof_begin(h, NNLS_PROF_CHOLESKY);
-      launch_cholesky(h->stream, fa, fp32);
-      prof_end(h, pe, chol_flops(nF));
-      SolveArgs sa = solve_args(h, nF, Flist, (const double*)h->c.p, x);
-      const int nb = fa.nb;
-      pe = prof_begin(h, NNLS_PROF_TRSV);
-      launch_trsv(h->stream, sa, fp32, false);
-      prof_end(h, pe, 2.0 * 8.0 * (double)tile_count(nb) * TILE_ELEMS);
+    bool y_done = false;
+    if (nF > 0) TRY(solve_free(h, P, nF, x, y, o, spmv_bytes, &y_done, info));
+    if (!y_done) {
+      pe = prof_begin(h, NNLS_PROF_RESIDUAL);
+      residual_dual(h, P, x, y, nullptr);
+      prof_end(h, pe, spmv_bytes);
     }
-    pe = prof_begin(h, NNLS_PROF_RESIDUAL);
-    if (P.sparse) {
-      launch_residual_csr(h->stream, m, (const int32_t*)h->rowptr.p, (const int32_t*)h->colidx.p,
-                          (const double*)h->valr.p, x, P.b, r);
-      launch_dual_csc(h->stream, n, P.colptr, P.rowidx, P.val, r, flags, y);
-    } else {
-      launch_residual_dense(h->stream, m, n, P.A, P.lda, x, P.b, r);
-      launch_dual_dense(h->stream, m, n, P.A, P.lda, r, flags, y);
-    }
-    prof_end(h, pe, spmv_bytes);
     if (hipGetLastError() != hipSuccess) return NNLS_ERR_DEVICE;
   }
   const Ctrl c = *h->h_ctrl;
@@ -397,7 +462,8 @@ int solve_common(nnls_handle* h, const Problem& P, double* x, double* y, const n
   if (!h) return set_info_status(info, NNLS_ERR_INVALID_ARG);
   h->trace.clear();
   if (check_options(o) != NNLS_OK) return set_info_status(info, NNLS_ERR_INVALID_ARG);
-  if (o.precision != NNLS_FP64) return set_info_status(info, NNLS_ERR_INVALID_ARG);
+  if (o.precision == NNLS_FP32_IR && (o.ir_max_steps < 0 || !(o.ir_rtol > 0.0)))
+    return set_info_status(info, NNLS_ERR_INVALID_ARG);
   if (P.n < 1 || P.m < P.n || !P.b || !x || !y) return set_info_status(info, NNLS_ERR_INVALID_ARG);
   if (P.sparse) {
     if (P.nnz < 0 || P.nnz > INT32_MAX || !P.colptr || (P.nnz > 0 && (!P.rowidx || !P.val)))
@@ -448,7 +514,7 @@ void nnls_default_options(nnls_options* o) {
   o->max_iter = 0;
   o->precision = NNLS_FP64;
   o->ir_max_steps = 10;
-  o->ir_rtol = 1e-13;
+  o->ir_rtol = 1e-12;
   o->flags = 0;
 }
 
@@ -486,7 +552,7 @@ int nnls_destroy(nnls_handle* h) {
   (void)hipStreamSynchronize(h->stream);
   DevBuf* bufs[] = {&h->err, &h->ctrl, &h->rowcnt, &h->rowptr, &h->colidx, &h->valr, &h->hptr,
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
-                    &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd};
+                    &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);

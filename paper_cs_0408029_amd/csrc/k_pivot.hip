@@ -201,6 +201,13 @@ __global__ void k_reset_tickets(Ctrl* ctrl) {
   ctrl->bwd_done = 0;
 }
 
+__global__ void k_ctrl_clear_breakdown(Ctrl* ctrl) {
+  if (ctrl->status == NNLS_ERR_NOT_PD) {
+    ctrl->status = 0;
+    ctrl->failed_pos = INT32_MAX;
+  }
+}
+
 __global__ void k_ctrl_set_state(Ctrl* ctrl, int N, int p, int iter) {
   Ctrl z = {};
   z.N = N;
@@ -232,6 +239,10 @@ void launch_pivot_control(hipStream_t s, int n, double* x, double* y, uint8_t* f
 
 void launch_ctrl_set_state(hipStream_t s, Ctrl* ctrl, int N, int p, int iter, int /*unused*/) {
   hipLaunchKernelGGL(k_ctrl_set_state, dim3(1), dim3(1), 0, s, ctrl, N, p, iter);
+}
+
+void launch_ctrl_clear_breakdown(hipStream_t s, Ctrl* ctrl) {
+  hipLaunchKernelGGL(k_ctrl_clear_breakdown, dim3(1), dim3(1), 0, s, ctrl);
 }
 
 void launch_reset_tickets(hipStream_t s, Ctrl* ctrl) {

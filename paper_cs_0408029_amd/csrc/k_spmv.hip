@@ -26,24 +26,63 @@ __global__ __launch_bounds__(256) void k_residual_csr(int m, const int32_t* __re
 }
 
 // 16 lanes per column: each lane takes a fixed stride of the column's entries, then a
-// fixed xor tree combines the 16 partial sums.
+// fixed xor tree combines the 16 partial sums.  With gfree, the same product on the free
+// columns (the normal-equations residual A_F^T r used by refinement) goes to gfree.
 __global__ __launch_bounds__(256) void k_dual_csc(int n, const int32_t* __restrict__ colptr,
                                                   const int32_t* __restrict__ rowidx,
                                                   const double* __restrict__ val,
                                                   const double* __restrict__ r,
                                                   const uint8_t* __restrict__ flags,
-                                                  double* __restrict__ y) {
+                                                  double* __restrict__ y,
+                                                  double* __restrict__ gfree) {
   const int sub = threadIdx.x & 15;
   const int j = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
   const bool active = j < n;
   double s = 0.0;
   const bool free_j = active ? (flags[j] != 0) : true;
-  if (active && !free_j) {
+  if (active && (!free_j || gfree)) {
     const int e1 = colptr[j + 1];
     for (int e = colptr[j] + sub; e < e1; e += 16) s = fma(val[e], r[rowidx[e]], s);
   }
   for (int d = 8; d >= 1; d >>= 1) s += __shfl_xor(s, d, 16);
-  if (active && sub == 0) y[j] = free_j ? 0.0 : s;
+  if (active && sub == 0) {
+    y[j] = free_j ? 0.0 : s;
+    if (gfree && free_j) gfree[j] = s;
+  }
+}
+
+// x[Flist[p]] -= d[p]; max |d| and max |x_F| by one workgroup (fixed reduction order).
+__global__ __launch_bounds__(1024) void k_ir_update(int nF, const int32_t* __restrict__ Flist,
+                                                    const double* __restrict__ d,
+                                                    double* __restrict__ x, Ctrl* ctrl) {
+  __shared__ double s_d[16], s_x[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double dm = 0.0, xm = 0.0;
+  for (int p = tid; p < nF; p += 1024) {
+    const int i = Flist[p];
+    const double v = x[i] - d[p];
+    x[i] = v;
+    dm = fmax(dm, fabs(d[p]));
+    xm = fmax(xm, fabs(v));
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    dm = fmax(dm, __shfl_xor(dm, o, 64));
+    xm = fmax(xm, __shfl_xor(xm, o, 64));
+  }
+  if (lane == 0) {
+    s_d[w] = dm;
+    s_x[w] = xm;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double a = 0.0, b = 0.0;
+    for (int q = 0; q < 16; ++q) {
+      a = fmax(a, s_d[q]);
+      b = fmax(b, s_x[q]);
+    }
+    ctrl->ir_dmax = a;
+    ctrl->ir_xmax = b;
+  }
 }
 
 // Dense r = A x - b: one thread per row, ascending column order.
@@ -58,15 +97,17 @@ __global__ __launch_bounds__(256) void k_residual_dense(int m, int n, const doub
   r[i] = s - b[i];
 }
 
-// Dense y_j = a_j^T r on G: one wave per column.
+// Dense y_j = a_j^T r on G (and on F into gfree when given): one wave per column.
 __global__ __launch_bounds__(256) void k_dual_dense(int m, int n, const double* __restrict__ A, int lda,
                                                     const double* __restrict__ r,
                                                     const uint8_t* __restrict__ flags,
-                                                    double* __restrict__ y) {
+                                                    double* __restrict__ y,
+                                                    double* __restrict__ gfree) {
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= n) return;
-  if (flags[j]) {
+  const bool free_j = flags[j] != 0;
+  if (free_j && !gfree) {
     if (lane == 0) y[j] = 0.0;
     return;
   }
@@ -74,7 +115,10 @@ __global__ __launch_bounds__(256) void k_dual_dense(int m, int n, const double* 
   double s = 0.0;
   for (int q = lane; q < m; q += 64) s = fma(col[q], r[q], s);
   for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
-  if (lane == 0) y[j] = s;
+  if (lane == 0) {
+    y[j] = free_j ? 0.0 : s;
+    if (free_j) gfree[j] = s;
+  }
 }
 
 }  // namespace
@@ -85,10 +129,16 @@ void launch_residual_csr(hipStream_t s, int m, const int32_t* rowptr, const int3
 }
 
 void launch_dual_csc(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx,
-                     const double* val, const double* r, const uint8_t* flags, double* y) {
+                     const double* val, const double* r, const uint8_t* flags, double* y,
+                     double* gfree) {
   const int64_t threads = (int64_t)n * 16;
   hipLaunchKernelGGL(k_dual_csc, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, n, colptr,
-                     rowidx, val, r, flags, y);
+                     rowidx, val, r, flags, y, gfree);
+}
+
+void launch_ir_update(hipStream_t s, int nF, const int32_t* Flist, const double* d, double* x,
+                      Ctrl* ctrl) {
+  hipLaunchKernelGGL(k_ir_update, dim3(1), dim3(1024), 0, s, nF, Flist, d, x, ctrl);
 }
 
 void launch_residual_dense(hipStream_t s, int m, int n, const double* A, int lda,
@@ -97,8 +147,8 @@ void launch_residual_dense(hipStream_t s, int m, int n, const double* A, int lda
 }
 
 void launch_dual_dense(hipStream_t s, int m, int n, const double* A, int lda, const double* r,
-                       const uint8_t* flags, double* y) {
-  hipLaunchKernelGGL(k_dual_dense, dim3((n + 3) / 4), dim3(256), 0, s, m, n, A, lda, r, flags, y);
+                       const uint8_t* flags, double* y, double* gfree) {
+  hipLaunchKernelGGL(k_dual_dense, dim3((n + 3) / 4), dim3(256), 0, s, m, n, A, lda, r, flags, y, gfree);
 }
 
 }  // namespace nnls

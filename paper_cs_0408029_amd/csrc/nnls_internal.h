@@ -31,6 +31,8 @@ struct Ctrl {
   int32_t fwd_done;    // frontier of the forward triangular solve (blocks finished)
   int32_t bwd_done;    // frontier of the backward triangular solve
   double min_margin;   // smallest |v| over the tested entries that were not zeroed
+  double ir_dmax;      // mixed precision: max |correction| of the last refinement step
+  double ir_xmax;      //                  max |x_F| after it
 };
 
 // Lower-triangle Gram matrix in padded CSC: column j occupies
@@ -85,11 +87,15 @@ void launch_ctrl_set_state(hipStream_t s, Ctrl* ctrl, int N, int p, int iter, in
 void launch_residual_csr(hipStream_t s, int m, const int32_t* rowptr, const int32_t* colidx,
                          const double* valr, const double* x, const double* b, double* r);
 void launch_dual_csc(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx,
-                     const double* val, const double* r, const uint8_t* flags, double* y);
+                     const double* val, const double* r, const uint8_t* flags, double* y,
+                     double* gfree = nullptr);
 void launch_residual_dense(hipStream_t s, int m, int n, const double* A, int lda,
                            const double* x, const double* b, double* r);
 void launch_dual_dense(hipStream_t s, int m, int n, const double* A, int lda, const double* r,
-                       const uint8_t* flags, double* y);
+                       const uint8_t* flags, double* y, double* gfree = nullptr);
+// x[Flist[p]] -= d[p] for p < nF; writes max |d| and max |x_F| into ctrl (one workgroup)
+void launch_ir_update(hipStream_t s, int nF, const int32_t* Flist, const double* d, double* x,
+                      Ctrl* ctrl);
 
 // factorisation and triangular solves (k_chol.hip)
 struct FactorArgs {
@@ -132,5 +138,6 @@ void launch_trsv(hipStream_t s, const SolveArgs& a, bool fp32, bool forward);
 void launch_tiles_to_dense(hipStream_t s, int n, int nb, const void* Ltiles, bool fp32,
                            double* L, int ldl);
 void launch_reset_tickets(hipStream_t s, Ctrl* ctrl);
+void launch_ctrl_clear_breakdown(hipStream_t s, Ctrl* ctrl);   // NOT_PD -> 0 (mixed retry)
 
 }  // namespace nnls

@@ -188,3 +188,56 @@ def test_invalid_inputs(h):
     bb = inst.b.copy(); bb[0] = np.inf
     assert run(cp, ri, va, bb) == N.NNLS_ERR_INVALID_VALUE
     assert run(cp[: n + 1], ri, va, inst.b[: n - 1], mm=n - 1) == N.NNLS_ERR_INVALID_ARG  # m < n
+
+
+# ------------------------------------------------------------------ mixed precision
+MIXED_RTOL = 1e-8
+
+
+def check_mixed(res, st, info, x, y, trace, scale=1.0):
+    assert st == N.NNLS_OK, N.status_string(st)
+    assert np.array_equal(np.flatnonzero(x != 0), np.flatnonzero(res.x != 0))
+    assert info.n_free == int(res.free.sum())
+    assert relerr(x, res.x) <= MIXED_RTOL
+    assert np.linalg.norm(y - res.y) <= MIXED_RTOL * max(np.linalg.norm(res.y), 1.0)
+    assert np.all(x >= 0) and np.all(y >= 0) and np.dot(x, y) == 0.0
+    if certified(res, scale, rel=1e-6):
+        assert trace == oracle_trace(res)
+
+
+@pytest.mark.parametrize("seed", [1001, 1002, 1003])
+def test_mixed_sparse_small(h, seed):
+    inst = W.sparse_small(seed)
+    res = bpp_solve(inst.A, inst.b)
+    st, info, x, y, trace = solve_csc(h, inst.A, inst.b, precision=N.NNLS_FP32_IR)
+    check_mixed(res, st, info, x, y, trace)
+    assert info.ir_steps >= info.iterations   # every factor was refined at least once
+
+
+@pytest.mark.parametrize("m,n,seed", [(300, 100, 2), (1100, 520, 4)])
+def test_mixed_dense_planted(h, m, n, seed):
+    inst = W.dense_planted(seed, m, n)
+    res = bpp_solve(inst.A, inst.b)
+    st, info, x, y, trace = solve_dense(h, inst.A, inst.b, precision=N.NNLS_FP32_IR)
+    check_mixed(res, st, info, x, y, trace)
+
+
+def test_mixed_sparse_large_full_size(h):
+    inst = W.sparse_large(1002)
+    st, info, x, y, trace = solve_csc(h, inst.A, inst.b, precision=N.NNLS_FP32_IR)
+    assert st == N.NNLS_OK
+    assert np.array_equal(x > 0, inst.active)
+    res = bpp_solve(inst.A, inst.b)
+    check_mixed(res, st, info, x, y, trace)
+
+
+@pytest.mark.parametrize("seed", range(1, 21))
+def test_mixed_ill_scaled_falls_back(h, seed):
+    """Ill-scaled problems where a float32 factor may break down or refinement may stall:
+    the iteration is redone in float64 and the result matches the float64 path."""
+    A, b = W.tiny_dense(seed)
+    st64, info64, x64, y64, tr64 = solve_dense(h, A, b)
+    st, info, x, y, tr = solve_dense(h, A, b, precision=N.NNLS_FP32_IR)
+    assert st == st64 == N.NNLS_OK
+    assert np.array_equal(x != 0, x64 != 0)
+    assert relerr(x, x64) <= 1e-6
