@@ -123,6 +123,21 @@ int nnls_solve_dense(nnls_handle* h, int32_t m, int32_t n, const double* A, int3
                      const double* b, double* x, double* y, const nnls_options* opts,
                      nnls_info* info);
 
+/* Solve `batch` independent dense problems in one launch (Eq. 1 for each).  m, n, lda:
+ * host int32[batch]; A, b, x, y: host arrays of `batch` DEVICE pointers (A column-major
+ * with lda >= m, b double[m], x and y double[n] outputs).  Each problem runs the whole
+ * pivoting loop of the Sec. 2 algorithm box on the device in one workgroup; its result
+ * does not depend on the other problems in the batch.  opts applies to every problem
+ * (NNLS_FP32_IR: float32 factor, float64 refinement).  info: host nnls_info[batch] or
+ * NULL.  Returns NNLS_OK when every problem succeeded, otherwise the first failing status
+ * (per-problem statuses are in info; a failed problem does not affect the others).
+ * Errors: INVALID_ARG for a bad size or null pointer (nothing runs); per problem
+ * INVALID_VALUE, NOT_PD, MAXITER as for nnls_solve_dense. */
+int nnls_solve_dense_batched(nnls_handle* h, int32_t batch, const int32_t* m, const int32_t* n,
+                             const double* const* A, const int32_t* lda, const double* const* b,
+                             double* const* x, double* const* y, const nnls_options* opts,
+                             nnls_info* info);
+
 /* Copy up to `cap` trace rows of the last solve on this handle into `rows` (host).
  * Returns the number of rows the solve recorded (which may exceed cap). */
 int nnls_get_trace(nnls_handle* h, nnls_trace_row* rows, int cap);
@@ -138,7 +153,8 @@ typedef enum {
   NNLS_PROF_CHOLESKY = 2,  /* gather + tiled Cholesky of the F-block (flops |F|^3/3)    */
   NNLS_PROF_TRSV = 3,      /* two triangular solves (bytes of L read)                   */
   NNLS_PROF_RESIDUAL = 4,  /* r = A x - b and y_G = A_G^T r (bytes)                     */
-  NNLS_PROF_REFINE = 5     /* mixed precision refinement (bytes)                        */
+  NNLS_PROF_REFINE = 5,    /* mixed precision refinement (bytes)                        */
+  NNLS_PROF_BATCHED = 6    /* one batched launch (flops sum n^2 m of the Gram matrices) */
 } nnls_profile_class;
 int nnls_get_profile(nnls_handle* h, int64_t* launches, double* total_ms, double* work);
 int nnls_reset_profile(nnls_handle* h);

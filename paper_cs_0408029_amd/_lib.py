@@ -26,7 +26,7 @@ NNLS_FP32_IR = 1
 NNLS_FLAG_PROFILE = 1
 
 NNLS_PROFILE_CLASSES = 8
-PROFILE_CLASS_NAMES = ["gram", "control", "cholesky", "trsv", "residual", "refine", "c6", "c7"]
+PROFILE_CLASS_NAMES = ["gram", "control", "cholesky", "trsv", "residual", "refine", "batched", "c7"]
 
 
 class nnls_options(C.Structure):
@@ -60,6 +60,8 @@ PROTOTYPES = {
                                  C.POINTER(nnls_options), C.POINTER(nnls_info)]),
     "nnls_solve_dense": (C.c_int, [_P, _I32, _I32, _P, _I32, _P, _P, _P,
                                    C.POINTER(nnls_options), C.POINTER(nnls_info)]),
+    "nnls_solve_dense_batched": (C.c_int, [_P, _I32, _P, _P, _P, _P, _P, _P, _P,
+                                           C.POINTER(nnls_options), _P]),
     "nnls_get_trace": (C.c_int, [_P, C.POINTER(nnls_trace_row), C.c_int]),
     "nnls_get_profile": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double)]),

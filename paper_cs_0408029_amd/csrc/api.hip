@@ -43,6 +43,7 @@ struct nnls_handle {
   // workspace
   DevBuf err, ctrl, rowcnt, rowptr, colidx, valr, hptr, hcnt, hrow, hval, c, r, flags, Flist, pos;
   DevBuf Lt, Dinv, colcnt, dflag, tflag, z, xF, Hd, gF;
+  DevBuf bprobs, border, binfo, bws;   // batched dense problems
   Ctrl* h_ctrl = nullptr;     // pinned
   int64_t* h_scalar = nullptr;  // pinned scratch for small reads
   int epoch = 0;
@@ -552,7 +553,8 @@ int nnls_destroy(nnls_handle* h) {
   (void)hipStreamSynchronize(h->stream);
   DevBuf* bufs[] = {&h->err, &h->ctrl, &h->rowcnt, &h->rowptr, &h->colidx, &h->valr, &h->hptr,
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
-                    &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF};
+                    &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF,
+                    &h->bprobs, &h->border, &h->binfo, &h->bws};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
@@ -593,6 +595,105 @@ int nnls_solve_dense(nnls_handle* h, int32_t m, int32_t n, const double* A, int3
   P.lda = lda;
   P.b = b;
   return solve_common(h, P, x, y, opts, info);
+}
+
+int nnls_solve_dense_batched(nnls_handle* h, int32_t batch, const int32_t* m, const int32_t* n,
+                             const double* const* A, const int32_t* lda, const double* const* b,
+                             double* const* x, double* const* y, const nnls_options* opts,
+                             nnls_info* info) {
+  nnls_options o;
+  nnls_default_options(&o);
+  if (opts) o = *opts;
+  if (!h || batch < 0 || (batch > 0 && (!m || !n || !A || !lda || !b || !x || !y)))
+    return NNLS_ERR_INVALID_ARG;
+  if (check_options(o) != NNLS_OK) return NNLS_ERR_INVALID_ARG;
+  if (o.precision == NNLS_FP32_IR && (o.ir_max_steps < 0 || !(o.ir_rtol > 0.0))) return NNLS_ERR_INVALID_ARG;
+  if (info)
+    for (int i = 0; i < batch; ++i) {
+      std::memset(&info[i], 0, sizeof(nnls_info));
+      info[i].failed_index = -1;
+    }
+  if (batch == 0) return NNLS_OK;
+  for (int i = 0; i < batch; ++i) {
+    if (n[i] < 1 || m[i] < n[i] || lda[i] < m[i] || !A[i] || !b[i] || !x[i] || !y[i]) {
+      if (info) info[i].status = NNLS_ERR_INVALID_ARG;
+      return NNLS_ERR_INVALID_ARG;
+    }
+  }
+  if (hipSetDevice(h->device) != hipSuccess) return NNLS_ERR_DEVICE;
+  const double t0 = now_ms();
+  std::vector<BatchProblem> probs((size_t)batch);
+  std::vector<int32_t> order((size_t)batch);
+  size_t total = 0;
+  for (int i = 0; i < batch; ++i) {
+    BatchProblem& bp = probs[(size_t)i];
+    bp.m = m[i];
+    bp.n = n[i];
+    bp.lda = lda[i];
+    bp.pad = 0;
+    bp.A = A[i];
+    bp.b = b[i];
+    bp.x = x[i];
+    bp.y = y[i];
+    bp.ws = (int64_t)total;
+    total += batched_workspace_bytes(m[i], n[i]);
+    order[(size_t)i] = i;
+  }
+  // largest work first, so the tail of the launch is made of small problems
+  std::stable_sort(order.begin(), order.end(), [&](int a_, int b_) {
+    const double wa = (double)n[a_] * n[a_] * (m[a_] + n[a_]);
+    const double wb = (double)n[b_] * n[b_] * (m[b_] + n[b_]);
+    return wa > wb;
+  });
+  TRY(ensure(h, h->bprobs, sizeof(BatchProblem) * (size_t)batch));
+  TRY(ensure(h, h->border, sizeof(int32_t) * (size_t)batch));
+  TRY(ensure(h, h->binfo, sizeof(BatchInfo) * (size_t)batch));
+  TRY(ensure(h, h->bws, total));
+  HIP_TRY(hipMemcpyAsync(h->bprobs.p, probs.data(), sizeof(BatchProblem) * (size_t)batch,
+                         hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipMemcpyAsync(h->border.p, order.data(), sizeof(int32_t) * (size_t)batch,
+                         hipMemcpyHostToDevice, h->stream));
+  BatchArgs ba;
+  std::memset(&ba, 0, sizeof(ba));
+  ba.count = batch;
+  ba.probs = (const BatchProblem*)h->bprobs.p;
+  ba.order = (const int32_t*)h->border.p;
+  ba.info = (BatchInfo*)h->binfo.p;
+  ba.ws = (char*)h->bws.p;
+  ba.tau = o.tau;
+  ba.p_max = o.p_max;
+  ba.max_iter = o.max_iter;
+  ba.fp32 = o.precision == NNLS_FP32_IR ? 1 : 0;
+  ba.ir_max_steps = o.ir_max_steps;
+  ba.ir_rtol = o.ir_rtol;
+  h->profiling = (o.flags & NNLS_FLAG_PROFILE) != 0;
+  double flops = 0.0;
+  for (int i = 0; i < batch; ++i) flops += (double)n[i] * n[i] * m[i];
+  const int64_t pe = prof_begin(h, NNLS_PROF_BATCHED);
+  launch_batched(h->stream, ba, batch);
+  prof_end(h, pe, flops);
+  std::vector<BatchInfo> bi((size_t)batch);
+  const int st = sync_read(h, bi.data(), h->binfo.p, sizeof(BatchInfo) * (size_t)batch);
+  h->profiling = false;
+  if (st != NNLS_OK) return st;
+  if (hipGetLastError() != hipSuccess) return NNLS_ERR_DEVICE;
+  const double el = now_ms() - t0;
+  int worst = NNLS_OK;
+  for (int i = 0; i < batch; ++i) {
+    const BatchInfo& q = bi[(size_t)i];
+    if (info) {
+      info[i].status = q.status;
+      info[i].iterations = q.iterations;
+      info[i].n_free = q.n_free;
+      info[i].last_ninf = q.last_ninf;
+      info[i].failed_index = q.failed_index;
+      info[i].ir_steps = q.ir_steps;
+      info[i].min_margin = q.min_margin;
+      info[i].solve_ms = el;
+    }
+    if (q.status != NNLS_OK && worst == NNLS_OK) worst = q.status;
+  }
+  return worst;
 }
 
 int nnls_get_trace(nnls_handle* h, nnls_trace_row* rows, int cap) {

@@ -25,93 +25,11 @@
 // every dependency.
 #include <climits>
 
-#include "nnls_internal.h"
+#include "tile_ops.h"
 
 namespace nnls {
 
 namespace {
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-template <typename T> struct MF;
-template <> struct MF<double> {
-  typedef d4 acc;
-  static __device__ inline acc op(double a, double b, acc c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  // element v of lane l holds row (l / 16) + 4 v, column l % 16 of the 16 x 16 block
-  static __device__ inline int row(int l, int v) { return (l >> 4) + 4 * v; }
-};
-template <> struct MF<float> {
-  typedef f4 acc;
-  static __device__ inline acc op(float a, float b, acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  // element v of lane l holds row 4 (l / 16) + v, column l % 16 of the 16 x 16 block
-  static __device__ inline int row(int l, int v) { return 4 * (l >> 4) + v; }
-};
-
-constexpr int LDT = TILE + 1;    // LDS leading dimension of a column-major staged tile
-
-__device__ inline int32_t ld_relaxed(const int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
-
-__device__ inline void raise_abort(Ctrl* ctrl) {
-  __hip_atomic_store(&ctrl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  atomicCAS(&ctrl->status, 0, (int)NNLS_ERR_DEVICE);
-}
-
-// Spin with relaxed loads until *p >= target (or == target when exact).  No fence: the
-// caller issues one acquire after it has learned all it can from the counters.
-__device__ inline bool spin_until(const int32_t* p, int target, bool exact, Ctrl* ctrl,
-                                  uint64_t wait_ticks) {
-  int32_t v = ld_relaxed(p);
-  if (exact ? v == target : v >= target) return true;
-  const uint64_t t0 = wall_clock64();
-  for (;;) {
-    __builtin_amdgcn_s_sleep(1);
-    v = ld_relaxed(p);
-    if (exact ? v == target : v >= target) return true;
-    if (ld_relaxed(&ctrl->abort)) return false;
-    if (wall_clock64() - t0 > wait_ticks) {
-      raise_abort(ctrl);
-      return false;
-    }
-  }
-}
-
-// Make every thread's global stores visible at agent scope, then let thread 0 bump a
-// counter (add) or set a flag (store).
-__device__ inline void publish_add(int32_t* counter) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void publish_tile(int32_t* flag, int32_t* counter, int epoch) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-__device__ inline void publish_store(int32_t* flag, int value) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ inline double bcast_lane(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
-}
-__device__ inline float bcast_lane(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
 
 // Stage tile (I, J) of H_FF in LDS (column-major, leading dimension LDT).  Positions at or
 // beyond nF are padding: identity on the diagonal, zero elsewhere.
@@ -160,168 +78,6 @@ __device__ inline void gather_tile(const FactorArgs& a, int I, int J, T* S) {
     }
   }
   __syncthreads();
-}
-
-// 16 x 16 block product on MFMA for one wave: acc += sign * A * op(B), where A is the
-// block of P at (pr, pc) and op(B) is the block of Q at (qr, qc), transposed when transB.
-// Both operands are column-major with leading dimension LDT.
-template <typename T>
-__device__ inline typename MF<T>::acc mm16(typename MF<T>::acc acc, T sign, const T* P, int pr, int pc,
-                                         const T* Q, int qr, int qc, bool transB) {
-  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
-#pragma unroll
-  for (int kk = 0; kk < 16; kk += 4) {
-    const T av = sign * P[(pr + lr) + (pc + kk + lk) * LDT];
-    const T bv = transB ? Q[(qr + lr) + (qc + kk + lk) * LDT] : Q[(qr + kk + lk) + (qc + lr) * LDT];
-    acc = MF<T>::op(av, bv, acc);
-  }
-  return acc;
-}
-
-template <typename T>
-__device__ inline typename MF<T>::acc load16(const T* X, int r0, int c0) {
-  const int lane = threadIdx.x & 63, lr = lane & 15;
-  typename MF<T>::acc v;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) v[e] = X[(r0 + MF<T>::row(lane, e)) + (c0 + lr) * LDT];
-  return v;
-}
-
-template <typename T>
-__device__ inline void store16(T* X, int r0, int c0, typename MF<T>::acc v) {
-  const int lane = threadIdx.x & 63, lr = lane & 15;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) X[(r0 + MF<T>::row(lane, e)) + (c0 + lr) * LDT] = v[e];
-}
-
-__device__ inline double rsqrt_refined(double d) {
-  double y = __builtin_amdgcn_rsq(d);
-  y = y * fma(-0.5 * d, y * y, 1.5);
-  y = y * fma(-0.5 * d, y * y, 1.5);
-  return y;
-}
-__device__ inline float rsqrt_refined(float d) {
-  float y = __builtin_amdgcn_rsqf(d);
-  y = y * fmaf(-0.5f * d, y * y, 1.5f);
-  return y;
-}
-
-// Factor and invert the 16 x 16 diagonal block at offset o of S (one wave).  Lane i keeps
-// row i in registers; pivots come from a refined reciprocal square root (no divide); the
-// scaled column of each step is broadcast through LDS (16-byte broadcast reads), and the
-// inverse reuses the pivot reciprocals.  L goes back into S, its inverse into W; the LDS
-// broadcast buffers live in the unused upper blocks of S.
-template <typename T>
-__device__ inline void diag16(T* S, T* W, int o, int J, const FactorArgs& a) {
-  const int lane = threadIdx.x & 63, i = lane & 15;
-  T* colbuf = S + 48 * LDT;          // column buffer: rows 0..15 of column 48 (upper block)
-  T* LR = S + 16 + 48 * LDT;         // rows of L: LR[i * LDT + k], in the upper block (16, 48)
-  T r[16], invd[16];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) r[j] = S[(o + i) + (o + j) * LDT];
-  int firstbad = -1;                 // uniform: pivots are read from one lane
-  T d = bcast_lane(r[0], 0);
-#pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    const bool bad = !(d > (T)0) || !isfinite(d);
-    if (bad && firstbad < 0) firstbad = c;
-    const T y = bad ? (T)1 : rsqrt_refined(d);   // 1 / L_cc
-    const T l = bad ? (T)1 : d * y;               // L_cc
-    invd[c] = y;
-    const T lic = (i == c) ? l : r[c] * y;
-    r[c] = lic;
-    // the next pivot only needs lane c+1's own diagonal update, off the LDS path
-    if (c + 1 < 16) d = bcast_lane(fma(-lic, lic, r[c + 1]), c + 1);
-    if (lane < 16) colbuf[i] = lic;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-#pragma unroll
-    for (int j = c + 1; j < 16; ++j) r[j] = fma(-lic, colbuf[j], r[j]);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
-  if (firstbad >= 0 && lane == 0 && J * TILE + o + firstbad < a.nF) {
-    atomicMin(&a.ctrl->failed_pos, J * TILE + o + firstbad);
-    atomicCAS(&a.ctrl->status, 0, (int)NNLS_ERR_NOT_PD);
-  }
-  if (lane < 16) {
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const T v = (j <= i) ? r[j] : (T)0;
-      S[(o + i) + (o + j) * LDT] = v;
-      LR[i * LDT + j] = v;
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  // inverse: lane i runs forward substitution down column i; the newest term is added
-  // last so each row waits on one product
-  T x[16];
-#pragma unroll
-  for (int ii = 0; ii < 16; ++ii) {
-    const T* row = LR + ii * LDT;
-    T s0 = (T)0, s1 = (T)0;
-    // terms k = 0 .. ii-2 in two chains, then k = ii-1
-#pragma unroll
-    for (int k = 0; k + 1 < ii - 1; k += 2) {
-      s0 += row[k] * x[k];
-      s1 += row[k + 1] * x[k + 1];
-    }
-    if (ii >= 2 && ((ii - 1) & 1)) s0 += row[ii - 2] * x[ii - 2];
-    T s = s0 + s1;
-    if (ii >= 1) s += row[ii - 1] * x[ii - 1];
-    x[ii] = ((i == ii ? (T)1 : (T)0) - s) * invd[ii];
-  }
-  if (lane < 16) {
-#pragma unroll
-    for (int ii = 0; ii < 16; ++ii) W[(o + ii) + (o + i) * LDT] = x[ii];
-  }
-}
-
-// Blocked Cholesky and inverse of the 64 x 64 tile in S (lower triangle) by the whole
-// workgroup: 4 x 4 blocks of 16; diagonal blocks by one wave, the panel and trailing
-// updates on MFMA across the four waves.  Leaves L in the lower triangle of S and L^-1
-// in the lower triangle of W.
-template <typename T>
-__device__ inline void factor_invert_tile(T* S, T* W, int J, const FactorArgs& a) {
-  typedef typename MF<T>::acc Acc;
-  const int w = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if (w == 0) diag16<T>(S, W, 16 * q, J, a);
-    __syncthreads();
-    // panel: L_pq = A_pq W_qq^T
-    const int p = q + 1 + w;
-    if (p < 4) {
-      Acc acc = {};
-      acc = mm16<T>(acc, (T)1, S, 16 * p, 16 * q, W, 16 * q, 16 * q, true);
-      store16<T>(S, 16 * p, 16 * q, acc);
-    }
-    __syncthreads();
-    // trailing update: A_pr -= L_pq L_rq^T for q < r <= p
-    int idx = 0;
-    for (int rr = q + 1; rr < 4; ++rr)
-      for (int pp = rr; pp < 4; ++pp, ++idx)
-        if ((idx & 3) == w) {
-          Acc acc = load16<T>(S, 16 * pp, 16 * rr);
-          acc = mm16<T>(acc, (T)-1, S, 16 * pp, 16 * q, S, 16 * rr, 16 * q, true);
-          store16<T>(S, 16 * pp, 16 * rr, acc);
-        }
-    __syncthreads();
-  }
-  // off-diagonal blocks of the inverse, by distance from the diagonal:
-  // W_pq = -W_pp sum_{k=q}^{p-1} L_pk W_kq
-  for (int dd = 1; dd < 4; ++dd) {
-    const int p = dd + w, q = w;
-    if (p < 4) {
-      Acc t = {};
-      for (int k = q; k < p; ++k) t = mm16<T>(t, (T)1, S, 16 * p, 16 * k, W, 16 * k, 16 * q, false);
-      // stage t in this wave's free upper block of S, then multiply by -W_pp
-      const int sr = (w == 3) ? 16 : 0, sc = (w == 3) ? 32 : 16 * (w + 1);
-      store16<T>(S, sr, sc, t);
-      Acc u = {};
-      u = mm16<T>(u, (T)-1, W, 16 * p, 16 * p, S, sr, sc, false);
-      store16<T>(W, 16 * p, 16 * q, u);
-    }
-    __syncthreads();
-  }
 }
 
 template <typename T>
@@ -421,7 +177,8 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wa
   T* dst = Lt + (int64_t)t * TILE_ELEMS;
   if (I == J) {
     if (fwd) s_part[w][lane] = tacc;
-    factor_invert_tile<T>(S, W, J, a);
+    const PivotReport rep = {J * TILE, a.nF, &a.ctrl->failed_pos, &a.ctrl->status};
+    factor_invert_tile<T>(S, W, rep);
     if (fwd) {
       if (tid < TILE) {
         const int p = J * TILE + tid;

@@ -138,6 +138,35 @@ void launch_trsv(hipStream_t s, const SolveArgs& a, bool fp32, bool forward);
 void launch_tiles_to_dense(hipStream_t s, int n, int nb, const void* Ltiles, bool fp32,
                            double* L, int ldl);
 void launch_reset_tickets(hipStream_t s, Ctrl* ctrl);
+
+// batched dense problems (k_batched.hip): one workgroup per problem
+struct BatchProblem {
+  int32_t m, n, lda, pad;
+  const double* A;
+  const double* b;
+  double* x;
+  double* y;
+  int64_t ws;             // byte offset of the problem's workspace in the arena
+};
+struct BatchInfo {
+  int32_t status, iterations, n_free, last_ninf, failed_index, ir_steps;
+  double min_margin;
+};
+struct BatchArgs {
+  int count;
+  const BatchProblem* probs;
+  const int32_t* order;   // launch order (workgroup b solves problem order[b]); may be null
+  BatchInfo* info;
+  char* ws;
+  double tau;
+  int p_max;
+  int max_iter;           // <= 0: 5 n + 100 per problem
+  int fp32;               // float32 factor + float64 refinement
+  int ir_max_steps;
+  double ir_rtol;
+};
+size_t batched_workspace_bytes(int m, int n);
+void launch_batched(hipStream_t s, const BatchArgs& a, int grid);
 void launch_ctrl_clear_breakdown(hipStream_t s, Ctrl* ctrl);   // NOT_PD -> 0 (mixed retry)
 
 }  // namespace nnls

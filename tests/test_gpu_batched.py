@@ -1,0 +1,120 @@
+"""Batched dense path (one launch, one workgroup per problem) against the oracle: identical
+free sets, x within 1e-10 (float64 factor) or 1e-8 (float32 factor + float64 refinement),
+and bitwise identical results alone and inside any batch."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import bpp_solve
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_cs_0408029_amd as N  # noqa: E402
+from _gpu_util import DEV, colmajor_dev, t  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def h():
+    with N.Handle(0) as hh:
+        yield hh
+
+
+def run_batch(h, problems, **opt):
+    As = [colmajor_dev(A) for A, _ in problems]
+    bs = [t(b) for _, b in problems]
+    xs = [torch.full((A.shape[1],), np.nan, dtype=torch.float64, device=DEV) for A, _ in problems]
+    ys = [torch.full((A.shape[1],), np.nan, dtype=torch.float64, device=DEV) for A, _ in problems]
+    st, infos = N.nnls_solve_dense_batched(h, As, bs, xs, ys, N.default_options(**opt))
+    return st, infos, [x.cpu().numpy() for x in xs], [y.cpu().numpy() for y in ys]
+
+
+def relerr(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def batch24():
+    insts = W.dense_batch(1003, count=24)
+    return [(i.A, i.b) for i in insts], insts
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-8)])
+def test_batch_matches_oracle(h, batch24, precision, tol):
+    problems, insts = batch24
+    st, infos, xs, ys = run_batch(h, problems, precision=precision)
+    assert st == N.NNLS_OK
+    for inst, info, x, y in zip(insts, infos, xs, ys):
+        res = bpp_solve(inst.A, inst.b)
+        assert info.status == N.NNLS_OK and res.status == "ok"
+        assert info.iterations == res.iterations
+        assert info.n_free == int(res.free.sum())
+        assert np.array_equal(x > 0, inst.active)
+        assert relerr(x, res.x) <= tol
+        assert np.linalg.norm(y - res.y) <= tol * max(np.linalg.norm(res.y), 1.0)
+        assert np.all(x >= 0) and np.all(y >= 0) and np.dot(x, y) == 0.0
+        if precision == 1:
+            assert info.ir_steps >= 1
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_alone_equals_in_batch(h, batch24, precision):
+    problems, _ = batch24
+    st, infos, xs, ys = run_batch(h, problems, precision=precision)
+    for k in (0, 7, 23):
+        st1, inf1, x1, y1 = run_batch(h, [problems[k]], precision=precision)
+        assert np.array_equal(x1[0], xs[k]) and np.array_equal(y1[0], ys[k])
+        assert inf1[0].iterations == infos[k].iterations
+    # reversed order, and a batch mixed with other problems
+    st2, inf2, x2, y2 = run_batch(h, problems[::-1], precision=precision)
+    for k in range(len(problems)):
+        assert np.array_equal(x2[len(problems) - 1 - k], xs[k])
+
+
+def test_multi_tile_and_ragged_sizes(h):
+    sizes = [(40, 16, 1), (300, 100, 2), (700, 256, 3), (1100, 520, 4), (200, 65, 5), (130, 64, 6)]
+    insts = [W.dense_planted(s, m, n) for m, n, s in sizes]
+    st, infos, xs, ys = run_batch(h, [(i.A, i.b) for i in insts])
+    assert st == N.NNLS_OK
+    for inst, info, x in zip(insts, infos, xs):
+        res = bpp_solve(inst.A, inst.b)
+        assert np.array_equal(x > 0, inst.active)
+        assert relerr(x, res.x) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_all_branches_in_batch(h, precision):
+    problems = [W.tiny_dense(s) for s in range(1, 21)]
+    st, infos, xs, ys = run_batch(h, problems, precision=precision)
+    assert st == N.NNLS_OK
+    for (A, b), info, x in zip(problems, infos, xs):
+        res = bpp_solve(A, b)
+        assert np.array_equal(x != 0, res.x != 0)
+        Hff = (A.T @ A)[np.ix_(res.free, res.free)]
+        kappa = np.linalg.cond(Hff) if res.free.any() else 1.0
+        assert relerr(x, res.x) <= max(1e-9, 100 * kappa * np.finfo(float).eps)
+
+
+def test_failures_stay_in_their_problem(h):
+    good = W.dense_planted(11, 120, 50)
+    bad_nan = good.A.copy()
+    bad_nan[3, 4] = np.nan
+    dup = np.array([[1.0, 1.0, 0.0], [0.0, 0.0, 1.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    problems = [(good.A, good.b), (bad_nan, good.b), (dup, np.array([1.0, 1.0, 0.0, 0.0])),
+                (good.A, good.b)]
+    st, infos, xs, ys = run_batch(h, problems)
+    assert st == N.NNLS_ERR_INVALID_VALUE
+    assert [i.status for i in infos] == [N.NNLS_OK, N.NNLS_ERR_INVALID_VALUE, N.NNLS_ERR_NOT_PD, N.NNLS_OK]
+    assert infos[2].failed_index == 1
+    assert np.array_equal(xs[0], xs[3])
+    res = bpp_solve(good.A, good.b)
+    assert relerr(xs[0], res.x) <= 1e-10
+
+
+def test_empty_and_invalid(h):
+    st, infos, xs, ys = run_batch(h, [])
+    assert st == N.NNLS_OK and infos == []
+    A = np.ones((3, 5))
+    st, infos, xs, ys = run_batch(h, [(A, np.ones(3))])   # m < n
+    assert st == N.NNLS_ERR_INVALID_ARG
