@@ -76,6 +76,107 @@ def cpu_baseline(inst, budget_s: float):
             "status": res.status}
 
 
+def bench_batch(args):
+    """Batched dense workload: `--batch` problems (default 4096), n ~ U{16..256},
+    m ~ U{2n..4n}, A = N(0,1)/sqrt(m), 40% active (seed 1003).  One step = one batched
+    launch over all problems.  Beside it: the plain float64 path (one nnls_solve_dense call
+    per problem) on the first --plain-sample problems."""
+    import torch
+    import paper_cs_0408029_amd as N
+    import workloads as W
+    t0 = time.perf_counter()
+    insts = W.dense_batch(1003, count=args.batch)
+    gen_s = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    As = [torch.from_numpy(np.ascontiguousarray(i.A.T)).to(dev).t() for i in insts]
+    bs = [torch.from_numpy(i.b).to(dev) for i in insts]
+    xs = [torch.empty(i.n, dtype=torch.float64, device=dev) for i in insts]
+    ys = [torch.empty(i.n, dtype=torch.float64, device=dev) for i in insts]
+    h = N.Handle(0)
+    prec = N.NNLS_FP64 if args.precision == "fp64" else N.NNLS_FP32_IR
+    opts = N.default_options(precision=prec)
+    popts = N.default_options(precision=prec, flags=N.NNLS_FLAG_PROFILE)
+
+    def step(o):
+        st, infos = N.nnls_solve_dense_batched(h, As, bs, xs, ys, o)
+        if st != N.NNLS_OK:
+            raise RuntimeError(f"batched solve failed: {N.status_string(st)}")
+        return infos
+
+    for _ in range(args.warmup):
+        step(opts)
+    N.nnls_reset_profile(h)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        infos = step(popts)
+        lat.append((time.perf_counter() - s0) * 1e3)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    prof = N.nnls_get_profile(h)["batched"]
+    # accuracy against the planted solutions and the free sets
+    errs, match = [], 0
+    for inst, x in zip(insts, xs):
+        xh = x.cpu().numpy()
+        errs.append(float(np.linalg.norm(xh - inst.x_star) / np.linalg.norm(inst.x_star)))
+        match += int(np.array_equal(xh > 0, inst.active))
+    # plain float64 path, one problem per call
+    k = min(args.plain_sample, len(insts))
+    o64 = N.default_options()
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    for i in range(k):
+        st, _ = N.nnls_solve_dense(h, As[i], bs[i], xs[i], ys[i], o64)
+        if st != N.NNLS_OK:
+            raise RuntimeError(f"plain solve failed: {N.status_string(st)}")
+    torch.cuda.synchronize()
+    plain = k / (time.perf_counter() - p0)
+    h.close()
+    gram_flops = sum(i.n * i.n * i.m for i in insts)
+    achieved = gram_flops / (prof["ms"] / max(prof["launches"], 1) * 1e-3) / 1e12 if prof["launches"] else None
+    out = {
+        "metric": METRIC,
+        "value": round(args.steps * len(insts) / total, 2),
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(total / args.steps * 1e3, 3),
+        "p50_ms": round(float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == N.NNLS_FP64 else "f32-factor+f64-refinement",
+        "data": "synthetic",
+        "config": {"workload": f"{len(insts)} dense problems, n~U{{16..256}}, m~U{{2n..4n}}, "
+                               "N(0,1)/sqrt(m), 40% active, seed 1003",
+                   "path": "batched, one launch"},
+        "max_rel_err_vs_planted": max(errs), "free_set_matches": f"{match}/{len(insts)}",
+        "plain_fp64_solves_per_s": round(plain, 2), "plain_sample": k,
+        "roofline": {"bound": "mfma", "kernel": "k_batched", "achieved": round(achieved, 4) if achieved else None,
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP64_TFLOPS, 5) if achieved else None, "traffic": None,
+                     "work_per_launch": "sum n^2 m (Gram) flops; the pivot loop adds the factors"},
+        "generation_s": round(gen_s, 1),
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        from oracle import bpp_solve
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        except Exception:
+            threads = os.cpu_count() or 1
+        c0 = time.perf_counter()
+        cnt = 0
+        while cnt < len(insts) and time.perf_counter() - c0 < args.cpu_budget:
+            bpp_solve(insts[cnt].A, insts[cnt].b)
+            cnt += 1
+        el = time.perf_counter() - c0
+        out["cpu_baseline"] = {"value": round(cnt / el, 2), "unit": "solves/s", "cores": int(threads),
+                               "kind": "oracle", "sample": f"first {cnt} problems of the batch, {el:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +189,9 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32ir"], default="fp64",
                     help="fp64: the plain FP64 path (the metric's reference); fp32ir: float32 factor "
                          "with float64 refinement")
+    ap.add_argument("--batch", type=int, default=4096, help="dense_batch: number of problems")
+    ap.add_argument("--plain-sample", type=int, default=256,
+                    help="dense_batch: problems solved one per call on the plain float64 path")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -112,6 +216,9 @@ def main():
     if not os.path.exists(N.LIB_PATH):
         from paper_cs_0408029_amd.build import build
         build()
+    if args.workload == "dense_batch":
+        bench_batch(args)
+        return
     inst, desc = make_instance(args.workload)
     dev = torch.device("cuda:0")
     A = inst.A
