@@ -177,6 +177,179 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serve(args):
+    """Serving workload: Poisson arrivals at --rate requests/s (seed 1004) of mixed sparse
+    problems, n log-uniform in [64, 8192], m = 3n, 20 N(0,1) entries per column plus a band
+    of sqrt(20) * (1, 1/2, 1/4), 30-60% active, margin 1e-3.  Requests cycle through a pool
+    of --pool seeded problems.  --warmup-s seconds of arrivals are served before the
+    statistics are reset; the next --duration seconds of arrivals are the timed window
+    (latency: submit to x, y in host memory).  Beside it: a saturation run (the whole pool
+    submitted at once) and the plain float64 path, one nnls_solve_csc call per problem."""
+    import threading
+    import torch
+    import paper_cs_0408029_amd as N
+    import workloads as W
+    t0 = time.perf_counter()
+    _, pool = W.serving_stream(1004, count=args.pool)
+    gen_s = time.perf_counter() - t0
+    arrs = [W.csc_arrays(p.A) + (np.ascontiguousarray(p.b),) for p in pool]
+    prec = N.NNLS_FP64 if args.precision == "fp64" else N.NNLS_FP32_IR
+    opts = N.default_options(precision=prec)
+    srv = N.Server(0, opts=opts, workers=args.workers, batch_lanes=args.batch_lanes,
+                   batch_max_n=args.batch_max_n)
+
+    def submit(i):
+        p = pool[i % len(pool)]
+        cp, ri, va, b = arrs[i % len(pool)]
+        st, tk = N.nnls_server_submit_csc(srv, p.m, p.n, cp, ri, va, b)
+        if st != N.NNLS_OK:
+            raise RuntimeError(f"submit failed: {N.status_string(st)}")
+        return tk
+
+    first = {}
+    errors = []
+
+    def collect(tickets, done_evt):
+        for i, tk in tickets:
+            p = pool[i % len(pool)]
+            st, x, y, info = N.nnls_server_wait(srv, tk, p.n, timeout_ms=-1)
+            if st != N.NNLS_OK:
+                errors.append((i, N.status_string(st)))
+            elif (i % len(pool)) not in first:
+                first[i % len(pool)] = x
+        done_evt.set()
+
+    # open loop: submit at the arrival times
+    rng = np.random.default_rng(1004)
+    total_s = args.warmup_s + args.duration
+    gaps = rng.exponential(1.0 / args.rate, size=int(args.rate * total_s * 1.5) + 16)
+    arrivals = np.cumsum(gaps)
+    arrivals = arrivals[arrivals < total_s]
+    n_warm = int(np.searchsorted(arrivals, args.warmup_s))
+    import queue as Q
+    tq = Q.Queue()
+    lag = []
+
+    def collector():
+        while True:
+            item = tq.get()
+            if item is None:
+                return
+            i, tk = item
+            p = pool[i % len(pool)]
+            st, x, y, info = N.nnls_server_wait(srv, tk, p.n, timeout_ms=-1)
+            if st != N.NNLS_OK:
+                errors.append((i, N.status_string(st)))
+            elif (i % len(pool)) not in first:
+                first[i % len(pool)] = x
+
+    col = threading.Thread(target=collector)
+    col.start()
+    start = time.perf_counter()
+    timed_start = None
+    for i, ta in enumerate(arrivals):
+        if i == n_warm:
+            # warm-up arrivals are all submitted; their completions still count until reset
+            N.nnls_server_reset_stats(srv)
+            timed_start = time.perf_counter()
+        now = time.perf_counter() - start
+        if ta > now:
+            time.sleep(ta - now)
+        lag.append(time.perf_counter() - start - ta)
+        tq.put((i, submit(i)))
+    tq.put(None)
+    col.join()
+    stats = N.nnls_server_stats(srv)
+    wall = time.perf_counter() - (timed_start or start)
+    timed = len(arrivals) - n_warm
+
+    # saturation: the whole pool at once, twice
+    N.nnls_server_reset_stats(srv)
+    s0 = time.perf_counter()
+    sat_tickets = [(i, submit(i)) for i in range(2 * len(pool))]
+    ev = threading.Event()
+    collect(sat_tickets, ev)
+    sat_wall = time.perf_counter() - s0
+    sat = N.nnls_server_stats(srv)
+    srv.close()
+
+    # plain float64 path: one problem per call on one stream
+    dev = torch.device("cuda:0")
+    h = N.Handle(0)
+    o64 = N.default_options()
+    plain_n = min(args.plain_sample, len(pool))
+    dev_in = []
+    for p, (cp, ri, va, b) in zip(pool[:plain_n], arrs[:plain_n]):
+        dev_in.append(tuple(torch.from_numpy(a).to(dev) for a in (cp, ri, va, b)) +
+                      (torch.empty(p.n, dtype=torch.float64, device=dev),
+                       torch.empty(p.n, dtype=torch.float64, device=dev)))
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    for p, (cp, ri, va, b, x, y) in zip(pool[:plain_n], dev_in):
+        st, _ = N.nnls_solve_csc(h, p.m, p.n, cp, ri, va, b, x, y, o64)
+        if st != N.NNLS_OK:
+            raise RuntimeError(f"plain solve failed: {N.status_string(st)}")
+    torch.cuda.synchronize()
+    plain = plain_n / (time.perf_counter() - p0)
+    h.close()
+
+    errs, match = [], 0
+    for k, x in first.items():
+        p = pool[k]
+        errs.append(float(np.linalg.norm(x - p.x_star) / np.linalg.norm(p.x_star)))
+        match += int(np.array_equal(x > 0, p.active))
+    ns = np.array([p.n for p in pool])
+    out = {
+        "metric": METRIC,
+        "value": round(stats["completed"] / wall, 2) if wall > 0 else None,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": timed, "warmup": n_warm,
+        "ms_per_step": round(stats["mean_ms"], 3),
+        "p50_ms": round(stats["p50_ms"], 3), "p99_ms": round(stats["p99_ms"], 3),
+        "max_ms": round(stats["max_ms"], 3),
+        "offered_rate": args.rate, "completed_in_window": stats["completed"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == N.NNLS_FP64 else "f32-factor+f64-refinement",
+        "data": "synthetic",
+        "config": {"workload": f"serving: Poisson {args.rate:g} req/s for {args.duration:g} s after "
+                               f"{args.warmup_s:g} s warm-up; sparse n log-uniform [64,8192], m=3n, "
+                               f"20 N(0,1)/col + band, 30-60% active, margin 1e-3; pool of {len(pool)} "
+                               "problems, seed 1004",
+                   "workers": args.workers, "batch_lanes": args.batch_lanes,
+                   "batch_max_n": args.batch_max_n,
+                   "pool_n_mean": float(ns.mean()), "pool_n_max": int(ns.max())},
+        "saturation_solves_per_s": round(2 * len(pool) / sat_wall, 2),
+        "saturation_p50_ms": round(sat["p50_ms"], 3), "saturation_p99_ms": round(sat["p99_ms"], 3),
+        "max_running": max(stats["max_running"], sat["max_running"]),
+        "batched_launches": stats["batches"] + sat["batches"],
+        "peak_committed_gb": round(max(stats["peak_committed_bytes"], sat["peak_committed_bytes"]) / 1e9, 3),
+        "plain_fp64_solves_per_s": round(plain, 2), "plain_sample": plain_n,
+        "max_rel_err_vs_planted": max(errs) if errs else None,
+        "free_set_matches": f"{match}/{len(first)}", "errors": errors[:5],
+        "submit_lag_p99_ms": round(float(np.percentile(lag, 99)) * 1e3, 3) if lag else None,
+        "generation_s": round(gen_s, 1),
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        from oracle import bpp_solve
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([q.get("num_threads", 1) for q in threadpool_info()] or [1])
+        except Exception:
+            threads = os.cpu_count() or 1
+        c0 = time.perf_counter()
+        cnt = 0
+        while cnt < len(pool) and time.perf_counter() - c0 < args.cpu_budget:
+            bpp_solve(pool[cnt].A, pool[cnt].b)
+            cnt += 1
+        el = time.perf_counter() - c0
+        out["cpu_baseline"] = {"value": round(cnt / el, 2), "unit": "solves/s", "cores": int(threads),
+                               "kind": "oracle",
+                               "sample": f"first {cnt} problems of the pool, one after another, {el:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +365,13 @@ def main():
     ap.add_argument("--batch", type=int, default=4096, help="dense_batch: number of problems")
     ap.add_argument("--plain-sample", type=int, default=256,
                     help="dense_batch: problems solved one per call on the plain float64 path")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve: offered requests/s")
+    ap.add_argument("--duration", type=float, default=10.0, help="serve: timed seconds of arrivals")
+    ap.add_argument("--warmup-s", type=float, default=1.0, help="serve: warm-up seconds of arrivals")
+    ap.add_argument("--pool", type=int, default=128, help="serve: distinct problems cycled")
+    ap.add_argument("--workers", type=int, default=8, help="serve: concurrent sparse solves")
+    ap.add_argument("--batch-lanes", type=int, default=2, help="serve: batched launches in flight")
+    ap.add_argument("--batch-max-n", type=int, default=256, help="serve: largest n sent to batched launches")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -218,6 +398,9 @@ def main():
         build()
     if args.workload == "dense_batch":
         bench_batch(args)
+        return
+    if args.workload == "serve":
+        bench_serve(args)
         return
     inst, desc = make_instance(args.workload)
     dev = torch.device("cuda:0")

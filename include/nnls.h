@@ -49,7 +49,8 @@ typedef enum {
   NNLS_ERR_NO_MEMORY = -5,     /* device or pinned host allocation failed                */
   NNLS_ERR_DEVICE = -6,        /* HIP runtime error, or a device-side wait exceeded its
                                   bound                                                  */
-  NNLS_ERR_REFINE = -7         /* mixed precision: refinement did not reach its target   */
+  NNLS_ERR_REFINE = -7,        /* mixed precision: refinement did not reach its target   */
+  NNLS_ERR_TIMEOUT = -8        /* nnls_server_wait: the request is not finished yet      */
 } nnls_status;
 
 typedef enum {
@@ -137,6 +138,84 @@ int nnls_solve_dense_batched(nnls_handle* h, int32_t batch, const int32_t* m, co
                              const double* const* A, const int32_t* lda, const double* const* b,
                              double* const* x, double* const* y, const nnls_options* opts,
                              nnls_info* info);
+
+/* ---------------------------------------------------------------------------------
+ * Serving engine: continuous batching of independent requests (Eq. 1 each) on one device.
+ *
+ * nnls_server_submit_csc copies a request's host arrays into pinned staging and returns a
+ * ticket at once.  Requests are admitted in arrival order as soon as the device memory
+ * they need (A, Gram matrix, factor at |F| = n, vectors; estimated on the host from the
+ * CSC) fits next to the requests already running; a request that is alone is always
+ * admitted.  Requests with n <= batch_max_n are gathered into batched launches (one
+ * workgroup per request, the whole pivoting loop on the device, as in
+ * nnls_solve_dense_batched); larger ones run the sparse solver of nnls_solve_csc, several
+ * at once on separate streams.  Which path a request takes depends on its n only, and both
+ * paths give results that do not depend on the other requests, so a result is the same
+ * whether the request ran alone or among others.  x and y are available in host memory
+ * when the request is reported done; latency is measured from submit to that point.
+ * All server calls are thread-safe.
+ * --------------------------------------------------------------------------------- */
+typedef struct nnls_server nnls_server;
+
+typedef struct {
+  size_t hbm_budget;        /* device bytes admitted requests may hold; 0: 90% of the free
+                               memory at create                                          */
+  int32_t workers;          /* sparse requests solved at once, each on its own stream;
+                               0: 8                                                      */
+  int32_t batch_lanes;      /* batched launches in flight at once; 0: 2                  */
+  int32_t batch_max_n;      /* n <= batch_max_n goes to batched launches; 0: 256; < 0:
+                               never                                                     */
+  int32_t batch_max_count;  /* requests per batched launch; 0: 1024                      */
+} nnls_server_config;
+
+typedef struct {
+  int64_t submitted;        /* since create or the last reset                            */
+  int64_t completed;        /* finished (any status)                                     */
+  int64_t pending;          /* queued, not admitted yet                                  */
+  int64_t batches;          /* batched launches issued                                   */
+  int32_t running;          /* admitted and not finished                                 */
+  int32_t max_running;
+  double committed_bytes;   /* estimated device bytes of the running requests            */
+  double peak_committed_bytes;
+  double budget_bytes;
+  double p50_ms, p99_ms, mean_ms, max_ms;   /* submit -> x, y in host memory             */
+  double solves_per_s;      /* completed / (last completion - first submit)              */
+} nnls_serving_stats;
+
+/* Start a server on device `device`.  cfg and opts may be NULL (defaults; opts applies to
+ * every request, NNLS_FLAG_PROFILE is ignored).  Errors: INVALID_ARG (bad config),
+ * DEVICE, NO_MEMORY. */
+int nnls_server_create(nnls_server** out, int device, const nnls_server_config* cfg,
+                       const nnls_options* opts);
+
+/* Queue one request.  colptr, rowidx, val, b are HOST arrays in the CSC convention above;
+ * they are copied before the call returns.  *ticket (host) names the request.  Errors:
+ * INVALID_ARG for sizes, null pointers or a malformed CSC structure (checked on the host;
+ * nothing is queued); NO_MEMORY. */
+int nnls_server_submit_csc(nnls_server* s, int32_t m, int32_t n, int64_t nnz,
+                           const int32_t* colptr, const int32_t* rowidx, const double* val,
+                           const double* b, uint64_t* ticket);
+
+/* Non-blocking check.  *done (host) is 1 when the request has finished: then x and y
+ * (HOST double[n], either may be NULL) and info (may be NULL) receive its result, the
+ * ticket is released, and the return value is the request's status.  *done is 0 and the
+ * return value NNLS_OK while it runs or waits.  INVALID_ARG for an unknown ticket.
+ * info->setup_ms is the time the request waited for admission and info->solve_ms its
+ * latency (submit to result in host memory). */
+int nnls_server_poll(nnls_server* s, uint64_t ticket, int32_t* done, double* x, double* y,
+                     nnls_info* info);
+
+/* Blocking form of nnls_server_poll: waits up to timeout_ms (< 0: without limit) and
+ * returns NNLS_ERR_TIMEOUT, keeping the ticket, if the request has not finished. */
+int nnls_server_wait(nnls_server* s, uint64_t ticket, double timeout_ms, double* x,
+                     double* y, nnls_info* info);
+
+/* Counters and latency percentiles over the requests completed since the last reset. */
+int nnls_server_stats(nnls_server* s, nnls_serving_stats* out);
+int nnls_server_reset_stats(nnls_server* s);
+
+/* Let running requests finish, drop queued ones and unclaimed results, free everything. */
+int nnls_server_destroy(nnls_server* s);
 
 /* Copy up to `cap` trace rows of the last solve on this handle into `rows` (host).
  * Returns the number of rows the solve recorded (which may exceed cap). */

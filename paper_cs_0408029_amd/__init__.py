@@ -13,9 +13,10 @@ from typing import List, Optional, Tuple
 
 from ._lib import (LIB_PATH, NNLS_ERR_DEVICE, NNLS_ERR_INVALID_ARG, NNLS_ERR_INVALID_VALUE,  # noqa: F401
                    NNLS_ERR_MAXITER, NNLS_ERR_NO_MEMORY, NNLS_ERR_NOT_PD, NNLS_ERR_REFINE,
-                   NNLS_FLAG_PROFILE, NNLS_FP32_IR, NNLS_FP64, NNLS_OK, NNLS_PROFILE_CLASSES,
-                   PROFILE_CLASS_NAMES, default_options, load, nnls_info, nnls_options,
-                   nnls_trace_row, status_string)
+                   NNLS_ERR_TIMEOUT, NNLS_FLAG_PROFILE, NNLS_FP32_IR, NNLS_FP64, NNLS_OK,
+                   NNLS_PROFILE_CLASSES, PROFILE_CLASS_NAMES, default_options, load, nnls_info,
+                   nnls_options, nnls_server_config, nnls_serving_stats, nnls_trace_row,
+                   status_string)
 
 
 def _torch():
@@ -215,3 +216,119 @@ def nnls_pivot_step(h: Handle, x, y, free_flags, tau: float, p_max: int, state: 
                                _ptr(free_flags, torch.uint8, "free", n), tau, p_max, st_arr, out)
     state[0], state[1] = st_arr[0], st_arr[1]
     return st, list(out)
+
+
+# ------------------------------------------------------------------------------------------
+# Serving engine (host arrays in, host arrays out)
+# ------------------------------------------------------------------------------------------
+
+class Server:
+    """Owns an nnls_server (continuous batching of independent requests on one device)."""
+
+    def __init__(self, device: int = 0, config: Optional[nnls_server_config] = None,
+                 opts: Optional[nnls_options] = None, **config_fields):
+        self.lib = load()
+        if config is None:
+            config = nnls_server_config()
+        for k, v in config_fields.items():
+            setattr(config, k, v)
+        s = C.c_void_p()
+        st = self.lib.nnls_server_create(C.byref(s), device, C.byref(config),
+                                         C.byref(opts) if opts else None)
+        if st != NNLS_OK:
+            raise RuntimeError(f"nnls_server_create failed: {status_string(st)}")
+        self._s = s
+
+    @property
+    def ptr(self):
+        return self._s
+
+    def close(self):
+        if self._s:
+            self.lib.nnls_server_destroy(self._s)
+            self._s = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _host(a, dtype, name):
+    import numpy as np
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    if arr.ndim != 1:
+        raise ValueError(f"{name}: expected a 1-D array")
+    return arr
+
+
+def nnls_server_create(device: int = 0, config: Optional[nnls_server_config] = None,
+                       opts: Optional[nnls_options] = None, **config_fields) -> Server:
+    return Server(device, config, opts, **config_fields)
+
+
+def nnls_server_submit_csc(srv: Server, m: int, n: int, colptr, rowidx, val, b) -> Tuple[int, int]:
+    """Host CSC arrays (numpy-convertible).  Returns (status, ticket)."""
+    import numpy as np
+    cp = _host(colptr, np.int32, "colptr")
+    ri = _host(rowidx, np.int32, "rowidx")
+    va = _host(val, np.float64, "val")
+    bb = _host(b, np.float64, "b")
+    if cp.size < n + 1 or bb.size < m or va.size < ri.size:
+        raise ValueError("array sizes do not match m, n, nnz")
+    ticket = C.c_uint64(0)
+    st = srv.lib.nnls_server_submit_csc(srv.ptr, m, n, int(ri.size), cp.ctypes.data, ri.ctypes.data,
+                                        va.ctypes.data, bb.ctypes.data, C.byref(ticket))
+    return st, ticket.value
+
+
+def _result_buffers(n):
+    import numpy as np
+    return np.empty(n, dtype=np.float64), np.empty(n, dtype=np.float64)
+
+
+def nnls_server_poll(srv: Server, ticket: int, n: int):
+    """Returns (status, done, x, y, info); x, y, info are None until done."""
+    x, y = _result_buffers(n)
+    info = nnls_info()
+    done = C.c_int32(0)
+    st = srv.lib.nnls_server_poll(srv.ptr, ticket, C.byref(done), x.ctypes.data, y.ctypes.data,
+                                  C.byref(info))
+    if not done.value:
+        return st, False, None, None, None
+    return st, True, x, y, info
+
+
+def nnls_server_wait(srv: Server, ticket: int, n: int, timeout_ms: float = -1.0):
+    """Returns (status, x, y, info); x, y, info are None on NNLS_ERR_TIMEOUT."""
+    x, y = _result_buffers(n)
+    info = nnls_info()
+    st = srv.lib.nnls_server_wait(srv.ptr, ticket, timeout_ms, x.ctypes.data, y.ctypes.data,
+                                  C.byref(info))
+    if st in (NNLS_ERR_TIMEOUT, NNLS_ERR_INVALID_ARG):
+        return st, None, None, None
+    return st, x, y, info
+
+
+def nnls_server_stats(srv: Server) -> dict:
+    out = nnls_serving_stats()
+    st = srv.lib.nnls_server_stats(srv.ptr, C.byref(out))
+    if st != NNLS_OK:
+        raise RuntimeError(f"nnls_server_stats failed: {status_string(st)}")
+    return {name: getattr(out, name) for name, _ in nnls_serving_stats._fields_}
+
+
+def nnls_server_reset_stats(srv: Server) -> int:
+    return srv.lib.nnls_server_reset_stats(srv.ptr)
+
+
+def nnls_server_destroy(srv: Server) -> int:
+    srv.close()
+    return NNLS_OK

@@ -19,6 +19,7 @@ NNLS_ERR_MAXITER = -4
 NNLS_ERR_NO_MEMORY = -5
 NNLS_ERR_DEVICE = -6
 NNLS_ERR_REFINE = -7
+NNLS_ERR_TIMEOUT = -8
 
 NNLS_FP64 = 0
 NNLS_FP32_IR = 1
@@ -46,6 +47,19 @@ class nnls_trace_row(C.Structure):
                 ("n_free", C.c_int32), ("reserved", C.c_int32)]
 
 
+class nnls_server_config(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("workers", C.c_int32), ("batch_lanes", C.c_int32),
+                ("batch_max_n", C.c_int32), ("batch_max_count", C.c_int32)]
+
+
+class nnls_serving_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("pending", C.c_int64),
+                ("batches", C.c_int64), ("running", C.c_int32), ("max_running", C.c_int32),
+                ("committed_bytes", C.c_double), ("peak_committed_bytes", C.c_double),
+                ("budget_bytes", C.c_double), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
+                ("mean_ms", C.c_double), ("max_ms", C.c_double), ("solves_per_s", C.c_double)]
+
+
 _P = C.c_void_p
 _I32 = C.c_int32
 _I64 = C.c_int64
@@ -62,6 +76,14 @@ PROTOTYPES = {
                                    C.POINTER(nnls_options), C.POINTER(nnls_info)]),
     "nnls_solve_dense_batched": (C.c_int, [_P, _I32, _P, _P, _P, _P, _P, _P, _P,
                                            C.POINTER(nnls_options), _P]),
+    "nnls_server_create": (C.c_int, [C.POINTER(_P), C.c_int, C.POINTER(nnls_server_config),
+                                     C.POINTER(nnls_options)]),
+    "nnls_server_submit_csc": (C.c_int, [_P, _I32, _I32, _I64, _P, _P, _P, _P, C.POINTER(C.c_uint64)]),
+    "nnls_server_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(_I32), _P, _P, C.POINTER(nnls_info)]),
+    "nnls_server_wait": (C.c_int, [_P, C.c_uint64, C.c_double, _P, _P, C.POINTER(nnls_info)]),
+    "nnls_server_stats": (C.c_int, [_P, C.POINTER(nnls_serving_stats)]),
+    "nnls_server_reset_stats": (C.c_int, [_P]),
+    "nnls_server_destroy": (C.c_int, [_P]),
     "nnls_get_trace": (C.c_int, [_P, C.POINTER(nnls_trace_row), C.c_int]),
     "nnls_get_profile": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double)]),

@@ -491,6 +491,26 @@ int solve_common(nnls_handle* h, const Problem& P, double* x, double* y, const n
 
 }  // namespace
 
+namespace nnls {
+
+// Give back every device buffer of the handle (the next solve allocates them again).
+void release_workspace(nnls_handle* h) {
+  if (!h) return;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  DevBuf* bufs[] = {&h->err, &h->ctrl, &h->rowcnt, &h->rowptr, &h->colidx, &h->valr, &h->hptr,
+                    &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
+                    &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF,
+                    &h->bprobs, &h->border, &h->binfo, &h->bws};
+  for (DevBuf* b : bufs) {
+    if (b->p) (void)hipFree(b->p);
+    b->p = nullptr;
+    b->bytes = 0;
+  }
+}
+
+}  // namespace nnls
+
 extern "C" {
 
 const char* nnls_status_string(int status) {
@@ -503,6 +523,7 @@ const char* nnls_status_string(int status) {
     case NNLS_ERR_NO_MEMORY: return "NNLS_ERR_NO_MEMORY";
     case NNLS_ERR_DEVICE: return "NNLS_ERR_DEVICE";
     case NNLS_ERR_REFINE: return "NNLS_ERR_REFINE";
+    case NNLS_ERR_TIMEOUT: return "NNLS_ERR_TIMEOUT";
     default: return "NNLS_ERR_UNKNOWN";
   }
 }

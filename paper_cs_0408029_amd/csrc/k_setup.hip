@@ -273,6 +273,25 @@ __global__ __launch_bounds__(256) void k_gemvT_dense(int m, int n, const double*
   if (lane == 0) out[j] = scale * s;
 }
 
+// One workgroup per packed request, one wave per column: dense[a_off + i + m j] = val
+// for every stored entry (i, j).  The dense blocks are zero-filled beforehand.
+__global__ void __launch_bounds__(256) k_csc_scatter(const ScatterDesc* __restrict__ desc,
+                                                     const char* __restrict__ packed,
+                                                     double* __restrict__ dense) {
+  const ScatterDesc d = desc[blockIdx.x];
+  const PackLayout L = pack_layout(d.m, d.n, d.nnz);
+  const char* base = packed + d.in_off;
+  const int32_t* colptr = (const int32_t*)base;
+  const int32_t* rowidx = (const int32_t*)(base + L.rowidx);
+  const double* val = (const double*)(base + L.val);
+  double* A = dense + d.a_off;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int j = wave; j < d.n; j += 4) {
+    const int e1 = colptr[j + 1];
+    for (int e = colptr[j] + lane; e < e1; e += 64) A[(int64_t)j * d.m + rowidx[e]] = val[e];
+  }
+}
+
 inline int blocks_for(int64_t n, int bs, int cap = 8192) {
   int64_t b = (n + bs - 1) / bs;
   if (b < 1) b = 1;
@@ -357,6 +376,12 @@ void launch_gram_dense(hipStream_t s, int m, int n, const double* A, int lda, do
 void launch_gemvT_dense(hipStream_t s, int m, int n, const double* A, int lda, const double* v,
                         double* out, double scale) {
   hipLaunchKernelGGL(k_gemvT_dense, dim3((n + 3) / 4), dim3(256), 0, s, m, n, A, lda, v, out, scale);
+}
+
+void launch_csc_scatter(hipStream_t s, int count, const ScatterDesc* desc, const char* packed,
+                        double* dense) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_csc_scatter, dim3(count), dim3(256), 0, s, desc, packed, dense);
 }
 
 }  // namespace nnls

@@ -169,4 +169,28 @@ size_t batched_workspace_bytes(int m, int n);
 void launch_batched(hipStream_t s, const BatchArgs& a, int grid);
 void launch_ctrl_clear_breakdown(hipStream_t s, Ctrl* ctrl);   // NOT_PD -> 0 (mixed retry)
 
+// One request packed into a single block (host staging and device copy share the layout):
+// colptr int32[n+1] | rowidx int32[nnz] | val double[nnz] | b double[m], 8-byte aligned.
+struct PackLayout {
+  int64_t rowidx, val, b, total;
+};
+__host__ __device__ inline PackLayout pack_layout(int m, int n, int64_t nnz) {
+  PackLayout L;
+  L.rowidx = ((int64_t)(n + 1) * 4 + 7) / 8 * 8;
+  L.val = (L.rowidx + nnz * 4 + 7) / 8 * 8;
+  L.b = L.val + nnz * 8;
+  L.total = (L.b + (int64_t)m * 8 + 255) / 256 * 256;
+  return L;
+}
+// Scatter packed CSC requests into zero-filled dense column-major blocks (lda = m).
+struct ScatterDesc {
+  int32_t m, n;
+  int64_t nnz;
+  int64_t in_off;   // byte offset of the packed block
+  int64_t a_off;    // element offset of the dense block
+};
+void release_workspace(::nnls_handle* h);   // api.hip: free the handle's device buffers
+void launch_csc_scatter(hipStream_t s, int count, const ScatterDesc* desc, const char* packed,
+                        double* dense);
+
 }  // namespace nnls

@@ -75,3 +75,28 @@ def test_create_reports_missing_device(lib):
         pytest.skip("a GPU is present")
     h = C.c_void_p()
     assert lib.nnls_create(C.byref(h), 0, None) == N.NNLS_ERR_DEVICE
+
+
+def test_server_structs_and_null_arguments(lib):
+    assert C.sizeof(N.nnls_server_config) == 24
+    assert C.sizeof(N.nnls_serving_stats) == 4 * 8 + 2 * 4 + 8 * 8
+    assert lib.nnls_server_create(None, 0, None, None) == N.NNLS_ERR_INVALID_ARG
+    assert lib.nnls_server_destroy(None) == N.NNLS_ERR_INVALID_ARG
+    assert lib.nnls_server_stats(None, None) == N.NNLS_ERR_INVALID_ARG
+    assert lib.nnls_server_reset_stats(None) == N.NNLS_ERR_INVALID_ARG
+    t = C.c_uint64()
+    assert lib.nnls_server_submit_csc(None, 4, 2, 0, None, None, None, None, C.byref(t)) == N.NNLS_ERR_INVALID_ARG
+    done = C.c_int32()
+    assert lib.nnls_server_poll(None, 1, C.byref(done), None, None, None) == N.NNLS_ERR_INVALID_ARG
+    assert lib.nnls_server_wait(None, 1, 0.0, None, None, None) == N.NNLS_ERR_INVALID_ARG
+    assert N.status_string(N.NNLS_ERR_TIMEOUT) == "NNLS_ERR_TIMEOUT"
+
+
+def test_server_rejects_bad_config_and_missing_device(lib):
+    torch = pytest.importorskip("torch")
+    s = C.c_void_p()
+    bad = N.nnls_server_config(workers=-1)
+    assert lib.nnls_server_create(C.byref(s), 0, C.byref(bad), None) == N.NNLS_ERR_INVALID_ARG
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert lib.nnls_server_create(C.byref(s), 0, None, None) == N.NNLS_ERR_DEVICE
