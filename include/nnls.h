@@ -70,7 +70,9 @@ typedef struct {
   int32_t ir_max_steps; /* NNLS_FP32_IR: refinement steps per pivot iteration            */
   double ir_rtol;       /* NNLS_FP32_IR: target ||A_F^T r||_inf / ||A_F^T b||_inf        */
   uint32_t flags;       /* NNLS_FLAG_*                                                   */
-  uint32_t reserved;
+  uint32_t max_workgroups; /* 0: the factor kernel runs one workgroup per tile; else a
+                              persistent grid of this many workgroups, so that several
+                              solves can share the device                              */
 } nnls_options;
 
 typedef struct {
@@ -183,7 +185,8 @@ typedef struct {
 } nnls_serving_stats;
 
 /* Start a server on device `device`.  cfg and opts may be NULL (defaults; opts applies to
- * every request, NNLS_FLAG_PROFILE is ignored).  Errors: INVALID_ARG (bad config),
+ * every request, NNLS_FLAG_PROFILE is ignored, and max_workgroups 0 becomes 128 so that
+ * concurrent factorisations share the device; results do not depend on it).  Errors: INVALID_ARG (bad config),
  * DEVICE, NO_MEMORY. */
 int nnls_server_create(nnls_server** out, int device, const nnls_server_config* cfg,
                        const nnls_options* opts);

@@ -33,7 +33,7 @@ PROFILE_CLASS_NAMES = ["gram", "control", "cholesky", "trsv", "residual", "refin
 class nnls_options(C.Structure):
     _fields_ = [("tau", C.c_double), ("p_max", C.c_int32), ("max_iter", C.c_int32),
                 ("precision", C.c_int32), ("ir_max_steps", C.c_int32), ("ir_rtol", C.c_double),
-                ("flags", C.c_uint32), ("reserved", C.c_uint32)]
+                ("flags", C.c_uint32), ("max_workgroups", C.c_uint32)]
 
 
 class nnls_info(C.Structure):

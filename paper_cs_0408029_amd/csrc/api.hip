@@ -40,6 +40,8 @@ struct nnls_handle {
   int device = 0;
   hipStream_t stream = nullptr;
   uint64_t wait_ticks = 0;
+  int default_wgs = 0;        // factor grid cap when the options give none (0: no cap)
+  int max_wgs = 0;            // the grid cap of the current solve
   // workspace
   DevBuf err, ctrl, rowcnt, rowptr, colidx, valr, hptr, hcnt, hrow, hval, c, r, flags, Flist, pos;
   DevBuf Lt, Dinv, colcnt, dflag, tflag, z, xF, Hd, gF;
@@ -274,6 +276,7 @@ FactorArgs factor_args(nnls_handle* h, int nF, const int32_t* Flist, const int32
   a.epoch = h->epoch;
   a.ctrl = (Ctrl*)h->ctrl.p;
   a.wait_ticks = h->wait_ticks;
+  a.max_wgs = h->max_wgs;
   return a;
 }
 
@@ -474,6 +477,7 @@ int solve_common(nnls_handle* h, const Problem& P, double* x, double* y, const n
   }
   if (hipSetDevice(h->device) != hipSuccess) return set_info_status(info, NNLS_ERR_DEVICE);
   h->profiling = (o.flags & NNLS_FLAG_PROFILE) != 0;
+  h->max_wgs = o.max_workgroups > 0 ? (int)std::min<uint32_t>(o.max_workgroups, 1u << 20) : h->default_wgs;
   int st = validate_device(h, P);
   if (st != NNLS_OK) return set_info_status(info, st);
   const int64_t pe = prof_begin(h, NNLS_PROF_GRAM);
@@ -557,6 +561,7 @@ int nnls_create(nnls_handle** out, int device, void* stream) {
   if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || rate_khz <= 0)
     rate_khz = 100000;
   h->wait_ticks = (uint64_t)rate_khz * 1000ull * 20ull;   // 20 s
+
   if (hipHostMalloc((void**)&h->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&h->h_scalar, 64, hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
@@ -783,6 +788,7 @@ int nnls_cholesky(nnls_handle* h, int32_t n, const double* S, int32_t lds, doubl
   launch_ctrl_set_state(h->stream, (Ctrl*)h->ctrl.p, INT32_MAX, 0, 0, 0);
   launch_fill_i32(h->stream, (int32_t*)h->colcnt.p, (n + TILE - 1) / TILE, 0);
   h->epoch += 1;
+  h->max_wgs = h->default_wgs;
   FactorArgs fa = factor_args(h, n, nullptr, nullptr, S, lds, false);
   launch_cholesky(h->stream, fa, fp32);
   launch_tiles_to_dense(h->stream, n, fa.nb, h->Lt.p, fp32, L, ldl);
@@ -805,6 +811,7 @@ int nnls_spd_solve(nnls_handle* h, int32_t n, const double* S, int32_t lds, cons
   launch_ctrl_set_state(h->stream, (Ctrl*)h->ctrl.p, INT32_MAX, 0, 0, 0);
   launch_fill_i32(h->stream, (int32_t*)h->colcnt.p, (n + TILE - 1) / TILE, 0);
   h->epoch += 1;
+  h->max_wgs = h->default_wgs;
   FactorArgs fa = factor_args(h, n, nullptr, nullptr, S, lds, false);
   fa.rhs = rhs;
   fa.z = (double*)h->z.p;

@@ -2,8 +2,9 @@
 // triangular solves of the normal equations (Sec. 2.1 and Sec. 3 of the tsnnls paper).
 //
 // Factorisation: one launch per pivot iteration.  The block is cut into 64 x 64 tiles and
-// every lower tile (I, J) is one workgroup.  A workgroup takes a ticket from a counter
-// (tickets are handed out in column-major lower-tile order), gathers its tile of H_FF
+// every lower tile (I, J) is one unit of work of a persistent grid.  A workgroup takes a
+// ticket from a counter (tickets are handed out in column-major lower-tile order) and,
+// for each ticket, gathers its tile of H_FF
 // straight from the Gram matrix into LDS, then computes, left-looking,
 //     S_IJ = H_IJ - sum_{k<J} L_Ik L_Jk^T        (MFMA, 16x16x4 blocks)
 // A diagonal tile is then factored and inverted in LDS; an off-diagonal tile becomes
@@ -33,9 +34,16 @@ namespace {
 
 // Stage tile (I, J) of H_FF in LDS (column-major, leading dimension LDT).  Positions at or
 // beyond nF are padding: identity on the diagonal, zero elsewhere.
+// threadIdx.x as a value the compiler cannot carry from one loop iteration to the next
+// (keeps the persistent kernel's register footprint at that of the one-tile kernel)
+__device__ inline int fresh_tid() {
+  int v = (int)threadIdx.x;
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 template <typename T>
-__device__ inline void gather_tile(const FactorArgs& a, int I, int J, T* S) {
-  const int tid = threadIdx.x;
+__device__ inline void gather_tile(const FactorArgs& a, int tid, int I, int J, T* S) {
   const int r0 = I * TILE, c0 = J * TILE;
   if (a.dense) {
     for (int e = tid; e < TILE_ELEMS; e += 256) {
@@ -80,37 +88,18 @@ __device__ inline void gather_tile(const FactorArgs& a, int I, int J, T* S) {
   __syncthreads();
 }
 
+// One lower tile (I, J) with ticket t; S, W, s_part, s_rhs are the workgroup's LDS.
 template <typename T>
-__global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wait_ticks) {
+__device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_ticks, int tid, int t, int I, int J,
+                                          T* S, T* W, double (*s_part)[TILE], double* s_rhs) {
   typedef MF<T> M;
   typedef typename M::acc Acc;
-  __shared__ T S[TILE * LDT];
-  __shared__ T W[TILE * LDT];
-  __shared__ double s_part[4][TILE];   // fused forward solve: partial sums per wave
-  __shared__ double s_rhs[TILE];
-  __shared__ int s_t, s_I, s_J;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lane = tid & 63, w = tid >> 6;
   const int nb = a.nb;
-  if (tid == 0) {
-    const int t = atomicAdd(&a.ctrl->chol_ticket, 1);
-    int J = 0, start = 0;
-    if (t < tile_count(nb)) {
-      while (t >= start + (nb - J)) {
-        start += nb - J;
-        ++J;
-      }
-    }
-    s_t = t;
-    s_I = J + (t - start);
-    s_J = J;
-  }
-  __syncthreads();
-  const int t = s_t, I = s_I, J = s_J;
-  if (t >= tile_count(nb)) return;   // counter not reset: do nothing rather than go out of range
   T* Lt = (T*)a.Ltiles;
   T* Dv = (T*)a.Dinv;
 
-  gather_tile<T>(a, I, J, S);
+  gather_tile<T>(a, tid, I, J, S);
 
   const int qr = (w & 1) * 32, qc = (w >> 1) * 32;
   const int lr = lane & 15, lk = lane >> 4;
@@ -245,6 +234,72 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wa
   __syncthreads();
   for (int e = tid; e < TILE_ELEMS; e += 256) dst[e] = S[(e & (TILE - 1)) + (e >> 6) * LDT];
   publish_tile(&a.tflag[t], &a.colcnt[J], a.epoch);
+}
+
+// Ticket t -> lower tile (I, J) in column-major order.
+__device__ inline void decode_ticket(int t, int nb, int* I, int* J) {
+  int j = 0, start = 0;
+  while (t >= start + (nb - j)) {
+    start += nb - j;
+    ++j;
+  }
+  *I = j + (t - start);
+  *J = j;
+}
+
+// One workgroup per lower tile.
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wait_ticks) {
+  __shared__ T S[TILE * LDT];
+  __shared__ T W[TILE * LDT];
+  __shared__ double s_part[4][TILE];   // fused forward solve: partial sums per wave
+  __shared__ double s_rhs[TILE];
+  __shared__ int s_t, s_I, s_J;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    const int t = atomicAdd(&a.ctrl->chol_ticket, 1);
+    int I = 0, J = 0;
+    if (t < tile_count(a.nb)) decode_ticket(t, a.nb, &I, &J);
+    s_t = t;
+    s_I = I;
+    s_J = J;
+  }
+  __syncthreads();
+  const int t = s_t;
+  if (t >= tile_count(a.nb)) return;   // counter not reset: do nothing rather than go out of range
+  chol_tile<T>(a, wait_ticks, tid, t, s_I, s_J, S, W, s_part, s_rhs);
+}
+
+// Persistent form for a capped grid: each workgroup takes tickets until none are left, so
+// a launch holds at most gridDim.x workgroups however large the F-block is (concurrent
+// solves share the device).  A workgroup holds one ticket at a time and only waits for
+// smaller tickets, which running workgroups hold, so the lowest unfinished ticket always
+// progresses.
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_chol_tiles_persistent(FactorArgs a, uint64_t wait_ticks) {
+  __shared__ T S[TILE * LDT];
+  __shared__ T W[TILE * LDT];
+  __shared__ double s_part[4][TILE];
+  __shared__ double s_rhs[TILE];
+  __shared__ int s_t, s_I, s_J;
+  const int64_t ntiles = tile_count(a.nb);
+  for (;;) {
+    const int tid = fresh_tid();
+    if (tid == 0) {
+      const int t = atomicAdd(&a.ctrl->chol_ticket, 1);
+      int I = 0, J = 0;
+      if (t < ntiles) decode_ticket(t, a.nb, &I, &J);
+      s_t = t;
+      s_I = I;
+      s_J = J;
+    }
+    __syncthreads();
+    const int t = s_t, I = s_I, J = s_J;
+    __syncthreads();   // every thread has its ticket before thread 0 may take the next
+    if (t >= ntiles) return;
+    chol_tile<T>(a, wait_ticks, tid, t, I, J, S, W, s_part, s_rhs);
+    __syncthreads();   // LDS is reused by the next tile
+  }
 }
 
 // z_I = L_II^-1 (rhs_I - sum_{k<I} L_Ik z_k)
@@ -389,6 +444,13 @@ __global__ void k_tiles_to_dense(int n, int nb, const T* __restrict__ Lt, double
 void launch_cholesky(hipStream_t s, const FactorArgs& a, bool fp32) {
   const int64_t grid = tile_count(a.nb);
   if (grid <= 0) return;
+  if (a.max_wgs > 0 && grid > a.max_wgs) {
+    if (fp32)
+      hipLaunchKernelGGL(k_chol_tiles_persistent<float>, dim3((unsigned)a.max_wgs), dim3(256), 0, s, a, a.wait_ticks);
+    else
+      hipLaunchKernelGGL(k_chol_tiles_persistent<double>, dim3((unsigned)a.max_wgs), dim3(256), 0, s, a, a.wait_ticks);
+    return;
+  }
   if (fp32)
     hipLaunchKernelGGL(k_chol_tiles<float>, dim3((unsigned)grid), dim3(256), 0, s, a, a.wait_ticks);
   else

@@ -475,6 +475,8 @@ int nnls_server_create(nnls_server** out, int device, const nnls_server_config* 
   nnls_default_options(&o);
   if (opts) o = *opts;
   o.flags &= ~NNLS_FLAG_PROFILE;
+  // several factorisations share the device: each takes a persistent grid of its own
+  if (o.max_workgroups == 0) o.max_workgroups = 128;
   if (!(o.tau >= 0.0) || o.p_max < 0 || (o.precision != NNLS_FP64 && o.precision != NNLS_FP32_IR) ||
       (o.precision == NNLS_FP32_IR && (o.ir_max_steps < 0 || !(o.ir_rtol > 0.0))))
     return NNLS_ERR_INVALID_ARG;

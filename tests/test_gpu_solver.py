@@ -124,6 +124,17 @@ def test_rerun_is_bitwise_identical(h):
     assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3]) and a[4] == b[4]
 
 
+@pytest.mark.parametrize("cap,precision", [(1, 0), (7, 0), (64, 0), (7, 1)])
+def test_capped_persistent_grid_is_bitwise_identical(h, cap, precision):
+    """A capped factor grid (persistent workgroups taking tickets) computes every tile with
+    the same operations in the same order as one workgroup per tile."""
+    inst = W.sparse_large(1002, m=6000, n=1200)
+    a = solve_csc(h, inst.A, inst.b, precision=precision)
+    b = solve_csc(h, inst.A, inst.b, precision=precision, max_workgroups=cap)
+    assert a[0] == b[0] == N.NNLS_OK
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3]) and a[4] == b[4]
+
+
 def test_empty_free_set(h):
     A = np.array([[1.0, 0.0], [0.0, 1.0], [1.0, 1.0]])
     b = np.array([-1.0, -2.0, 0.5])
