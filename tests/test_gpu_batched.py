@@ -118,3 +118,21 @@ def test_empty_and_invalid(h):
     A = np.ones((3, 5))
     st, infos, xs, ys = run_batch(h, [(A, np.ones(3))])   # m < n
     assert st == N.NNLS_ERR_INVALID_ARG
+
+
+def test_packed_descriptors_reused(h, batch24):
+    problems, insts = batch24
+    As = [colmajor_dev(A) for A, _ in problems]
+    bs = [t(b) for _, b in problems]
+    xs = [torch.full((A.shape[1],), np.nan, dtype=torch.float64, device=DEV) for A, _ in problems]
+    ys = [torch.full((A.shape[1],), np.nan, dtype=torch.float64, device=DEV) for A, _ in problems]
+    packed = N.BatchedArgs(As, bs, xs, ys)
+    st1, _ = N.nnls_solve_dense_batched(h, packed=packed)
+    first = [x.cpu().numpy().copy() for x in xs]
+    for x in xs:
+        x.fill_(np.nan)
+    st2, infos = N.nnls_solve_dense_batched(h, packed=packed)
+    assert st1 == st2 == N.NNLS_OK
+    for a, x, inst in zip(first, xs, insts):
+        assert np.array_equal(a, x.cpu().numpy())
+        assert np.array_equal(a > 0, inst.active)
