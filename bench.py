@@ -371,7 +371,7 @@ def main():
     ap.add_argument("--duration", type=float, default=10.0, help="serve: timed seconds of arrivals")
     ap.add_argument("--warmup-s", type=float, default=1.0, help="serve: warm-up seconds of arrivals")
     ap.add_argument("--pool", type=int, default=128, help="serve: distinct problems cycled")
-    ap.add_argument("--workers", type=int, default=8, help="serve: concurrent sparse solves")
+    ap.add_argument("--workers", type=int, default=12, help="serve: concurrent sparse solves")
     ap.add_argument("--batch-lanes", type=int, default=2, help="serve: batched launches in flight")
     ap.add_argument("--batch-max-n", type=int, default=256, help="serve: largest n sent to batched launches")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -382,6 +382,10 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "serve":
+        # one hardware queue per stream of the serving engine (HIP's default is 4), set
+        # before the runtime starts
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
     import torch
     import paper_cs_0408029_amd as N
 

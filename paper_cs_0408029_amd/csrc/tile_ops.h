@@ -68,25 +68,26 @@ __device__ inline bool spin_until(const int32_t* p, int target, bool exact, Ctrl
   }
 }
 
-// Make every thread's global stores visible at agent scope, then let thread 0 bump a
-// counter (add) or set a flag (store).
-__device__ inline void publish_add(int32_t* counter) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
+// Make every thread's global stores visible at agent scope, then let thread 0 set a flag
+// (and bump a counter).  The barrier completes the workgroup's stores into this XCD's L2
+// (workgroup-scope release); thread 0's agent-scope release fence then writes that L2
+// back once, and the flag writes after it need no ordering of their own.  (A full
+// __threadfence in every thread would write the L2 back three times and also invalidate
+// it, throwing away lines the other workgroups on this XCD are still reading.)
 __device__ inline void publish_tile(int32_t* flag, int32_t* counter, int epoch) {
-  __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 __device__ inline void publish_store(int32_t* flag, int value) {
-  __threadfence();
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 __device__ inline double bcast_lane(double v, int l) {
