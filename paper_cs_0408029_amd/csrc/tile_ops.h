@@ -143,20 +143,22 @@ __device__ inline float rsqrt_refined(float d) {
   return y;
 }
 
-// Factor and invert the 16 x 16 diagonal block at offset o of S (one wave).  Lane i keeps
-// row i in registers; pivots come from a refined reciprocal square root (no divide); the
-// scaled column of each step is broadcast through LDS (16-byte broadcast reads), and the
-// inverse reuses the pivot reciprocals.  L goes back into S, its inverse into W; the LDS
-// broadcast buffers live in the unused upper blocks of S.
+// Factor and invert the 16 x 16 diagonal block at offset o of S (one wave).  Lanes 0..15
+// keep row i of the block in registers; lanes 16..31 start from column i of the identity
+// and go through the very same updates, which turns them into column i of L^-1 (forward
+// substitution, one column per lane, in step with the factorisation).  Pivots come from a
+// refined reciprocal square root (no divide); the next pivot's diagonal update stays off
+// the LDS path; each step's column of L is broadcast through LDS (16-byte broadcast reads)
+// in the unused upper block of S.  L goes back into S, its inverse into W.
 template <typename T>
 __device__ inline void diag16(T* S, T* W, int o, const PivotReport& rep) {
   const int lane = threadIdx.x & 63, i = lane & 15;
-  T* colbuf = S + 48 * LDT;          // column buffer: rows 0..15 of column 48 (upper block)
-  T* LR = S + 16 + 48 * LDT;         // rows of L: LR[i * LDT + k], in the upper block (16, 48)
-  T r[16], invd[16];
+  const bool inv = (lane >> 4) == 1;   // lanes 16..31 carry the inverse
+  T* colbuf = S + 48 * LDT;            // column buffer: rows 0..15 of column 48 (upper block)
+  T r[16];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) r[j] = S[(o + i) + (o + j) * LDT];
-  int firstbad = -1;                 // uniform: pivots are read from one lane
+  for (int j = 0; j < 16; ++j) r[j] = inv ? ((j == i) ? (T)1 : (T)0) : S[(o + i) + (o + j) * LDT];
+  int firstbad = -1;                   // uniform: pivots are read from one lane
   T d = bcast_lane(r[0], 0);
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
@@ -164,10 +166,9 @@ __device__ inline void diag16(T* S, T* W, int o, const PivotReport& rep) {
     if (bad && firstbad < 0) firstbad = c;
     const T y = bad ? (T)1 : rsqrt_refined(d);   // 1 / L_cc
     const T l = bad ? (T)1 : d * y;               // L_cc
-    invd[c] = y;
-    const T lic = (i == c) ? l : r[c] * y;
+    // factor lanes: L_ic (L_cc on the diagonal); inverse lanes: (L^-1)_ci
+    const T lic = (i == c && !inv) ? l : r[c] * y;
     r[c] = lic;
-    // the next pivot only needs lane c+1's own diagonal update, off the LDS path
     if (c + 1 < 16) d = bcast_lane(fma(-lic, lic, r[c + 1]), c + 1);
     if (lane < 16) colbuf[i] = lic;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -181,34 +182,10 @@ __device__ inline void diag16(T* S, T* W, int o, const PivotReport& rep) {
   }
   if (lane < 16) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const T v = (j <= i) ? r[j] : (T)0;
-      S[(o + i) + (o + j) * LDT] = v;
-      LR[i * LDT + j] = v;
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  // inverse: lane i runs forward substitution down column i; the newest term is added
-  // last so each row waits on one product
-  T x[16];
+    for (int j = 0; j < 16; ++j) S[(o + i) + (o + j) * LDT] = (j <= i) ? r[j] : (T)0;
+  } else if (inv) {
 #pragma unroll
-  for (int ii = 0; ii < 16; ++ii) {
-    const T* row = LR + ii * LDT;
-    T s0 = (T)0, s1 = (T)0;
-    // terms k = 0 .. ii-2 in two chains, then k = ii-1
-#pragma unroll
-    for (int k = 0; k + 1 < ii - 1; k += 2) {
-      s0 += row[k] * x[k];
-      s1 += row[k + 1] * x[k + 1];
-    }
-    if (ii >= 2 && ((ii - 1) & 1)) s0 += row[ii - 2] * x[ii - 2];
-    T s = s0 + s1;
-    if (ii >= 1) s += row[ii - 1] * x[ii - 1];
-    x[ii] = ((i == ii ? (T)1 : (T)0) - s) * invd[ii];
-  }
-  if (lane < 16) {
-#pragma unroll
-    for (int ii = 0; ii < 16; ++ii) W[(o + ii) + (o + i) * LDT] = x[ii];
+    for (int k = 0; k < 16; ++k) W[(o + k) + (o + i) * LDT] = (k >= i) ? r[k] : (T)0;
   }
 }
 
