@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix) peak
 PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 (matrix) peak
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E peak
+CHOL_SOURCES = ("paper_cs_0408029_amd/csrc/k_chol.hip", "paper_cs_0408029_amd/csrc/tile_ops.h")
 METRIC = "NNLS solves/s + p50/p99 latency vs plain FP64 GPU path at ≤1e-8 rel err"
 
 
@@ -39,13 +40,13 @@ def make_instance(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def profiled_traffic(kernel_src: str, summary: str):
+def profiled_traffic(kernel_srcs, summary: str):
     """HBM bytes per launch from a committed rocprofv3 counter summary, or None when the
-    kernel source has changed since the counters were taken."""
+    kernel's sources have changed since the counters were taken."""
     import hashlib
     try:
         text = open(os.path.join(ROOT, summary)).read()
-        src = open(os.path.join(ROOT, kernel_src), "rb").read()
+        src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in kernel_srcs)
     except OSError:
         return None
     fields = dict(l.strip().split(": ", 1) for l in text.splitlines() if ": " in l and l.startswith("    "))
@@ -459,8 +460,7 @@ def main():
         roof = {"bound": "mfma", "kernel": "k_chol_tiles<float>" if fp32 else "k_chol_tiles<double>",
                 "achieved": round(achieved, 3),
                 "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": profiled_traffic("paper_cs_0408029_amd/csrc/k_chol.hip",
-                                            "profiles/k_chol_tiles_sparse_large_m60000_n12000.md")
+                "traffic": profiled_traffic(CHOL_SOURCES, "profiles/k_chol_tiles_sparse_large_m60000_n12000.md")
                 if args.workload == "sparse_large" and not fp32 else None,
                 "launches": chol["launches"],
                 "avg_launch_ms": round(chol["ms"] / chol["launches"], 4),
