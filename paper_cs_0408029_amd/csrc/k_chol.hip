@@ -113,12 +113,17 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
         acc[bi][bj][v] = S[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT];
 
   const bool skip = (I == J) && (qr < qc);   // upper quadrant of a diagonal tile
-  // The diagonal tile also runs the forward solve L z = c_F for its block: it streams
-  // every L_Jk anyway, and z_k is published before column k completes.
+  // The diagonal tile stops one step short: the walker applies the last term, L_{J,J-1}
+  // being its own output.  The sub-diagonal tile runs its whole update and leaves the
+  // triangular solve with L_JJ to the walker.  The diagonal tile also runs the forward
+  // solve L z = c_F for its block up to its last step: it streams every L_Jk anyway, and
+  // z_k is published before column k completes.
+  const bool partial = (I - J <= 1);
+  const int kend = (I == J) ? max(J - 1, 0) : J;
   const bool fwd = (I == J) && (a.rhs != nullptr);
   double tacc = 0.0;                         // row `lane`, columns 16 w .. 16 w + 15
   int known = 0;                             // leading columns this wave knows are complete
-  for (int k = 0; k < J; ++k) {
+  for (int k = 0; k < kend; ++k) {
     if (k >= known) {
       if (ld_relaxed(&a.colcnt[k]) >= nb - k) {
         known = k + 1;
@@ -164,41 +169,16 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
   __syncthreads();
 
   T* dst = Lt + (int64_t)t * TILE_ELEMS;
-  if (I == J) {
+  if (partial) {
+    // hand the partial sum (and the diagonal's partial forward-solve sums) to the walker
     if (fwd) s_part[w][lane] = tacc;
-    const PivotReport rep = {J * TILE, a.nF, &a.ctrl->failed_pos, &a.ctrl->status};
-    factor_invert_tile<T>(S, W, rep);
+    for (int e = tid; e < TILE_ELEMS; e += 256) dst[e] = S[(e & (TILE - 1)) + (e >> 6) * LDT];
     if (fwd) {
-      if (tid < TILE) {
-        const int p = J * TILE + tid;
-        double c = 0.0;
-        if (p < a.nF) c = a.rhs[a.Flist ? a.Flist[p] : p];
-        s_rhs[tid] = c - (((s_part[0][tid] + s_part[1][tid]) + s_part[2][tid]) + s_part[3][tid]);
-      }
-      __syncthreads();
-      double zz = 0.0;
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int c = w * 16 + q;   // W holds L_JJ^-1 in its lower triangle only
-        if (c <= lane) zz = fma((double)W[lane + c * LDT], s_rhs[c], zz);
-      }
-      s_part[w][lane] = zz;
       __syncthreads();
       if (tid < TILE)
         a.z[(int64_t)J * TILE + tid] = ((s_part[0][tid] + s_part[1][tid]) + s_part[2][tid]) + s_part[3][tid];
     }
-    // the inverse first: it is what the rest of the column waits for
-    T* dinv = Dv + (int64_t)J * TILE_ELEMS;
-    for (int e = tid; e < TILE_ELEMS; e += 256) {
-      const int r = e & (TILE - 1), c = e >> 6;
-      dinv[e] = (r >= c) ? W[r + c * LDT] : (T)0;
-    }
-    publish_store(&a.dflag[J], a.epoch);
-    for (int e = tid; e < TILE_ELEMS; e += 256) {
-      const int r = e & (TILE - 1), c = e >> 6;
-      dst[e] = (r >= c) ? S[r + c * LDT] : (T)0;
-    }
-    publish_tile(&a.tflag[t], &a.colcnt[J], a.epoch);
+    publish_store(&a.tflag[t], -a.epoch);
     return;
   }
 
@@ -236,6 +216,236 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
   publish_tile(&a.tflag[t], &a.colcnt[J], a.epoch);
 }
 
+// acc (MFMA accumulator layout of this wave's 32 x 32 quadrant) -= P Q^T, P from global
+// (column-major, leading dimension TILE) or LDS (leading dimension LDT), Q from LDS.
+template <typename T, bool P_LDS>
+__device__ __forceinline__ void quad_update(typename MF<T>::acc (&acc)[2][2], const T* P, const T* Q, int qr, int qc,
+                                            int lane) {
+  typedef MF<T> M;
+  const int lr = lane & 15, lk = lane >> 4;
+  constexpr int LDP = P_LDS ? LDT : TILE;
+#pragma unroll
+  for (int kk = 0; kk < TILE; kk += 4) {
+    const int kc = kk + lk;
+    const T a0 = -P[(qr + lr) + kc * LDP], a1 = -P[(qr + 16 + lr) + kc * LDP];
+    const T b0 = Q[(qc + lr) + kc * LDT], b1 = Q[(qc + 16 + lr) + kc * LDT];
+    acc[0][0] = M::op(a0, b0, acc[0][0]);
+    acc[0][1] = M::op(a0, b1, acc[0][1]);
+    acc[1][0] = M::op(a1, b0, acc[1][0]);
+    acc[1][1] = M::op(a1, b1, acc[1][1]);
+  }
+}
+
+// Copy a 64 x 64 tile (column-major, leading dimension TILE) from global memory into LDS
+// (leading dimension LDT) with all sixteen loads of a thread in flight at once.
+template <typename T>
+__device__ __forceinline__ void tile_to_lds(const T* __restrict__ g, T* X, int tid) {
+  T v[TILE_ELEMS / 256];
+#pragma unroll
+  for (int q = 0; q < TILE_ELEMS / 256; ++q) v[q] = g[tid + q * 256];
+#pragma unroll
+  for (int q = 0; q < TILE_ELEMS / 256; ++q) {
+    const int e = tid + q * 256;
+    X[(e & (TILE - 1)) + (e >> 6) * LDT] = v[q];
+  }
+}
+
+// Store the lower triangle of an LDS tile (zeros above the diagonal) to global memory,
+// all of a thread's LDS reads first.
+template <typename T>
+__device__ __forceinline__ void lower_to_global(T* __restrict__ g, const T* X, int tid) {
+  T v[TILE_ELEMS / 256];
+#pragma unroll
+  for (int q = 0; q < TILE_ELEMS / 256; ++q) {
+    const int e = tid + q * 256, r = e & (TILE - 1), c = e >> 6;
+    v[q] = (r >= c) ? X[r + c * LDT] : (T)0;
+  }
+#pragma unroll
+  for (int q = 0; q < TILE_ELEMS / 256; ++q) g[tid + q * 256] = v[q];
+}
+
+template <typename T>
+__device__ __forceinline__ void tile_to_global(T* __restrict__ g, const T* X, int tid) {
+  T v[TILE_ELEMS / 256];
+#pragma unroll
+  for (int q = 0; q < TILE_ELEMS / 256; ++q) {
+    const int e = tid + q * 256;
+    v[q] = X[(e & (TILE - 1)) + (e >> 6) * LDT];
+  }
+#pragma unroll
+  for (int q = 0; q < TILE_ELEMS / 256; ++q) g[tid + q * 256] = v[q];
+}
+
+template <typename T>
+__device__ __forceinline__ void quad_store_lds(T* X, const typename MF<T>::acc (&acc)[2][2], int qr, int qc, int lane) {
+  typedef MF<T> M;
+  const int lr = lane & 15;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT] = acc[bi][bj][v];
+}
+
+// The walker: one workgroup carries the column-to-column chain of the factorisation.  For
+// each column J it takes the partial sum that the diagonal tile (J, J) published (every
+// left-looking term except the one with L_{J,J-1}), applies that last term from LDS
+// (L_{J,J-1} is its own previous output), factors and inverts the diagonal tile, emits
+// z_J of the forward solve, publishes L_JJ^-1 for the other tiles of the column, and
+// finishes the sub-diagonal tile L_{J+1,J} = S_{J+1,J} L_JJ^-T with the inverse still in
+// LDS (S_{J+1,J} being fully updated by its own workgroup meanwhile).  It then prefetches
+// the next diagonal partial sum into the buffer the inverse leaves free.  Per column the
+// chain keeps one hand-over from another workgroup (S_{J+1,J}) instead of three.
+template <typename T>
+__device__ __forceinline__ void walker(const FactorArgs& a, uint64_t wait_ticks, T* Pbuf, T* Qbuf,
+                                       double (*s_part)[TILE], double* s_rhs, double* s_z, double* s_tp) {
+  typedef MF<T> M;
+  typedef typename M::acc Acc;
+  const int nb = a.nb;
+  const bool fwd = a.rhs != nullptr;
+  T* Lt = (T*)a.Ltiles;
+  T* Dv = (T*)a.Dinv;
+  T* X = Pbuf;   // L_{J,J-1} from the previous column (J >= 1)
+  T* U = Qbuf;   // partial sum of the diagonal tile (J, J)
+  // column 0's diagonal tile
+  {
+    const int tid = fresh_tid();
+    spin_until(&a.tflag[tile_index(0, 0, nb)], -a.epoch, true, a.ctrl, wait_ticks);
+    acquire_agent();
+    tile_to_lds<T>(Lt + tile_index(0, 0, nb) * TILE_ELEMS, U, tid);
+    if (fwd && tid < TILE) s_tp[tid] = a.z[tid];
+    __syncthreads();
+  }
+  for (int J = 0; J < nb; ++J) {
+    const int tid = fresh_tid(), lane = tid & 63, w = tid >> 6;
+    const int qr = (w & 1) * 32, qc = (w >> 1) * 32;
+    const int64_t td = tile_index(J, J, nb);
+    const bool sub = J + 1 < nb;
+    const int64_t ts = sub ? tile_index(J + 1, J, nb) : td;
+    if (J >= 1) {
+      // last term of the diagonal tile, from LDS
+      Acc acc[2][2];
+      {
+        const int lr = lane & 15;
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[bi][bj][v] = U[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT];
+      }
+      if (!(qr < qc)) quad_update<T, true>(acc, X, X, qr, qc, lane);
+      if (fwd) {   // row `lane`, columns 16 w .. 16 w + 15 of L_{J,J-1} z_{J-1}
+        double t2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int cc = w * 16 + q;
+          t2 = fma((double)X[lane + cc * LDT], s_z[cc], t2);
+        }
+        s_part[w][lane] = t2;
+      }
+      __syncthreads();   // U and X fully read
+      quad_store_lds<T>(U, acc, qr, qc, lane);
+    }
+    if (fwd && tid < TILE) {
+      const int p = J * TILE + tid;
+      double c = 0.0;
+      if (p < a.nF) c = a.rhs[a.Flist ? a.Flist[p] : p];
+      const double last = (J >= 1) ? (((s_part[0][tid] + s_part[1][tid]) + s_part[2][tid]) + s_part[3][tid]) : 0.0;
+      s_rhs[tid] = c - (s_tp[tid] + last);
+    }
+    __syncthreads();
+    const PivotReport rep = {J * TILE, a.nF, &a.ctrl->failed_pos, &a.ctrl->status};
+    factor_invert_tile<T>(U, X, rep);   // L_JJ in U, L_JJ^-1 in X (lower triangles)
+    if (fwd) {
+      double zz = 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int c = w * 16 + q;
+        if (c <= lane) zz = fma((double)X[lane + c * LDT], s_rhs[c], zz);
+      }
+      s_part[w][lane] = zz;
+      __syncthreads();
+      if (tid < TILE) {
+        const double z = ((s_part[0][tid] + s_part[1][tid]) + s_part[2][tid]) + s_part[3][tid];
+        a.z[(int64_t)J * TILE + tid] = z;
+        s_z[tid] = z;
+      }
+    }
+    // the inverse first: the rest of the column waits for it
+    lower_to_global<T>(Dv + (int64_t)J * TILE_ELEMS, X, tid);
+    publish_store(&a.dflag[J], a.epoch);
+    lower_to_global<T>(Lt + td * TILE_ELEMS, U, tid);
+    if (!sub) {
+      publish_tile(&a.tflag[td], &a.colcnt[J], a.epoch);
+      break;
+    }
+    // S_{J+1,J}, fully updated by its own workgroup, and the next diagonal partial sum
+    T* dsub = Lt + ts * TILE_ELEMS;
+    const int64_t tn = tile_index(J + 1, J + 1, nb);
+    spin_until(&a.tflag[ts], -a.epoch, true, a.ctrl, wait_ticks);
+    spin_until(&a.tflag[tn], -a.epoch, true, a.ctrl, wait_ticks);
+    acquire_agent();
+    T vn[TILE_ELEMS / 256];   // next partial sum, parked in registers until X is free
+    {
+      const T* gn = Lt + tn * TILE_ELEMS;
+#pragma unroll
+      for (int q = 0; q < TILE_ELEMS / 256; ++q) vn[q] = gn[tid + q * 256];
+    }
+    const double tpn = (fwd && tid < TILE) ? a.z[(int64_t)(J + 1) * TILE + tid] : 0.0;
+    __syncthreads();   // L_JJ stored from U
+    tile_to_lds<T>(dsub, U, tid);
+    __syncthreads();
+    // L_{J+1,J} = S_{J+1,J} (L_JJ^-1)^T, the inverse's strict upper part being zero
+    Acc o[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[bi][bj][v] = (T)0;
+    {
+      const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+      for (int kk = 0; kk < TILE; kk += 4) {
+        const int kc = kk + lk;
+        const T a0 = U[(qr + lr) + kc * LDT], a1 = U[(qr + 16 + lr) + kc * LDT];
+        const T b0 = (kc <= qc + lr) ? X[(qc + lr) + kc * LDT] : (T)0;
+        const T b1 = (kc <= qc + 16 + lr) ? X[(qc + 16 + lr) + kc * LDT] : (T)0;
+        o[0][0] = M::op(a0, b0, o[0][0]);
+        o[0][1] = M::op(a0, b1, o[0][1]);
+        o[1][0] = M::op(a1, b0, o[1][0]);
+        o[1][1] = M::op(a1, b1, o[1][1]);
+      }
+    }
+    __syncthreads();   // U and X fully read
+    quad_store_lds<T>(U, o, qr, qc, lane);
+    __syncthreads();
+    tile_to_global<T>(dsub, U, tid);
+    // one release covers L_JJ and L_{J+1,J}
+    __syncthreads();
+    if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&a.tflag[td], a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&a.tflag[ts], a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&a.colcnt[J], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // the next diagonal partial sum into the buffer the inverse leaves free
+#pragma unroll
+    for (int q = 0; q < TILE_ELEMS / 256; ++q) {
+      const int e = tid + q * 256;
+      X[(e & (TILE - 1)) + (e >> 6) * LDT] = vn[q];
+    }
+    if (fwd && tid < TILE) s_tp[tid] = tpn;
+    __syncthreads();
+    // U holds L_{J+1,J}: the next column's X; X holds the next partial sum
+    T* tmp = X;
+    X = U;
+    U = tmp;
+  }
+}
+
 // Ticket t -> lower tile (I, J) in column-major order.
 __device__ inline void decode_ticket(int t, int nb, int* I, int* J) {
   int j = 0, start = 0;
@@ -254,18 +464,24 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wa
   __shared__ T W[TILE * LDT];
   __shared__ double s_part[4][TILE];   // fused forward solve: partial sums per wave
   __shared__ double s_rhs[TILE];
+  __shared__ double s_z[TILE];
+  __shared__ double s_tp[TILE];
   __shared__ int s_t, s_I, s_J;
   const int tid = threadIdx.x;
   if (tid == 0) {
-    const int t = atomicAdd(&a.ctrl->chol_ticket, 1);
+    const int t = atomicAdd(&a.ctrl->chol_ticket, 1) - 1;   // ticket 0 is the walker
     int I = 0, J = 0;
-    if (t < tile_count(a.nb)) decode_ticket(t, a.nb, &I, &J);
+    if (t >= 0 && t < tile_count(a.nb)) decode_ticket(t, a.nb, &I, &J);
     s_t = t;
     s_I = I;
     s_J = J;
   }
   __syncthreads();
   const int t = s_t;
+  if (t < 0) {
+    walker<T>(a, wait_ticks, S, W, s_part, s_rhs, s_z, s_tp);
+    return;
+  }
   if (t >= tile_count(a.nb)) return;   // counter not reset: do nothing rather than go out of range
   chol_tile<T>(a, wait_ticks, tid, t, s_I, s_J, S, W, s_part, s_rhs);
 }
@@ -281,14 +497,16 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles_persistent(FactorArgs a, 
   __shared__ T W[TILE * LDT];
   __shared__ double s_part[4][TILE];
   __shared__ double s_rhs[TILE];
+  __shared__ double s_z[TILE];
+  __shared__ double s_tp[TILE];
   __shared__ int s_t, s_I, s_J;
   const int64_t ntiles = tile_count(a.nb);
   for (;;) {
     const int tid = fresh_tid();
     if (tid == 0) {
-      const int t = atomicAdd(&a.ctrl->chol_ticket, 1);
+      const int t = atomicAdd(&a.ctrl->chol_ticket, 1) - 1;   // ticket 0 is the walker
       int I = 0, J = 0;
-      if (t < ntiles) decode_ticket(t, a.nb, &I, &J);
+      if (t >= 0 && t < ntiles) decode_ticket(t, a.nb, &I, &J);
       s_t = t;
       s_I = I;
       s_J = J;
@@ -296,6 +514,10 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles_persistent(FactorArgs a, 
     __syncthreads();
     const int t = s_t, I = s_I, J = s_J;
     __syncthreads();   // every thread has its ticket before thread 0 may take the next
+    if (t < 0) {
+      walker<T>(a, wait_ticks, S, W, s_part, s_rhs, s_z, s_tp);
+      return;
+    }
     if (t >= ntiles) return;
     chol_tile<T>(a, wait_ticks, tid, t, I, J, S, W, s_part, s_rhs);
     __syncthreads();   // LDS is reused by the next tile
@@ -442,13 +664,14 @@ __global__ void k_tiles_to_dense(int n, int nb, const T* __restrict__ Lt, double
 }  // namespace
 
 void launch_cholesky(hipStream_t s, const FactorArgs& a, bool fp32) {
-  const int64_t grid = tile_count(a.nb);
-  if (grid <= 0) return;
+  if (a.nb <= 0) return;
+  const int64_t grid = tile_count(a.nb) + 1;   // the tiles and the walker
   if (a.max_wgs > 0 && grid > a.max_wgs) {
+    const int g = a.max_wgs < 2 ? 2 : a.max_wgs;   // the walker and at least one tile worker
     if (fp32)
-      hipLaunchKernelGGL(k_chol_tiles_persistent<float>, dim3((unsigned)a.max_wgs), dim3(256), 0, s, a, a.wait_ticks);
+      hipLaunchKernelGGL(k_chol_tiles_persistent<float>, dim3((unsigned)g), dim3(256), 0, s, a, a.wait_ticks);
     else
-      hipLaunchKernelGGL(k_chol_tiles_persistent<double>, dim3((unsigned)a.max_wgs), dim3(256), 0, s, a, a.wait_ticks);
+      hipLaunchKernelGGL(k_chol_tiles_persistent<double>, dim3((unsigned)g), dim3(256), 0, s, a, a.wait_ticks);
     return;
   }
   if (fp32)
