@@ -234,12 +234,19 @@ typedef enum {
   NNLS_PROF_CONTROL = 1,   /* classify, count, exchange, rebuild F (bytes)              */
   NNLS_PROF_CHOLESKY = 2,  /* gather + tiled Cholesky of the F-block (flops |F|^3/3)    */
   NNLS_PROF_TRSV = 3,      /* two triangular solves (bytes of L read)                   */
-  NNLS_PROF_RESIDUAL = 4,  /* r = A x - b and y_G = A_G^T r (bytes)                     */
+  NNLS_PROF_RESIDUAL = 4,  /* r = A x - b and y_G = A_G^T r (bytes; in nnls_dual_csc the
+                              residual alone, the dual being NNLS_PROF_DUAL)            */
   NNLS_PROF_REFINE = 5,    /* mixed precision refinement (bytes)                        */
-  NNLS_PROF_BATCHED = 6    /* one batched launch (flops sum n^2 m of the Gram matrices) */
+  NNLS_PROF_BATCHED = 6,   /* one batched launch (flops sum n^2 m of the Gram matrices) */
+  NNLS_PROF_DUAL = 7       /* y_G = A_G^T r on its own (bytes); inside NNLS_PROF_RESIDUAL
+                              when timed as part of a solve                             */
 } nnls_profile_class;
 int nnls_get_profile(nnls_handle* h, int64_t* launches, double* total_ms, double* work);
 int nnls_reset_profile(nnls_handle* h);
+
+/* Time kernel classes on every call made on this handle from now on (on != 0), the step
+ * entry points included, as NNLS_FLAG_PROFILE does for one solve; on == 0 turns it off. */
+int nnls_set_profiling(nnls_handle* h, int on);
 
 /* ---------------------------------------------------------------------------------
  * Step entry points.  Each runs one step of the pivot iteration on its own, with the
@@ -273,6 +280,13 @@ int nnls_spd_solve(nnls_handle* h, int32_t n, const double* S, int32_t lds, cons
 int nnls_dual_csc(nnls_handle* h, int32_t m, int32_t n, int64_t nnz, const int32_t* colptr,
                   const int32_t* rowidx, const double* val, const double* b,
                   const uint8_t* free_flags, const double* x, double* r, double* y);
+
+/* Eq. 5 on a given split for dense column-major A (device, lda >= m): r = A x - b and
+ * y_i = a_i^T r for i in G, y_i = 0 for i in F.  Same arguments as nnls_dual_csc
+ * otherwise; r may be NULL. */
+int nnls_dual_dense(nnls_handle* h, int32_t m, int32_t n, const double* A, int32_t lda,
+                    const double* b, const uint8_t* free_flags, const double* x, double* r,
+                    double* y);
 
 /* One classify-and-exchange step (Sec. 2 box): zero tested entries with |v| < tau (v = x_i
  * on F, y_i on G), count the negative ones (k), apply the counter rule to (N, p) and flip

@@ -172,6 +172,10 @@ def nnls_reset_profile(h: Handle) -> int:
     return h.lib.nnls_reset_profile(h.ptr)
 
 
+def nnls_set_profiling(h: Handle, on: bool) -> int:
+    return h.lib.nnls_set_profiling(h.ptr, 1 if on else 0)
+
+
 def nnls_gram_csc(h: Handle, m: int, n: int, colptr, rowidx, val, b, H, c) -> int:
     torch = _torch()
     nnz = int(rowidx.numel())
@@ -218,6 +222,17 @@ def nnls_dual_csc(h: Handle, m: int, n: int, colptr, rowidx, val, b, free_flags,
                                _ptr(x, torch.float64, "x", n),
                                _ptr(r, torch.float64, "r", m) if r is not None else None,
                                _ptr(y, torch.float64, "y", n))
+
+
+def nnls_dual_dense(h: Handle, A, b, free_flags, x, r, y) -> int:
+    """A: column-major float64 device matrix (m, n)."""
+    torch = _torch()
+    m, n = A.shape
+    ap, lda = _colmajor(A, "A")
+    return h.lib.nnls_dual_dense(h.ptr, m, n, ap, lda, _ptr(b, torch.float64, "b", m),
+                                 _ptr(free_flags, torch.uint8, "free", n), _ptr(x, torch.float64, "x", n),
+                                 _ptr(r, torch.float64, "r", m) if r is not None else None,
+                                 _ptr(y, torch.float64, "y", n))
 
 
 def nnls_pivot_step(h: Handle, x, y, free_flags, tau: float, p_max: int, state: List[int]):

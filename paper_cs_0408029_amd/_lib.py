@@ -27,7 +27,7 @@ NNLS_FP32_IR = 1
 NNLS_FLAG_PROFILE = 1
 
 NNLS_PROFILE_CLASSES = 8
-PROFILE_CLASS_NAMES = ["gram", "control", "cholesky", "trsv", "residual", "refine", "batched", "c7"]
+PROFILE_CLASS_NAMES = ["gram", "control", "cholesky", "trsv", "residual", "refine", "batched", "dual"]
 
 
 class nnls_options(C.Structure):
@@ -88,10 +88,12 @@ PROTOTYPES = {
     "nnls_get_profile": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double)]),
     "nnls_reset_profile": (C.c_int, [_P]),
+    "nnls_set_profiling": (C.c_int, [_P, C.c_int]),
     "nnls_gram_csc": (C.c_int, [_P, _I32, _I32, _I64, _P, _P, _P, _P, _P, _I32, _P]),
     "nnls_cholesky": (C.c_int, [_P, _I32, _P, _I32, _P, _I32, _I32, C.POINTER(_I32)]),
     "nnls_spd_solve": (C.c_int, [_P, _I32, _P, _I32, _P, _P, C.POINTER(_I32)]),
     "nnls_dual_csc": (C.c_int, [_P, _I32, _I32, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "nnls_dual_dense": (C.c_int, [_P, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P]),
     "nnls_pivot_step": (C.c_int, [_P, _I32, _P, _P, _P, C.c_double, _I32, C.POINTER(_I32),
                                   C.POINTER(_I32)]),
 }

@@ -44,7 +44,7 @@ struct nnls_handle {
   int max_wgs = 0;            // the grid cap of the current solve
   // workspace
   DevBuf err, ctrl, rowcnt, rowptr, colidx, valr, hptr, hcnt, hrow, hval, c, r, flags, Flist, pos;
-  DevBuf Lt, Dinv, colcnt, dflag, tflag, z, xF, Hd, gF;
+  DevBuf Lt, Dinv, colcnt, dflag, tflag, z, xF, Hd, gF, rpart;
   DevBuf bprobs, border, binfo, bws;   // batched dense problems
   Ctrl* h_ctrl = nullptr;     // pinned
   int64_t* h_scalar = nullptr;  // pinned scratch for small reads
@@ -52,6 +52,7 @@ struct nnls_handle {
   std::vector<nnls_trace_row> trace;
   // profiling
   bool profiling = false;
+  bool profile_always = false;   // nnls_set_profiling
   int64_t prof_launches[NNLS_PROFILE_CLASSES] = {};
   double prof_ms[NNLS_PROFILE_CLASSES] = {};
   double prof_work[NNLS_PROFILE_CLASSES] = {};
@@ -226,6 +227,7 @@ int build_gram_sparse(nnls_handle* h, const Problem& P) {
 }
 
 int build_gram_dense(nnls_handle* h, const Problem& P) {
+  TRY(ensure(h, h->rpart, sizeof(double) * (size_t)dense_residual_chunks(P.m, P.n) * (size_t)P.m));
   TRY(ensure(h, h->Hd, sizeof(double) * (size_t)P.n * (size_t)P.n));
   launch_gram_dense(h->stream, P.m, P.n, P.A, P.lda, (double*)h->Hd.p, P.n);
   TRY(ensure(h, h->c, sizeof(double) * (size_t)P.n));
@@ -306,11 +308,11 @@ void residual_dual(nnls_handle* h, const Problem& P, const double* x, double* y,
   double* r = (double*)h->r.p;
   const uint8_t* flags = (const uint8_t*)h->flags.p;
   if (P.sparse) {
-    launch_residual_csr(h->stream, P.m, (const int32_t*)h->rowptr.p, (const int32_t*)h->colidx.p,
+    launch_residual_csr(h->stream, P.m, P.nnz, (const int32_t*)h->rowptr.p, (const int32_t*)h->colidx.p,
                         (const double*)h->valr.p, x, P.b, r);
     launch_dual_csc(h->stream, P.n, P.colptr, P.rowidx, P.val, r, flags, y, gfree);
   } else {
-    launch_residual_dense(h->stream, P.m, P.n, P.A, P.lda, x, P.b, r);
+    launch_residual_dense(h->stream, P.m, P.n, P.A, P.lda, x, P.b, r, (double*)h->rpart.p);
     launch_dual_dense(h->stream, P.m, P.n, P.A, P.lda, r, flags, y, gfree);
   }
 }
@@ -476,7 +478,7 @@ int solve_common(nnls_handle* h, const Problem& P, double* x, double* y, const n
     if (!P.A || P.lda < P.m) return set_info_status(info, NNLS_ERR_INVALID_ARG);
   }
   if (hipSetDevice(h->device) != hipSuccess) return set_info_status(info, NNLS_ERR_DEVICE);
-  h->profiling = (o.flags & NNLS_FLAG_PROFILE) != 0;
+  h->profiling = h->profile_always || (o.flags & NNLS_FLAG_PROFILE) != 0;
   h->max_wgs = o.max_workgroups > 0 ? (int)std::min<uint32_t>(o.max_workgroups, 1u << 20) : h->default_wgs;
   int st = validate_device(h, P);
   if (st != NNLS_OK) return set_info_status(info, st);
@@ -489,7 +491,7 @@ int solve_common(nnls_handle* h, const Problem& P, double* x, double* y, const n
   if (info) info->setup_ms = now_ms() - t0;
   st = pivot_loop(h, P, x, y, o, info);
   if (info) info->solve_ms = now_ms() - t0;
-  h->profiling = false;
+  h->profiling = h->profile_always;
   return set_info_status(info, st);
 }
 
@@ -504,7 +506,7 @@ void release_workspace(nnls_handle* h) {
   (void)hipStreamSynchronize(h->stream);
   DevBuf* bufs[] = {&h->err, &h->ctrl, &h->rowcnt, &h->rowptr, &h->colidx, &h->valr, &h->hptr,
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
-                    &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF,
+                    &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart,
                     &h->bprobs, &h->border, &h->binfo, &h->bws};
   for (DevBuf* b : bufs) {
     if (b->p) (void)hipFree(b->p);
@@ -579,7 +581,7 @@ int nnls_destroy(nnls_handle* h) {
   (void)hipStreamSynchronize(h->stream);
   DevBuf* bufs[] = {&h->err, &h->ctrl, &h->rowcnt, &h->rowptr, &h->colidx, &h->valr, &h->hptr,
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
-                    &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF,
+                    &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart,
                     &h->bprobs, &h->border, &h->binfo, &h->bws};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
@@ -692,7 +694,7 @@ int nnls_solve_dense_batched(nnls_handle* h, int32_t batch, const int32_t* m, co
   ba.fp32 = o.precision == NNLS_FP32_IR ? 1 : 0;
   ba.ir_max_steps = o.ir_max_steps;
   ba.ir_rtol = o.ir_rtol;
-  h->profiling = (o.flags & NNLS_FLAG_PROFILE) != 0;
+  h->profiling = h->profile_always || (o.flags & NNLS_FLAG_PROFILE) != 0;
   double flops = 0.0;
   for (int i = 0; i < batch; ++i) flops += (double)n[i] * n[i] * m[i];
   const int64_t pe = prof_begin(h, NNLS_PROF_BATCHED);
@@ -700,7 +702,7 @@ int nnls_solve_dense_batched(nnls_handle* h, int32_t batch, const int32_t* m, co
   prof_end(h, pe, flops);
   std::vector<BatchInfo> bi((size_t)batch);
   const int st = sync_read(h, bi.data(), h->binfo.p, sizeof(BatchInfo) * (size_t)batch);
-  h->profiling = false;
+  h->profiling = h->profile_always;
   if (st != NNLS_OK) return st;
   if (hipGetLastError() != hipSuccess) return NNLS_ERR_DEVICE;
   const double el = now_ms() - t0;
@@ -736,6 +738,13 @@ int nnls_get_profile(nnls_handle* h, int64_t* launches, double* total_ms, double
     if (total_ms) total_ms[c] = h->prof_ms[c];
     if (work) work[c] = h->prof_work[c];
   }
+  return NNLS_OK;
+}
+
+int nnls_set_profiling(nnls_handle* h, int on) {
+  if (!h) return NNLS_ERR_INVALID_ARG;
+  h->profile_always = on != 0;
+  h->profiling = h->profile_always;
   return NNLS_OK;
 }
 
@@ -848,10 +857,46 @@ int nnls_dual_csc(nnls_handle* h, int32_t m, int32_t n, int64_t nnz, const int32
     TRY(ensure(h, h->r, sizeof(double) * (size_t)m));
     rr = (double*)h->r.p;
   }
-  launch_residual_csr(h->stream, m, (const int32_t*)h->rowptr.p, (const int32_t*)h->colidx.p,
+  int64_t pe = prof_begin(h, NNLS_PROF_RESIDUAL);
+  launch_residual_csr(h->stream, m, nnz, (const int32_t*)h->rowptr.p, (const int32_t*)h->colidx.p,
                       (const double*)h->valr.p, x, b, rr);
+  prof_end(h, pe, 12.0 * (double)nnz + 20.0 * m + 8.0 * n);
+  pe = prof_begin(h, NNLS_PROF_DUAL);
   launch_dual_csc(h->stream, n, colptr, rowidx, val, rr, free_flags, y);
+  prof_end(h, pe, 12.0 * (double)nnz + 8.0 * m + 13.0 * n);
   HIP_TRY(hipStreamSynchronize(h->stream));
+  prof_flush(h);
+  return NNLS_OK;
+}
+
+int nnls_dual_dense(nnls_handle* h, int32_t m, int32_t n, const double* A, int32_t lda, const double* b,
+                    const uint8_t* free_flags, const double* x, double* r, double* y) {
+  if (!h || n < 1 || m < 1 || lda < m || !A || !b || !free_flags || !x || !y) return NNLS_ERR_INVALID_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return NNLS_ERR_DEVICE;
+  Problem P;
+  std::memset(&P, 0, sizeof(P));
+  P.sparse = false;
+  P.m = m;
+  P.n = n;
+  P.A = A;
+  P.lda = lda;
+  P.b = b;
+  TRY(validate_device(h, P));
+  TRY(ensure(h, h->rpart, sizeof(double) * (size_t)dense_residual_chunks(m, n) * (size_t)m));
+  double* rr = r;
+  if (!rr) {
+    TRY(ensure(h, h->r, sizeof(double) * (size_t)m));
+    rr = (double*)h->r.p;
+  }
+  const double mn = (double)m * (double)n;
+  int64_t pe = prof_begin(h, NNLS_PROF_RESIDUAL);
+  launch_residual_dense(h->stream, m, n, A, lda, x, b, rr, (double*)h->rpart.p);
+  prof_end(h, pe, 8.0 * mn + 8.0 * n + 16.0 * m);
+  pe = prof_begin(h, NNLS_PROF_DUAL);
+  launch_dual_dense(h->stream, m, n, A, lda, rr, free_flags, y);
+  prof_end(h, pe, 8.0 * mn + 8.0 * m + 9.0 * n);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  prof_flush(h);
   return NNLS_OK;
 }
 

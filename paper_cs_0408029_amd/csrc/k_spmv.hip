@@ -11,18 +11,26 @@ namespace nnls {
 namespace {
 
 // One wave handles 64 consecutive rows, one row per lane.
+// r = A x - b over the row-major copy, L lanes per row: each lane takes a fixed stride of
+// the row's entries (consecutive lanes read consecutive entries, and consecutive rows are
+// adjacent, so the loads coalesce), then a fixed xor tree combines the L partial sums.
+template <int L>
 __global__ __launch_bounds__(256) void k_residual_csr(int m, const int32_t* __restrict__ rowptr,
                                                       const int32_t* __restrict__ colidx,
                                                       const double* __restrict__ valr,
                                                       const double* __restrict__ x,
                                                       const double* __restrict__ b,
                                                       double* __restrict__ r) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
+  const int sub = threadIdx.x & (L - 1);
+  const int i = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / L);
   double s = 0.0;
-  const int e1 = rowptr[i + 1];
-  for (int e = rowptr[i]; e < e1; ++e) s = fma(valr[e], x[colidx[e]], s);
-  r[i] = s - b[i];
+  if (i < m) {
+    const int e1 = rowptr[i + 1];
+    for (int e = rowptr[i] + sub; e < e1; e += L) s = fma(valr[e], x[colidx[e]], s);
+  }
+#pragma unroll
+  for (int d = L / 2; d >= 1; d >>= 1) s += __shfl_xor(s, d, L);
+  if (i < m && sub == 0) r[i] = s - b[i];
 }
 
 // 16 lanes per column: each lane takes a fixed stride of the column's entries, then a
@@ -86,14 +94,34 @@ __global__ __launch_bounds__(1024) void k_ir_update(int nF, const int32_t* __res
 }
 
 // Dense r = A x - b: one thread per row, ascending column order.
+// Dense r = A x - b, one thread per row (column-major A: a wave reads 512 contiguous bytes
+// per column).  With `part`, column chunk blockIdx.y of width `chunk` writes its partial
+// sums to part[blockIdx.y * m + i] instead, so that tall-and-narrow grids still fill the
+// device; k_residual_dense_combine then adds the chunks in order.
 __global__ __launch_bounds__(256) void k_residual_dense(int m, int n, const double* __restrict__ A,
                                                         int lda, const double* __restrict__ x,
                                                         const double* __restrict__ b,
-                                                        double* __restrict__ r) {
+                                                        double* __restrict__ r, int chunk,
+                                                        double* __restrict__ part) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int j0 = part ? blockIdx.y * chunk : 0;
+  const int j1 = part ? min(n, j0 + chunk) : n;
+  double s = 0.0;
+  for (int j = j0; j < j1; ++j) s = fma(A[i + (int64_t)j * lda], x[j], s);
+  if (part)
+    part[(int64_t)blockIdx.y * m + i] = s;
+  else
+    r[i] = s - b[i];
+}
+
+__global__ __launch_bounds__(256) void k_residual_dense_combine(int m, int nchunk, const double* __restrict__ part,
+                                                                const double* __restrict__ b,
+                                                                double* __restrict__ r) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
   double s = 0.0;
-  for (int j = 0; j < n; ++j) s = fma(A[i + (int64_t)j * lda], x[j], s);
+  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * m + i];
   r[i] = s - b[i];
 }
 
@@ -123,9 +151,19 @@ __global__ __launch_bounds__(256) void k_dual_dense(int m, int n, const double* 
 
 }  // namespace
 
-void launch_residual_csr(hipStream_t s, int m, const int32_t* rowptr, const int32_t* colidx,
+void launch_residual_csr(hipStream_t s, int m, int64_t nnz, const int32_t* rowptr, const int32_t* colidx,
                          const double* valr, const double* x, const double* b, double* r) {
-  hipLaunchKernelGGL(k_residual_csr, dim3((m + 255) / 256), dim3(256), 0, s, m, rowptr, colidx, valr, x, b, r);
+  // lanes per row: the average row length rounded up to a power of two, at most 16
+  const double avg = m > 0 ? (double)nnz / m : 0.0;
+  const int L = avg > 8 ? 16 : avg > 4 ? 8 : avg > 2 ? 4 : avg > 1 ? 2 : 1;
+  const unsigned grid = (unsigned)(((int64_t)m * L + 255) / 256);
+  switch (L) {
+    case 16: hipLaunchKernelGGL(k_residual_csr<16>, dim3(grid), dim3(256), 0, s, m, rowptr, colidx, valr, x, b, r); break;
+    case 8: hipLaunchKernelGGL(k_residual_csr<8>, dim3(grid), dim3(256), 0, s, m, rowptr, colidx, valr, x, b, r); break;
+    case 4: hipLaunchKernelGGL(k_residual_csr<4>, dim3(grid), dim3(256), 0, s, m, rowptr, colidx, valr, x, b, r); break;
+    case 2: hipLaunchKernelGGL(k_residual_csr<2>, dim3(grid), dim3(256), 0, s, m, rowptr, colidx, valr, x, b, r); break;
+    default: hipLaunchKernelGGL(k_residual_csr<1>, dim3(grid), dim3(256), 0, s, m, rowptr, colidx, valr, x, b, r); break;
+  }
 }
 
 void launch_dual_csc(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx,
@@ -142,8 +180,25 @@ void launch_ir_update(hipStream_t s, int nF, const int32_t* Flist, const double*
 }
 
 void launch_residual_dense(hipStream_t s, int m, int n, const double* A, int lda,
-                           const double* x, const double* b, double* r) {
-  hipLaunchKernelGGL(k_residual_dense, dim3((m + 255) / 256), dim3(256), 0, s, m, n, A, lda, x, b, r);
+                           const double* x, const double* b, double* r, double* part) {
+  const int rows = (m + 255) / 256;
+  const int nchunk = dense_residual_chunks(m, n);
+  if (nchunk <= 1 || !part) {
+    hipLaunchKernelGGL(k_residual_dense, dim3(rows), dim3(256), 0, s, m, n, A, lda, x, b, r, n, (double*)nullptr);
+    return;
+  }
+  const int chunk = (n + nchunk - 1) / nchunk;
+  hipLaunchKernelGGL(k_residual_dense, dim3(rows, nchunk), dim3(256), 0, s, m, n, A, lda, x, b, r, chunk, part);
+  hipLaunchKernelGGL(k_residual_dense_combine, dim3(rows), dim3(256), 0, s, m, nchunk, (const double*)part, b, r);
+}
+
+int dense_residual_chunks(int m, int n) {
+  // enough workgroups for the device (about 1024), chunks of at least 64 columns
+  const int rows = (m + 255) / 256;
+  int c = (1024 + rows - 1) / rows;
+  const int cmax = (n + 63) / 64;
+  if (c > cmax) c = cmax;
+  return c < 1 ? 1 : c;
 }
 
 void launch_dual_dense(hipStream_t s, int m, int n, const double* A, int lda, const double* r,

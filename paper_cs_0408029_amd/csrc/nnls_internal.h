@@ -84,13 +84,15 @@ void launch_pivot_control(hipStream_t s, int n, double* x, double* y, uint8_t* f
 void launch_ctrl_set_state(hipStream_t s, Ctrl* ctrl, int N, int p, int iter, int max_iter_flag);
 
 // residual and dual (k_spmv.hip)
-void launch_residual_csr(hipStream_t s, int m, const int32_t* rowptr, const int32_t* colidx,
+void launch_residual_csr(hipStream_t s, int m, int64_t nnz, const int32_t* rowptr, const int32_t* colidx,
                          const double* valr, const double* x, const double* b, double* r);
 void launch_dual_csc(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx,
                      const double* val, const double* r, const uint8_t* flags, double* y,
                      double* gfree = nullptr);
 void launch_residual_dense(hipStream_t s, int m, int n, const double* A, int lda,
-                           const double* x, const double* b, double* r);
+                           const double* x, const double* b, double* r, double* part = nullptr);
+// column chunks the dense residual splits into (part needs chunks * m doubles; 1: no split)
+int dense_residual_chunks(int m, int n);
 void launch_dual_dense(hipStream_t s, int m, int n, const double* A, int lda, const double* r,
                        const uint8_t* flags, double* y, double* gfree = nullptr);
 // x[Flist[p]] -= d[p] for p < nF; writes max |d| and max |x_F| into ctrl (one workgroup)

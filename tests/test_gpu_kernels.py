@@ -118,6 +118,53 @@ def test_dual_step(h, seed):
     assert np.all(np.abs(yg - y_or) <= bound + 1e-300)
 
 
+@pytest.mark.parametrize("m,n,density", [(3000, 400, 0.0015), (3000, 400, 0.004), (3000, 400, 0.008),
+                                           (3000, 400, 0.016), (3000, 400, 0.04), (900, 600, 0.08)])
+def test_residual_every_lane_width(h, m, n, density):
+    """The row-major residual uses 1..16 lanes per row by average row length; every width
+    must give r = A x - b and y = A^T r within the rounding bound."""
+    inst = W.sparse_small(7, m=m, n=n, density=density)
+    rng = np.random.default_rng(3)
+    free = np.zeros(inst.n, dtype=bool)
+    x = rng.standard_normal(inst.n)
+    colptr, rowidx, val = csc_dev(inst.A)
+    yd = torch.full((inst.n,), np.nan, dtype=torch.float64, device=DEV)
+    rd = torch.empty(inst.m, dtype=torch.float64, device=DEV)
+    st = N.nnls_dual_csc(h, inst.m, inst.n, colptr, rowidx, val, t(inst.b), t(free, np.uint8), t(x), rd, yd)
+    assert st == N.NNLS_OK
+    absA = abs(inst.A)
+    r_ref = inst.A @ x - inst.b
+    rbound = (absA @ np.abs(x) + np.abs(inst.b)) * 4 * inst.n * EPS
+    assert np.all(np.abs(rd.cpu().numpy() - r_ref) <= rbound + 1e-300)
+    y_ref = inst.A.T @ r_ref
+    ybound = (absA.T @ (absA @ np.abs(x) + np.abs(inst.b))) * 8 * inst.m * EPS
+    assert np.all(np.abs(yd.cpu().numpy() - y_ref) <= ybound + 1e-300)
+
+
+@pytest.mark.parametrize("m,n", [(40, 30), (300, 70), (5000, 40), (20000, 700), (1000, 1000)])
+def test_dual_dense_step(h, m, n):
+    """Dense Eq. 5 step (the residual splits over column chunks when the grid is short)."""
+    rng = np.random.default_rng(m + n)
+    A = rng.standard_normal((m, n))
+    b = rng.standard_normal(m)
+    free = rng.random(n) < 0.4
+    x = np.where(free, rng.standard_normal(n), 0.0)
+    yd = torch.full((n,), np.nan, dtype=torch.float64, device=DEV)
+    rd = torch.empty(m, dtype=torch.float64, device=DEV)
+    st = N.nnls_dual_dense(h, colmajor_dev(A), t(b), t(free, np.uint8), t(x), rd, yd)
+    assert st == N.NNLS_OK
+    r_ref = A @ x - b
+    rbound = (np.abs(A) @ np.abs(x) + np.abs(b)) * 4 * n * EPS
+    assert np.all(np.abs(rd.cpu().numpy() - r_ref) <= rbound + 1e-300)
+    idx_f, idx_g = np.flatnonzero(free), np.flatnonzero(~free)
+    y_or = np.zeros(n)
+    y_or[idx_g] = dual(sp.csc_matrix(A), b, idx_f, x[idx_f], idx_g)
+    yg = yd.cpu().numpy()
+    assert np.all(yg[free] == 0.0)
+    bound = (np.abs(A).T @ (np.abs(A) @ np.abs(x) + np.abs(b))) * 8 * m * EPS
+    assert np.all(np.abs(yg - y_or) <= bound + 1e-300)
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_pivot_step_matches_rule(h, seed):
     """Classify, count, counter rule and exchange: bit-exact against the oracle's steps."""
