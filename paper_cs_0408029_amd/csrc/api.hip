@@ -44,11 +44,12 @@ struct nnls_handle {
   int max_wgs = 0;            // the grid cap of the current solve
   // workspace
   DevBuf err, ctrl, rowcnt, rowptr, colidx, valr, hptr, hcnt, hrow, hval, c, r, flags, Flist, pos;
-  DevBuf Lt, Dinv, colcnt, dflag, tflag, z, xF, Hd, gF, rpart;
+  DevBuf Lt, Dinv, colcnt, dflag, tflag, z, xF, Hd, gF, rpart, spart, spflag;
   DevBuf bprobs, border, binfo, bws;   // batched dense problems
   Ctrl* h_ctrl = nullptr;     // pinned
   int64_t* h_scalar = nullptr;  // pinned scratch for small reads
   int epoch = 0;
+  int trsv_tag = 0;           // flag values of the triangular-solve hand-overs, never reused
   std::vector<nnls_trace_row> trace;
   // profiling
   bool profiling = false;
@@ -256,6 +257,8 @@ int ensure_factor(nnls_handle* h, int nF, bool fp32) {
   TRY(ensure(h, h->tflag, ntiles * sizeof(int32_t), true));
   TRY(ensure(h, h->z, (size_t)nb * TILE * sizeof(double)));
   TRY(ensure(h, h->xF, (size_t)nb * TILE * sizeof(double)));
+  TRY(ensure(h, h->spart, (size_t)nb * TILE * sizeof(double)));
+  TRY(ensure(h, h->spflag, (size_t)nb * sizeof(int32_t), true));
   return NNLS_OK;
 }
 
@@ -298,6 +301,14 @@ SolveArgs solve_args(nnls_handle* h, int nF, const int32_t* Flist, const double*
   a.epoch = h->epoch;
   a.ctrl = (Ctrl*)h->ctrl.p;
   a.wait_ticks = h->wait_ticks;
+  a.part = (double*)h->spart.p;
+  a.pflag = (int32_t*)h->spflag.p;
+  h->trsv_tag += 2;   // forward and backward
+  if (h->trsv_tag > (1 << 30)) {   // values are never reused while flags may hold them
+    launch_fill_i32(h->stream, (int32_t*)h->spflag.p, a.nb, 0);
+    h->trsv_tag = 2;
+  }
+  a.tag = h->trsv_tag;
   return a;
 }
 
@@ -506,7 +517,7 @@ void release_workspace(nnls_handle* h) {
   (void)hipStreamSynchronize(h->stream);
   DevBuf* bufs[] = {&h->err, &h->ctrl, &h->rowcnt, &h->rowptr, &h->colidx, &h->valr, &h->hptr,
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
-                    &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart,
+                    &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart, &h->spart, &h->spflag,
                     &h->bprobs, &h->border, &h->binfo, &h->bws};
   for (DevBuf* b : bufs) {
     if (b->p) (void)hipFree(b->p);
@@ -581,7 +592,7 @@ int nnls_destroy(nnls_handle* h) {
   (void)hipStreamSynchronize(h->stream);
   DevBuf* bufs[] = {&h->err, &h->ctrl, &h->rowcnt, &h->rowptr, &h->colidx, &h->valr, &h->hptr,
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
-                    &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart,
+                    &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart, &h->spart, &h->spflag,
                     &h->bprobs, &h->border, &h->binfo, &h->bws};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);

@@ -524,129 +524,157 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles_persistent(FactorArgs a, 
   }
 }
 
-// z_I = L_II^-1 (rhs_I - sum_{k<I} L_Ik z_k)
-template <typename T>
-__global__ __launch_bounds__(256) void k_trsv_fwd(SolveArgs a, uint64_t wait_ticks) {
-  __shared__ double part[4][TILE];
-  __shared__ double srhs[TILE];
-  __shared__ int s_I;
-  const int tid = threadIdx.x, r = tid & (TILE - 1), g = tid >> 6;
-  if (tid == 0) s_I = atomicAdd(&a.ctrl->fwd_ticket, 1);
-  __syncthreads();
-  const int I = s_I, nb = a.nb;
-  if (I >= nb) return;
-  const T* Lt = (const T*)a.Ltiles;
-  const T* Dv = (const T*)a.Dinv;
-  int32_t* done = &a.ctrl->fwd_done;   // blocks 0 .. done-1 of z are final
-  double acc = 0.0;
-  int known = 0;
-  for (int k = 0; k < I; ++k) {
-    if (k >= known) {
-      spin_until(done, k + 1, false, a.ctrl, wait_ticks);
-      known = ld_relaxed(done);
-      acquire_agent();
-    }
-    const T* tl = Lt + tile_index(I, k, nb) * TILE_ELEMS;
-    const double* zk = a.z + (int64_t)k * TILE;
+// Triangular solves with a walker.  Forward: z_I = L_II^-1 (rhs_I - sum_{k<I} L_Ik z_k),
+// blocks in ascending order; backward: x_I = L_II^-T (z_I - sum_{k>I} L_kI^T x_k), blocks in
+// descending order.  Step s solves block blk(s).  Ticket 0 is the walker: it solves the
+// blocks one after another, adding the TD newest terms itself from an LDS ring of its own
+// outputs (tiles of the next step are loaded during the current one).  Ticket s+1 is the
+// helper of step s: it accumulates every older term as the walker publishes blocks and
+// hands the partial sum over (flag = this launch's tag).  A helper waits only for walker
+// steps that precede its own, and the walker waits for helpers of steps it has reached, so
+// every wait ends; each wait is also bounded in wall time.
+constexpr int TD = 2;
+
+template <bool FWD>
+__device__ inline int blk(int s, int nb) { return FWD ? s : nb - 1 - s; }
+
+template <typename T, bool FWD>
+__device__ inline void load_term_tile(const T* Lt, int I, int K, int nb, int r, int g, T (&v)[16]) {
+  if (FWD) {   // L_IK, thread (r, g) takes row r, columns 16 g .. 16 g + 15
+    const T* tl = Lt + tile_index(I, K, nb) * TILE_ELEMS;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int cc = g * 16 + q;
-      acc = fma((double)tl[cc * TILE + r], zk[cc], acc);
-    }
-  }
-  part[g][r] = acc;
-  __syncthreads();
-  if (tid < TILE) {
-    const int p = I * TILE + tid;
-    double rhs = 0.0;
-    if (p < a.nF) rhs = a.rhs_full ? a.rhs_full[a.Flist ? a.Flist[p] : p] : a.rhs_dense[p];
-    srhs[tid] = rhs - (((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid]);
-  }
-  __syncthreads();
-  const T* D = Dv + (int64_t)I * TILE_ELEMS;
-  double zz = 0.0;
+    for (int q = 0; q < 16; ++q) v[q] = tl[(g * 16 + q) * TILE + r];
+  } else {     // L_KI^T: thread (r, g) takes column r, rows 16 g .. 16 g + 15 of L_KI
+    const T* tl = Lt + tile_index(K, I, nb) * TILE_ELEMS;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int c = g * 16 + q;
-    zz = fma((double)D[c * TILE + r], srhs[c], zz);
+    for (int q = 0; q < 16; ++q) v[q] = tl[r * TILE + g * 16 + q];
   }
-  part[g][r] = zz;
-  __syncthreads();
-  if (tid < TILE)
-    a.z[(int64_t)I * TILE + tid] = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
-  // blocks finish in order (block I needs every earlier block), so done == I here
-  publish_store(done, I + 1);
 }
 
-// x_I = L_II^-T (z_I - sum_{k>I} L_kI^T x_k); scatter x_I through F.  The tile of the
-// next step and the inverse diagonal block are loaded before waiting on the frontier, so
-// a step on the critical path waits only for x_k itself.
-template <typename T>
-__global__ __launch_bounds__(256) void k_trsv_bwd(SolveArgs a, uint64_t wait_ticks) {
-  __shared__ double ssum[TILE];
-  __shared__ double srhs[TILE];
+template <typename T, bool FWD>
+__device__ inline void load_dinv(const T* Dv, int I, int r, int g, T (&v)[16]) {
+  const T* D = Dv + (int64_t)I * TILE_ELEMS;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) v[q] = FWD ? D[(g * 16 + q) * TILE + r] : D[r * TILE + g * 16 + q];
+}
+
+template <typename T, bool FWD>
+__global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ticks, int tag) {
   __shared__ double part[4][TILE];
-  __shared__ int s_I;
+  __shared__ double srhs[TILE];
+  __shared__ double ring[TD][TILE];
+  __shared__ int s_t;
   const int tid = threadIdx.x, r = tid & (TILE - 1), g = tid >> 6;
-  if (tid == 0) s_I = a.nb - 1 - atomicAdd(&a.ctrl->bwd_ticket, 1);
+  int32_t* ticket = FWD ? &a.ctrl->fwd_ticket : &a.ctrl->bwd_ticket;
+  int32_t* done = FWD ? &a.ctrl->fwd_done : &a.ctrl->bwd_done;   // steps 0 .. done-1 are solved
+  if (tid == 0) s_t = atomicAdd(ticket, 1) - 1;
   __syncthreads();
-  const int I = s_I, nb = a.nb;
-  if (I < 0) return;
+  const int t = s_t, nb = a.nb;
+  if (t >= nb) return;   // also covers a counter that was not reset
   const T* Lt = (const T*)a.Ltiles;
-  const T* D = (const T*)a.Dinv + (int64_t)I * TILE_ELEMS;
-  int32_t* done = &a.ctrl->bwd_done;   // blocks nb-done .. nb-1 of x are final
-  T dv[16];
+  const T* Dv = (const T*)a.Dinv;
+  double* outv = FWD ? a.z : a.xF;
+
+  if (t >= 0) {
+    // helper of step t: every term from steps 0 .. t-TD-1
+    const int I = blk<FWD>(t, nb);
+    const int last = t - TD;   // steps < last
+    double acc = 0.0;          // FWD: row r, columns of group g
+    double accl[16];           // BWD: columns 16 g + q, rows spread over the lanes
 #pragma unroll
-  for (int q = 0; q < 16; ++q) dv[q] = D[r * TILE + g * 16 + q];
-  double accl[16];
+    for (int q = 0; q < 16; ++q) accl[q] = 0.0;
+    int known = 0;
+    T tv[16];
+    if (last > 0) load_term_tile<T, FWD>(Lt, I, blk<FWD>(0, nb), nb, r, g, tv);
+    for (int u = 0; u < last; ++u) {
+      if (u >= known) {
+        spin_until(done, u + 1, false, a.ctrl, wait_ticks);
+        known = ld_relaxed(done);
+        acquire_agent();
+      }
+      const int K = blk<FWD>(u, nb);
+      T cur[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) accl[q] = 0.0;
-  int known = 0;
-  T tv[16];
-  if (I < nb - 1) {
-    const T* tl = Lt + tile_index(nb - 1, I, nb) * TILE_ELEMS;
+      for (int q = 0; q < 16; ++q) cur[q] = tv[q];
+      if (u + 1 < last) load_term_tile<T, FWD>(Lt, I, blk<FWD>(u + 1, nb), nb, r, g, tv);
+      if (FWD) {
+        const double* zk = outv + (int64_t)K * TILE;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) tv[q] = tl[(g * 16 + q) * TILE + r];
-  }
-  for (int k = nb - 1; k > I; --k) {
-    if (nb - k > known) {
-      spin_until(done, nb - k, false, a.ctrl, wait_ticks);
-      known = ld_relaxed(done);
-      acquire_agent();
+        for (int q = 0; q < 16; ++q) acc = fma((double)cur[q], zk[g * 16 + q], acc);
+      } else {
+        // the transposed tile: thread (r, g) holds column r of L_KI^T's rows 16 g ..
+        const double* xk = outv + (int64_t)K * TILE;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc = fma((double)cur[q], xk[g * 16 + q], acc);
+      }
     }
-    const double xr = a.xF[(int64_t)k * TILE + r];
-    T cur[16];
+    part[g][r] = acc;
+    __syncthreads();
+    if (tid < TILE) a.part[(int64_t)I * TILE + tid] = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
+    publish_store(&a.pflag[I], tag);
+    return;
+  }
+
+  // the walker
+  T td[TD][16], dv[16];
+  {
+    const int I0 = blk<FWD>(0, nb);
+    load_dinv<T, FWD>(Dv, I0, r, g, dv);
+  }
+  for (int s = 0; s < nb; ++s) {
+    const int I = blk<FWD>(s, nb);
+    spin_until(&a.pflag[I], tag, true, a.ctrl, wait_ticks);
+    acquire_agent();
+    // newest terms: steps max(0, s-TD) .. s-1, oldest first
+    double acc = 0.0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) cur[q] = tv[q];
-    if (k - 1 > I) {
-      const T* tl = Lt + tile_index(k - 1, I, nb) * TILE_ELEMS;
+    for (int j = 0; j < TD; ++j) {
+      const int u = s - TD + j;
+      if (u >= 0) {
+        const double* xk = ring[u % TD];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) tv[q] = tl[(g * 16 + q) * TILE + r];
+        for (int q = 0; q < 16; ++q) acc = fma((double)td[j][q], xk[g * 16 + q], acc);
+      }
     }
+    part[g][r] = acc;
+    __syncthreads();
+    if (tid < TILE) {
+      const int p = I * TILE + tid;
+      double rhs;
+      if (FWD) {
+        rhs = 0.0;
+        if (p < a.nF) rhs = a.rhs_full ? a.rhs_full[a.Flist ? a.Flist[p] : p] : a.rhs_dense[p];
+      } else {
+        rhs = a.z[p];
+      }
+      const double older = a.part[p];
+      srhs[tid] = rhs - (older + (((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid]));
+    }
+    __syncthreads();
+    double xx = 0.0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) accl[q] = fma((double)cur[q], xr, accl[q]);
-  }
+    for (int q = 0; q < 16; ++q) xx = fma((double)dv[q], srhs[g * 16 + q], xx);
+    // tiles of the next step, in flight while this one finishes
+    if (s + 1 < nb) {
+      const int In = blk<FWD>(s + 1, nb);
+      load_dinv<T, FWD>(Dv, In, r, g, dv);
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    double v = accl[q];
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    if (r == 0) ssum[g * 16 + q] = v;
+      for (int j = 0; j < TD; ++j) {
+        const int u = s + 1 - TD + j;
+        if (u >= 0) load_term_tile<T, FWD>(Lt, In, blk<FWD>(u, nb), nb, r, g, td[j]);
+      }
+    }
+    part[g][r] = xx;
+    __syncthreads();
+    if (tid < TILE) {
+      const double v = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
+      const int p = I * TILE + tid;
+      outv[p] = v;
+      ring[s % TD][tid] = v;
+      if (!FWD && a.out && p < a.nF) a.out[a.Flist ? a.Flist[p] : p] = v;
+    }
+    publish_store(done, s + 1);
   }
-  __syncthreads();
-  if (tid < TILE) srhs[tid] = a.z[(int64_t)I * TILE + tid] - ssum[tid];
-  __syncthreads();
-  double xx = 0.0;
-#pragma unroll
-  for (int q = 0; q < 16; ++q) xx = fma((double)dv[q], srhs[g * 16 + q], xx);
-  part[g][r] = xx;
-  __syncthreads();
-  if (tid < TILE) {
-    const double v = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
-    const int p = I * TILE + tid;
-    a.xF[p] = v;
-    if (a.out && p < a.nF) a.out[a.Flist ? a.Flist[p] : p] = v;
-  }
-  publish_store(done, nb - I);
 }
 
 template <typename T>
@@ -682,12 +710,13 @@ void launch_cholesky(hipStream_t s, const FactorArgs& a, bool fp32) {
 
 void launch_trsv(hipStream_t s, const SolveArgs& a, bool fp32, bool forward) {
   if (a.nb <= 0) return;
+  const dim3 grid(a.nb + 1);   // the helpers and the walker
   if (fp32) {
-    if (forward) hipLaunchKernelGGL(k_trsv_fwd<float>, dim3(a.nb), dim3(256), 0, s, a, a.wait_ticks);
-    hipLaunchKernelGGL(k_trsv_bwd<float>, dim3(a.nb), dim3(256), 0, s, a, a.wait_ticks);
+    if (forward) hipLaunchKernelGGL((k_trsv_walk<float, true>), grid, dim3(256), 0, s, a, a.wait_ticks, a.tag);
+    hipLaunchKernelGGL((k_trsv_walk<float, false>), grid, dim3(256), 0, s, a, a.wait_ticks, a.tag + 1);
   } else {
-    if (forward) hipLaunchKernelGGL(k_trsv_fwd<double>, dim3(a.nb), dim3(256), 0, s, a, a.wait_ticks);
-    hipLaunchKernelGGL(k_trsv_bwd<double>, dim3(a.nb), dim3(256), 0, s, a, a.wait_ticks);
+    if (forward) hipLaunchKernelGGL((k_trsv_walk<double, true>), grid, dim3(256), 0, s, a, a.wait_ticks, a.tag);
+    hipLaunchKernelGGL((k_trsv_walk<double, false>), grid, dim3(256), 0, s, a, a.wait_ticks, a.tag + 1);
   }
 }
 

@@ -136,6 +136,9 @@ struct SolveArgs {
   int epoch;
   Ctrl* ctrl;
   uint64_t wait_ticks;
+  double* part;             // nb * TILE: partial sums handed to the walker
+  int32_t* pflag;           // nb flags: partial sum of block I ready when == tag
+  int tag;                  // this call's flag value (forward tag, backward tag + 1)
 };
 void launch_trsv(hipStream_t s, const SolveArgs& a, bool fp32, bool forward);
 void launch_tiles_to_dense(hipStream_t s, int n, int nb, const void* Ltiles, bool fp32,
