@@ -68,7 +68,9 @@ typedef struct {
   int32_t max_iter;     /* pivot iteration cap; <= 0 means 5 n + 100 (paper gives none)  */
   int32_t precision;    /* nnls_precision                                                */
   int32_t ir_max_steps; /* NNLS_FP32_IR: refinement steps per pivot iteration            */
-  double ir_rtol;       /* NNLS_FP32_IR: target ||A_F^T r||_inf / ||A_F^T b||_inf        */
+  double ir_rtol;       /* NNLS_FP32_IR: stop when the last correction of x_F, or the
+                           bound on the corrections still to come, is below ir_rtol
+                           max|x_F|                                                     */
   uint32_t flags;       /* NNLS_FLAG_*                                                   */
   uint32_t max_workgroups; /* 0: the factor kernel runs one workgroup per tile; else a
                               persistent grid of this many workgroups, so that several

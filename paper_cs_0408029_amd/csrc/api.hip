@@ -332,8 +332,9 @@ void residual_dual(nnls_handle* h, const Problem& P, const double* x, double* y,
 // the forward solve fused, then the backward solve scattered into x.  In NNLS_FP32_IR the
 // factor is float32 and x_F is refined in float64 against the residual from A,
 //   g_F = A_F^T (A x - b),  x_F <- x_F - (L L^T)^-1 g_F,
-// until the correction is below ir_rtol relative to x_F; if it stalls or the step cap is
-// reached, the iteration is redone with a float64 factor.  *y_done is set when the last
+// until the correction, or the bound on the corrections still to come, is below ir_rtol
+// relative to x_F; if it stalls or the step cap is reached, the iteration is redone with a
+// float64 factor.  *y_done is set when the last
 // refinement pass already left y_G for the final x.
 int solve_free(nnls_handle* h, const Problem& P, int nF, double* x, double* y, const nnls_options& o,
                double spmv_bytes, bool* y_done, nnls_info* info) {
@@ -384,10 +385,16 @@ int solve_free(nnls_handle* h, const Problem& P, int nF, double* x, double* y, c
       if (info) info->ir_steps += 1;
       const double dmax = h->h_ctrl->ir_dmax, xmax = h->h_ctrl->ir_xmax;
       if (!(dmax <= INFINITY) || !(xmax <= INFINITY)) break;
+      // stop once the last correction, or the corrections still to come, are below the
+      // target: with the measured contraction rho = dmax / prev (at most 1/2 here) the
+      // rest sum to at most dmax * rho / (1 - rho)
+      const double rho = dmax / prev;               // 0 on the first step
       if (dmax <= o.ir_rtol * xmax) {
         converged = true;
-      } else if (dmax > 0.5 * prev) {
+      } else if (rho > 0.5) {
         break;                                      // not contracting: factor in float64
+      } else if (prev < INFINITY && dmax * rho / (1.0 - rho) <= o.ir_rtol * xmax) {
+        converged = true;
       }
       prev = dmax;
     }

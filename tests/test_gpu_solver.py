@@ -225,6 +225,20 @@ def test_mixed_sparse_small(h, seed):
     assert info.ir_steps >= info.iterations   # every factor was refined at least once
 
 
+def test_mixed_stays_in_float32_when_well_conditioned(h):
+    """On a well-conditioned problem every iteration keeps its float32 factor (one factor
+    launch per iteration, no float64 redo) and refinement stops within three steps per
+    iteration; the result still matches the oracle to the mixed-precision tolerance."""
+    inst = W.sparse_large(1002, m=6000, n=1200)
+    res = bpp_solve(inst.A, inst.b)
+    N.nnls_reset_profile(h)
+    st, info, x, y, trace = solve_csc(h, inst.A, inst.b, precision=N.NNLS_FP32_IR, flags=N.NNLS_FLAG_PROFILE)
+    check_mixed(res, st, info, x, y, trace)
+    prof = N.nnls_get_profile(h)
+    assert prof["cholesky"]["launches"] == info.iterations
+    assert info.iterations <= info.ir_steps <= 3 * info.iterations
+
+
 @pytest.mark.parametrize("m,n,seed", [(300, 100, 2), (1100, 520, 4)])
 def test_mixed_dense_planted(h, m, n, seed):
     inst = W.dense_planted(seed, m, n)
