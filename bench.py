@@ -493,6 +493,142 @@ def bench_spmv_dense(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_kappa(args):
+    """Relative error against condition number, the analog of the paper's Fig. 1: 80 x 70
+    matrices U diag(s) V^T with each singular value repeated 4 times and kappa from 1e1 to
+    1e8 (half decades, --kappa-seeds problems each), known all-positive solution.  All
+    problems of a precision go through one batched launch; beside them the CPU oracle on the
+    same problems and the law fitted to the paper's printed points."""
+    import torch
+    import paper_cs_0408029_amd as N
+    import workloads as W
+    from oracle import bpp_solve
+    d = np.loadtxt(os.path.join(ROOT, "tests", "golden", "fig1_normal_equations_error.txt"))
+    slope, icpt = np.polyfit(1 + (d[:, 0] - 120) * 7 / 1319, -16 + (d[:, 1] - 82) * 18 / 778, 1)
+    lks = np.arange(1.0, 8.01, 0.5)
+    probs, keys = [], []
+    for lk in lks:
+        for s in range(args.kappa_seeds):
+            probs.append(W.svd_conditioned(300 + s, 10 ** lk))
+            keys.append(lk)
+    dev = torch.device("cuda:0")
+    As = [torch.from_numpy(np.ascontiguousarray(A.T)).to(dev).t() for A, _, _ in probs]
+    bs = [torch.from_numpy(b).to(dev) for _, _, b in probs]
+    h = N.Handle(0)
+    rows = {}
+    t0 = time.perf_counter()
+    for name, prec in (("gpu_fp64", N.NNLS_FP64), ("gpu_fp32ir", N.NNLS_FP32_IR)):
+        xs = [torch.empty(A.shape[1], dtype=torch.float64, device=dev) for A, _, _ in probs]
+        ys = [torch.empty_like(x) for x in xs]
+        st, infos = N.nnls_solve_dense_batched(h, As, bs, xs, ys, N.default_options(precision=prec))
+        for (A, xt, b), x, info, lk in zip(probs, xs, infos, keys):
+            e = np.linalg.norm(x.cpu().numpy() - xt) / np.linalg.norm(xt) if info.status == N.NNLS_OK else np.nan
+            rows.setdefault(lk, {}).setdefault(name, []).append(e)
+    gpu_s = time.perf_counter() - t0
+    h.close()
+    for (A, xt, b), lk in zip(probs, keys):
+        r = bpp_solve(A, b)
+        e = np.linalg.norm(r.x - xt) / np.linalg.norm(xt) if r.status == "ok" else np.nan
+        rows[lk].setdefault("oracle", []).append(e)
+    table = []
+    for lk in lks:
+        row = {"log10_kappa": float(lk), "paper_law": round(float(slope * lk + icpt), 2)}
+        for k, v in rows[lk].items():
+            v = np.asarray(v)
+            ok = v[np.isfinite(v)]
+            row[k] = round(float(np.median(np.log10(ok))), 2) if ok.size else None
+            row[k + "_failed"] = int(v.size - ok.size)
+        table.append(row)
+    fit = [(r["log10_kappa"], r["gpu_fp64"]) for r in table if r["gpu_fp64"] is not None and 1.5 <= r["log10_kappa"] <= 6]
+    gslope = float(np.polyfit([a for a, _ in fit], [b for _, b in fit], 1)[0])
+    out = {
+        "metric": "relative error vs condition number (normal equations, Fig. 1 analog)",
+        "value": round(gslope, 3), "unit": "log10 error per log10 kappa (GPU float64, kappa 1e1.5..1e6)",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(gpu_s * 1e3, 1),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"80x70 U diag(s) V^T, singular values repeated 4 times, kappa 1e1..1e8, "
+                               f"{args.kappa_seeds} problems per half decade, seeds 300+"},
+        "paper_law_slope": round(float(slope), 3), "paper_law_intercept": round(float(icpt), 2),
+        "table": table, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_fig2(args):
+    """The paper's speed workload (Fig. 2): random n x (n-10) matrices, N(0,1) values at a
+    random density-1.0 or density-0.01 pattern, b ~ N(0,1) (seed 1008), at the paper's sizes;
+    --fig2-reps matrices per point.  GPU time per solve on the plain float64 path (inputs
+    resident, one call per problem) and the CPU oracle on the same matrices; the paper's
+    tsnnls times (G5, serial C, final LSQR included) are context."""
+    import scipy.sparse as sp
+    import torch
+    import paper_cs_0408029_amd as N
+    from oracle import bpp_solve
+    paper = {"dense": {120: 0.031, 200: 0.063, 300: 0.23, 499: 0.93, 699: 2.42, 938: 5.72},
+             "sparse": {820: 0.12, 1000: 0.24, 1200: 0.47, 1420: 0.79}}
+    rng = np.random.default_rng(1008)
+    dev = torch.device("cuda:0")
+    h = N.Handle(0)
+    o = N.default_options()
+    table = []
+    for kind, pts in paper.items():
+        for n_rows, t_paper in pts.items():
+            m, n = n_rows, n_rows - 10
+            gpu_t, cpu_t, stat, iters = [], [], [], []
+            for rep in range(args.fig2_reps):
+                if kind == "dense":
+                    A = rng.standard_normal((m, n))
+                else:
+                    A = sp.random(m, n, density=0.01, format="csc", random_state=rng,
+                                  data_rvs=rng.standard_normal)
+                    A.sort_indices()
+                b = rng.standard_normal(m)
+                x = torch.empty(n, dtype=torch.float64, device=dev)
+                y = torch.empty_like(x)
+                bd = torch.from_numpy(b).to(dev)
+                if kind == "dense":
+                    Ad = torch.from_numpy(np.ascontiguousarray(A.T)).to(dev).t()
+                    call = lambda: N.nnls_solve_dense(h, Ad, bd, x, y, o)
+                else:
+                    cp = torch.from_numpy(A.indptr.astype(np.int32)).to(dev)
+                    ri = torch.from_numpy(A.indices.astype(np.int32)).to(dev)
+                    va = torch.from_numpy(A.data).to(dev)
+                    call = lambda: N.nnls_solve_csc(h, m, n, cp, ri, va, bd, x, y, o)
+                call()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, info = call()
+                torch.cuda.synchronize()
+                gpu_t.append(time.perf_counter() - t0)
+                stat.append(N.status_string(st))
+                iters.append(info.iterations)
+                c0 = time.perf_counter()
+                r = bpp_solve(A, b)
+                cpu_t.append(time.perf_counter() - c0)
+                if st == N.NNLS_OK and r.status == "ok":
+                    xh = x.cpu().numpy()
+                    if not np.array_equal(xh > 0, r.x > 0):
+                        stat[-1] = "free-set mismatch"
+            table.append({"kind": kind, "m": m, "n": n, "gpu_ms": round(1e3 * float(np.mean(gpu_t)), 3),
+                          "oracle_ms": round(1e3 * float(np.mean(cpu_t)), 2),
+                          "paper_tsnnls_ms": round(1e3 * t_paper, 1), "iterations": float(np.mean(iters)),
+                          "status": sorted(set(stat))})
+    h.close()
+    ok = all(r["status"] == ["NNLS_OK"] for r in table)
+    out = {
+        "metric": "solve time on the paper's Fig. 2 matrices (plain float64 path, one call per problem)",
+        "value": round(float(np.mean([r["paper_tsnnls_ms"] / r["gpu_ms"] for r in table])), 1),
+        "unit": "mean speed-up over the paper's tsnnls times (other hardware: context only)",
+        "n_gpus": 1, "steps": args.fig2_reps, "warmup": 1,
+        "ms_per_step": round(float(np.mean([r["gpu_ms"] for r in table])), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "random n x (n-10), density 1.0 (n 120..938) and 0.01 (n 820..1420), "
+                               f"N(0,1), {args.fig2_reps} matrices per point, seed 1008"},
+        "all_ok_and_free_sets_match_oracle": ok, "table": table, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -515,6 +651,8 @@ def main():
     ap.add_argument("--workers", type=int, default=12, help="serve: concurrent sparse solves")
     ap.add_argument("--batch-lanes", type=int, default=2, help="serve: batched launches in flight")
     ap.add_argument("--batch-max-n", type=int, default=256, help="serve: largest n sent to batched launches")
+    ap.add_argument("--fig2-reps", type=int, default=3, help="fig2: matrices per point")
+    ap.add_argument("--kappa-seeds", type=int, default=8, help="kappa: problems per half decade")
     ap.add_argument("--spmv-dense", action="store_true", help="spmv: dense column-major A instead")
     ap.add_argument("--dense-m", type=int, default=65536, help="spmv --spmv-dense: rows")
     ap.add_argument("--dense-n", type=int, default=4096, help="spmv --spmv-dense: columns")
@@ -557,6 +695,12 @@ def main():
         return
     if args.workload == "spmv":
         bench_spmv(args)
+        return
+    if args.workload == "kappa":
+        bench_kappa(args)
+        return
+    if args.workload == "fig2":
+        bench_fig2(args)
         return
     inst, desc = make_instance(args.workload)
     dev = torch.device("cuda:0")

@@ -1,0 +1,87 @@
+"""Accuracy against condition number on the GPU, the analog of the paper's Fig. 1: on
+80 x 70 matrices with prescribed condition number and a known all-positive solution, the
+normal-equations solution's relative error follows the law fitted to the paper's printed
+points (kappa^2 eps, Sec. 2.1 and Sec. 4) on both precisions, and stays within a decade of
+the CPU oracle's error on the same problems."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import bpp_solve
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_cs_0408029_amd as N  # noqa: E402
+from _gpu_util import DEV, colmajor_dev, t  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def fig1_law():
+    d = np.loadtxt(os.path.join(GOLDEN, "fig1_normal_equations_error.txt"))
+    lk = 1 + (d[:, 0] - 120) * 7 / 1319
+    le = -16 + (d[:, 1] - 82) * 18 / 778
+    return np.polyfit(lk, le, 1)
+
+
+@pytest.fixture(scope="module")
+def h():
+    with N.Handle(0) as hh:
+        yield hh
+
+
+def batched_errors(h, probs, precision):
+    As = [colmajor_dev(A) for A, _, _ in probs]
+    bs = [t(b) for _, _, b in probs]
+    xs = [torch.empty(A.shape[1], dtype=torch.float64, device=DEV) for A, _, _ in probs]
+    ys = [torch.empty(A.shape[1], dtype=torch.float64, device=DEV) for A, _, _ in probs]
+    st, infos = N.nnls_solve_dense_batched(h, As, bs, xs, ys, N.default_options(precision=precision))
+    assert st == N.NNLS_OK
+    return [np.linalg.norm(x.cpu().numpy() - xt) / np.linalg.norm(xt) for x, (_, xt, _) in zip(xs, probs)]
+
+
+def oracle_median(probs):
+    orc = []
+    for A, xt, b in probs:
+        r = bpp_solve(A, b)
+        orc.append(np.linalg.norm(r.x - xt) / np.linalg.norm(xt))
+    return np.median(np.log10(orc))
+
+
+def test_float64_error_follows_fig1_law(h):
+    slope, icpt = fig1_law()
+    for lkap in (1.5, 2.5, 3.5, 4.5, 5.5, 6.0):
+        probs = [W.svd_conditioned(100 + s, 10 ** lkap) for s in range(5)]
+        gpu = np.median(np.log10(batched_errors(h, probs, N.NNLS_FP64)))
+        assert abs(gpu - (slope * lkap + icpt)) < 0.75, (lkap, gpu)
+        assert abs(gpu - oracle_median(probs)) < 1.0, (lkap, gpu)
+
+
+def test_mixed_error_no_worse_than_normal_equations(h):
+    """The float32 factor refined against the float64 residual from A is never less accurate
+    than the float64 normal equations (the law's band), and usually more accurate: the
+    refinement's residual does not square the condition number."""
+    slope, icpt = fig1_law()
+    for lkap in (1.5, 2.5, 3.5, 4.5, 5.5, 6.0):
+        probs = [W.svd_conditioned(100 + s, 10 ** lkap) for s in range(5)]
+        gpu = np.median(np.log10(batched_errors(h, probs, N.NNLS_FP32_IR)))
+        assert gpu < slope * lkap + icpt + 0.75, (lkap, gpu)
+        assert gpu < oracle_median(probs) + 1.0, (lkap, gpu)
+
+
+def test_single_problem_path_matches_batched_accuracy(h):
+    """The dense single-problem path (tiled factor, walker) gives errors of the same size."""
+    slope, icpt = fig1_law()
+    for lkap in (2.0, 4.0, 6.0):
+        errs = []
+        for s in range(3):
+            A, xt, b = W.svd_conditioned(200 + s, 10 ** lkap)
+            x = torch.empty(A.shape[1], dtype=torch.float64, device=DEV)
+            y = torch.empty_like(x)
+            st, info = N.nnls_solve_dense(h, colmajor_dev(A), t(b), x, y)
+            assert st == N.NNLS_OK
+            errs.append(np.linalg.norm(x.cpu().numpy() - xt) / np.linalg.norm(xt))
+        assert abs(np.median(np.log10(errs)) - (slope * lkap + icpt)) < 0.75, lkap
