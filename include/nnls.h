@@ -61,6 +61,11 @@ typedef enum {
 
 /* flags */
 #define NNLS_FLAG_PROFILE 1u   /* time kernel classes with HIP events (nnls_get_profile) */
+#define NNLS_FLAG_REFINE_FINAL 2u /* NNLS_FP64: once the split is feasible, recompute x_F more
+                                     accurately (the final step of Sec. 3) by float64
+                                     refinement against the residual from A with the split's
+                                     cached factor, then classify the refined x and y again
+                                     (pivoting resumes if that finds infeasible entries)    */
 
 typedef struct {
   double tau;           /* zeroing threshold; paper: 1e-12 (Sec. 2)                      */

@@ -25,6 +25,7 @@ NNLS_FP64 = 0
 NNLS_FP32_IR = 1
 
 NNLS_FLAG_PROFILE = 1
+NNLS_FLAG_REFINE_FINAL = 2
 
 NNLS_PROFILE_CLASSES = 8
 PROFILE_CLASS_NAMES = ["gram", "control", "cholesky", "trsv", "residual", "refine", "batched", "dual"]

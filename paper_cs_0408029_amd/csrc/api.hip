@@ -328,14 +328,73 @@ void residual_dual(nnls_handle* h, const Problem& P, const double* x, double* y,
   }
 }
 
+// Float64 iterative refinement of x_F against the residual from A with the factor in the
+// handle (float32 when fp32):  g_F = A_F^T (A x - b),  x_F <- x_F - (L L^T)^-1 g_F,  until the
+// last correction, or the bound on the corrections still to come, is below ir_rtol
+// max|x_F|; it stops early when the corrections do not contract or the float32 factor
+// breaks down.  *outcome: REFINED (target reached; y_G was formed from the final x),
+// STALLED (not reached: redo or keep), or REPORT (the control block holds an error status
+// for the next control step to report).
+enum RefineOutcome { REFINED = 0, STALLED = 1, REPORT = 2 };
+int refine(nnls_handle* h, const Problem& P, int nF, double* x, double* y, const nnls_options& o,
+           double spmv_bytes, bool fp32, double l_bytes, nnls_info* info, int* outcome) {
+  const int32_t* Flist = (const int32_t*)h->Flist.p;
+  Ctrl* ctrl = (Ctrl*)h->ctrl.p;
+  *outcome = STALLED;
+  TRY(ensure(h, h->gF, sizeof(double) * (size_t)P.n));
+  double* gF = (double*)h->gF.p;
+  bool converged = false;
+  double prev = INFINITY;
+  for (int step = 0;; ++step) {
+    int64_t pe = prof_begin(h, NNLS_PROF_RESIDUAL);
+    residual_dual(h, P, x, y, gF);
+    prof_end(h, pe, spmv_bytes);
+    if (converged) break;
+    if (step >= o.ir_max_steps) break;
+    pe = prof_begin(h, NNLS_PROF_REFINE);
+    launch_reset_tickets(h->stream, ctrl);
+    SolveArgs ca = solve_args(h, nF, Flist, gF, nullptr);
+    launch_trsv(h->stream, ca, fp32, true);
+    launch_ir_update(h->stream, nF, Flist, (const double*)h->xF.p, x, ctrl);
+    prof_end(h, pe, 2.0 * l_bytes);
+    TRY(sync_read(h, h->h_ctrl, ctrl, sizeof(Ctrl)));
+    if (h->h_ctrl->status == NNLS_ERR_NOT_PD && fp32) {   // float32 breakdown: the caller redoes it
+      launch_ctrl_clear_breakdown(h->stream, ctrl);
+      h->h_ctrl->status = 0;
+      return NNLS_OK;
+    }
+    if (h->h_ctrl->status != 0) {                  // reported by the next control step
+      *outcome = REPORT;
+      return NNLS_OK;
+    }
+    if (info) info->ir_steps += 1;
+    const double dmax = h->h_ctrl->ir_dmax, xmax = h->h_ctrl->ir_xmax;
+    if (!(dmax <= INFINITY) || !(xmax <= INFINITY)) break;
+    // stop once the last correction, or the corrections still to come, are below the
+    // target: with the measured contraction rho = dmax / prev (at most 1/2 here) the rest
+    // sum to at most dmax * rho / (1 - rho)
+    const double rho = dmax / prev;                 // 0 on the first step
+    if (dmax <= o.ir_rtol * xmax) {
+      converged = true;
+    } else if (rho > 0.5) {
+      break;                                        // not contracting
+    } else if (prev < INFINITY && dmax * rho / (1.0 - rho) <= o.ir_rtol * xmax) {
+      converged = true;
+    }
+    prev = dmax;
+  }
+  *outcome = converged ? REFINED : STALLED;
+  return NNLS_OK;
+}
+
 // x_F for the current split (Eq. 4 by the normal equations, Sec. 2.1): factor H_FF with
 // the forward solve fused, then the backward solve scattered into x.  In NNLS_FP32_IR the
 // factor is float32 and x_F is refined in float64 against the residual from A,
 //   g_F = A_F^T (A x - b),  x_F <- x_F - (L L^T)^-1 g_F,
 // until the correction, or the bound on the corrections still to come, is below ir_rtol
 // relative to x_F; if it stalls or the step cap is reached, the iteration is redone with a
-// float64 factor.  *y_done is set when the last
-// refinement pass already left y_G for the final x.
+// float64 factor (and refined with it).  *y_done is set when the last refinement pass
+// already left y_G for the final x.
 int solve_free(nnls_handle* h, const Problem& P, int nF, double* x, double* y, const nnls_options& o,
                double spmv_bytes, bool* y_done, nnls_info* info) {
   const int32_t* Flist = (const int32_t*)h->Flist.p;
@@ -358,50 +417,18 @@ int solve_free(nnls_handle* h, const Problem& P, int nF, double* x, double* y, c
     pe = prof_begin(h, NNLS_PROF_TRSV);
     launch_trsv(h->stream, sa, fp32, false);
     prof_end(h, pe, l_bytes);
-    if (!fp32) return NNLS_OK;
+    if (o.precision != NNLS_FP32_IR) return NNLS_OK;
 
-    TRY(ensure(h, h->gF, sizeof(double) * (size_t)P.n));
-    double* gF = (double*)h->gF.p;
-    bool converged = false;
-    double prev = INFINITY;
-    for (int step = 0;; ++step) {
-      pe = prof_begin(h, NNLS_PROF_RESIDUAL);
-      residual_dual(h, P, x, y, gF);
-      prof_end(h, pe, spmv_bytes);
-      if (converged) break;
-      if (step >= o.ir_max_steps) break;
-      pe = prof_begin(h, NNLS_PROF_REFINE);
-      launch_reset_tickets(h->stream, ctrl);
-      SolveArgs ca = solve_args(h, nF, Flist, gF, nullptr);
-      launch_trsv(h->stream, ca, true, true);
-      launch_ir_update(h->stream, nF, Flist, (const double*)h->xF.p, x, ctrl);
-      prof_end(h, pe, 2.0 * l_bytes);
-      TRY(sync_read(h, h->h_ctrl, ctrl, sizeof(Ctrl)));
-      if (h->h_ctrl->status == NNLS_ERR_NOT_PD) {     // float32 breakdown: redo in float64
-        launch_ctrl_clear_breakdown(h->stream, ctrl);
-        break;
-      }
-      if (h->h_ctrl->status != 0) return NNLS_OK;   // reported by the next control step
-      if (info) info->ir_steps += 1;
-      const double dmax = h->h_ctrl->ir_dmax, xmax = h->h_ctrl->ir_xmax;
-      if (!(dmax <= INFINITY) || !(xmax <= INFINITY)) break;
-      // stop once the last correction, or the corrections still to come, are below the
-      // target: with the measured contraction rho = dmax / prev (at most 1/2 here) the
-      // rest sum to at most dmax * rho / (1 - rho)
-      const double rho = dmax / prev;               // 0 on the first step
-      if (dmax <= o.ir_rtol * xmax) {
-        converged = true;
-      } else if (rho > 0.5) {
-        break;                                      // not contracting: factor in float64
-      } else if (prev < INFINITY && dmax * rho / (1.0 - rho) <= o.ir_rtol * xmax) {
-        converged = true;
-      }
-      prev = dmax;
-    }
-    if (converged) {
+    // refined against the residual from A; after a float64 redo as well, so that the mixed
+    // path is never less accurate than the refined float64 solution
+    int outcome = STALLED;
+    TRY(refine(h, P, nF, x, y, o, spmv_bytes, fp32, l_bytes, info, &outcome));
+    if (outcome == REPORT) return NNLS_OK;          // reported by the next control step
+    if (outcome == REFINED) {
       *y_done = true;
       return NNLS_OK;
     }
+    if (!fp32) return NNLS_OK;   // the float64 factor does not contract either: keep x_F
     fp32 = false;
   }
   return NNLS_OK;
@@ -430,6 +457,11 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
   const double ctrl_bytes = 2.0 * 17.0 * n;
   const double spmv_bytes = P.sparse ? (2.0 * 12.0 * (double)P.nnz + 32.0 * m + 24.0 * n)
                                      : (2.0 * 8.0 * (double)m * n + 32.0 * m + 24.0 * n);
+  // NNLS_FLAG_REFINE_FINAL: once a split is feasible, refine its x_F in float64 against the
+  // residual from A with the split's own factor, and classify the refined x and y again
+  const bool final_refine = (o.flags & NNLS_FLAG_REFINE_FINAL) != 0 && o.precision == NNLS_FP64;
+  bool refined = false;
+  int last_nF = 0;
   for (;;) {
     int64_t pe = prof_begin(h, NNLS_PROF_CONTROL);
     launch_pivot_control(h->stream, n, x, y, flags, Flist, pos, ctrl, o.tau, o.p_max, max_iter,
@@ -437,7 +469,25 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
     prof_end(h, pe, ctrl_bytes);
     TRY(sync_read(h, h->h_ctrl, ctrl, sizeof(Ctrl)));
     const Ctrl c = *h->h_ctrl;
-    if (c.status != 0 || c.done) break;
+    if (c.status != 0) break;
+    if (c.done) {
+      if (!final_refine || refined || last_nF == 0) break;
+      int outcome = STALLED;
+      const double l_bytes = 8.0 * (double)tile_count((last_nF + TILE - 1) / TILE) * TILE_ELEMS;
+      TRY(refine(h, P, last_nF, x, y, o, spmv_bytes, false, l_bytes, info, &outcome));
+      if (outcome == REPORT) {       // keep the split; the control step reports the status
+        refined = true;
+        continue;
+      }
+      if (outcome != REFINED) {
+        pe = prof_begin(h, NNLS_PROF_RESIDUAL);
+        residual_dual(h, P, x, y, nullptr);
+        prof_end(h, pe, spmv_bytes);
+      }
+      refined = true;
+      continue;
+    }
+    refined = false;
     nnls_trace_row row;
     row.k = c.k;
     row.branch = c.branch;
@@ -447,6 +497,7 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
     row.reserved = 0;
     h->trace.push_back(row);
     const int nF = c.n_free;
+    last_nF = nF;
     bool y_done = false;
     if (nF > 0) TRY(solve_free(h, P, nF, x, y, o, spmv_bytes, &y_done, info));
     if (!y_done) {

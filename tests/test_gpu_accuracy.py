@@ -72,6 +72,24 @@ def test_mixed_error_no_worse_than_normal_equations(h):
         assert gpu < oracle_median(probs) + 1.0, (lkap, gpu)
 
 
+def test_mixed_single_problem_path_refines_after_fallback(h):
+    """Above kappa ~ 1e3.5 the float32 factor no longer contracts and the iteration is
+    redone with a float64 factor, which is then refined as well: the mixed single-problem
+    path keeps the accuracy of the refined float64 solution."""
+    for lkap in (4.0, 5.0, 6.0):
+        errs = []
+        for s in range(3):
+            A, xt, b = W.svd_conditioned(500 + s, 10 ** lkap)
+            x = torch.empty(A.shape[1], dtype=torch.float64, device=DEV)
+            y = torch.empty_like(x)
+            st, info = N.nnls_solve_dense(h, colmajor_dev(A), t(b), x, y,
+                                          N.default_options(precision=N.NNLS_FP32_IR))
+            assert st == N.NNLS_OK
+            errs.append(np.linalg.norm(x.cpu().numpy() - xt) / np.linalg.norm(xt))
+        slope, icpt = fig1_law()
+        assert np.median(np.log10(errs)) <= slope * lkap + icpt - 2.0, lkap
+
+
 def test_single_problem_path_matches_batched_accuracy(h):
     """The dense single-problem path (tiled factor, walker) gives errors of the same size."""
     slope, icpt = fig1_law()
@@ -85,3 +103,38 @@ def test_single_problem_path_matches_batched_accuracy(h):
             assert st == N.NNLS_OK
             errs.append(np.linalg.norm(x.cpu().numpy() - xt) / np.linalg.norm(xt))
         assert abs(np.median(np.log10(errs)) - (slope * lkap + icpt)) < 0.75, lkap
+
+
+def test_final_refinement_gains_orders_of_magnitude(h):
+    """NNLS_FLAG_REFINE_FINAL (the final recomputation of Sec. 3): float64 refinement of the
+    final x_F against the residual from A gains at least two orders of magnitude over the
+    normal equations where the paper's final step does (kappa 1e3 .. 1e6), and never loses."""
+    slope, icpt = fig1_law()
+    for lkap in (1.5, 3.0, 4.0, 5.0, 6.0):
+        plain, refd = [], []
+        for s in range(3):
+            A, xt, b = W.svd_conditioned(400 + s, 10 ** lkap)
+            for flags, out in ((0, plain), (N.NNLS_FLAG_REFINE_FINAL, refd)):
+                x = torch.empty(A.shape[1], dtype=torch.float64, device=DEV)
+                y = torch.empty_like(x)
+                st, info = N.nnls_solve_dense(h, colmajor_dev(A), t(b), x, y, N.default_options(flags=flags))
+                assert st == N.NNLS_OK
+                xh, yh = x.cpu().numpy(), y.cpu().numpy()
+                assert np.all(xh >= 0) and np.all(yh >= 0) and np.dot(xh, yh) == 0.0
+                out.append(np.linalg.norm(xh - xt) / np.linalg.norm(xt))
+        gp, gr = np.median(np.log10(plain)), np.median(np.log10(refd))
+        assert gr <= gp + 0.1, (lkap, gp, gr)
+        if lkap >= 3.0:
+            assert gr <= gp - 2.0, (lkap, gp, gr)
+
+
+def test_final_refinement_keeps_parity_on_sparse_workload(h):
+    inst = W.sparse_large(1002, m=6000, n=1200)
+    res = bpp_solve(inst.A, inst.b)
+    from _gpu_util import solve_csc
+    st, info, x, y, trace = solve_csc(h, inst.A, inst.b, flags=N.NNLS_FLAG_REFINE_FINAL)
+    assert st == N.NNLS_OK
+    assert np.array_equal(x > 0, inst.active) and np.array_equal(x > 0, res.x > 0)
+    assert np.linalg.norm(x - res.x) <= 1e-10 * np.linalg.norm(res.x)
+    assert np.linalg.norm(x - inst.x_star) <= np.linalg.norm(res.x - inst.x_star) + 1e-14 * np.linalg.norm(inst.x_star)
+    assert info.ir_steps >= 1
