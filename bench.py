@@ -34,6 +34,10 @@ def make_instance(name: str):
     if name == "sparse_large":
         return W.sparse_large(1002), ("sparse m=60000 n=12000, 25 N(0,1)/col + band(5,2.5,1.25), "
                                       "30% active, margin 1e-3, seed 1002")
+    if name == "sparse_xl":
+        return W.sparse_blockband(1005), ("sparse m=400000 n=50000, 20 N(0,1)/col + block band (rows "
+                                          "[8j, 8j+64) N(0,1), A[8j,j] += sqrt(84)), 25% active, margin "
+                                          "1e-3, seed 1005")
     if name == "sparse_small":
         return W.sparse_small(1001), ("sparse m=2000 n=400, Bernoulli(0.02) N(0,1) + diag, "
                                       "50% active, margin 0.1, seed 1001")

@@ -256,6 +256,25 @@ def test_mixed_sparse_large_full_size(h):
     check_mixed(res, st, info, x, y, trace)
 
 
+@pytest.fixture(scope="module")
+def blockband():
+    return W.sparse_blockband(1005)
+
+
+@pytest.mark.parametrize("precision,tol", [(N.NNLS_FP64, 1e-10), (N.NNLS_FP32_IR, 1e-8)])
+def test_large_blockband_full_size(h, blockband, precision, tol):
+    """The large sparse instance (m = 400000, n = 50000, block band, 25% active) at full
+    size: the free set is the planted one and x is the planted x* (an exact NNLS solution
+    by construction, to the z-solve's accuracy) within the path's tolerance."""
+    inst = blockband
+    st, info, x, y, trace = solve_csc(h, inst.A, inst.b, precision=precision)
+    assert st == N.NNLS_OK, N.status_string(st)
+    assert np.array_equal(x > 0, inst.active)
+    assert info.n_free == int(inst.active.sum())
+    assert relerr(x, inst.x_star) <= tol
+    assert np.all(x >= 0) and np.all(y >= 0) and np.dot(x, y) == 0.0
+
+
 @pytest.mark.parametrize("seed", range(1, 21))
 def test_mixed_ill_scaled_falls_back(h, seed):
     """Ill-scaled problems where a float32 factor may break down or refinement may stall:
