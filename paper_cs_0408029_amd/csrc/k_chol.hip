@@ -122,42 +122,84 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
   const int kend = (I == J) ? max(J - 1, 0) : J;
   const bool fwd = (I == J) && (a.rhs != nullptr);
   double tacc = 0.0;                         // row `lane`, columns 16 w .. 16 w + 15
-  int known = 0;                             // leading columns this wave knows are complete
+  // Software pipeline: the tiles of step k sit in LDS (S takes L_Ik, W takes L_Jk; neither
+  // is needed during the update) while the loads of step k+1 are in flight in registers.
+  // Step k+1 is prefetched only when its tiles are already known to be final; at the
+  // frontier its loads wait until step k's products are issued.
+  T* SA = S;
+  T* SB = (I == J) ? S : W;
+  T ra[TILE_ELEMS / 256], rb[TILE_ELEMS / 256];
+  int known = 0;                             // leading columns this thread knows are complete
+  auto ready = [&](int k1, bool block) -> bool {
+    if (k1 < known) return true;
+    if (ld_relaxed(&a.colcnt[k1]) >= nb - k1) {
+      known = k1 + 1;
+      while (known < J && ld_relaxed(&a.colcnt[known]) >= nb - known) ++known;
+    } else if (!block) {
+      if (ld_relaxed(&a.tflag[tile_index(I, k1, nb)]) != a.epoch) return false;
+      if (I != J && ld_relaxed(&a.tflag[tile_index(J, k1, nb)]) != a.epoch) return false;
+    } else {
+      // at the frontier: wait only for the two tiles this step reads
+      spin_until(&a.tflag[tile_index(I, k1, nb)], a.epoch, true, a.ctrl, wait_ticks);
+      if (I != J) spin_until(&a.tflag[tile_index(J, k1, nb)], a.epoch, true, a.ctrl, wait_ticks);
+    }
+    acquire_agent();
+    return true;
+  };
+  auto load = [&](int k1) {
+    const T* gi = Lt + tile_index(I, k1, nb) * TILE_ELEMS;
+#pragma unroll
+    for (int q = 0; q < TILE_ELEMS / 256; ++q) ra[q] = gi[tid + q * 256];
+    if (I != J) {
+      const T* gj = Lt + tile_index(J, k1, nb) * TILE_ELEMS;
+#pragma unroll
+      for (int q = 0; q < TILE_ELEMS / 256; ++q) rb[q] = gj[tid + q * 256];
+    }
+  };
+  if (kend > 0) {
+    ready(0, true);
+    load(0);
+  }
   for (int k = 0; k < kend; ++k) {
-    if (k >= known) {
-      if (ld_relaxed(&a.colcnt[k]) >= nb - k) {
-        known = k + 1;
-        while (known < J && ld_relaxed(&a.colcnt[known]) >= nb - known) ++known;
-      } else {
-        // at the frontier: wait only for the two tiles this step reads
-        spin_until(&a.tflag[tile_index(I, k, nb)], a.epoch, true, a.ctrl, wait_ticks);
-        if (I != J) spin_until(&a.tflag[tile_index(J, k, nb)], a.epoch, true, a.ctrl, wait_ticks);
-      }
-      acquire_agent();
+    __syncthreads();   // the previous step's products (or the accumulator set-up) have read LDS
+#pragma unroll
+    for (int q = 0; q < TILE_ELEMS / 256; ++q) {
+      const int e = tid + q * 256, o = (e & (TILE - 1)) + (e >> 6) * LDT;
+      SA[o] = ra[q];
+      if (I != J) SB[o] = rb[q];
+    }
+    __syncthreads();
+    bool pre = false;
+    if (k + 1 < kend) {
+      pre = ready(k + 1, false);
+      if (pre) load(k + 1);
     }
     if (fwd) {
-      const T* LJk = Lt + tile_index(J, k, nb) * TILE_ELEMS;
       const double* zk = a.z + (int64_t)k * TILE;
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int cc = w * 16 + q;
-        tacc = fma((double)LJk[cc * TILE + lane], zk[cc], tacc);
+        tacc = fma((double)SB[lane + cc * LDT], zk[cc], tacc);
       }
     }
-    if (skip) continue;
-    const T* LI = Lt + tile_index(I, k, nb) * TILE_ELEMS;
-    const T* LJ = Lt + tile_index(J, k, nb) * TILE_ELEMS;
+    if (!skip) {
 #pragma unroll
-    for (int kk = 0; kk < TILE; kk += 4) {
-      const int col = (kk + lk) * TILE;
-      const T a0 = -LI[col + qr + lr], a1 = -LI[col + qr + 16 + lr];
-      const T b0 = LJ[col + qc + lr], b1 = LJ[col + qc + 16 + lr];
-      acc[0][0] = M::op(a0, b0, acc[0][0]);
-      acc[0][1] = M::op(a0, b1, acc[0][1]);
-      acc[1][0] = M::op(a1, b0, acc[1][0]);
-      acc[1][1] = M::op(a1, b1, acc[1][1]);
+      for (int kk = 0; kk < TILE; kk += 4) {
+        const int col = (kk + lk) * LDT;
+        const T a0 = -SA[col + qr + lr], a1 = -SA[col + qr + 16 + lr];
+        const T b0 = SB[col + qc + lr], b1 = SB[col + qc + 16 + lr];
+        acc[0][0] = M::op(a0, b0, acc[0][0]);
+        acc[0][1] = M::op(a0, b1, acc[0][1]);
+        acc[1][0] = M::op(a1, b0, acc[1][0]);
+        acc[1][1] = M::op(a1, b1, acc[1][1]);
+      }
+    }
+    if (k + 1 < kend && !pre) {
+      ready(k + 1, true);
+      load(k + 1);
     }
   }
+  __syncthreads();   // the last products have read S and W
 
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
