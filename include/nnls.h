@@ -66,6 +66,10 @@ typedef enum {
                                      refinement against the residual from A with the split's
                                      cached factor, then classify the refined x and y again
                                      (pivoting resumes if that finds infeasible entries)    */
+#define NNLS_FLAG_NO_FACTOR_REUSE 4u /* refactor the whole F-block in every pivot
+                                     iteration.  By default F is ordered so that the leading
+                                     tile columns no exchange touched come first, and their
+                                     factor tiles (exact for that leading block) are kept    */
 
 typedef struct {
   double tau;           /* zeroing threshold; paper: 1e-12 (Sec. 2)                      */
@@ -101,7 +105,8 @@ typedef struct {
   int32_t N;        /* best count after the rule                                         */
   int32_t p;        /* remaining budget after the rule                                   */
   int32_t n_free;   /* |F| after the exchange                                            */
-  int32_t reserved;
+  int32_t n_reused; /* leading F positions whose factor tiles were kept from the previous
+                       iteration's factor (a multiple of 64; 0 when refactored whole)      */
 } nnls_trace_row;
 
 typedef struct nnls_handle nnls_handle;

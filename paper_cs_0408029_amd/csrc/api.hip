@@ -45,11 +45,16 @@ struct nnls_handle {
   // workspace
   DevBuf err, ctrl, rowcnt, rowptr, colidx, valr, hptr, hcnt, hrow, hval, c, r, flags, Flist, pos;
   DevBuf Lt, Dinv, colcnt, dflag, tflag, z, xF, Hd, gF, rpart, spart, spflag;
+  DevBuf upcnt, prow, pval, pcnt, Fold, zr;   // F-position Gram lists, order scratch, refinement z
   DevBuf bprobs, border, binfo, bws;   // batched dense problems
   Ctrl* h_ctrl = nullptr;     // pinned
   int64_t* h_scalar = nullptr;  // pinned scratch for small reads
   int epoch = 0;
   int trsv_tag = 0;           // flag values of the triangular-solve hand-overs, never reused
+  // precision of the factor tiles that belong to the current F order (and the forward-solve
+  // blocks with them): 0 float64, 1 float32, -1 none; the next factor of the same
+  // precision may keep their untouched leading columns
+  int fact_prec = -1;
   std::vector<nnls_trace_row> trace;
   // profiling
   bool profiling = false;
@@ -209,7 +214,26 @@ int build_csr(nnls_handle* h, const Problem& P) {
   return NNLS_OK;
 }
 
-// Gram matrix (lower, padded CSC) and c = A^T b for a validated CSC problem.
+GramLower gram_view(nnls_handle* h) {
+  GramLower g;
+  g.hptr = (const int64_t*)h->hptr.p;
+  g.hcnt = (const int32_t*)h->hcnt.p;
+  g.hrow = (const int32_t*)h->hrow.p;
+  g.hval = (const double*)h->hval.p;
+  return g;
+}
+
+GramPos gram_pos_view(nnls_handle* h) {
+  GramPos g;
+  g.pptr = (const int64_t*)h->hptr.p;
+  g.pcnt = (const int32_t*)h->pcnt.p;
+  g.prow = (const int32_t*)h->prow.p;
+  g.pval = (const double*)h->pval.p;
+  return g;
+}
+
+// Gram matrix (lower, padded CSC, then whole columns) and c = A^T b for a validated CSC
+// problem.
 int build_gram_sparse(nnls_handle* h, const Problem& P) {
   TRY(build_csr(h, P));
   TRY(ensure(h, h->hptr, sizeof(int64_t) * ((size_t)P.n + 1)));
@@ -222,6 +246,13 @@ int build_gram_sparse(nnls_handle* h, const Problem& P) {
   launch_gram_lower(h->stream, P.n, P.colptr, P.rowidx, P.val, (const int32_t*)h->rowptr.p,
                     (const int32_t*)h->colidx.p, (const double*)h->valr.p, (const int64_t*)h->hptr.p,
                     (int32_t*)h->hcnt.p, (int32_t*)h->hrow.p, (double*)h->hval.p);
+  // whole columns (upper entries appended) and room for the F-position lists
+  TRY(ensure(h, h->upcnt, sizeof(int32_t) * (size_t)P.n));
+  TRY(ensure(h, h->pcnt, sizeof(int32_t) * (size_t)P.n));
+  TRY(ensure(h, h->prow, sizeof(int32_t) * (size_t)ub));
+  TRY(ensure(h, h->pval, sizeof(double) * (size_t)ub));
+  launch_fill_i32(h->stream, (int32_t*)h->upcnt.p, P.n, 0);
+  launch_gram_mirror(h->stream, P.n, gram_view(h), (int32_t*)h->upcnt.p, (int32_t*)h->hrow.p, (double*)h->hval.p);
   TRY(ensure(h, h->c, sizeof(double) * (size_t)P.n));
   launch_spmvT_csc(h->stream, P.n, P.colptr, P.rowidx, P.val, P.b, (double*)h->c.p, 1.0);
   return NNLS_OK;
@@ -236,41 +267,36 @@ int build_gram_dense(nnls_handle* h, const Problem& P) {
   return NNLS_OK;
 }
 
-GramLower gram_view(nnls_handle* h) {
-  GramLower g;
-  g.hptr = (const int64_t*)h->hptr.p;
-  g.hcnt = (const int32_t*)h->hcnt.p;
-  g.hrow = (const int32_t*)h->hrow.p;
-  g.hval = (const double*)h->hval.p;
-  return g;
-}
-
-// Factor-and-solve workspace for an F-block of order nF.
-int ensure_factor(nnls_handle* h, int nF, bool fp32) {
+// Factor-and-solve workspace for an F-block of order nF.  *lost (optional) is set when the
+// tiles, inverted diagonal tiles or forward-solve blocks had to be reallocated.
+int ensure_factor(nnls_handle* h, int nF, bool fp32, bool* lost = nullptr) {
   const int nb = (nF + TILE - 1) / TILE;
   const size_t w = fp32 ? sizeof(float) : sizeof(double);
   const size_t ntiles = (size_t)tile_count(nb);
+  const void* before[3] = {h->Lt.p, h->Dinv.p, h->z.p};
   TRY(ensure(h, h->Lt, ntiles * TILE_ELEMS * w));
   TRY(ensure(h, h->Dinv, (size_t)nb * TILE_ELEMS * w));
   TRY(ensure(h, h->colcnt, (size_t)nb * sizeof(int32_t), true));
   TRY(ensure(h, h->dflag, (size_t)nb * sizeof(int32_t), true));
   TRY(ensure(h, h->tflag, ntiles * sizeof(int32_t), true));
   TRY(ensure(h, h->z, (size_t)nb * TILE * sizeof(double)));
+  TRY(ensure(h, h->zr, (size_t)nb * TILE * sizeof(double)));
   TRY(ensure(h, h->xF, (size_t)nb * TILE * sizeof(double)));
   TRY(ensure(h, h->spart, (size_t)nb * TILE * sizeof(double)));
   TRY(ensure(h, h->spflag, (size_t)nb * sizeof(int32_t), true));
+  if (lost) *lost = before[0] != h->Lt.p || before[1] != h->Dinv.p || before[2] != h->z.p;
   return NNLS_OK;
 }
 
-FactorArgs factor_args(nnls_handle* h, int nF, const int32_t* Flist, const int32_t* pos,
-                       const double* dense, int64_t ldd, bool sparse) {
+FactorArgs factor_args(nnls_handle* h, int nF, const int32_t* Flist, const double* dense, int64_t ldd,
+                       bool sparse) {
   FactorArgs a;
   std::memset(&a, 0, sizeof(a));
   a.nF = nF;
   a.nb = (nF + TILE - 1) / TILE;
+  a.j0 = 0;
   a.Flist = Flist;
-  a.pos = pos;
-  if (sparse) a.lower = gram_view(h);
+  if (sparse) a.gpos = gram_pos_view(h);
   a.dense = dense;
   a.ldd = ldd;
   a.Ltiles = h->Lt.p;
@@ -313,6 +339,8 @@ SolveArgs solve_args(nnls_handle* h, int nF, const int32_t* Flist, const double*
 }
 
 double chol_flops(double nF) { return nF * nF * nF / 3.0; }
+// flops of a factor that keeps its leading p0 columns
+double chol_flops_from(double nF, double p0) { return (nF * nF * nF - p0 * p0 * p0) / 3.0; }
 
 // Eq. 5: r = A x - b, then y_G = A_G^T r (y_F = 0); with gfree also A_F^T r on F.
 void residual_dual(nnls_handle* h, const Problem& P, const double* x, double* y, double* gfree) {
@@ -354,6 +382,7 @@ int refine(nnls_handle* h, const Problem& P, int nF, double* x, double* y, const
     pe = prof_begin(h, NNLS_PROF_REFINE);
     launch_reset_tickets(h->stream, ctrl);
     SolveArgs ca = solve_args(h, nF, Flist, gF, nullptr);
+    ca.z = (double*)h->zr.p;   // the factor's own forward-solve blocks stay for the next factor
     launch_trsv(h->stream, ca, fp32, true);
     launch_ir_update(h->stream, nF, Flist, (const double*)h->xF.p, x, ctrl);
     prof_end(h, pe, 2.0 * l_bytes);
@@ -395,23 +424,32 @@ int refine(nnls_handle* h, const Problem& P, int nF, double* x, double* y, const
 // relative to x_F; if it stalls or the step cap is reached, the iteration is redone with a
 // float64 factor (and refined with it).  *y_done is set when the last refinement pass
 // already left y_G for the final x.
-int solve_free(nnls_handle* h, const Problem& P, int nF, double* x, double* y, const nnls_options& o,
-               double spmv_bytes, bool* y_done, nnls_info* info) {
+// j0: leading tile columns the control step kept from the previous factor (the first
+// attempt may use them; *j0_used reports what it did).
+int solve_free(nnls_handle* h, const Problem& P, int nF, int j0, double* x, double* y, const nnls_options& o,
+               double spmv_bytes, bool* y_done, int* j0_used, nnls_info* info) {
   const int32_t* Flist = (const int32_t*)h->Flist.p;
-  const int32_t* pos = (const int32_t*)h->pos.p;
-  Ctrl* ctrl = (Ctrl*)h->ctrl.p;
   bool fp32 = o.precision == NNLS_FP32_IR;
   *y_done = false;
+  *j0_used = 0;
+  if (P.sparse)
+    launch_gram_positions(h->stream, nF, gram_view(h), (const int32_t*)h->upcnt.p, Flist,
+                          (const int32_t*)h->pos.p, (int32_t*)h->pcnt.p, (int32_t*)h->prow.p,
+                          (double*)h->pval.p);
   for (int attempt = 0; attempt < 2; ++attempt) {
-    TRY(ensure_factor(h, nF, fp32));
+    bool lost = false;
+    TRY(ensure_factor(h, nF, fp32, &lost));
     h->epoch += 1;
-    FactorArgs fa = factor_args(h, nF, Flist, pos, P.sparse ? nullptr : (const double*)h->Hd.p,
+    FactorArgs fa = factor_args(h, nF, Flist, P.sparse ? nullptr : (const double*)h->Hd.p,
                                 P.sparse ? 0 : P.n, P.sparse);
+    fa.j0 = (attempt == 0 && !lost && h->fact_prec == (fp32 ? 1 : 0)) ? std::min(j0, fa.nb - 1) : 0;
+    if (attempt == 0) *j0_used = fa.j0;
     fa.rhs = (const double*)h->c.p;
     fa.z = (double*)h->z.p;
     int64_t pe = prof_begin(h, NNLS_PROF_CHOLESKY);
     launch_cholesky(h->stream, fa, fp32);
-    prof_end(h, pe, chol_flops(nF));
+    prof_end(h, pe, chol_flops_from(nF, (double)fa.j0 * TILE));
+    h->fact_prec = fp32 ? 1 : 0;
     const double l_bytes = (fp32 ? 4.0 : 8.0) * (double)tile_count(fa.nb) * TILE_ELEMS;
     SolveArgs sa = solve_args(h, nF, Flist, (const double*)h->c.p, x);
     pe = prof_begin(h, NNLS_PROF_TRSV);
@@ -441,9 +479,13 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
   TRY(ensure(h, h->flags, (size_t)n));
   TRY(ensure(h, h->Flist, sizeof(int32_t) * (size_t)n));
   TRY(ensure(h, h->pos, sizeof(int32_t) * (size_t)n));
+  TRY(ensure(h, h->Fold, sizeof(int32_t) * (size_t)n));
   TRY(ensure(h, h->r, sizeof(double) * (size_t)m));
   TRY(ensure(h, h->ctrl, sizeof(Ctrl)));
   const int ncol = (n + TILE - 1) / TILE;
+  h->fact_prec = -1;
+  const int want_prec = o.precision == NNLS_FP32_IR ? 1 : 0;
+  const bool reuse = (o.flags & NNLS_FLAG_NO_FACTOR_REUSE) == 0;
   TRY(ensure(h, h->colcnt, sizeof(int32_t) * (size_t)ncol, true));
   TRY(ensure(h, h->dflag, sizeof(int32_t) * (size_t)ncol, true));
   const int max_iter = o.max_iter > 0 ? o.max_iter : 5 * n + 100;
@@ -464,8 +506,11 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
   int last_nF = 0;
   for (;;) {
     int64_t pe = prof_begin(h, NNLS_PROF_CONTROL);
+    // ordered F; the previous factor's untouched leading tiles are kept when its
+    // precision is the one the next factor starts in
     launch_pivot_control(h->stream, n, x, y, flags, Flist, pos, ctrl, o.tau, o.p_max, max_iter,
-                         (int32_t*)h->colcnt.p, ncol);
+                         (int32_t*)h->colcnt.p, ncol, (int32_t*)h->Fold.p,
+                         reuse && h->fact_prec == want_prec ? 2 : 1);
     prof_end(h, pe, ctrl_bytes);
     TRY(sync_read(h, h->h_ctrl, ctrl, sizeof(Ctrl)));
     const Ctrl c = *h->h_ctrl;
@@ -494,12 +539,14 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
     row.N = c.N;
     row.p = c.p;
     row.n_free = c.n_free;
-    row.reserved = 0;
-    h->trace.push_back(row);
+    row.n_reused = 0;
     const int nF = c.n_free;
     last_nF = nF;
     bool y_done = false;
-    if (nF > 0) TRY(solve_free(h, P, nF, x, y, o, spmv_bytes, &y_done, info));
+    int j0_used = 0;
+    if (nF > 0) TRY(solve_free(h, P, nF, c.j0, x, y, o, spmv_bytes, &y_done, &j0_used, info));
+    row.n_reused = j0_used * TILE;
+    h->trace.push_back(row);
     if (!y_done) {
       pe = prof_begin(h, NNLS_PROF_RESIDUAL);
       residual_dual(h, P, x, y, nullptr);
@@ -573,9 +620,11 @@ void release_workspace(nnls_handle* h) {
   if (!h) return;
   (void)hipSetDevice(h->device);
   (void)hipStreamSynchronize(h->stream);
+  h->fact_prec = -1;
   DevBuf* bufs[] = {&h->err, &h->ctrl, &h->rowcnt, &h->rowptr, &h->colidx, &h->valr, &h->hptr,
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
                     &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart, &h->spart, &h->spflag,
+                    &h->upcnt, &h->prow, &h->pval, &h->pcnt, &h->Fold, &h->zr,
                     &h->bprobs, &h->border, &h->binfo, &h->bws};
   for (DevBuf* b : bufs) {
     if (b->p) (void)hipFree(b->p);
@@ -651,6 +700,7 @@ int nnls_destroy(nnls_handle* h) {
   DevBuf* bufs[] = {&h->err, &h->ctrl, &h->rowcnt, &h->rowptr, &h->colidx, &h->valr, &h->hptr,
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
                     &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart, &h->spart, &h->spflag,
+                    &h->upcnt, &h->prow, &h->pval, &h->pcnt, &h->Fold, &h->zr,
                     &h->bprobs, &h->border, &h->binfo, &h->bws};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
@@ -867,7 +917,8 @@ int nnls_cholesky(nnls_handle* h, int32_t n, const double* S, int32_t lds, doubl
   launch_fill_i32(h->stream, (int32_t*)h->colcnt.p, (n + TILE - 1) / TILE, 0);
   h->epoch += 1;
   h->max_wgs = h->default_wgs;
-  FactorArgs fa = factor_args(h, n, nullptr, nullptr, S, lds, false);
+  h->fact_prec = -1;
+  FactorArgs fa = factor_args(h, n, nullptr, S, lds, false);
   launch_cholesky(h->stream, fa, fp32);
   launch_tiles_to_dense(h->stream, n, fa.nb, h->Lt.p, fp32, L, ldl);
   TRY(sync_read(h, h->h_ctrl, h->ctrl.p, sizeof(Ctrl)));
@@ -890,7 +941,8 @@ int nnls_spd_solve(nnls_handle* h, int32_t n, const double* S, int32_t lds, cons
   launch_fill_i32(h->stream, (int32_t*)h->colcnt.p, (n + TILE - 1) / TILE, 0);
   h->epoch += 1;
   h->max_wgs = h->default_wgs;
-  FactorArgs fa = factor_args(h, n, nullptr, nullptr, S, lds, false);
+  h->fact_prec = -1;
+  FactorArgs fa = factor_args(h, n, nullptr, S, lds, false);
   fa.rhs = rhs;
   fa.z = (double*)h->z.p;
   launch_cholesky(h->stream, fa, false);
@@ -980,9 +1032,10 @@ int nnls_pivot_step(nnls_handle* h, int32_t n, double* x, double* y, uint8_t* fr
   const int N = state[0] < 0 ? INT32_MAX : state[0];
   launch_ctrl_set_state(h->stream, (Ctrl*)h->ctrl.p, N, state[1], 0, 0);
   TRY(ensure(h, h->colcnt, sizeof(int32_t) * (size_t)((n + TILE - 1) / TILE), true));
+  h->fact_prec = -1;
   launch_pivot_control(h->stream, n, x, y, free_flags, (int32_t*)h->Flist.p, (int32_t*)h->pos.p,
                        (Ctrl*)h->ctrl.p, tau, p_max, INT32_MAX, (int32_t*)h->colcnt.p,
-                       (n + TILE - 1) / TILE);
+                       (n + TILE - 1) / TILE, nullptr, 0);
   TRY(sync_read(h, h->h_ctrl, h->ctrl.p, sizeof(Ctrl)));
   const Ctrl c = *h->h_ctrl;
   state[0] = c.N == INT32_MAX ? -1 : c.N;

@@ -173,8 +173,8 @@ __device__ __noinline__ void wg_factor(const double* __restrict__ H, int n, cons
       const bool skip = (I == J) && (qr < qc);
       if (!skip)
         for (int k = 0; k < J; ++k) {
-          const T* LI = Lt + tile_index(I, k, nb) * TILE_ELEMS;
-          const T* LJ = Lt + tile_index(J, k, nb) * TILE_ELEMS;
+          const T* LI = Lt + tile_index(I, k) * TILE_ELEMS;
+          const T* LJ = Lt + tile_index(J, k) * TILE_ELEMS;
 #pragma unroll
           for (int kk = 0; kk < TILE; kk += 4) {
             const int col = (kk + lk) * TILE;
@@ -194,7 +194,7 @@ __device__ __noinline__ void wg_factor(const double* __restrict__ H, int n, cons
           for (int v = 0; v < 4; ++v)
             S[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT] = acc[bi][bj][v];
       __syncthreads();
-      T* dst = Lt + tile_index(I, J, nb) * TILE_ELEMS;
+      T* dst = Lt + tile_index(I, J) * TILE_ELEMS;
       if (I == J) {
         PivotReport rep = rep0;
         rep.base = J * TILE;
@@ -249,7 +249,7 @@ __device__ __noinline__ void wg_solve(const T* Lt, const T* Dv, int nF, const do
   for (int I = 0; I < nb; ++I) {
     double acc = 0.0;
     for (int k = 0; k < I; ++k) {
-      const T* tl = Lt + tile_index(I, k, nb) * TILE_ELEMS;
+      const T* tl = Lt + tile_index(I, k) * TILE_ELEMS;
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int cc = g * 16 + q;
@@ -278,7 +278,7 @@ __device__ __noinline__ void wg_solve(const T* Lt, const T* Dv, int nF, const do
   for (int I = nb - 1; I >= 0; --I) {
     double acc = 0.0;
     for (int k = nb - 1; k > I; --k) {
-      const T* tl = Lt + tile_index(k, I, nb) * TILE_ELEMS;
+      const T* tl = Lt + tile_index(k, I) * TILE_ELEMS;
       // (L_kI^T u_k)[c] for c = tid & 63, rows split over the four waves
 #pragma unroll
       for (int q = 0; q < 16; ++q) {

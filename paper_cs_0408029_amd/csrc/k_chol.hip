@@ -10,6 +10,12 @@
 // A diagonal tile is then factored and inverted in LDS; an off-diagonal tile becomes
 // L_IJ = S_IJ (L_JJ^-1)^T once the diagonal tile of its column is ready.
 //
+// Kept leading block: when the F order starts with j0 whole tile columns of the previous
+// factor (same positions, same variables), the tiles (I, J) with I < j0 and the inverted
+// diagonal tiles and forward-solve blocks of those columns are the previous launch's, and
+// only the rows I >= j0 are computed (tiles of the kept columns are plain off-diagonal
+// tiles; the walker starts at column j0).
+//
 // Dependencies: colcnt[J] counts the finished tiles of column J (complete at nb - J), and
 // every finished tile also sets its own ready flag.  Every tile of column J+1 needs all of
 // column J, so columns complete in order; each wave caches how many leading columns it
@@ -63,22 +69,19 @@ __device__ inline void gather_tile(const FactorArgs& a, int tid, int I, int J, T
     for (int e = tid; e < TILE_ELEMS; e += 256) S[(e & (TILE - 1)) + (e >> 6) * LDT] = (T)0;
     __syncthreads();
     if (tid < TILE) {
+      // position q's list holds the rows p >= q in ascending order: find p >= r0
       const int c = tid, q = c0 + c;
-      const int phi = min(r0 + TILE, a.nF) - 1;
-      if (q < a.nF && r0 <= phi) {
-        const int j = a.Flist[q];
-        const int lo = a.Flist[r0], hi = a.Flist[phi];
-        const int64_t s = a.lower.hptr[j], e = s + a.lower.hcnt[j];
+      if (q < a.nF && r0 < a.nF) {
+        const int64_t s = a.gpos.pptr[a.Flist[q]], e = s + a.gpos.pcnt[q];
         int64_t L = s, R = e;
         while (L < R) {
           const int64_t M = (L + R) >> 1;
-          if (a.lower.hrow[M] < lo) L = M + 1; else R = M;
+          if (a.gpos.prow[M] < r0) L = M + 1; else R = M;
         }
         for (int64_t t = L; t < e; ++t) {
-          const int i = a.lower.hrow[t];
-          if (i > hi) break;
-          const int p = a.pos[i];
-          if (p >= 0) S[(p - r0) + c * LDT] = (T)a.lower.hval[t];
+          const int p = a.gpos.prow[t];
+          if (p >= r0 + TILE) break;
+          S[(p - r0) + c * LDT] = (T)a.gpos.pval[t];
         }
       } else if (q >= a.nF && I == J) {
         S[c + c * LDT] = (T)1;
@@ -88,14 +91,14 @@ __device__ inline void gather_tile(const FactorArgs& a, int tid, int I, int J, T
   __syncthreads();
 }
 
-// One lower tile (I, J) with ticket t; S, W, s_part, s_rhs are the workgroup's LDS.
+// One lower tile (I, J), I >= j0; S, W, s_part, s_rhs are the workgroup's LDS.
 template <typename T>
-__device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_ticks, int tid, int t, int I, int J,
+__device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_ticks, int tid, int I, int J,
                                           T* S, T* W, double (*s_part)[TILE], double* s_rhs) {
   typedef MF<T> M;
   typedef typename M::acc Acc;
   const int lane = tid & 63, w = tid >> 6;
-  const int nb = a.nb;
+  const int nb = a.nb, j0 = a.j0;
   T* Lt = (T*)a.Ltiles;
   T* Dv = (T*)a.Dinv;
 
@@ -114,12 +117,14 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
 
   const bool skip = (I == J) && (qr < qc);   // upper quadrant of a diagonal tile
   // The diagonal tile stops one step short: the walker applies the last term, L_{J,J-1}
-  // being its own output.  The sub-diagonal tile runs its whole update and leaves the
-  // triangular solve with L_JJ to the walker.  The diagonal tile also runs the forward
-  // solve L z = c_F for its block up to its last step: it streams every L_Jk anyway, and
-  // z_k is published before column k completes.
-  const bool partial = (I - J <= 1);
-  const int kend = (I == J) ? max(J - 1, 0) : J;
+  // being its own output (except in the walker's first column j0).  The sub-diagonal tile
+  // runs its whole update and leaves the triangular solve with L_JJ to the walker.  The
+  // diagonal tile also runs the forward solve L z = c_F for its block up to its last step:
+  // it streams every L_Jk anyway, and z_k is published before column k completes.  Tiles
+  // of the kept columns (J < j0) read L_Jk and L_JJ^-1 from the previous launch.
+  const bool partial = (I - J <= 1) && (J >= j0);
+  const int kend = (I == J && J > j0) ? J - 1 : J;
+  const bool needJ = (I != J) && (J >= j0);   // L_Jk is computed in this launch
   const bool fwd = (I == J) && (a.rhs != nullptr);
   double tacc = 0.0;                         // row `lane`, columns 16 w .. 16 w + 15
   // Software pipeline: the tiles of step k sit in LDS (S takes L_Ik, W takes L_Jk; neither
@@ -130,28 +135,29 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
   T* SB = (I == J) ? S : W;
   T ra[TILE_ELEMS / 256], rb[TILE_ELEMS / 256];
   int known = 0;                             // leading columns this thread knows are complete
+  // column k is complete when its nb - max(k, j0) computed tiles are
   auto ready = [&](int k1, bool block) -> bool {
     if (k1 < known) return true;
-    if (ld_relaxed(&a.colcnt[k1]) >= nb - k1) {
+    if (ld_relaxed(&a.colcnt[k1]) >= nb - max(k1, j0)) {
       known = k1 + 1;
-      while (known < J && ld_relaxed(&a.colcnt[known]) >= nb - known) ++known;
+      while (known < J && ld_relaxed(&a.colcnt[known]) >= nb - max(known, j0)) ++known;
     } else if (!block) {
-      if (ld_relaxed(&a.tflag[tile_index(I, k1, nb)]) != a.epoch) return false;
-      if (I != J && ld_relaxed(&a.tflag[tile_index(J, k1, nb)]) != a.epoch) return false;
+      if (ld_relaxed(&a.tflag[tile_index(I, k1)]) != a.epoch) return false;
+      if (needJ && ld_relaxed(&a.tflag[tile_index(J, k1)]) != a.epoch) return false;
     } else {
-      // at the frontier: wait only for the two tiles this step reads
-      spin_until(&a.tflag[tile_index(I, k1, nb)], a.epoch, true, a.ctrl, wait_ticks);
-      if (I != J) spin_until(&a.tflag[tile_index(J, k1, nb)], a.epoch, true, a.ctrl, wait_ticks);
+      // at the frontier: wait only for the tiles this step reads
+      spin_until(&a.tflag[tile_index(I, k1)], a.epoch, true, a.ctrl, wait_ticks);
+      if (needJ) spin_until(&a.tflag[tile_index(J, k1)], a.epoch, true, a.ctrl, wait_ticks);
     }
     acquire_agent();
     return true;
   };
   auto load = [&](int k1) {
-    const T* gi = Lt + tile_index(I, k1, nb) * TILE_ELEMS;
+    const T* gi = Lt + tile_index(I, k1) * TILE_ELEMS;
 #pragma unroll
     for (int q = 0; q < TILE_ELEMS / 256; ++q) ra[q] = gi[tid + q * 256];
     if (I != J) {
-      const T* gj = Lt + tile_index(J, k1, nb) * TILE_ELEMS;
+      const T* gj = Lt + tile_index(J, k1) * TILE_ELEMS;
 #pragma unroll
       for (int q = 0; q < TILE_ELEMS / 256; ++q) rb[q] = gj[tid + q * 256];
     }
@@ -210,7 +216,8 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
         S[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT] = acc[bi][bj][v];
   __syncthreads();
 
-  T* dst = Lt + (int64_t)t * TILE_ELEMS;
+  const int64_t ti = tile_index(I, J);
+  T* dst = Lt + ti * TILE_ELEMS;
   if (partial) {
     // hand the partial sum (and the diagonal's partial forward-solve sums) to the walker
     if (fwd) s_part[w][lane] = tacc;
@@ -220,13 +227,15 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
       if (tid < TILE)
         a.z[(int64_t)J * TILE + tid] = ((s_part[0][tid] + s_part[1][tid]) + s_part[2][tid]) + s_part[3][tid];
     }
-    publish_store(&a.tflag[t], -a.epoch);
+    publish_store(&a.tflag[ti], -a.epoch);
     return;
   }
 
   // off-diagonal: L_IJ = S_IJ (L_JJ^-1)^T once the diagonal tile of column J is ready
-  spin_until(&a.dflag[J], a.epoch, true, a.ctrl, wait_ticks);
-  acquire_agent();
+  if (J >= j0) {
+    spin_until(&a.dflag[J], a.epoch, true, a.ctrl, wait_ticks);
+    acquire_agent();
+  }
   const T* D = Dv + (int64_t)J * TILE_ELEMS;
   Acc o[2][2];
 #pragma unroll
@@ -255,7 +264,7 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
         S[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT] = o[bi][bj][v];
   __syncthreads();
   for (int e = tid; e < TILE_ELEMS; e += 256) dst[e] = S[(e & (TILE - 1)) + (e >> 6) * LDT];
-  publish_tile(&a.tflag[t], &a.colcnt[J], a.epoch);
+  publish_tile(&a.tflag[ti], &a.colcnt[J], a.epoch);
 }
 
 // acc (MFMA accumulator layout of this wave's 32 x 32 quadrant) -= P Q^T, P from global
@@ -344,28 +353,28 @@ __device__ __forceinline__ void walker(const FactorArgs& a, uint64_t wait_ticks,
                                        double (*s_part)[TILE], double* s_rhs, double* s_z, double* s_tp) {
   typedef MF<T> M;
   typedef typename M::acc Acc;
-  const int nb = a.nb;
+  const int nb = a.nb, j0 = a.j0;
   const bool fwd = a.rhs != nullptr;
   T* Lt = (T*)a.Ltiles;
   T* Dv = (T*)a.Dinv;
-  T* X = Pbuf;   // L_{J,J-1} from the previous column (J >= 1)
+  T* X = Pbuf;   // L_{J,J-1} from the previous column (J > j0)
   T* U = Qbuf;   // partial sum of the diagonal tile (J, J)
-  // column 0's diagonal tile
+  // column j0's diagonal tile, fully updated by its own workgroup
   {
     const int tid = fresh_tid();
-    spin_until(&a.tflag[tile_index(0, 0, nb)], -a.epoch, true, a.ctrl, wait_ticks);
+    spin_until(&a.tflag[tile_index(j0, j0)], -a.epoch, true, a.ctrl, wait_ticks);
     acquire_agent();
-    tile_to_lds<T>(Lt + tile_index(0, 0, nb) * TILE_ELEMS, U, tid);
-    if (fwd && tid < TILE) s_tp[tid] = a.z[tid];
+    tile_to_lds<T>(Lt + tile_index(j0, j0) * TILE_ELEMS, U, tid);
+    if (fwd && tid < TILE) s_tp[tid] = a.z[(int64_t)j0 * TILE + tid];
     __syncthreads();
   }
-  for (int J = 0; J < nb; ++J) {
+  for (int J = j0; J < nb; ++J) {
     const int tid = fresh_tid(), lane = tid & 63, w = tid >> 6;
     const int qr = (w & 1) * 32, qc = (w >> 1) * 32;
-    const int64_t td = tile_index(J, J, nb);
+    const int64_t td = tile_index(J, J);
     const bool sub = J + 1 < nb;
-    const int64_t ts = sub ? tile_index(J + 1, J, nb) : td;
-    if (J >= 1) {
+    const int64_t ts = sub ? tile_index(J + 1, J) : td;
+    if (J > j0) {
       // last term of the diagonal tile, from LDS
       Acc acc[2][2];
       {
@@ -394,7 +403,7 @@ __device__ __forceinline__ void walker(const FactorArgs& a, uint64_t wait_ticks,
       const int p = J * TILE + tid;
       double c = 0.0;
       if (p < a.nF) c = a.rhs[a.Flist ? a.Flist[p] : p];
-      const double last = (J >= 1) ? (((s_part[0][tid] + s_part[1][tid]) + s_part[2][tid]) + s_part[3][tid]) : 0.0;
+      const double last = (J > j0) ? (((s_part[0][tid] + s_part[1][tid]) + s_part[2][tid]) + s_part[3][tid]) : 0.0;
       s_rhs[tid] = c - (s_tp[tid] + last);
     }
     __syncthreads();
@@ -425,7 +434,7 @@ __device__ __forceinline__ void walker(const FactorArgs& a, uint64_t wait_ticks,
     }
     // S_{J+1,J}, fully updated by its own workgroup, and the next diagonal partial sum
     T* dsub = Lt + ts * TILE_ELEMS;
-    const int64_t tn = tile_index(J + 1, J + 1, nb);
+    const int64_t tn = tile_index(J + 1, J + 1);
     spin_until(&a.tflag[ts], -a.epoch, true, a.ctrl, wait_ticks);
     spin_until(&a.tflag[tn], -a.epoch, true, a.ctrl, wait_ticks);
     acquire_agent();
@@ -488,14 +497,14 @@ __device__ __forceinline__ void walker(const FactorArgs& a, uint64_t wait_ticks,
   }
 }
 
-// Ticket t -> lower tile (I, J) in column-major order.
-__device__ inline void decode_ticket(int t, int nb, int* I, int* J) {
+// Ticket t -> lower tile (I, J) in column-major order over the rows I >= max(J, j0).
+__device__ inline void decode_ticket(int t, int nb, int j0, int* I, int* J) {
   int j = 0, start = 0;
-  while (t >= start + (nb - j)) {
-    start += nb - j;
+  while (t >= start + (nb - max(j, j0))) {
+    start += nb - max(j, j0);
     ++j;
   }
-  *I = j + (t - start);
+  *I = max(j, j0) + (t - start);
   *J = j;
 }
 
@@ -513,7 +522,7 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wa
   if (tid == 0) {
     const int t = atomicAdd(&a.ctrl->chol_ticket, 1) - 1;   // ticket 0 is the walker
     int I = 0, J = 0;
-    if (t >= 0 && t < tile_count(a.nb)) decode_ticket(t, a.nb, &I, &J);
+    if (t >= 0 && t < tile_count_from(a.nb, a.j0)) decode_ticket(t, a.nb, a.j0, &I, &J);
     s_t = t;
     s_I = I;
     s_J = J;
@@ -524,8 +533,8 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wa
     walker<T>(a, wait_ticks, S, W, s_part, s_rhs, s_z, s_tp);
     return;
   }
-  if (t >= tile_count(a.nb)) return;   // counter not reset: do nothing rather than go out of range
-  chol_tile<T>(a, wait_ticks, tid, t, s_I, s_J, S, W, s_part, s_rhs);
+  if (t >= tile_count_from(a.nb, a.j0)) return;   // counter not reset: do nothing rather than go out of range
+  chol_tile<T>(a, wait_ticks, tid, s_I, s_J, S, W, s_part, s_rhs);
 }
 
 // Persistent form for a capped grid: each workgroup takes tickets until none are left, so
@@ -542,13 +551,13 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles_persistent(FactorArgs a, 
   __shared__ double s_z[TILE];
   __shared__ double s_tp[TILE];
   __shared__ int s_t, s_I, s_J;
-  const int64_t ntiles = tile_count(a.nb);
+  const int64_t ntiles = tile_count_from(a.nb, a.j0);
   for (;;) {
     const int tid = fresh_tid();
     if (tid == 0) {
       const int t = atomicAdd(&a.ctrl->chol_ticket, 1) - 1;   // ticket 0 is the walker
       int I = 0, J = 0;
-      if (t >= 0 && t < ntiles) decode_ticket(t, a.nb, &I, &J);
+      if (t >= 0 && t < ntiles) decode_ticket(t, a.nb, a.j0, &I, &J);
       s_t = t;
       s_I = I;
       s_J = J;
@@ -561,7 +570,7 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles_persistent(FactorArgs a, 
       return;
     }
     if (t >= ntiles) return;
-    chol_tile<T>(a, wait_ticks, tid, t, I, J, S, W, s_part, s_rhs);
+    chol_tile<T>(a, wait_ticks, tid, I, J, S, W, s_part, s_rhs);
     __syncthreads();   // LDS is reused by the next tile
   }
 }
@@ -581,13 +590,13 @@ template <bool FWD>
 __device__ inline int blk(int s, int nb) { return FWD ? s : nb - 1 - s; }
 
 template <typename T, bool FWD>
-__device__ inline void load_term_tile(const T* Lt, int I, int K, int nb, int r, int g, T (&v)[16]) {
+__device__ inline void load_term_tile(const T* Lt, int I, int K, int r, int g, T (&v)[16]) {
   if (FWD) {   // L_IK, thread (r, g) takes row r, columns 16 g .. 16 g + 15
-    const T* tl = Lt + tile_index(I, K, nb) * TILE_ELEMS;
+    const T* tl = Lt + tile_index(I, K) * TILE_ELEMS;
 #pragma unroll
     for (int q = 0; q < 16; ++q) v[q] = tl[(g * 16 + q) * TILE + r];
   } else {     // L_KI^T: thread (r, g) takes column r, rows 16 g .. 16 g + 15 of L_KI
-    const T* tl = Lt + tile_index(K, I, nb) * TILE_ELEMS;
+    const T* tl = Lt + tile_index(K, I) * TILE_ELEMS;
 #pragma unroll
     for (int q = 0; q < 16; ++q) v[q] = tl[r * TILE + g * 16 + q];
   }
@@ -627,7 +636,7 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
     for (int q = 0; q < 16; ++q) accl[q] = 0.0;
     int known = 0;
     T tv[16];
-    if (last > 0) load_term_tile<T, FWD>(Lt, I, blk<FWD>(0, nb), nb, r, g, tv);
+    if (last > 0) load_term_tile<T, FWD>(Lt, I, blk<FWD>(0, nb), r, g, tv);
     for (int u = 0; u < last; ++u) {
       if (u >= known) {
         spin_until(done, u + 1, false, a.ctrl, wait_ticks);
@@ -638,7 +647,7 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
       T cur[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) cur[q] = tv[q];
-      if (u + 1 < last) load_term_tile<T, FWD>(Lt, I, blk<FWD>(u + 1, nb), nb, r, g, tv);
+      if (u + 1 < last) load_term_tile<T, FWD>(Lt, I, blk<FWD>(u + 1, nb), r, g, tv);
       if (FWD) {
         const double* zk = outv + (int64_t)K * TILE;
 #pragma unroll
@@ -703,7 +712,7 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
 #pragma unroll
       for (int j = 0; j < TD; ++j) {
         const int u = s + 1 - TD + j;
-        if (u >= 0) load_term_tile<T, FWD>(Lt, In, blk<FWD>(u, nb), nb, r, g, td[j]);
+        if (u >= 0) load_term_tile<T, FWD>(Lt, In, blk<FWD>(u, nb), r, g, td[j]);
       }
     }
     part[g][r] = xx;
@@ -726,7 +735,7 @@ __global__ void k_tiles_to_dense(int n, int nb, const T* __restrict__ Lt, double
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
     const int c = (int)(e / n), r = (int)(e - (int64_t)c * n);
     double v = 0.0;
-    if (r >= c) v = (double)Lt[tile_index(r / TILE, c / TILE, nb) * TILE_ELEMS + (c % TILE) * TILE + (r % TILE)];
+    if (r >= c) v = (double)Lt[tile_index(r / TILE, c / TILE) * TILE_ELEMS + (c % TILE) * TILE + (r % TILE)];
     L[r + (int64_t)c * ldl] = v;
   }
 }
@@ -734,8 +743,8 @@ __global__ void k_tiles_to_dense(int n, int nb, const T* __restrict__ Lt, double
 }  // namespace
 
 void launch_cholesky(hipStream_t s, const FactorArgs& a, bool fp32) {
-  if (a.nb <= 0) return;
-  const int64_t grid = tile_count(a.nb) + 1;   // the tiles and the walker
+  if (a.nb <= 0 || a.j0 < 0 || a.j0 >= a.nb) return;
+  const int64_t grid = tile_count_from(a.nb, a.j0) + 1;   // the tiles and the walker
   if (a.max_wgs > 0 && grid > a.max_wgs) {
     const int g = a.max_wgs < 2 ? 2 : a.max_wgs;   // the walker and at least one tile worker
     if (fp32)

@@ -3,8 +3,11 @@
 // and the right-hand side c = A^T b of the normal equations (Sec. 2.1).
 //
 // H is kept as its lower triangle in a padded CSC layout: column j holds the rows i >= j
-// with a structurally nonzero a_i^T a_j, ascending.  The pivot loop only ever gathers
-// lower tiles of the F-principal block from it, so the upper half is never needed.
+// with a structurally nonzero a_i^T a_j, ascending.  For the pivot loop each column's
+// region is then completed with its rows i < j (copied from the lower triangle, unordered),
+// and for every new F order the F-block is re-indexed into F-position space, each
+// position keeping the entries at or below the diagonal in position order: the factor
+// gathers its tiles from that.
 #include "nnls_internal.h"
 
 namespace nnls {
@@ -215,6 +218,80 @@ __global__ __launch_bounds__(256) void k_gram_lower(
   if (lane == 0) hcnt[j] = count;
 }
 
+// Column j's strictly lower entries (i > j) become the upper entries of column i, appended
+// after its lower ones (slot from a counter per column, so in no particular order).  Every
+// column's region holds its whole column: its size bounds the count of distinct rows.
+__global__ __launch_bounds__(256) void k_gram_mirror(int n, GramLower g, int32_t* __restrict__ upcnt,
+                                                     int32_t* __restrict__ hrow, double* __restrict__ hval) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= n) return;
+  const int64_t s = g.hptr[j];
+  const int cnt = g.hcnt[j];
+  for (int q = lane; q < cnt; q += 64) {
+    const int i = hrow[s + q];
+    if (i == j) continue;
+    const int slot = atomicAdd(&upcnt[i], 1);
+    const int64_t o = g.hptr[i] + g.hcnt[i] + slot;
+    hrow[o] = j;
+    hval[o] = hval[s + q];
+  }
+}
+
+// F-position lists: position q (column j = Flist[q]) keeps the entries p = pos[i] >= q of
+// its whole column, written in ascending p.  One wave per position; each pass places the
+// entries with p in [base, base + GRAM_CHUNK) into a dense LDS window, then compacts it in
+// order, so the output is sorted by construction and does not depend on the launch.
+__global__ __launch_bounds__(256) void k_gram_positions(int nF, GramLower g, const int32_t* __restrict__ upcnt,
+                                                        const int32_t* __restrict__ Flist,
+                                                        const int32_t* __restrict__ pos,
+                                                        int32_t* __restrict__ pcnt, int32_t* __restrict__ prow,
+                                                        double* __restrict__ pval) {
+  __shared__ double s_val[4][GRAM_CHUNK];
+  __shared__ uint32_t s_mark[4][GRAM_CHUNK / 32];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int q = blockIdx.x * 4 + w;
+  if (q >= nF) return;   // whole wave leaves; no workgroup barrier follows
+  double* val = s_val[w];
+  uint32_t* mark = s_mark[w];
+  const int j = Flist[q];
+  const int64_t s = g.hptr[j];
+  const int cnt = g.hcnt[j] + upcnt[j];
+  // largest position in the column bounds the passes
+  int pmax = q;
+  for (int t = lane; t < cnt; t += 64) pmax = max(pmax, pos[g.hrow[s + t]]);
+  for (int d = 32; d >= 1; d >>= 1) pmax = max(pmax, __shfl_xor(pmax, d, 64));
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int count = 0;
+  for (int base = q; base <= pmax; base += GRAM_CHUNK) {
+    for (int k = lane; k < GRAM_CHUNK / 32; k += 64) mark[k] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    for (int t = lane; t < cnt; t += 64) {
+      const int p = pos[g.hrow[s + t]];
+      const int k = p - base;
+      if (p >= q && k >= 0 && k < GRAM_CHUNK) {
+        val[k] = g.hval[s + t];
+        atomicOr(&mark[k >> 5], 1u << (k & 31));
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int span = min(GRAM_CHUNK, pmax + 1 - base);
+    for (int k0 = 0; k0 < span; k0 += 64) {
+      const int k = k0 + lane;
+      const bool hit = k < span && ((mark[k >> 5] >> (k & 31)) & 1u);
+      const uint64_t bal = __ballot(hit);
+      if (hit) {
+        const int slot = count + __popcll(bal & lt_mask);
+        prow[s + slot] = base + k;
+        pval[s + slot] = val[k];
+      }
+      count += __popcll(bal);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (lane == 0) pcnt[q] = count;
+}
+
 // out_j = scale * sum_r a_rj v_r  (ascending r), one thread per column.
 __global__ void k_spmvT_csc(int n, const int32_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
                             const double* __restrict__ val, const double* __restrict__ v,
@@ -356,6 +433,18 @@ void launch_gram_lower(hipStream_t s, int n, const int32_t* colptr, const int32_
                        double* hval) {
   hipLaunchKernelGGL(k_gram_lower, dim3((n + 3) / 4), dim3(256), 0, s, n, colptr, rowidx, val, rowptr,
                      colidx, valr, hptr, hcnt, hrow, hval);
+}
+
+void launch_gram_mirror(hipStream_t s, int n, GramLower g, int32_t* upcnt, int32_t* hrow, double* hval) {
+  hipLaunchKernelGGL(k_gram_mirror, dim3((n + 3) / 4), dim3(256), 0, s, n, g, upcnt, hrow, hval);
+}
+
+void launch_gram_positions(hipStream_t s, int nF, GramLower g, const int32_t* upcnt,
+                           const int32_t* Flist, const int32_t* pos, int32_t* pcnt, int32_t* prow,
+                           double* pval) {
+  if (nF <= 0) return;
+  hipLaunchKernelGGL(k_gram_positions, dim3((nF + 3) / 4), dim3(256), 0, s, nF, g, upcnt, Flist, pos,
+                     pcnt, prow, pval);
 }
 
 void launch_spmvT_csc(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx,

@@ -30,13 +30,17 @@ struct Ctrl {
   int32_t bwd_ticket;
   int32_t fwd_done;    // frontier of the forward triangular solve (blocks finished)
   int32_t bwd_done;    // frontier of the backward triangular solve
+  int32_t j0;          // leading tile columns of the previous factor that the new F order keeps
+  int32_t pad_;
   double min_margin;   // smallest |v| over the tested entries that were not zeroed
   double ir_dmax;      // mixed precision: max |correction| of the last refinement step
   double ir_xmax;      //                  max |x_F| after it
 };
 
 // Lower-triangle Gram matrix in padded CSC: column j occupies
-// [hptr[j], hptr[j] + hcnt[j]) of hrow / hval, rows ascending and >= j.
+// [hptr[j], hptr[j] + hcnt[j]) of hrow / hval, rows ascending and >= j.  After the mirror
+// step the same region continues with the upcnt[j] entries of rows < j, in no particular
+// order, so that [hptr[j], hptr[j] + hcnt[j] + upcnt[j]) is the whole column.
 struct GramLower {
   const int64_t* hptr;
   const int32_t* hcnt;
@@ -44,11 +48,25 @@ struct GramLower {
   const double* hval;
 };
 
-// Tile index of lower tile (I, J), I >= J, in column-major packed order.
-__host__ __device__ inline int64_t tile_index(int I, int J, int nb) {
-  return (int64_t)J * nb - (int64_t)J * (J - 1) / 2 + (I - J);
-}
+// The F-block of the Gram matrix in F-position space, rebuilt for every new F order:
+// position q keeps the entries (p, H_{F_p F_q}) with p >= q, p ascending, at
+// [pptr[F_q], pptr[F_q] + pcnt[q]) of prow / pval (the Gram column's own region size).
+struct GramPos {
+  const int64_t* pptr;
+  const int32_t* pcnt;
+  const int32_t* prow;
+  const double* pval;
+};
+
+// Tile index of lower tile (I, J), I >= J, in row-major packed order.  The index does not
+// depend on the number of tile rows, so the leading tiles of a factor stay in place when
+// the F-block grows or shrinks behind them.
+__host__ __device__ inline int64_t tile_index(int I, int J) { return (int64_t)I * (I + 1) / 2 + J; }
 __host__ __device__ inline int64_t tile_count(int nb) { return (int64_t)nb * (nb + 1) / 2; }
+// Tiles a factor with j0 reused leading tile columns computes: rows I >= max(J, j0).
+__host__ __device__ inline int64_t tile_count_from(int nb, int j0) {
+  return (int64_t)j0 * (nb - j0) + tile_count(nb - j0);
+}
 
 // ---------------------------------------------------------------- launchers
 // setup (k_setup.hip)
@@ -65,6 +83,13 @@ void launch_gram_lower(hipStream_t s, int n, const int32_t* colptr, const int32_
                        const double* val, const int32_t* rowptr, const int32_t* colidx,
                        const double* valr, const int64_t* hptr, int32_t* hcnt, int32_t* hrow,
                        double* hval);
+// append the strictly lower entries of every column as the upper entries of their row's
+// column (upcnt zero on entry)
+void launch_gram_mirror(hipStream_t s, int n, GramLower g, int32_t* upcnt, int32_t* hrow, double* hval);
+// position-space lists of the F-block for the current F order (Flist, pos)
+void launch_gram_positions(hipStream_t s, int nF, GramLower g, const int32_t* upcnt,
+                           const int32_t* Flist, const int32_t* pos, int32_t* pcnt, int32_t* prow,
+                           double* pval);
 void launch_spmvT_csc(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx,
                       const double* val, const double* v, double* out, double scale);
 void launch_gram_dense(hipStream_t s, int m, int n, const double* A, int lda, double* H, int ldh);
@@ -78,9 +103,11 @@ void launch_fill_2d(hipStream_t s, int rows, int cols, double* p, int ld, double
 // pivot control (k_pivot.hip)
 void launch_pivot_init(hipStream_t s, int n, const double* c, double* x, double* y,
                        uint8_t* flags, Ctrl* ctrl, int p_max);
+// reuse: the tiles of the factor of the current F order are valid for the next factor of
+// the same precision; Fold: n ints of scratch
 void launch_pivot_control(hipStream_t s, int n, double* x, double* y, uint8_t* flags,
                           int32_t* Flist, int32_t* pos, Ctrl* ctrl, double tau, int p_max,
-                          int max_iter, int32_t* colcnt, int ncol);
+                          int max_iter, int32_t* colcnt, int ncol, int32_t* Fold, int reuse);
 void launch_ctrl_set_state(hipStream_t s, Ctrl* ctrl, int N, int p, int iter, int max_iter_flag);
 
 // residual and dual (k_spmv.hip)
@@ -104,10 +131,10 @@ struct FactorArgs {
   int nF;                 // order of the F-block
   int nb;                 // ceil(nF / TILE)
   const int32_t* Flist;   // F positions -> column numbers (nullptr: identity)
-  const int32_t* pos;     // column number -> F position or -1 (sparse source only)
-  GramLower lower;        // sparse source (used when dense == nullptr)
+  GramPos gpos;           // sparse source (used when dense == nullptr)
   const double* dense;    // dense symmetric source, column-major
   int64_t ldd;
+  int j0;                 // leading tile columns kept from the previous factor (rows < j0)
   void* Ltiles;           // tile storage, tile_count(nb) tiles of TILE_ELEMS
   void* Dinv;             // nb inverted diagonal tiles
   int32_t* colcnt;        // nb counters of finished tiles per column, zero at launch

@@ -152,9 +152,9 @@ size_t sparse_footprint(int m, int n, int64_t nnz, const int32_t* rowidx) {
   const size_t tiles = (size_t)tile_count(nb);
   size_t f = (size_t)pack_layout(m, n, nnz).total + (size_t)n * 16;          // input, x | y
   f += (size_t)(m + 1) * 4 + (size_t)nnz * 12 + (size_t)m * 4;                 // CSR copy
-  f += (size_t)(n + 1) * 8 + (size_t)n * 4 + (size_t)ub * 12;                  // Gram (lower)
-  f += (size_t)n * (8 + 8 + 1 + 4 + 4) + (size_t)m * 8;                        // c, g, flags, F, pos, r
-  f += (tiles + (size_t)nb) * TILE_ELEMS * 8 + tiles * 4 + (size_t)nb * (8 + 2 * TILE * 8);
+  f += (size_t)(n + 1) * 8 + (size_t)n * 8 + (size_t)ub * 24;                  // Gram + F-position lists
+  f += (size_t)n * (8 + 8 + 1 + 4 + 4 + 4 + 4) + (size_t)m * 8;                // c, g, flags, F, pos, order, r
+  f += (tiles + (size_t)nb) * TILE_ELEMS * 8 + tiles * 4 + (size_t)nb * (8 + 3 * TILE * 8);
   return f;
 }
 

@@ -135,6 +135,29 @@ def test_capped_persistent_grid_is_bitwise_identical(h, cap, precision):
     assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3]) and a[4] == b[4]
 
 
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-10)])
+@pytest.mark.parametrize("m,n,cap", [(6000, 1200, 0), (60000, 12000, 0), (6000, 1200, 7)])
+def test_kept_factor_tiles_match_full_refactor(h, m, n, cap, precision, tol):
+    """The factor keeps the leading tile columns that no exchange touched (F ordered so
+    that they come first); against refactoring the whole F-block every iteration it takes
+    the same pivot steps and gives x within rounding, and the later iterations keep tiles."""
+    inst = W.sparse_large(1002, m=m, n=n)
+    kw = dict(precision=precision, max_workgroups=cap)
+    st1, info1, x1, y1, _ = solve_csc(h, inst.A, inst.b, **kw)
+    tr1 = N.nnls_get_trace(h, reused=True)
+    st2, info2, x2, y2, _ = solve_csc(h, inst.A, inst.b, flags=N.NNLS_FLAG_NO_FACTOR_REUSE, **kw)
+    tr2 = N.nnls_get_trace(h, reused=True)
+    assert st1 == st2 == N.NNLS_OK
+    assert [r[:5] for r in tr1] == [r[:5] for r in tr2]
+    assert all(r[5] == 0 for r in tr2)
+    kept = [r[5] for r in tr1]
+    assert kept[0] == 0 and all(k % 64 == 0 and k < nf for k, nf in zip(kept, [r[4] for r in tr1]))
+    assert sum(kept) > 0
+    assert np.array_equal(x1 > 0, x2 > 0) and np.array_equal(x1 > 0, inst.active)
+    assert relerr(x1, x2) <= tol
+    assert np.linalg.norm(y1 - y2) <= tol * max(np.linalg.norm(y2), 1.0)
+
+
 def test_empty_free_set(h):
     A = np.array([[1.0, 0.0], [0.0, 1.0], [1.0, 1.0]])
     b = np.array([-1.0, -2.0, 0.5])
