@@ -771,7 +771,7 @@ def main():
                 if args.workload == "sparse_large" and not fp32 else None,
                 "launches": chol["launches"],
                 "avg_launch_ms": round(chol["ms"] / chol["launches"], 4),
-                "work_per_launch": "nF^3/3 flops of the F-block factor"}
+                "work_per_launch": "(nF^3 - p^3)/3 flops: the F-block factor less its kept leading p columns"}
     breakdown = {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in prof.items()
                  if v["launches"]}
     out = {

@@ -81,9 +81,10 @@ typedef struct {
                            bound on the corrections still to come, is below ir_rtol
                            max|x_F|                                                     */
   uint32_t flags;       /* NNLS_FLAG_*                                                   */
-  uint32_t max_workgroups; /* 0: the factor kernel runs one workgroup per tile; else a
-                              persistent grid of this many workgroups, so that several
-                              solves can share the device                              */
+  uint32_t max_workgroups; /* cap on the factor kernel's grid: above it, a persistent grid
+                              of this many workgroups takes the tiles from a queue (so
+                              that several solves can share the device).  0: two per
+                              compute unit, the kernel's occupancy                     */
 } nnls_options;
 
 typedef struct {

@@ -40,7 +40,9 @@ struct nnls_handle {
   int device = 0;
   hipStream_t stream = nullptr;
   uint64_t wait_ticks = 0;
-  int default_wgs = 0;        // factor grid cap when the options give none (0: no cap)
+  int default_wgs = 0;        // factor grid cap when the options give none: the workgroups
+                              // the device holds at once (launching one per tile costs
+                              // more on large F-blocks)
   int max_wgs = 0;            // the grid cap of the current solve
   // workspace
   DevBuf err, ctrl, rowcnt, rowptr, colidx, valr, hptr, hcnt, hrow, hval, c, r, flags, Flist, pos;
@@ -681,6 +683,10 @@ int nnls_create(nnls_handle** out, int device, void* stream) {
   if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || rate_khz <= 0)
     rate_khz = 100000;
   h->wait_ticks = (uint64_t)rate_khz * 1000ull * 20ull;   // 20 s
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
+    cus = 256;
+  h->default_wgs = 2 * cus;
 
   if (hipHostMalloc((void**)&h->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&h->h_scalar, 64, hipHostMallocDefault) != hipSuccess) {

@@ -41,7 +41,7 @@ namespace {
 // Stage tile (I, J) of H_FF in LDS (column-major, leading dimension LDT).  Positions at or
 // beyond nF are padding: identity on the diagonal, zero elsewhere.
 // threadIdx.x as a value the compiler cannot carry from one loop iteration to the next
-// (keeps the persistent kernel's register footprint at that of the one-tile kernel)
+// (keeps the register footprint of the ticket loop at that of a single tile)
 __device__ inline int fresh_tid() {
   int v = (int)threadIdx.x;
   asm volatile("" : "+v"(v));
@@ -508,42 +508,13 @@ __device__ inline void decode_ticket(int t, int nb, int j0, int* I, int* J) {
   *J = j;
 }
 
-// One workgroup per lower tile.
+// A persistent grid: each workgroup takes tickets until none are left, so a launch holds
+// at most gridDim.x workgroups however large the F-block is (the device's resident
+// workgroups by default, fewer when concurrent solves share the device).  A workgroup
+// holds one ticket at a time and only waits for smaller tickets, which running workgroups
+// hold, so the lowest unfinished ticket always progresses.
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wait_ticks) {
-  __shared__ T S[TILE * LDT];
-  __shared__ T W[TILE * LDT];
-  __shared__ double s_part[4][TILE];   // fused forward solve: partial sums per wave
-  __shared__ double s_rhs[TILE];
-  __shared__ double s_z[TILE];
-  __shared__ double s_tp[TILE];
-  __shared__ int s_t, s_I, s_J;
-  const int tid = threadIdx.x;
-  if (tid == 0) {
-    const int t = atomicAdd(&a.ctrl->chol_ticket, 1) - 1;   // ticket 0 is the walker
-    int I = 0, J = 0;
-    if (t >= 0 && t < tile_count_from(a.nb, a.j0)) decode_ticket(t, a.nb, a.j0, &I, &J);
-    s_t = t;
-    s_I = I;
-    s_J = J;
-  }
-  __syncthreads();
-  const int t = s_t;
-  if (t < 0) {
-    walker<T>(a, wait_ticks, S, W, s_part, s_rhs, s_z, s_tp);
-    return;
-  }
-  if (t >= tile_count_from(a.nb, a.j0)) return;   // counter not reset: do nothing rather than go out of range
-  chol_tile<T>(a, wait_ticks, tid, s_I, s_J, S, W, s_part, s_rhs);
-}
-
-// Persistent form for a capped grid: each workgroup takes tickets until none are left, so
-// a launch holds at most gridDim.x workgroups however large the F-block is (concurrent
-// solves share the device).  A workgroup holds one ticket at a time and only waits for
-// smaller tickets, which running workgroups hold, so the lowest unfinished ticket always
-// progresses.
-template <typename T>
-__global__ __launch_bounds__(256, 2) void k_chol_tiles_persistent(FactorArgs a, uint64_t wait_ticks) {
   __shared__ T S[TILE * LDT];
   __shared__ T W[TILE * LDT];
   __shared__ double s_part[4][TILE];
@@ -744,15 +715,8 @@ __global__ void k_tiles_to_dense(int n, int nb, const T* __restrict__ Lt, double
 
 void launch_cholesky(hipStream_t s, const FactorArgs& a, bool fp32) {
   if (a.nb <= 0 || a.j0 < 0 || a.j0 >= a.nb) return;
-  const int64_t grid = tile_count_from(a.nb, a.j0) + 1;   // the tiles and the walker
-  if (a.max_wgs > 0 && grid > a.max_wgs) {
-    const int g = a.max_wgs < 2 ? 2 : a.max_wgs;   // the walker and at least one tile worker
-    if (fp32)
-      hipLaunchKernelGGL(k_chol_tiles_persistent<float>, dim3((unsigned)g), dim3(256), 0, s, a, a.wait_ticks);
-    else
-      hipLaunchKernelGGL(k_chol_tiles_persistent<double>, dim3((unsigned)g), dim3(256), 0, s, a, a.wait_ticks);
-    return;
-  }
+  int64_t grid = tile_count_from(a.nb, a.j0) + 1;   // the tiles and the walker
+  if (a.max_wgs > 0 && grid > a.max_wgs) grid = a.max_wgs < 2 ? 2 : a.max_wgs;   // walker + >= 1 worker
   if (fp32)
     hipLaunchKernelGGL(k_chol_tiles<float>, dim3((unsigned)grid), dim3(256), 0, s, a, a.wait_ticks);
   else

@@ -145,7 +145,7 @@ struct FactorArgs {
   uint64_t wait_ticks;    // bound of one device-side wait, in wall-clock ticks
   const double* rhs;      // optional: forward-solve L z = rhs_F during the factorisation
   double* z;              // nb * TILE, written when rhs != nullptr
-  int max_wgs;            // cap on the persistent grid (0: one workgroup per tile)
+  int max_wgs;            // cap on the persistent grid (0: one workgroup per tile and the walker)
 };
 void launch_cholesky(hipStream_t s, const FactorArgs& a, bool fp32);
 // z = L^-1 rhs (rhs gathered through Flist when gather != nullptr); x = L^-T z and

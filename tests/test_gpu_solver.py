@@ -126,8 +126,8 @@ def test_rerun_is_bitwise_identical(h):
 
 @pytest.mark.parametrize("cap,precision", [(1, 0), (7, 0), (64, 0), (7, 1)])
 def test_capped_persistent_grid_is_bitwise_identical(h, cap, precision):
-    """A capped factor grid (persistent workgroups taking tickets) computes every tile with
-    the same operations in the same order as one workgroup per tile."""
+    """A capped factor grid (fewer persistent workgroups taking the tile tickets) computes
+    every tile with the same operations in the same order as one workgroup per tile."""
     inst = W.sparse_large(1002, m=6000, n=1200)
     a = solve_csc(h, inst.A, inst.b, precision=precision)
     b = solve_csc(h, inst.A, inst.b, precision=precision, max_workgroups=cap)
