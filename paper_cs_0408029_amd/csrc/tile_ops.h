@@ -147,14 +147,14 @@ __device__ inline float rsqrt_refined(float d) {
 // keep row i of the block in registers; lanes 16..31 start from column i of the identity
 // and go through the very same updates, which turns them into column i of L^-1 (forward
 // substitution, one column per lane, in step with the factorisation).  Pivots come from a
-// refined reciprocal square root (no divide); the next pivot's diagonal update stays off
-// the LDS path; each step's column of L is broadcast through LDS (16-byte broadcast reads)
-// in the unused upper block of S.  L goes back into S, its inverse into W.
+// reciprocal square root refined by two Newton steps (the hardware estimate is good to
+// about 2^-24, one step leaves ~40 ulp); each step's column of L reaches every lane as
+// wave-uniform values read from the factor lanes, so the pivot chain never touches LDS.
+// L goes back into S, its inverse into W.
 template <typename T>
 __device__ inline void diag16(T* S, T* W, int o, const PivotReport& rep) {
   const int lane = threadIdx.x & 63, i = lane & 15;
   const bool inv = (lane >> 4) == 1;   // lanes 16..31 carry the inverse
-  T* colbuf = S + 48 * LDT;            // column buffer: rows 0..15 of column 48 (upper block)
   T r[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) r[j] = inv ? ((j == i) ? (T)1 : (T)0) : S[(o + i) + (o + j) * LDT];
@@ -170,11 +170,9 @@ __device__ inline void diag16(T* S, T* W, int o, const PivotReport& rep) {
     const T lic = (i == c && !inv) ? l : r[c] * y;
     r[c] = lic;
     if (c + 1 < 16) d = bcast_lane(fma(-lic, lic, r[c + 1]), c + 1);
-    if (lane < 16) colbuf[i] = lic;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    // column c of L below the pivot, as wave-uniform values read from the factor lanes
 #pragma unroll
-    for (int j = c + 1; j < 16; ++j) r[j] = fma(-lic, colbuf[j], r[j]);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int j = c + 1; j < 16; ++j) r[j] = fma(-lic, bcast_lane(lic, j), r[j]);
   }
   if (firstbad >= 0 && lane == 0 && rep.base + o + firstbad < rep.nF) {
     atomicMin(rep.failed_pos, rep.base + o + firstbad);
