@@ -637,16 +637,29 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
     return;
   }
 
-  // the walker
-  T td[TD][16], dv[16];
+  // the walker.  The tiles of step s+1 (its newest-term tiles of L and its inverted
+  // diagonal tile, two sets of registers) are requested at the start of step s, as soon as
+  // step s has read its own, so that their latency hides behind step s.  Only wave 0 waits
+  // for the helper and reads the hand-over and the right-hand side.
+  T td[TD][16], dv[16], dn[16];
   {
     const int I0 = blk<FWD>(0, nb);
     load_dinv<T, FWD>(Dv, I0, r, g, dv);
   }
   for (int s = 0; s < nb; ++s) {
     const int I = blk<FWD>(s, nb);
-    spin_until(&a.pflag[I], tag, true, a.ctrl, wait_ticks);
-    acquire_agent();
+    double rhs = 0.0, older = 0.0;
+    if (tid < TILE) {
+      spin_until(&a.pflag[I], tag, true, a.ctrl, wait_ticks);
+      acquire_agent();
+      const int p = I * TILE + tid;
+      if (FWD) {
+        if (p < a.nF) rhs = a.rhs_full ? a.rhs_full[a.Flist ? a.Flist[p] : p] : a.rhs_dense[p];
+      } else {
+        rhs = a.z[p];
+      }
+      older = a.part[p];
+    }
     // newest terms: steps max(0, s-TD) .. s-1, oldest first
     double acc = 0.0;
 #pragma unroll
@@ -658,34 +671,26 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
         for (int q = 0; q < 16; ++q) acc = fma((double)td[j][q], xk[g * 16 + q], acc);
       }
     }
-    part[g][r] = acc;
-    __syncthreads();
-    if (tid < TILE) {
-      const int p = I * TILE + tid;
-      double rhs;
-      if (FWD) {
-        rhs = 0.0;
-        if (p < a.nF) rhs = a.rhs_full ? a.rhs_full[a.Flist ? a.Flist[p] : p] : a.rhs_dense[p];
-      } else {
-        rhs = a.z[p];
-      }
-      const double older = a.part[p];
-      srhs[tid] = rhs - (older + (((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid]));
-    }
-    __syncthreads();
-    double xx = 0.0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) xx = fma((double)dv[q], srhs[g * 16 + q], xx);
-    // tiles of the next step, in flight while this one finishes
+    // step s+1's tiles: its newest-term tiles (td is free now) and its inverse
     if (s + 1 < nb) {
       const int In = blk<FWD>(s + 1, nb);
-      load_dinv<T, FWD>(Dv, In, r, g, dv);
 #pragma unroll
       for (int j = 0; j < TD; ++j) {
         const int u = s + 1 - TD + j;
         if (u >= 0) load_term_tile<T, FWD>(Lt, In, blk<FWD>(u, nb), r, g, td[j]);
       }
+      load_dinv<T, FWD>(Dv, In, r, g, dn);
     }
+    part[g][r] = acc;
+    __syncthreads();
+    if (tid < TILE)
+      srhs[tid] = rhs - (older + (((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid]));
+    __syncthreads();
+    double xx = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) xx = fma((double)dv[q], srhs[g * 16 + q], xx);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) dv[q] = dn[q];
     part[g][r] = xx;
     __syncthreads();
     if (tid < TILE) {
