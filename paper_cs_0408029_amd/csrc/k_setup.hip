@@ -81,40 +81,54 @@ __global__ void k_row_count(int64_t nnz, const int32_t* __restrict__ rowidx, int
 }
 
 // Exclusive scan of count[0..n) into out[0..n], out[n] = total.  One workgroup of 1024
-// threads; each thread scans a contiguous segment.
+// threads walks the array in chunks of 1024 * SCAN_PER: each thread loads SCAN_PER
+// consecutive entries (all loads in flight at once), scans them in registers, and the
+// thread totals are scanned across the workgroup; a running carry joins the chunks.
+// Every chunk is read into registers before it is written, so count may alias out.
+constexpr int SCAN_PER = 16;
 template <typename Tin, typename Tout>
 __global__ __launch_bounds__(1024) void k_scan_single(int64_t n, const Tin* count,
                                                       Tout* out) {
   __shared__ Tout s_wave[16];
+  __shared__ Tout s_total;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t seg = (n + 1023) / 1024;
-  const int64_t s0 = min(n, (int64_t)tid * seg), s1 = min(n, s0 + seg);
-  Tout local = 0;
-  for (int64_t i = s0; i < s1; ++i) local += (Tout)count[i];
-  // inclusive scan inside the wave
-  Tout v = local;
-  for (int d = 1; d < 64; d <<= 1) {
-    Tout o = __shfl_up(v, d, 64);
-    if (lane >= d) v += o;
-  }
-  if (lane == 63) s_wave[w] = v;
-  __syncthreads();
-  if (tid == 0) {
-    Tout run = 0;
-    for (int q = 0; q < 16; ++q) {
-      Tout t = s_wave[q];
-      s_wave[q] = run;
-      run += t;
+  Tout carry = 0;
+  for (int64_t base = 0; base < n; base += 1024 * SCAN_PER) {
+    const int64_t i0 = base + (int64_t)tid * SCAN_PER;
+    Tout v[SCAN_PER];
+#pragma unroll
+    for (int q = 0; q < SCAN_PER; ++q) v[q] = (i0 + q < n) ? (Tout)count[i0 + q] : (Tout)0;
+    Tout local = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_PER; ++q) local += v[q];
+    // inclusive scan of the thread totals inside the wave
+    Tout t = local;
+    for (int d = 1; d < 64; d <<= 1) {
+      const Tout o = __shfl_up(t, d, 64);
+      if (lane >= d) t += o;
     }
+    if (lane == 63) s_wave[w] = t;
+    __syncthreads();
+    if (tid == 0) {
+      Tout run = 0;
+      for (int q = 0; q < 16; ++q) {
+        const Tout c = s_wave[q];
+        s_wave[q] = run;
+        run += c;
+      }
+      s_total = run;
+    }
+    __syncthreads();
+    Tout off = carry + s_wave[w] + t - local;
+#pragma unroll
+    for (int q = 0; q < SCAN_PER; ++q) {
+      if (i0 + q < n) out[i0 + q] = off;
+      off += v[q];
+    }
+    carry += s_total;
+    __syncthreads();   // s_wave and s_total are reused by the next chunk
   }
-  __syncthreads();
-  Tout off = s_wave[w] + v - local;
-  for (int64_t i = s0; i < s1; ++i) {   // read before write: count may alias out
-    const Tout c = (Tout)count[i];
-    out[i] = off;
-    off += c;
-  }
-  if (tid == 1023) out[n] = off;   // thread 1023 owns the last (possibly empty) segment
+  if (tid == 0) out[n] = carry;
 }
 
 __global__ void k_csr_fill(int n, const int32_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
