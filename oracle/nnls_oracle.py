@@ -199,3 +199,66 @@ def kkt_residuals(A, b, x, y):
         g = A.T @ (A @ x - b)
     return (float(min(x.min(), 0.0)), float(min(y.min(), 0.0)),
             float(abs(np.dot(x, y))), float(np.max(np.abs(y - g))))
+
+
+def inverse_onenorm_estimate(H, max_iter: int = 5) -> float:
+    """Lower-bound estimate of ||H^-1||_1 for a symmetric positive definite H, from its
+    Cholesky factor.  Sec. 3 estimates the condition of A_F^T A_F from the factor it already
+    has (LAPACK dpocon); this is the estimator behind such routines: Hager's method
+    (1984) with Higham's refinements (1988).  Every value it forms is ||H^-1 v||_1 / ||v||_1
+    for some v, so the result never exceeds the true norm.
+
+    1. v = (1/n, ..., 1/n): est = ||H^-1 v||_1, xi = sign(H^-1 v) (+1 for >= 0).
+    2. z = H^-1 xi (H is symmetric); j = first index of max |z_j|.
+    3. Repeat: v = e_j, est' = ||H^-1 e_j||_1; stop if the signs of H^-1 e_j equal xi or
+       est' does not grow; else xi = those signs, z = H^-1 xi, and stop if max |z| sits at
+       the previous j again or after max_iter rounds in all; j = the new index.
+    4. v_i = (-1)^i (1 + i / (n - 1)): the result is the larger of est and
+       ||H^-1 v||_1 / ||v||_1 = 2 ||H^-1 v||_1 / (3 n).
+    """
+    H = np.asarray(H, dtype=np.float64)
+    n = H.shape[0]
+    fac = sla.cho_factor(H, lower=True)
+
+    def solve(v):
+        return sla.cho_solve(fac, v)
+
+    def signs(y):
+        return np.where(y >= 0.0, 1.0, -1.0)
+
+    if n == 1:
+        return float(abs(solve(np.ones(1))[0]))
+    y = solve(np.full(n, 1.0 / n))
+    est = float(np.abs(y).sum())
+    xi = signs(y)
+    z = solve(xi)
+    j = int(np.argmax(np.abs(z)))
+    rounds = 2
+    while True:
+        e = np.zeros(n)
+        e[j] = 1.0
+        y = solve(e)
+        new = float(np.abs(y).sum())
+        xin = signs(y)
+        if np.array_equal(xin, xi) or new <= est:
+            est = max(est, new)
+            break
+        est = new
+        xi = xin
+        z = solve(xi)
+        jlast = j
+        j = int(np.argmax(np.abs(z)))
+        rounds += 1
+        if abs(z[jlast]) == abs(z[j]) or rounds > max_iter:
+            break
+    v = np.array([(-1.0) ** i * (1.0 + i / (n - 1)) for i in range(n)])
+    alt = 2.0 * float(np.abs(solve(v)).sum()) / (3.0 * n)
+    return max(est, alt)
+
+
+def predicted_rel_error(H) -> float:
+    """Predicted relative error of a normal-equations solution with the Gram block H
+    (Sec. 2.1: about c kappa^2 eps with kappa^2 the condition of A_F^T A_F; Sec. 4 fits
+    c = 1/10): 0.1 * ||H||_1 * est(||H^-1||_1) * eps, eps = 2^-52."""
+    H = np.asarray(H, dtype=np.float64)
+    return 0.1 * float(np.abs(H).sum(axis=0).max()) * inverse_onenorm_estimate(H) * np.finfo(np.float64).eps

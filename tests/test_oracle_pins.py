@@ -19,7 +19,8 @@ import scipy.sparse as sp
 
 import workloads as W
 from oracle import (BRANCH_BLOCK_BUDGET, BRANCH_BLOCK_IMPROVED, BRANCH_SINGLE, bpp_solve,
-                    kkt_residuals)
+                    kkt_residuals,
+                    gram, inverse_onenorm_estimate, predicted_rel_error, principal_block)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -231,3 +232,47 @@ def test_sparse_and_dense_inputs_agree():
     rd = bpp_solve(inst.A.toarray(), inst.b)
     assert np.array_equal(rs.free, rd.free)
     assert np.allclose(rs.x, rd.x, rtol=1e-13, atol=1e-15)
+
+
+# ---- condition estimate of the final F-block (Sec. 3: dpocon-style error control) ----
+
+def _exact_inv_onenorm(H):
+    return float(np.abs(np.linalg.inv(H)).sum(axis=0).max())
+
+
+def test_inverse_onenorm_estimate_is_a_tight_lower_bound():
+    """Hager/Higham estimate: never above the true ||H^-1||_1, and within a factor 3 of it
+    on random SPD matrices with condition numbers up to 1e8."""
+    rng = np.random.default_rng(11)
+    for _ in range(150):
+        n = int(rng.integers(2, 60))
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        H = (Q * np.geomspace(1.0, 10.0 ** rng.uniform(0, 8), n)) @ Q.T
+        H = (H + H.T) / 2
+        exact, est = _exact_inv_onenorm(H), inverse_onenorm_estimate(H)
+        assert est <= exact * (1 + 1e-6)
+        assert est >= exact / 3
+
+
+def test_inverse_onenorm_estimate_closed_forms():
+    # diagonal: the method finds the largest 1/d_i exactly
+    d = np.array([4.0, 0.5, 2.0, 8.0, 0.25, 1.0])
+    assert inverse_onenorm_estimate(np.diag(d)) == pytest.approx(4.0, rel=1e-15)
+    # [[2,-1],[-1,2]]^-1 = [[2,1],[1,2]] / 3, whose 1-norm is 1
+    assert inverse_onenorm_estimate(np.array([[2.0, -1.0], [-1.0, 2.0]])) == pytest.approx(1.0, rel=1e-14)
+    assert inverse_onenorm_estimate(np.array([[4.0]])) == pytest.approx(0.25, rel=1e-15)
+
+
+def test_predicted_error_bounds_the_fig1_errors():
+    """0.1 kappa_1(A_F^T A_F) eps (Sec. 2.1, Sec. 4's constant) against the oracle's actual
+    error on the Fig. 1 problems: above it, by less than a factor 30."""
+    for lk in (1.5, 2.0, 3.0, 4.0, 5.0, 6.0):
+        for seed in range(3):
+            A, xt, b = W.svd_conditioned(seed, kappa=10.0 ** lk)
+            res = bpp_solve(A, b)
+            H, _ = gram(A, b)
+            Hff = principal_block(H, np.flatnonzero(res.free))
+            Hff = Hff.toarray() if hasattr(Hff, "toarray") else Hff
+            err = np.linalg.norm(res.x - xt) / np.linalg.norm(xt)
+            pred = predicted_rel_error(Hff)
+            assert err <= pred <= 30 * err, (lk, seed, err, pred)
