@@ -66,6 +66,12 @@ typedef enum {
                                      refinement against the residual from A with the split's
                                      cached factor, then classify the refined x and y again
                                      (pivoting resumes if that finds infeasible entries)    */
+#define NNLS_FLAG_REFINE_AUTO 8u /* NNLS_FP64: once the split is feasible, estimate the
+                                     condition of A_F^T A_F from the split's factor (Hager /
+                                     Higham 1-norm estimate: a few solves with the factor)
+                                     and run the NNLS_FLAG_REFINE_FINAL step only when the
+                                     predicted error 0.1 kappa_1 eps exceeds ir_rtol (the
+                                     error control of Sec. 3)                                */
 #define NNLS_FLAG_NO_FACTOR_REUSE 4u /* refactor the whole F-block in every pivot
                                      iteration.  By default F is ordered so that the leading
                                      tile columns no exchange touched come first, and their
@@ -97,6 +103,9 @@ typedef struct {
   double min_margin;    /* smallest |v| over the final sign tests that were not zeroed   */
   double setup_ms;      /* host wall time of validation + Gram formation                 */
   double solve_ms;      /* host wall time of the whole call                              */
+  double est_rel_err;   /* NNLS_FLAG_REFINE_AUTO: predicted relative error of the final
+                           normal-equations solution, 0.1 kappa_1(A_F^T A_F) 2^-52 with the
+                           1-norm condition estimated from the factor; -1 when not formed */
 } nnls_info;
 
 /* One row of the per-iteration trace recorded by the last solve on a handle. */

@@ -27,6 +27,7 @@ NNLS_FP32_IR = 1
 NNLS_FLAG_PROFILE = 1
 NNLS_FLAG_REFINE_FINAL = 2
 NNLS_FLAG_NO_FACTOR_REUSE = 4
+NNLS_FLAG_REFINE_AUTO = 8
 
 NNLS_PROFILE_CLASSES = 8
 PROFILE_CLASS_NAMES = ["gram", "control", "cholesky", "trsv", "residual", "refine", "batched", "dual"]
@@ -41,7 +42,8 @@ class nnls_options(C.Structure):
 class nnls_info(C.Structure):
     _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("n_free", C.c_int32),
                 ("last_ninf", C.c_int32), ("failed_index", C.c_int32), ("ir_steps", C.c_int32),
-                ("min_margin", C.c_double), ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
+                ("min_margin", C.c_double), ("setup_ms", C.c_double), ("solve_ms", C.c_double),
+                ("est_rel_err", C.c_double)]
 
 
 class nnls_trace_row(C.Structure):

@@ -48,6 +48,7 @@ struct nnls_handle {
   DevBuf err, ctrl, rowcnt, rowptr, colidx, valr, hptr, hcnt, hrow, hval, c, r, flags, Flist, pos;
   DevBuf Lt, Dinv, colcnt, dflag, tflag, z, xF, Hd, gF, rpart, spart, spflag;
   DevBuf upcnt, prow, pval, pcnt, Fold, zr;   // F-position Gram lists, order scratch, refinement z
+  DevBuf est, ev, exi;                         // condition estimate: state, probe vector, signs
   DevBuf bprobs, border, binfo, bws;   // batched dense problems
   Ctrl* h_ctrl = nullptr;     // pinned
   int64_t* h_scalar = nullptr;  // pinned scratch for small reads
@@ -418,6 +419,87 @@ int refine(nnls_handle* h, const Problem& P, int nF, double* x, double* y, const
   return NNLS_OK;
 }
 
+// Predicted relative error of the current split's normal-equations solution (the error
+// control of Sec. 3): 0.1 * ||H_FF||_1 * est(||H_FF^-1||_1) * 2^-52, with the 1-norm of the
+// inverse estimated by Hager's method with Higham's refinements (every solve uses the
+// split's float64 factor).  Steps, on F-position vectors:
+//   v = 1/n; y = H^-1 v; est = ||y||_1; xi = sign(y); z = H^-1 xi; j = argmax |z|;
+//   repeat: y = H^-1 e_j; stop if sign(y) == xi or ||y||_1 <= est (est = the larger);
+//           est = ||y||_1; xi = sign(y); z = H^-1 xi; stop if |z| peaks at j again or
+//           after five rounds; j = argmax |z|;
+//   finally est = max(est, 2 ||H^-1 v'||_1 / (3 n)) with v'_p = (-1)^p (1 + p / (n - 1)).
+int estimate_rel_err(nnls_handle* h, const Problem& P, int nF, double* out) {
+  const int32_t* Flist = (const int32_t*)h->Flist.p;
+  TRY(ensure(h, h->est, sizeof(CondEst)));
+  TRY(ensure(h, h->ev, sizeof(double) * (size_t)nF));
+  TRY(ensure(h, h->exi, sizeof(double) * (size_t)nF));
+  CondEst* est = (CondEst*)h->est.p;
+  double* v = (double*)h->ev.p;
+  double* xi = (double*)h->exi.p;
+  const double* yv = (const double*)h->xF.p;
+  Ctrl* ctrl = (Ctrl*)h->ctrl.p;
+  CondEst init;
+  std::memset(&init, 0, sizeof(init));
+  init.j = -1;
+  HIP_TRY(hipMemcpyAsync(est, &init, sizeof(init), hipMemcpyHostToDevice, h->stream));
+  launch_block_onenorm(h->stream, nF, gram_view(h), (const int32_t*)h->upcnt.p, (const int32_t*)h->pos.p,
+                       P.sparse ? nullptr : (const double*)h->Hd.p, P.n, Flist, est);
+  // y = H^-1 rhs into xF, with the split's factor
+  auto solve = [&](const double* rhs) {
+    launch_reset_tickets(h->stream, ctrl);
+    SolveArgs sa = solve_args(h, nF, Flist, nullptr, nullptr);
+    sa.rhs_full = nullptr;
+    sa.rhs_dense = rhs;
+    sa.z = (double*)h->zr.p;
+    launch_trsv(h->stream, sa, false, true);
+  };
+  CondEst st;
+  auto read = [&]() { return sync_read(h, &st, est, sizeof(CondEst)); };
+  double e = 0.0;
+  if (nF == 1) {
+    launch_est_vec(h->stream, EST_SET_UNIFORM, nF, v, yv, xi, est);
+    solve(v);
+    launch_est_vec(h->stream, EST_SIGNS, nF, v, yv, xi, est);
+    TRY(read());
+    e = st.ynorm;
+  } else {
+    launch_est_vec(h->stream, EST_SET_UNIFORM, nF, v, yv, xi, est);
+    solve(v);
+    launch_est_vec(h->stream, EST_SIGNS, nF, v, yv, xi, est);
+    solve(xi);
+    launch_est_vec(h->stream, EST_ARGMAX, nF, v, yv, xi, est);
+    TRY(read());
+    e = st.ynorm;
+    for (int rounds = 2;;) {
+      launch_est_vec(h->stream, EST_SET_UNIT, nF, v, yv, xi, est);
+      solve(v);
+      launch_est_vec(h->stream, EST_SIGNS, nF, v, yv, xi, est);
+      TRY(read());
+      if (!st.changed || st.ynorm <= e) {
+        e = std::max(e, st.ynorm);
+        break;
+      }
+      e = st.ynorm;
+      solve(xi);
+      launch_est_vec(h->stream, EST_ARGMAX, nF, v, yv, xi, est);
+      TRY(read());
+      ++rounds;
+      if (st.zjlast == st.zmax || rounds > 5) break;
+    }
+    launch_est_vec(h->stream, EST_SET_ALT, nF, v, yv, xi, est);
+    solve(v);
+    launch_est_vec(h->stream, EST_SIGNS, nF, v, yv, xi, est);
+    TRY(read());
+    e = std::max(e, 2.0 * st.ynorm / (3.0 * nF));
+  }
+  if (!(e < INFINITY) || !(st.hnorm < INFINITY)) {
+    *out = INFINITY;
+    return NNLS_OK;
+  }
+  *out = 0.1 * st.hnorm * e * 2.220446049250313e-16;
+  return NNLS_OK;
+}
+
 // x_F for the current split (Eq. 4 by the normal equations, Sec. 2.1): factor H_FF with
 // the forward solve fused, then the backward solve scattered into x.  In NNLS_FP32_IR the
 // factor is float32 and x_F is refined in float64 against the residual from A,
@@ -503,7 +585,8 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
                                      : (2.0 * 8.0 * (double)m * n + 32.0 * m + 24.0 * n);
   // NNLS_FLAG_REFINE_FINAL: once a split is feasible, refine its x_F in float64 against the
   // residual from A with the split's own factor, and classify the refined x and y again
-  const bool final_refine = (o.flags & NNLS_FLAG_REFINE_FINAL) != 0 && o.precision == NNLS_FP64;
+  const bool auto_refine = (o.flags & NNLS_FLAG_REFINE_AUTO) != 0 && o.precision == NNLS_FP64;
+  const bool final_refine = ((o.flags & NNLS_FLAG_REFINE_FINAL) != 0 || auto_refine) && o.precision == NNLS_FP64;
   bool refined = false;
   int last_nF = 0;
   for (;;) {
@@ -519,6 +602,15 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
     if (c.status != 0) break;
     if (c.done) {
       if (!final_refine || refined || last_nF == 0) break;
+      if (auto_refine && !(o.flags & NNLS_FLAG_REFINE_FINAL)) {
+        // refine only when the split's predicted error misses the target
+        double est_rel = INFINITY;
+        const int64_t pe2 = prof_begin(h, NNLS_PROF_REFINE);
+        TRY(estimate_rel_err(h, P, last_nF, &est_rel));
+        prof_end(h, pe2, 0.0);
+        if (info) info->est_rel_err = est_rel;
+        if (est_rel <= o.ir_rtol) break;
+      }
       int outcome = STALLED;
       const double l_bytes = 8.0 * (double)tile_count((last_nF + TILE - 1) / TILE) * TILE_ELEMS;
       TRY(refine(h, P, last_nF, x, y, o, spmv_bytes, false, l_bytes, info, &outcome));
@@ -582,6 +674,7 @@ int solve_common(nnls_handle* h, const Problem& P, double* x, double* y, const n
   if (info) {
     std::memset(info, 0, sizeof(*info));
     info->failed_index = -1;
+    info->est_rel_err = -1.0;
   }
   if (!h) return set_info_status(info, NNLS_ERR_INVALID_ARG);
   h->trace.clear();
@@ -626,7 +719,7 @@ void release_workspace(nnls_handle* h) {
   DevBuf* bufs[] = {&h->err, &h->ctrl, &h->rowcnt, &h->rowptr, &h->colidx, &h->valr, &h->hptr,
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
                     &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart, &h->spart, &h->spflag,
-                    &h->upcnt, &h->prow, &h->pval, &h->pcnt, &h->Fold, &h->zr,
+                    &h->upcnt, &h->prow, &h->pval, &h->pcnt, &h->Fold, &h->zr, &h->est, &h->ev, &h->exi,
                     &h->bprobs, &h->border, &h->binfo, &h->bws};
   for (DevBuf* b : bufs) {
     if (b->p) (void)hipFree(b->p);
@@ -706,7 +799,7 @@ int nnls_destroy(nnls_handle* h) {
   DevBuf* bufs[] = {&h->err, &h->ctrl, &h->rowcnt, &h->rowptr, &h->colidx, &h->valr, &h->hptr,
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
                     &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart, &h->spart, &h->spflag,
-                    &h->upcnt, &h->prow, &h->pval, &h->pcnt, &h->Fold, &h->zr,
+                    &h->upcnt, &h->prow, &h->pval, &h->pcnt, &h->Fold, &h->zr, &h->est, &h->ev, &h->exi,
                     &h->bprobs, &h->border, &h->binfo, &h->bws};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
@@ -765,6 +858,7 @@ int nnls_solve_dense_batched(nnls_handle* h, int32_t batch, const int32_t* m, co
     for (int i = 0; i < batch; ++i) {
       std::memset(&info[i], 0, sizeof(nnls_info));
       info[i].failed_index = -1;
+      info[i].est_rel_err = -1.0;
     }
   if (batch == 0) return NNLS_OK;
   for (int i = 0; i < batch; ++i) {

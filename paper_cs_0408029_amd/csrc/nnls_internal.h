@@ -126,6 +126,20 @@ void launch_dual_dense(hipStream_t s, int m, int n, const double* A, int lda, co
 void launch_ir_update(hipStream_t s, int nF, const int32_t* Flist, const double* d, double* x,
                       Ctrl* ctrl);
 
+// condition estimate of the final F-block (k_cond.hip)
+struct CondEst {
+  double hnorm;    // ||H_FF||_1 (set to 0 before the norm kernel)
+  double ynorm;    // ||y||_1 of the last EST_SIGNS step
+  double zmax;     // max |z| of the last EST_ARGMAX step
+  double zjlast;   // |z| at the index chosen before that step
+  int32_t j;       // current index (-1: none yet)
+  int32_t changed; // EST_SIGNS: some sign differed from the stored ones
+};
+enum { EST_SET_UNIFORM = 0, EST_SET_UNIT = 1, EST_SET_ALT = 2, EST_SIGNS = 3, EST_ARGMAX = 4 };
+void launch_block_onenorm(hipStream_t s, int nF, GramLower g, const int32_t* upcnt, const int32_t* pos,
+                          const double* Hd, int64_t ldh, const int32_t* Flist, CondEst* est);
+void launch_est_vec(hipStream_t s, int mode, int nF, double* v, const double* y, double* xi, CondEst* est);
+
 // factorisation and triangular solves (k_chol.hip)
 struct FactorArgs {
   int nF;                 // order of the F-block

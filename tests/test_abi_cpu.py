@@ -57,7 +57,7 @@ def test_status_strings(lib):
 
 def test_struct_sizes_match_header(lib):
     assert C.sizeof(N.nnls_options) == 40
-    assert C.sizeof(N.nnls_info) == 48
+    assert C.sizeof(N.nnls_info) == 56
     assert C.sizeof(N.nnls_trace_row) == 24
 
 

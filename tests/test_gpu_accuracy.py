@@ -138,3 +138,64 @@ def test_final_refinement_keeps_parity_on_sparse_workload(h):
     assert np.linalg.norm(x - res.x) <= 1e-10 * np.linalg.norm(res.x)
     assert np.linalg.norm(x - inst.x_star) <= np.linalg.norm(res.x - inst.x_star) + 1e-14 * np.linalg.norm(inst.x_star)
     assert info.ir_steps >= 1
+
+
+def _solve_dense_flags(h, A, b, flags):
+    x = torch.empty(A.shape[1], dtype=torch.float64, device=DEV)
+    y = torch.empty_like(x)
+    st, info = N.nnls_solve_dense(h, colmajor_dev(A), t(b), x, y, N.default_options(flags=flags))
+    assert st == N.NNLS_OK
+    return x.cpu().numpy(), y.cpu().numpy(), info
+
+
+def test_condition_estimate_matches_oracle_and_brackets_exact(h):
+    """NNLS_FLAG_REFINE_AUTO forms 0.1 kappa_1(A_F^T A_F) eps from the split's factor (Sec. 3's
+    dpocon test): the same estimate as the oracle's on the same F-block, at most the exact
+    value and at least a third of it."""
+    from oracle import gram, predicted_rel_error, principal_block
+    eps = np.finfo(np.float64).eps
+    for lkap in (1.5, 2.5, 3.5, 4.5):
+        for s in range(3):
+            A, xt, b = W.svd_conditioned(500 + s, 10 ** lkap)
+            x, y, info = _solve_dense_flags(h, A, b, N.NNLS_FLAG_REFINE_AUTO)
+            H, _ = gram(A, b)
+            Hff = principal_block(H, np.flatnonzero(x > 0))
+            Hff = Hff.toarray() if hasattr(Hff, "toarray") else Hff
+            exact = 0.1 * np.abs(Hff).sum(axis=0).max() * np.abs(np.linalg.inv(Hff)).sum(axis=0).max() * eps
+            est = info.est_rel_err
+            assert exact / 3 <= est <= exact * (1 + 1e-4), (lkap, s, est, exact)
+            assert est == pytest.approx(predicted_rel_error(Hff), rel=1e-4), (lkap, s)
+
+
+def test_auto_refinement_runs_only_when_the_estimate_misses_the_target(h):
+    """Well conditioned: no refinement, the plain float64 result bit for bit.  kappa(A) = 1e4
+    (predicted error ~1e-8 > ir_rtol): refined, the REFINE_FINAL result bit for bit."""
+    A, xt, b = W.svd_conditioned(601, 10 ** 1.5)
+    x0, _, _ = _solve_dense_flags(h, A, b, 0)
+    xa, _, ia = _solve_dense_flags(h, A, b, N.NNLS_FLAG_REFINE_AUTO)
+    assert 0 < ia.est_rel_err <= 1e-12 and ia.ir_steps == 0
+    assert np.array_equal(x0, xa)
+    A, xt, b = W.svd_conditioned(602, 1e4)
+    xf, _, i_f = _solve_dense_flags(h, A, b, N.NNLS_FLAG_REFINE_FINAL)
+    xa, ya, ia = _solve_dense_flags(h, A, b, N.NNLS_FLAG_REFINE_AUTO)
+    assert ia.est_rel_err > 1e-12 and ia.ir_steps == i_f.ir_steps >= 1
+    assert i_f.est_rel_err == -1.0
+    assert np.array_equal(xf, xa)
+    assert np.linalg.norm(xa - xt) / np.linalg.norm(xt) < 1e-11
+
+
+def test_auto_refinement_on_the_sparse_workload(h):
+    """Sparse source (whole Gram columns restricted to F): the estimate brackets the exact
+    value; this well-conditioned workload needs no refinement."""
+    from _gpu_util import solve_csc
+    from oracle import gram, principal_block
+    inst = W.sparse_large(1002, m=6000, n=1200)
+    st, info, x, y, trace = solve_csc(h, inst.A, inst.b, flags=N.NNLS_FLAG_REFINE_AUTO)
+    assert st == N.NNLS_OK and np.array_equal(x > 0, inst.active)
+    H, _ = gram(inst.A, inst.b)
+    Hff = principal_block(H, np.flatnonzero(x > 0))
+    Hff = Hff.toarray() if hasattr(Hff, "toarray") else np.asarray(Hff)
+    eps = np.finfo(np.float64).eps
+    exact = 0.1 * np.abs(Hff).sum(axis=0).max() * np.abs(np.linalg.inv(Hff)).sum(axis=0).max() * eps
+    assert exact / 3 <= info.est_rel_err <= exact * (1 + 1e-4)
+    assert info.ir_steps == 0
