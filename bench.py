@@ -99,8 +99,9 @@ def bench_batch(args):
     ys = [torch.empty(i.n, dtype=torch.float64, device=dev) for i in insts]
     h = N.Handle(0)
     prec = N.NNLS_FP64 if args.precision == "fp64" else N.NNLS_FP32_IR
-    opts = N.default_options(precision=prec)
-    popts = N.default_options(precision=prec, flags=N.NNLS_FLAG_PROFILE)
+    gflag = N.NNLS_FLAG_GRAM_DUAL if args.gram_dual else 0
+    opts = N.default_options(precision=prec, flags=gflag)
+    popts = N.default_options(precision=prec, flags=N.NNLS_FLAG_PROFILE | gflag)
 
     packed = N.BatchedArgs(As, bs, xs, ys)   # descriptors marshalled once, outside the timing
 
@@ -156,7 +157,7 @@ def bench_batch(args):
         "data": "synthetic",
         "config": {"workload": f"{len(insts)} dense problems, n~U{{16..256}}, m~U{{2n..4n}}, "
                                "N(0,1)/sqrt(m), 40% active, seed 1003",
-                   "path": "batched, one launch"},
+                   "path": "batched, one launch" + (", y_G from the Gram matrix (Eq. 3)" if args.gram_dual else "")},
         "max_rel_err_vs_planted": max(errs), "free_set_matches": f"{match}/{len(insts)}",
         "plain_fp64_solves_per_s": round(plain, 2), "plain_sample": k,
         "roofline": {"bound": "mfma", "kernel": "k_batched", "achieved": round(achieved, 4) if achieved else None,
@@ -656,6 +657,8 @@ def main():
                     help="fp64: the plain FP64 path (the metric's reference); fp32ir: float32 factor "
                          "with float64 refinement")
     ap.add_argument("--batch", type=int, default=4096, help="dense_batch: number of problems")
+    ap.add_argument("--gram-dual", action="store_true",
+                    help="dense_batch: y_G = H_GF x_F - c_G (Eq. 3) instead of the residual form (Eq. 5)")
     ap.add_argument("--plain-sample", type=int, default=256,
                     help="dense_batch: problems solved one per call on the plain float64 path")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: offered requests/s")

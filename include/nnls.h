@@ -72,6 +72,11 @@ typedef enum {
                                      and run the NNLS_FLAG_REFINE_FINAL step only when the
                                      predicted error 0.1 kappa_1 eps exceeds ir_rtol (the
                                      error control of Sec. 3)                                */
+#define NNLS_FLAG_GRAM_DUAL 16u  /* dense problems (single and batched): y_G for the sign
+                                     tests from the cached Gram matrix, H_GF x_F - c_G (Eq. 3),
+                                     which reads |G| x |F| of H instead of A twice (Eq. 5,
+                                     the default); the sparse path ignores it, refinement
+                                     and the final recomputation keep Eq. 5               */
 #define NNLS_FLAG_NO_FACTOR_REUSE 4u /* refactor the whole F-block in every pivot
                                      iteration.  By default F is ordered so that the leading
                                      tile columns no exchange touched come first, and their

@@ -28,6 +28,7 @@ NNLS_FLAG_PROFILE = 1
 NNLS_FLAG_REFINE_FINAL = 2
 NNLS_FLAG_NO_FACTOR_REUSE = 4
 NNLS_FLAG_REFINE_AUTO = 8
+NNLS_FLAG_GRAM_DUAL = 16
 
 NNLS_PROFILE_CLASSES = 8
 PROFILE_CLASS_NAMES = ["gram", "control", "cholesky", "trsv", "residual", "refine", "batched", "dual"]

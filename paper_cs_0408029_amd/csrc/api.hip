@@ -570,6 +570,7 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
   h->fact_prec = -1;
   const int want_prec = o.precision == NNLS_FP32_IR ? 1 : 0;
   const bool reuse = (o.flags & NNLS_FLAG_NO_FACTOR_REUSE) == 0;
+  const bool gram_dual = (o.flags & NNLS_FLAG_GRAM_DUAL) != 0 && !P.sparse;   // Eq. 3 for y_G
   TRY(ensure(h, h->colcnt, sizeof(int32_t) * (size_t)ncol, true));
   TRY(ensure(h, h->dflag, sizeof(int32_t) * (size_t)ncol, true));
   const int max_iter = o.max_iter > 0 ? o.max_iter : 5 * n + 100;
@@ -641,7 +642,11 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
     if (nF > 0) TRY(solve_free(h, P, nF, c.j0, x, y, o, spmv_bytes, &y_done, &j0_used, info));
     row.n_reused = j0_used * TILE;
     h->trace.push_back(row);
-    if (!y_done) {
+    if (!y_done && gram_dual) {
+      pe = prof_begin(h, NNLS_PROF_DUAL);
+      launch_dual_gram_dense(h->stream, n, (const double*)h->Hd.p, n, (const double*)h->c.p, flags, Flist, nF, x, y);
+      prof_end(h, pe, 8.0 * (double)(n - nF) * nF + 8.0 * nF + 17.0 * n);
+    } else if (!y_done) {
       pe = prof_begin(h, NNLS_PROF_RESIDUAL);
       residual_dual(h, P, x, y, nullptr);
       prof_end(h, pe, spmv_bytes);
@@ -913,6 +918,7 @@ int nnls_solve_dense_batched(nnls_handle* h, int32_t batch, const int32_t* m, co
   ba.fp32 = o.precision == NNLS_FP32_IR ? 1 : 0;
   ba.ir_max_steps = o.ir_max_steps;
   ba.ir_rtol = o.ir_rtol;
+  ba.gram_dual = (o.flags & NNLS_FLAG_GRAM_DUAL) != 0 ? 1 : 0;
   h->profiling = h->profile_always || (o.flags & NNLS_FLAG_PROFILE) != 0;
   double flops = 0.0;
   for (int i = 0; i < batch; ++i) flops += (double)n[i] * n[i] * m[i];

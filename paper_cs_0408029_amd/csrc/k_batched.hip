@@ -351,6 +351,28 @@ __device__ __noinline__ void wg_residual_dual(const double* __restrict__ A, int 
   __syncthreads();
 }
 
+// Eq. 3 on G: y_j = sum_p H[F_p, j] x[F_p] - c_j (H symmetric: column j), y_F = 0.
+__device__ __noinline__ void wg_dual_gram(const double* __restrict__ H, int n, const double* __restrict__ c,
+                                          const uint8_t* flags, const int32_t* Flist, int nF,
+                                          const double* x, double* y) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int j = w; j < n; j += BT / 64) {
+    if (flags[j]) {
+      if (lane == 0) y[j] = 0.0;
+      continue;
+    }
+    const double* col = H + (int64_t)j * n;
+    double s = 0.0;
+    for (int p = lane; p < nF; p += 64) {
+      const int i = Flist[p];
+      s = fma(col[i], x[i], s);
+    }
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+    if (lane == 0) y[j] = s - c[j];
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
   __shared__ double S64[TILE * LDT];
   __shared__ double W64[TILE * LDT];
@@ -549,7 +571,10 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
         break;
       }
     }
-    if (!y_done) wg_residual_dual(P.A, P.lda, m, n, P.b, flags, Flist, nF, x, r, y, nullptr);
+    if (!y_done) {
+      if (a.gram_dual) wg_dual_gram(H, n, c, flags, Flist, nF, x, y);
+      else wg_residual_dual(P.A, P.lda, m, n, P.b, flags, Flist, nF, x, r, y, nullptr);
+    }
   }
   __syncthreads();
   if (tid == 0) {

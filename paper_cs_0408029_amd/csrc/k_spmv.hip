@@ -149,6 +149,30 @@ __global__ __launch_bounds__(256) void k_dual_dense(int m, int n, const double* 
   }
 }
 
+// Eq. 3 on G: y_j = sum_p H[F_p, j] x[F_p] - c_j for j in G (H symmetric, so column j),
+// y_j = 0 on F.  One wave per column, lane-strided over the F positions, fixed xor tree.
+__global__ __launch_bounds__(256) void k_dual_gram_dense(int n, const double* __restrict__ H, int64_t ldh,
+                                                         const double* __restrict__ c,
+                                                         const uint8_t* __restrict__ flags,
+                                                         const int32_t* __restrict__ Flist, int nF,
+                                                         const double* __restrict__ x, double* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= n) return;
+  if (flags[j]) {
+    if (lane == 0) y[j] = 0.0;
+    return;
+  }
+  const double* col = H + (int64_t)j * ldh;
+  double s = 0.0;
+  for (int p = lane; p < nF; p += 64) {
+    const int i = Flist[p];
+    s = fma(col[i], x[i], s);
+  }
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+  if (lane == 0) y[j] = s - c[j];
+}
+
 }  // namespace
 
 void launch_residual_csr(hipStream_t s, int m, int64_t nnz, const int32_t* rowptr, const int32_t* colidx,
@@ -204,6 +228,13 @@ int dense_residual_chunks(int m, int n) {
 void launch_dual_dense(hipStream_t s, int m, int n, const double* A, int lda, const double* r,
                        const uint8_t* flags, double* y, double* gfree) {
   hipLaunchKernelGGL(k_dual_dense, dim3((n + 3) / 4), dim3(256), 0, s, m, n, A, lda, r, flags, y, gfree);
+}
+
+void launch_dual_gram_dense(hipStream_t s, int n, const double* H, int64_t ldh, const double* c,
+                            const uint8_t* flags, const int32_t* Flist, int nF, const double* x,
+                            double* y) {
+  hipLaunchKernelGGL(k_dual_gram_dense, dim3((n + 3) / 4), dim3(256), 0, s, n, H, ldh, c, flags, Flist, nF,
+                     x, y);
 }
 
 }  // namespace nnls

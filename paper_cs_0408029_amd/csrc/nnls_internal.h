@@ -122,6 +122,10 @@ void launch_residual_dense(hipStream_t s, int m, int n, const double* A, int lda
 int dense_residual_chunks(int m, int n);
 void launch_dual_dense(hipStream_t s, int m, int n, const double* A, int lda, const double* r,
                        const uint8_t* flags, double* y, double* gfree = nullptr);
+// y_G = H_GF x_F - c_G from a dense symmetric H (Eq. 3), y_F = 0
+void launch_dual_gram_dense(hipStream_t s, int n, const double* H, int64_t ldh, const double* c,
+                            const uint8_t* flags, const int32_t* Flist, int nF, const double* x,
+                            double* y);
 // x[Flist[p]] -= d[p] for p < nF; writes max |d| and max |x_F| into ctrl (one workgroup)
 void launch_ir_update(hipStream_t s, int nF, const int32_t* Flist, const double* d, double* x,
                       Ctrl* ctrl);
@@ -211,6 +215,7 @@ struct BatchArgs {
   int fp32;               // float32 factor + float64 refinement
   int ir_max_steps;
   double ir_rtol;
+  int gram_dual;          // y_G from the cached Gram matrix (Eq. 3) instead of Eq. 5
 };
 size_t batched_workspace_bytes(int m, int n);
 void launch_batched(hipStream_t s, const BatchArgs& a, int grid);

@@ -136,3 +136,21 @@ def test_packed_descriptors_reused(h, batch24):
     for a, x, inst in zip(first, xs, insts):
         assert np.array_equal(a, x.cpu().numpy())
         assert np.array_equal(a > 0, inst.active)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-8)])
+def test_gram_dual_matches_oracle(h, batch24, precision, tol):
+    """NNLS_FLAG_GRAM_DUAL (y_G = H_GF x_F - c_G, Eq. 3, from the workspace Gram matrix): the
+    oracle's free sets and x, and y within the same tolerance; the same pivot steps as the
+    residual form (Eq. 5)."""
+    problems, insts = batch24
+    st, infos, xs, ys = run_batch(h, problems, precision=precision, flags=N.NNLS_FLAG_GRAM_DUAL)
+    st0, infos0, xs0, ys0 = run_batch(h, problems, precision=precision)
+    assert st == st0 == N.NNLS_OK
+    for inst, info, info0, x, y, x0 in zip(insts, infos, infos0, xs, ys, xs0):
+        res = bpp_solve(inst.A, inst.b)
+        assert info.status == N.NNLS_OK and info.iterations == info0.iterations
+        assert np.array_equal(x > 0, res.x > 0) and np.array_equal(x > 0, x0 > 0)
+        assert relerr(x, res.x) <= tol
+        assert np.linalg.norm(y - res.y) <= tol * max(np.linalg.norm(res.y), 1.0)
+        assert np.all(x >= 0) and np.all(y >= 0) and np.dot(x, y) == 0.0

@@ -158,6 +158,23 @@ def test_kept_factor_tiles_match_full_refactor(h, m, n, cap, precision, tol):
     assert np.linalg.norm(y1 - y2) <= tol * max(np.linalg.norm(y2), 1.0)
 
 
+@pytest.mark.parametrize("m,n,seed", [(300, 100, 2), (1100, 520, 4), (3000, 1000, 5)])
+def test_gram_dual_dense_matches_oracle(h, m, n, seed):
+    """NNLS_FLAG_GRAM_DUAL on the dense single-problem path (y_G from the cached dense Gram
+    matrix, Eq. 3): the oracle's pivot steps, free set, x and y."""
+    inst = W.dense_planted(seed, m, n)
+    res = bpp_solve(inst.A, inst.b)
+    st, info, x, y, trace = solve_dense(h, inst.A, inst.b, flags=N.NNLS_FLAG_GRAM_DUAL)
+    check_parity(res, st, info, x, y, trace)
+
+
+def test_gram_dual_is_ignored_on_the_sparse_path(h):
+    inst = W.sparse_large(1002, m=6000, n=1200)
+    a = solve_csc(h, inst.A, inst.b)
+    b = solve_csc(h, inst.A, inst.b, flags=N.NNLS_FLAG_GRAM_DUAL)
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3]) and a[4] == b[4]
+
+
 def test_empty_free_set(h):
     A = np.array([[1.0, 0.0], [0.0, 1.0], [1.0, 1.0]])
     b = np.array([-1.0, -2.0, 0.5])
