@@ -39,28 +39,44 @@ double now_ms() {
 
 // Pinned host blocks in power-of-two size classes from 4 KiB, reused across requests so
 // that submit does not pay for a page-locking allocation each time.
+// Pinned host blocks in power-of-two size classes (4 KiB << c).  Blocks up to SLAB / 4
+// are carved from SLAB-byte slabs, so that a growing backlog of requests costs one
+// page-locking allocation per slab rather than one per request; larger blocks are
+// allocated alone.  Blocks go back to their class's free list and are reused; everything
+// is released when the pool ends.
 class PinnedPool {
  public:
   ~PinnedPool() {
-    for (auto& cls : free_)
-      for (void* p : cls) (void)hipHostFree(p);
+    for (void* p : slabs_) (void)hipHostFree(p);
+    for (void* p : singles_) (void)hipHostFree(p);
   }
   void* get(size_t bytes, int* cls_out) {
     const int c = size_class(bytes);
     *cls_out = c;
-    {
-      std::lock_guard<std::mutex> lk(mu_);
-      if ((int)free_.size() > c && !free_[(size_t)c].empty()) {
-        void* p = free_[(size_t)c].back();
-        free_[(size_t)c].pop_back();
+    std::lock_guard<std::mutex> lk(mu_);
+    if ((int)free_.size() <= c) free_.resize((size_t)c + 1);
+    std::vector<void*>& fl = free_[(size_t)c];
+    if (fl.empty()) {
+      const size_t blk = (size_t)4096 << c;
+      void* p = nullptr;
+      if (blk <= SLAB / 4) {
+        if (hipHostMalloc(&p, SLAB, hipHostMallocDefault) != hipSuccess) {
+          (void)hipGetLastError();
+          return nullptr;
+        }
+        slabs_.push_back(p);
+        for (size_t o = blk; o + blk <= SLAB; o += blk) fl.push_back((char*)p + o);
         return p;
       }
+      if (hipHostMalloc(&p, blk, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+      singles_.push_back(p);
+      return p;
     }
-    void* p = nullptr;
-    if (hipHostMalloc(&p, (size_t)4096 << c, hipHostMallocDefault) != hipSuccess) {
-      (void)hipGetLastError();
-      return nullptr;
-    }
+    void* p = fl.back();
+    fl.pop_back();
     return p;
   }
   void put(void* p, int cls) {
@@ -71,6 +87,7 @@ class PinnedPool {
   }
 
  private:
+  static constexpr size_t SLAB = (size_t)64 << 20;
   static int size_class(size_t bytes) {
     int c = 0;
     while (((size_t)4096 << c) < bytes) ++c;
@@ -78,6 +95,7 @@ class PinnedPool {
   }
   std::mutex mu_;
   std::vector<std::vector<void*>> free_;
+  std::vector<void*> slabs_, singles_;
 };
 
 struct DevVec {
