@@ -698,9 +698,13 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
       const int p = I * TILE + tid;
       outv[p] = v;
       ring[s % TD][tid] = v;
-      if (!FWD && a.out && p < a.nF) a.out[a.Flist ? a.Flist[p] : p] = v;
     }
     publish_store(done, s + 1);
+  }
+  // x into the caller's vector through the F list, off the chain (this workgroup wrote outv)
+  if (!FWD && a.out) {
+    __syncthreads();
+    for (int p = tid; p < a.nF; p += 256) a.out[a.Flist ? a.Flist[p] : p] = outv[p];
   }
 }
 
