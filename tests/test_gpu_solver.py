@@ -175,6 +175,28 @@ def test_gram_dual_is_ignored_on_the_sparse_path(h):
     assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3]) and a[4] == b[4]
 
 
+def test_kept_tiles_when_the_free_set_grows(h):
+    """|F| grows from 439 to 515 in the second iteration (7 -> 9 tile rows): on a fresh
+    handle the factor buffers are reallocated there, which must end the reuse for that
+    iteration only.  Oracle parity, and the same result as refactoring every iteration."""
+    rng = np.random.default_rng(3)
+    n = int(rng.choice([150, 300, 600]))
+    m = n + int(rng.integers(5, n))
+    A = rng.standard_normal((m, n))
+    xs = np.where(rng.random(n) < 0.7, rng.uniform(0.1, 1, n), 0.0)
+    b = A @ xs + 0.5 * rng.standard_normal(m)
+    assert (m, n) == (655, 600)
+    res = bpp_solve(A, b)
+    with N.Handle(0) as fresh:
+        st, info, x, y, trace = solve_dense(fresh, A, b)
+        tr = N.nnls_get_trace(fresh, reused=True)
+    assert [r[4] for r in tr][:2] == [439, 515] and tr[1][5] == 0
+    check_parity(res, st, info, x, y, trace, rtol=1e-9)
+    st2, info2, x2, y2, trace2 = solve_dense(h, A, b, flags=N.NNLS_FLAG_NO_FACTOR_REUSE)
+    assert trace2 == trace and np.array_equal(x > 0, x2 > 0)
+    assert relerr(x, x2) <= 1e-11
+
+
 def test_empty_free_set(h):
     A = np.array([[1.0, 0.0], [0.0, 1.0], [1.0, 1.0]])
     b = np.array([-1.0, -2.0, 0.5])
