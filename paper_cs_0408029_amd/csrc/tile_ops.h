@@ -132,10 +132,9 @@ __device__ inline void store16(T* X, int r0, int c0, typename MF<T>::acc v) {
 }
 
 __device__ inline double rsqrt_refined(double d) {
-  double y = __builtin_amdgcn_rsq(d);
-  y = y * fma(-0.5 * d, y * y, 1.5);
-  y = y * fma(-0.5 * d, y * y, 1.5);
-  return y;
+  const double y = __builtin_amdgcn_rsq(d);
+  const double e = fma(-d, y * y, 1.0);
+  return fma(y * e, fma(0.375, e, 0.5), y);
 }
 __device__ inline float rsqrt_refined(float d) {
   float y = __builtin_amdgcn_rsqf(d);
@@ -147,9 +146,11 @@ __device__ inline float rsqrt_refined(float d) {
 // keep row i of the block in registers; lanes 16..31 start from column i of the identity
 // and go through the very same updates, which turns them into column i of L^-1 (forward
 // substitution, one column per lane, in step with the factorisation).  Pivots come from a
-// reciprocal square root refined by two Newton steps (the hardware estimate is good to
-// about 2^-24, one step leaves ~40 ulp); each step's column of L reaches every lane as
-// wave-uniform values read from the factor lanes, so the pivot chain never touches LDS.
+// reciprocal square root refined by one third-order step (the hardware estimate is good to
+// about 2^-24; with e = 1 - d y^2 the step y (1 + e/2 + 3e^2/8) leaves about (5/16) e^3,
+// under one ulp); a pivot that is not positive and finite is flagged and continues as 1
+// without a branch.  Each step's column of L reaches every lane as wave-uniform values
+// read from the factor lanes, so the pivot chain never touches LDS.
 // L goes back into S, its inverse into W.
 template <typename T>
 __device__ inline void diag16(T* S, T* W, int o, const PivotReport& rep) {
@@ -164,8 +165,9 @@ __device__ inline void diag16(T* S, T* W, int o, const PivotReport& rep) {
   for (int c = 0; c < 16; ++c) {
     const bool bad = !(d > (T)0) || !isfinite(d);
     if (bad && firstbad < 0) firstbad = c;
-    const T y = bad ? (T)1 : rsqrt_refined(d);   // 1 / L_cc
-    const T l = bad ? (T)1 : d * y;               // L_cc
+    const T dd = bad ? (T)1 : d;
+    const T y = rsqrt_refined(dd);    // 1 / L_cc
+    const T l = dd * y;               // L_cc
     // factor lanes: L_ic (L_cc on the diagonal); inverse lanes: (L^-1)_ci
     const T lic = (i == c && !inv) ? l : r[c] * y;
     r[c] = lic;
