@@ -18,8 +18,6 @@ namespace {
 
 constexpr int BT = 256;   // threads per workgroup
 
-__device__ inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
-
 // Workspace layout of one problem (byte offsets from its base).
 struct WsLayout {
   size_t H, c, r, flags, Flist, Lt, Dv, z, xF, g, total;

@@ -267,24 +267,36 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
   publish_tile(&a.tflag[ti], &a.colcnt[J], a.epoch);
 }
 
-// acc (MFMA accumulator layout of this wave's 32 x 32 quadrant) -= P Q^T, P from global
-// (column-major, leading dimension TILE) or LDS (leading dimension LDT), Q from LDS.
-template <typename T, bool P_LDS>
-__device__ __forceinline__ void quad_update(typename MF<T>::acc (&acc)[2][2], const T* P, const T* Q, int qr, int qc,
-                                            int lane) {
+// The walker's update of the ten lower 16 x 16 blocks of a diagonal tile, U -= X X^T,
+// spread over four waves (three blocks for waves 0..2, one for wave 3).  A wave's blocks
+// (I0, J0), (I1, J1), (I2, J2), the first NB of them, share the block rows of X they read.
+template <typename T, int NB, int I0, int J0, int I1, int J1, int I2, int J2>
+__device__ __forceinline__ void lower_update(typename MF<T>::acc (&acc)[3], const T* U, const T* X, int lane) {
   typedef MF<T> M;
+  constexpr int BI[3] = {I0, I1, I2}, BJ[3] = {J0, J1, J2};
   const int lr = lane & 15, lk = lane >> 4;
-  constexpr int LDP = P_LDS ? LDT : TILE;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = load16<T>(U, 16 * BI[b], 16 * BJ[b]);
 #pragma unroll
   for (int kk = 0; kk < TILE; kk += 4) {
     const int kc = kk + lk;
-    const T a0 = -P[(qr + lr) + kc * LDP], a1 = -P[(qr + 16 + lr) + kc * LDP];
-    const T b0 = Q[(qc + lr) + kc * LDT], b1 = Q[(qc + 16 + lr) + kc * LDT];
-    acc[0][0] = M::op(a0, b0, acc[0][0]);
-    acc[0][1] = M::op(a0, b1, acc[0][1]);
-    acc[1][0] = M::op(a1, b0, acc[1][0]);
-    acc[1][1] = M::op(a1, b1, acc[1][1]);
+    T x[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      bool used = false;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) used = used || BI[b] == rb || BJ[b] == rb;
+      x[rb] = used ? X[(16 * rb + lr) + kc * LDT] : (T)0;
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = M::op(-x[BI[b]], x[BJ[b]], acc[b]);
   }
+}
+template <typename T, int NB, int I0, int J0, int I1, int J1, int I2, int J2>
+__device__ __forceinline__ void lower_store(const typename MF<T>::acc (&acc)[3], T* U, int lane) {
+  constexpr int BI[3] = {I0, I1, I2}, BJ[3] = {J0, J1, J2};
+#pragma unroll
+  for (int b = 0; b < NB; ++b) store16<T>(U, 16 * BI[b], 16 * BJ[b], acc[b]);
 }
 
 // Copy a 64 x 64 tile (column-major, leading dimension TILE) from global memory into LDS
@@ -327,18 +339,6 @@ __device__ __forceinline__ void tile_to_global(T* __restrict__ g, const T* X, in
   for (int q = 0; q < TILE_ELEMS / 256; ++q) g[tid + q * 256] = v[q];
 }
 
-template <typename T>
-__device__ __forceinline__ void quad_store_lds(T* X, const typename MF<T>::acc (&acc)[2][2], int qr, int qc, int lane) {
-  typedef MF<T> M;
-  const int lr = lane & 15;
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) X[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT] = acc[bi][bj][v];
-}
-
 // The walker: one workgroup carries the column-to-column chain of the factorisation.  For
 // each column J it takes the partial sum that the diagonal tile (J, J) published (every
 // left-looking term except the one with L_{J,J-1}), applies that last term from LDS
@@ -370,23 +370,19 @@ __device__ __forceinline__ void walker(const FactorArgs& a, uint64_t wait_ticks,
   }
   for (int J = j0; J < nb; ++J) {
     const int tid = fresh_tid(), lane = tid & 63, w = tid >> 6;
-    const int qr = (w & 1) * 32, qc = (w >> 1) * 32;
     const int64_t td = tile_index(J, J);
     const bool sub = J + 1 < nb;
     const int64_t ts = sub ? tile_index(J + 1, J) : td;
     if (J > j0) {
-      // last term of the diagonal tile, from LDS
-      Acc acc[2][2];
-      {
-        const int lr = lane & 15;
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-          for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[bi][bj][v] = U[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT];
+      // last term of the diagonal tile, from LDS: the ten lower 16 x 16 blocks of
+      // U -= X X^T (X = L_{J,J-1}), three blocks per wave at most
+      Acc acc[3];
+      switch (__builtin_amdgcn_readfirstlane(w)) {
+        case 0: lower_update<T, 3, 0, 0, 3, 0, 3, 1>(acc, U, X, lane); break;
+        case 1: lower_update<T, 3, 1, 0, 1, 1, 3, 2>(acc, U, X, lane); break;
+        case 2: lower_update<T, 3, 2, 0, 2, 1, 3, 3>(acc, U, X, lane); break;
+        default: lower_update<T, 1, 2, 2, 0, 0, 0, 0>(acc, U, X, lane); break;
       }
-      if (!(qr < qc)) quad_update<T, true>(acc, X, X, qr, qc, lane);
       if (fwd) {   // row `lane`, columns 16 w .. 16 w + 15 of L_{J,J-1} z_{J-1}
         double t2 = 0.0;
 #pragma unroll
@@ -397,7 +393,12 @@ __device__ __forceinline__ void walker(const FactorArgs& a, uint64_t wait_ticks,
         s_part[w][lane] = t2;
       }
       __syncthreads();   // U and X fully read
-      quad_store_lds<T>(U, acc, qr, qc, lane);
+      switch (__builtin_amdgcn_readfirstlane(w)) {
+        case 0: lower_store<T, 3, 0, 0, 3, 0, 3, 1>(acc, U, lane); break;
+        case 1: lower_store<T, 3, 1, 0, 1, 1, 3, 2>(acc, U, lane); break;
+        case 2: lower_store<T, 3, 2, 0, 2, 1, 3, 3>(acc, U, lane); break;
+        default: lower_store<T, 1, 2, 2, 0, 0, 0, 0>(acc, U, lane); break;
+      }
     }
     if (fwd && tid < TILE) {
       const int p = J * TILE + tid;
@@ -448,30 +449,27 @@ __device__ __forceinline__ void walker(const FactorArgs& a, uint64_t wait_ticks,
     __syncthreads();   // L_JJ stored from U
     tile_to_lds<T>(dsub, U, tid);
     __syncthreads();
-    // L_{J+1,J} = S_{J+1,J} (L_JJ^-1)^T, the inverse's strict upper part being zero
-    Acc o[2][2];
+    // L_{J+1,J} = S_{J+1,J} (L_JJ^-1)^T: wave w forms block row w; block column bj takes
+    // the inverse's blocks (bj, kb) for kb <= bj only (the rest of its row is zero), which
+    // spreads the 160 block products evenly over the four waves
+    Acc o[4];
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) o[bi][bj][v] = (T)0;
+    for (int bj = 0; bj < 4; ++bj) o[bj] = Acc{};
     {
       const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
-      for (int kk = 0; kk < TILE; kk += 4) {
-        const int kc = kk + lk;
-        const T a0 = U[(qr + lr) + kc * LDT], a1 = U[(qr + 16 + lr) + kc * LDT];
-        const T b0 = (kc <= qc + lr) ? X[(qc + lr) + kc * LDT] : (T)0;
-        const T b1 = (kc <= qc + 16 + lr) ? X[(qc + 16 + lr) + kc * LDT] : (T)0;
-        o[0][0] = M::op(a0, b0, o[0][0]);
-        o[0][1] = M::op(a0, b1, o[0][1]);
-        o[1][0] = M::op(a1, b0, o[1][0]);
-        o[1][1] = M::op(a1, b1, o[1][1]);
-      }
+      for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+          const int kc = 16 * kb + kk + lk;
+          const T av = U[(16 * w + lr) + kc * LDT];
+#pragma unroll
+          for (int bj = kb; bj < 4; ++bj) o[bj] = M::op(av, X[(16 * bj + lr) + kc * LDT], o[bj]);
+        }
     }
     __syncthreads();   // U and X fully read
-    quad_store_lds<T>(U, o, qr, qc, lane);
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) store16<T>(U, 16 * w, 16 * bj, o[bj]);
     __syncthreads();
     tile_to_global<T>(dsub, U, tid);
     // one release covers L_JJ and L_{J+1,J}

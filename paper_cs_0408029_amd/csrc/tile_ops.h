@@ -189,53 +189,103 @@ __device__ inline void diag16(T* S, T* W, int o, const PivotReport& rep) {
   }
 }
 
+// Waits (bounded) until the workgroup-shared counter reaches `target`.
+__device__ inline void lds_wait_count(const int* cnt, int target) {
+  for (int guard = 0; guard < (1 << 22); ++guard) {
+    if (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= target) return;
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+__device__ inline void lds_post(int* cnt) {
+  if ((threadIdx.x & 63) == 0) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// The 16 x 16 block operations of the tile factor, all by one wave.
+template <typename T>
+__device__ inline void blk_panel(T* S, const T* W, int p, int q) {   // L_pq = A_pq W_qq^T
+  typename MF<T>::acc acc = {};
+  acc = mm16<T>(acc, (T)1, S, 16 * p, 16 * q, W, 16 * q, 16 * q, true);
+  store16<T>(S, 16 * p, 16 * q, acc);
+}
+template <typename T>
+__device__ inline void blk_trail(T* S, int p, int r, int q) {       // A_pr -= L_pq L_rq^T
+  typename MF<T>::acc acc = load16<T>(S, 16 * p, 16 * r);
+  acc = mm16<T>(acc, (T)-1, S, 16 * p, 16 * q, S, 16 * r, 16 * q, true);
+  store16<T>(S, 16 * p, 16 * r, acc);
+}
+// W_pq = -W_pp sum_{k=q}^{p-1} L_pk W_kq, the sum staged in the free upper block (0, sc) of S
+template <typename T>
+__device__ inline void blk_inverse(T* S, T* W, int p, int q, int sc) {
+  typename MF<T>::acc t = {};
+  for (int k = q; k < p; ++k) t = mm16<T>(t, (T)1, S, 16 * p, 16 * k, W, 16 * k, 16 * q, false);
+  store16<T>(S, 0, 16 * sc, t);
+  typename MF<T>::acc u = {};
+  u = mm16<T>(u, (T)-1, W, 16 * p, 16 * p, S, 0, 16 * sc, false);
+  store16<T>(W, 16 * p, 16 * q, u);
+}
+
 // Blocked Cholesky and inverse of the 64 x 64 tile in S (lower triangle) by the whole
-// workgroup: 4 x 4 blocks of 16; diagonal blocks by one wave, the panel and trailing
-// updates on MFMA across the four waves.  Leaves L in the lower triangle of S and L^-1
-// in the lower triangle of W.
+// workgroup: 4 x 4 blocks of 16.  Wave 0 carries the chain: after diagonal block q it
+// forms the panel block (q+1, q), applies its term to diagonal block q+1 and factors that
+// block at once.  Meanwhile waves 1..3 form the other panel blocks of column q, wait (on a
+// shared counter) for wave 0's panel block, apply the remaining trailing updates, and
+// build the off-diagonal blocks of the inverse whose inputs are final.  Leaves L in the
+// lower triangle of S and L^-1 in the lower triangle of W; the upper blocks of S are
+// scratch.
 template <typename T>
 __device__ inline void factor_invert_tile(T* S, T* W, const PivotReport& rep) {
-  typedef typename MF<T>::acc Acc;
+  __shared__ int cnt[3];
   const int w = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if (w == 0) diag16<T>(S, W, 16 * q, rep);
-    __syncthreads();
-    // panel: L_pq = A_pq W_qq^T
-    const int p = q + 1 + w;
-    if (p < 4) {
-      Acc acc = {};
-      acc = mm16<T>(acc, (T)1, S, 16 * p, 16 * q, W, 16 * q, 16 * q, true);
-      store16<T>(S, 16 * p, 16 * q, acc);
-    }
-    __syncthreads();
-    // trailing update: A_pr -= L_pq L_rq^T for q < r <= p
-    int idx = 0;
-    for (int rr = q + 1; rr < 4; ++rr)
-      for (int pp = rr; pp < 4; ++pp, ++idx)
-        if ((idx & 3) == w) {
-          Acc acc = load16<T>(S, 16 * pp, 16 * rr);
-          acc = mm16<T>(acc, (T)-1, S, 16 * pp, 16 * q, S, 16 * rr, 16 * q, true);
-          store16<T>(S, 16 * pp, 16 * rr, acc);
-        }
-    __syncthreads();
+  if (threadIdx.x == 64) cnt[0] = cnt[1] = cnt[2] = 0;
+  if (w == 0) diag16<T>(S, W, 0, rep);
+  __syncthreads();
+  // column 0: wave 0 -> (1,0), (1,1), diagonal 1; waves 1..3 -> (2,0), (3,0), then the
+  // trailing blocks (2,1) (3,1) (2,2) (3,2) (3,3) once all three panel blocks are in
+  if (w == 0) {
+    blk_panel<T>(S, W, 1, 0);
+    lds_post(&cnt[0]);
+    blk_trail<T>(S, 1, 1, 0);
+    diag16<T>(S, W, 16, rep);
+  } else {
+    if (w == 1) { blk_panel<T>(S, W, 2, 0); lds_post(&cnt[0]); }
+    if (w == 2) { blk_panel<T>(S, W, 3, 0); lds_post(&cnt[0]); }
+    lds_wait_count(&cnt[0], 3);
+    if (w == 1) { blk_trail<T>(S, 2, 1, 0); blk_trail<T>(S, 3, 2, 0); }
+    if (w == 2) { blk_trail<T>(S, 3, 1, 0); blk_trail<T>(S, 3, 3, 0); }
+    if (w == 3) blk_trail<T>(S, 2, 2, 0);
   }
-  // off-diagonal blocks of the inverse, by distance from the diagonal:
-  // W_pq = -W_pp sum_{k=q}^{p-1} L_pk W_kq
-  for (int dd = 1; dd < 4; ++dd) {
-    const int p = dd + w, q = w;
-    if (p < 4) {
-      Acc t = {};
-      for (int k = q; k < p; ++k) t = mm16<T>(t, (T)1, S, 16 * p, 16 * k, W, 16 * k, 16 * q, false);
-      // stage t in this wave's free upper block of S, then multiply by -W_pp
-      const int sr = (w == 3) ? 16 : 0, sc = (w == 3) ? 32 : 16 * (w + 1);
-      store16<T>(S, sr, sc, t);
-      Acc u = {};
-      u = mm16<T>(u, (T)-1, W, 16 * p, 16 * p, S, sr, sc, false);
-      store16<T>(W, 16 * p, 16 * q, u);
-    }
-    __syncthreads();
+  __syncthreads();
+  // column 1: wave 0 -> (2,1), (2,2), diagonal 2; wave 1 -> (3,1), then W_10;
+  // waves 2, 3 -> (3,2), (3,3) once (2,1) and (3,1) are in
+  if (w == 0) {
+    blk_panel<T>(S, W, 2, 1);
+    lds_post(&cnt[1]);
+    blk_trail<T>(S, 2, 2, 1);
+    diag16<T>(S, W, 32, rep);
+  } else if (w == 1) {
+    blk_panel<T>(S, W, 3, 1);
+    lds_post(&cnt[1]);
+    blk_inverse<T>(S, W, 1, 0, 1);
+  } else {
+    lds_wait_count(&cnt[1], 2);
+    if (w == 2) blk_trail<T>(S, 3, 2, 1);
+    else blk_trail<T>(S, 3, 3, 1);
   }
+  __syncthreads();
+  // column 2: wave 0 -> (3,2), (3,3), diagonal 3; waves 1, 2 -> W_21, W_20
+  if (w == 0) {
+    blk_panel<T>(S, W, 3, 2);
+    blk_trail<T>(S, 3, 3, 2);
+    diag16<T>(S, W, 48, rep);
+  } else if (w == 1) {
+    blk_inverse<T>(S, W, 2, 1, 1);
+  } else if (w == 2) {
+    blk_inverse<T>(S, W, 2, 0, 2);
+  }
+  __syncthreads();
+  // last block row of the inverse: W_3q for q = 0, 1, 2
+  if (w < 3) blk_inverse<T>(S, W, 3, w, w + 1);
+  __syncthreads();
 }
 
 
