@@ -14,7 +14,7 @@ namespace nnls {
 
 namespace {
 
-constexpr int GRAM_CHUNK = 2048;   // dense accumulator span per wave (doubles)
+constexpr int GRAM_CHUNK = 2048;   // position window of the F-position lists (positions)
 
 __global__ void k_validate_csc(int m, int n, int64_t nnz, const int32_t* __restrict__ colptr,
                                const int32_t* __restrict__ rowidx, const double* __restrict__ val,
@@ -177,57 +177,136 @@ __global__ void k_gram_bound(int n, const int32_t* __restrict__ colptr, const in
   ub[j] = s;
 }
 
-// H_ij = a_i^T a_j for i >= j.  One wave per column j; a dense accumulator of
-// GRAM_CHUNK doubles in LDS covers rows [base, base + GRAM_CHUNK) per pass.  The rows r
-// of column j are visited in ascending order and, inside row r, each i appears once, so
-// every H_ij is summed in ascending r: a fixed order, independent of the launch.
+// H_ij = a_i^T a_j for i >= j.  One wave per column j, over windows of GRAM_WIN rows
+// [base, base + GRAM_WIN) (one window unless n > GRAM_WIN).  Pass 1 marks in an LDS bitmap
+// the rows i of the window that column j meets; a scan of the bitmap's popcounts gives each
+// marked row its slot, in ascending i, which is also the output order.  Pass 2 sums
+// a_rj a_ri into the slots (GRAM_SLOTS at a time).  The column's entries are fetched four
+// at a time, one group of 16 lanes each, but applied one entry after the other in
+// ascending r, and inside row r each i appears once: every H_ij is summed in ascending r,
+// a fixed order independent of the launch.
+constexpr int GRAM_WIN = 32768;
+constexpr int GRAM_WORDS = GRAM_WIN / 32;
+constexpr int GRAM_SLOTS = 1024;
+
+__device__ inline int wave_excl_scan(int v, int lane, int* total) {
+  int x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  *total = __shfl(x, 63, 64);
+  return x - v;
+}
+
 __global__ __launch_bounds__(256) void k_gram_lower(
     int n, const int32_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
     const double* __restrict__ val, const int32_t* __restrict__ rowptr,
     const int32_t* __restrict__ colidx, const double* __restrict__ valr,
     const int64_t* __restrict__ hptr, int32_t* __restrict__ hcnt, int32_t* __restrict__ hrow,
     double* __restrict__ hval) {
-  __shared__ double s_acc[4][GRAM_CHUNK];
-  __shared__ uint32_t s_mark[4][GRAM_CHUNK / 32];
+  __shared__ uint32_t s_bits[4][GRAM_WORDS];
+  __shared__ int32_t s_rank[4][GRAM_WORDS];
+  __shared__ double s_acc[4][GRAM_SLOTS];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int j = blockIdx.x * 4 + w;
   if (j >= n) return;   // whole wave leaves; no workgroup barrier follows
+  uint32_t* bits = s_bits[w];
+  int32_t* rank = s_rank[w];
   double* acc = s_acc[w];
-  uint32_t* mark = s_mark[w];
+  const int grp = lane >> 4, gl = lane & 15;
   const int cs = colptr[j], ce = colptr[j + 1];
   const int64_t out = hptr[j];
   int count = 0;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int base = j; base < n; base += GRAM_CHUNK) {
-    for (int q = lane; q < GRAM_CHUNK; q += 64) acc[q] = 0.0;
-    for (int q = lane; q < GRAM_CHUNK / 32; q += 64) mark[q] = 0u;
+  for (int base = j; base < n; base += GRAM_WIN) {
+    const int span = min(GRAM_WIN, n - base);
+    const int nwords = (span + 31) >> 5;
+    for (int q = lane; q < nwords; q += 64) bits[q] = 0u;
     __builtin_amdgcn_wave_barrier();
-    for (int e = cs; e < ce; ++e) {
-      const int r = rowidx[e];
-      const double a = val[e];
-      const int rs = rowptr[r], re = rowptr[r + 1];
-      for (int t = rs + lane; t < re; t += 64) {
-        const int i = colidx[t];
-        const int q = i - base;
-        if (q >= 0 && q < GRAM_CHUNK) {
-          acc[q] = fma(a, valr[t], acc[q]);
-          atomicOr(&mark[q >> 5], 1u << (q & 31));
+    // pass 1: mark the rows met
+    for (int e0 = cs; e0 < ce; e0 += 4) {
+      const int e = e0 + grp;
+      if (e < ce) {
+        const int r = rowidx[e];
+        const int rs = rowptr[r], re = rowptr[r + 1];
+        for (int t = rs + gl; t < re; t += 16) {
+          const int q = colidx[t] - base;
+          if (q >= 0 && q < span) atomicOr(&bits[q >> 5], 1u << (q & 31));
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    // slots: exclusive prefix of the words' popcounts
+    int total = 0;
+    for (int q0 = 0; q0 < nwords; q0 += 64) {
+      const int q = q0 + lane;
+      const int c = (q < nwords) ? __popc(bits[q]) : 0;
+      int chunk;
+      const int ex = wave_excl_scan(c, lane, &chunk);
+      if (q < nwords) rank[q] = total + ex;
+      total += chunk;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // pass 2, GRAM_SLOTS slots at a time
+    for (int s0 = 0; s0 < total; s0 += GRAM_SLOTS) {
+      const int sn = min(GRAM_SLOTS, total - s0);
+      for (int q = lane; q < sn; q += 64) acc[q] = 0.0;
+      __builtin_amdgcn_wave_barrier();
+      for (int e0 = cs; e0 < ce; e0 += 4) {
+        const int e = e0 + grp;
+        int r = 0, rs = 0, re = 0;
+        double a = 0.0;
+        if (e < ce) {
+          r = rowidx[e];
+          a = val[e];
+          rs = rowptr[r];
+          re = rowptr[r + 1];
+        }
+        // first 16 entries of each group's row, all in flight together
+        int q1 = -1;
+        double v1 = 0.0;
+        if (rs + gl < re) {
+          q1 = colidx[rs + gl] - base;
+          v1 = valr[rs + gl];
+        }
+        // apply the four entries one after the other (ascending r)
+        for (int k = 0; k < 4; ++k) {
+          if (grp == k) {
+            if (q1 >= 0 && q1 < span) {
+              const int slot = rank[q1 >> 5] + __popc(bits[q1 >> 5] & ((1u << (q1 & 31)) - 1u)) - s0;
+              if (slot >= 0 && slot < sn) acc[slot] = fma(a, v1, acc[slot]);
+            }
+            // the rest of a row longer than 16 entries
+            for (int t = rs + 16 + gl; t < re; t += 16) {
+              const int q = colidx[t] - base;
+              if (q >= 0 && q < span) {
+                const int slot = rank[q >> 5] + __popc(bits[q >> 5] & ((1u << (q & 31)) - 1u)) - s0;
+                if (slot >= 0 && slot < sn) acc[slot] = fma(a, valr[t], acc[slot]);
+              }
+            }
+          }
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      // write the slots out: word q holds the rows base + 32 q + b of its set bits b
+      for (int q = lane; q < nwords; q += 64) {
+        uint32_t m = bits[q];
+        int slot = rank[q];
+        while (m) {
+          const int b = __ffs(m) - 1;
+          if (slot >= s0 && slot < s0 + sn) {
+            hrow[out + count + slot] = base + 32 * q + b;
+            hval[out + count + slot] = acc[slot - s0];
+          }
+          ++slot;
+          m &= m - 1u;
         }
       }
       __builtin_amdgcn_wave_barrier();
     }
-    for (int q0 = 0; q0 < GRAM_CHUNK && base + q0 < n; q0 += 64) {
-      const int q = q0 + lane;
-      const bool hit = (base + q < n) && ((mark[q >> 5] >> (q & 31)) & 1u);
-      const uint64_t bal = __ballot(hit);
-      if (hit) {
-        const int slot = count + __popcll(bal & lt_mask);
-        hrow[out + slot] = base + q;
-        hval[out + slot] = acc[q];
-      }
-      count += __popcll(bal);
-    }
-    __builtin_amdgcn_wave_barrier();
+    count += total;
   }
   if (lane == 0) hcnt[j] = count;
 }

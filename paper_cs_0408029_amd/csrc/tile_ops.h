@@ -189,12 +189,15 @@ __device__ inline void diag16(T* S, T* W, int o, const PivotReport& rep) {
   }
 }
 
-// Waits (bounded) until the workgroup-shared counter reaches `target`.
-__device__ inline void lds_wait_count(const int* cnt, int target) {
+// Waits until the workgroup-shared counter reaches `target`.  The other waves of the
+// workgroup always post, so the wait ends; its bound only turns a broken invariant into a
+// device error instead of a hang.
+__device__ inline void lds_wait_count(const int* cnt, int target, const PivotReport& rep) {
   for (int guard = 0; guard < (1 << 22); ++guard) {
     if (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= target) return;
     __builtin_amdgcn_s_sleep(1);
   }
+  if ((threadIdx.x & 63) == 0) atomicCAS(rep.status, 0, (int)NNLS_ERR_DEVICE);
 }
 __device__ inline void lds_post(int* cnt) {
   if ((threadIdx.x & 63) == 0) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -249,7 +252,7 @@ __device__ inline void factor_invert_tile(T* S, T* W, const PivotReport& rep) {
   } else {
     if (w == 1) { blk_panel<T>(S, W, 2, 0); lds_post(&cnt[0]); }
     if (w == 2) { blk_panel<T>(S, W, 3, 0); lds_post(&cnt[0]); }
-    lds_wait_count(&cnt[0], 3);
+    lds_wait_count(&cnt[0], 3, rep);
     if (w == 1) { blk_trail<T>(S, 2, 1, 0); blk_trail<T>(S, 3, 2, 0); }
     if (w == 2) { blk_trail<T>(S, 3, 1, 0); blk_trail<T>(S, 3, 3, 0); }
     if (w == 3) blk_trail<T>(S, 2, 2, 0);
@@ -267,7 +270,7 @@ __device__ inline void factor_invert_tile(T* S, T* W, const PivotReport& rep) {
     lds_post(&cnt[1]);
     blk_inverse<T>(S, W, 1, 0, 1);
   } else {
-    lds_wait_count(&cnt[1], 2);
+    lds_wait_count(&cnt[1], 2, rep);
     if (w == 2) blk_trail<T>(S, 3, 2, 1);
     else blk_trail<T>(S, 3, 3, 1);
   }
