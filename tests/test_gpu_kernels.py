@@ -41,6 +41,51 @@ def test_gram_and_rhs(h, m, n, density, seed):
     assert np.allclose(c.cpu().numpy(), c_or, rtol=1e-13, atol=1e-13 * np.abs(c_or).max())
 
 
+def test_gram_windows_sweeps_and_long_rows(h):
+    """The Gram kernel's rarer paths: more than one 32768-row window (n = 33000, with one
+    row of A meeting columns on both sides of the window edge), columns of H with more than
+    1024 rows (several accumulator sweeps), and rows of A longer than 16 entries.  Sampled
+    columns of the dense H are compared with the oracle's sparse product, and with the
+    matching rows for symmetry."""
+    m, n = 300, 33000
+    rng = np.random.default_rng(33000)
+    rows = [rng.integers(0, m, size=2 * n)]
+    cols = [np.repeat(np.arange(n), 2)]
+    dense_cols = np.unique(np.concatenate([np.arange(0, 40), rng.choice(n, 2500, replace=False),
+                                           np.arange(n - 40, n)]))
+    rows.append(np.zeros(dense_cols.size, dtype=np.int64))            # one long row of A
+    cols.append(dense_cols)
+    mid = np.arange(32700, 32840)                                      # across the window edge
+    rows.append(np.ones(mid.size, dtype=np.int64))
+    cols.append(mid)
+    A = sp.csc_matrix((rng.standard_normal(sum(r.size for r in rows)),
+                       (np.concatenate(rows), np.concatenate(cols))), shape=(m, n))
+    A.sum_duplicates()
+    A.sort_indices()
+    b = rng.standard_normal(m)
+    colptr, rowidx, val = csc_dev(A)
+    H = torch.full((n, n), float("nan"), dtype=torch.float64, device=DEV).t()
+    c = torch.empty(n, dtype=torch.float64, device=DEV)
+    assert N.nnls_gram_csc(h, m, n, colptr, rowidx, val, t(b), H, c) == N.NNLS_OK
+    H_or, c_or = gram(A, b)
+    H_or = sp.csc_matrix(H_or)
+    absA = abs(A)
+    bound_all = sp.csc_matrix(absA.T @ absA)
+    sample = np.unique(np.concatenate([[0, 1, 39, 32700, 32767, 32768, 32839, n - 1],
+                                       dense_cols[:: max(1, dense_cols.size // 12)]]))
+    assert (H_or[:, [0]] != 0).sum() > 1024                            # several sweeps
+    for j in sample:
+        col = H[:, j].cpu().numpy()
+        row = H[j, :].cpu().numpy()
+        ref = H_or[:, [j]].toarray().ravel()
+        bound = bound_all[:, [j]].toarray().ravel() * (m * EPS) + 1e-300
+        assert np.all(np.abs(col - ref) <= bound), j
+        assert np.array_equal(col, row), j
+    assert np.allclose(c.cpu().numpy(), c_or, rtol=1e-13, atol=1e-13 * np.abs(c_or).max())
+    del H
+    torch.cuda.empty_cache()
+
+
 def spd(n, seed, cond=100.0):
     rng = np.random.default_rng(seed)
     Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
