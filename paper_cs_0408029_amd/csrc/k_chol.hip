@@ -552,8 +552,11 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wa
 // helper of step s: it accumulates every older term as the walker publishes blocks and
 // hands the partial sum over (flag = this launch's tag).  A helper waits only for walker
 // steps that precede its own, and the walker waits for helpers of steps it has reached, so
-// every wait ends; each wait is also bounded in wall time.
-constexpr int TD = 2;
+// every wait ends; each wait is also bounded in wall time.  TD is 1 for chains of at most
+// TD1_MAX_BLOCKS blocks and 2 above: one own term is cheaper for the walker, and with few
+// helpers polling the frontier their hand-over arrives within one step; longer chains keep
+// a second step of slack (measured at 57..152 and 196..469 blocks).
+constexpr int TD1_MAX_BLOCKS = 160;
 
 template <bool FWD>
 __device__ inline int blk(int s, int nb) { return FWD ? s : nb - 1 - s; }
@@ -578,7 +581,7 @@ __device__ inline void load_dinv(const T* Dv, int I, int r, int g, T (&v)[16]) {
   for (int q = 0; q < 16; ++q) v[q] = FWD ? D[(g * 16 + q) * TILE + r] : D[r * TILE + g * 16 + q];
 }
 
-template <typename T, bool FWD>
+template <typename T, bool FWD, int TD>
 __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ticks, int tag) {
   __shared__ double part[4][TILE];
   __shared__ double srhs[TILE];
@@ -730,16 +733,22 @@ void launch_cholesky(hipStream_t s, const FactorArgs& a, bool fp32) {
     hipLaunchKernelGGL(k_chol_tiles<double>, dim3((unsigned)grid), dim3(256), 0, s, a, a.wait_ticks);
 }
 
-void launch_trsv(hipStream_t s, const SolveArgs& a, bool fp32, bool forward) {
-  if (a.nb <= 0) return;
+template <int TD>
+static void launch_trsv_td(hipStream_t s, const SolveArgs& a, bool fp32, bool forward) {
   const dim3 grid(a.nb + 1);   // the helpers and the walker
   if (fp32) {
-    if (forward) hipLaunchKernelGGL((k_trsv_walk<float, true>), grid, dim3(256), 0, s, a, a.wait_ticks, a.tag);
-    hipLaunchKernelGGL((k_trsv_walk<float, false>), grid, dim3(256), 0, s, a, a.wait_ticks, a.tag + 1);
+    if (forward) hipLaunchKernelGGL((k_trsv_walk<float, true, TD>), grid, dim3(256), 0, s, a, a.wait_ticks, a.tag);
+    hipLaunchKernelGGL((k_trsv_walk<float, false, TD>), grid, dim3(256), 0, s, a, a.wait_ticks, a.tag + 1);
   } else {
-    if (forward) hipLaunchKernelGGL((k_trsv_walk<double, true>), grid, dim3(256), 0, s, a, a.wait_ticks, a.tag);
-    hipLaunchKernelGGL((k_trsv_walk<double, false>), grid, dim3(256), 0, s, a, a.wait_ticks, a.tag + 1);
+    if (forward) hipLaunchKernelGGL((k_trsv_walk<double, true, TD>), grid, dim3(256), 0, s, a, a.wait_ticks, a.tag);
+    hipLaunchKernelGGL((k_trsv_walk<double, false, TD>), grid, dim3(256), 0, s, a, a.wait_ticks, a.tag + 1);
   }
+}
+
+void launch_trsv(hipStream_t s, const SolveArgs& a, bool fp32, bool forward) {
+  if (a.nb <= 0) return;
+  if (a.nb <= TD1_MAX_BLOCKS) launch_trsv_td<1>(s, a, fp32, forward);
+  else launch_trsv_td<2>(s, a, fp32, forward);
 }
 
 void launch_tiles_to_dense(hipStream_t s, int n, int nb, const void* Ltiles, bool fp32, double* L, int ldl) {
