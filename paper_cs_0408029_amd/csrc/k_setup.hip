@@ -14,8 +14,6 @@ namespace nnls {
 
 namespace {
 
-constexpr int GRAM_CHUNK = 2048;   // position window of the F-position lists (positions)
-
 __global__ void k_validate_csc(int m, int n, int64_t nnz, const int32_t* __restrict__ colptr,
                                const int32_t* __restrict__ rowidx, const double* __restrict__ val,
                                const double* __restrict__ b, int32_t* err) {
@@ -332,55 +330,61 @@ __global__ __launch_bounds__(256) void k_gram_mirror(int n, GramLower g, int32_t
 }
 
 // F-position lists: position q (column j = Flist[q]) keeps the entries p = pos[i] >= q of
-// its whole column, written in ascending p.  One wave per position; each pass places the
-// entries with p in [base, base + GRAM_CHUNK) into a dense LDS window, then compacts it in
-// order, so the output is sorted by construction and does not depend on the launch.
+// its whole column, written in ascending p.  One wave per position, over windows of
+// GRAM_WIN positions: the entries' positions are marked in an LDS bitmap (each position
+// occurs once in a column), a scan of the words' popcounts ranks them, and each entry is
+// written at its rank.  The output is sorted by construction and does not depend on the
+// launch.
 __global__ __launch_bounds__(256) void k_gram_positions(int nF, GramLower g, const int32_t* __restrict__ upcnt,
                                                         const int32_t* __restrict__ Flist,
                                                         const int32_t* __restrict__ pos,
                                                         int32_t* __restrict__ pcnt, int32_t* __restrict__ prow,
                                                         double* __restrict__ pval) {
-  __shared__ double s_val[4][GRAM_CHUNK];
-  __shared__ uint32_t s_mark[4][GRAM_CHUNK / 32];
+  __shared__ uint32_t s_bits[4][GRAM_WORDS];
+  __shared__ int32_t s_rank[4][GRAM_WORDS];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int q = blockIdx.x * 4 + w;
   if (q >= nF) return;   // whole wave leaves; no workgroup barrier follows
-  double* val = s_val[w];
-  uint32_t* mark = s_mark[w];
+  uint32_t* bits = s_bits[w];
+  int32_t* rank = s_rank[w];
   const int j = Flist[q];
   const int64_t s = g.hptr[j];
   const int cnt = g.hcnt[j] + upcnt[j];
-  // largest position in the column bounds the passes
+  // largest position in the column bounds the windows
   int pmax = q;
   for (int t = lane; t < cnt; t += 64) pmax = max(pmax, pos[g.hrow[s + t]]);
   for (int d = 32; d >= 1; d >>= 1) pmax = max(pmax, __shfl_xor(pmax, d, 64));
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   int count = 0;
-  for (int base = q; base <= pmax; base += GRAM_CHUNK) {
-    for (int k = lane; k < GRAM_CHUNK / 32; k += 64) mark[k] = 0u;
+  for (int base = q; base <= pmax; base += GRAM_WIN) {
+    const int span = min(GRAM_WIN, pmax + 1 - base);
+    const int nwords = (span + 31) >> 5;
+    for (int k = lane; k < nwords; k += 64) bits[k] = 0u;
     __builtin_amdgcn_wave_barrier();
     for (int t = lane; t < cnt; t += 64) {
-      const int p = pos[g.hrow[s + t]];
-      const int k = p - base;
-      if (p >= q && k >= 0 && k < GRAM_CHUNK) {
-        val[k] = g.hval[s + t];
-        atomicOr(&mark[k >> 5], 1u << (k & 31));
-      }
+      const int k = pos[g.hrow[s + t]] - base;
+      if (k >= 0 && k < span) atomicOr(&bits[k >> 5], 1u << (k & 31));
     }
     __builtin_amdgcn_wave_barrier();
-    const int span = min(GRAM_CHUNK, pmax + 1 - base);
-    for (int k0 = 0; k0 < span; k0 += 64) {
+    int total = 0;
+    for (int k0 = 0; k0 < nwords; k0 += 64) {
       const int k = k0 + lane;
-      const bool hit = k < span && ((mark[k >> 5] >> (k & 31)) & 1u);
-      const uint64_t bal = __ballot(hit);
-      if (hit) {
-        const int slot = count + __popcll(bal & lt_mask);
-        prow[s + slot] = base + k;
-        pval[s + slot] = val[k];
-      }
-      count += __popcll(bal);
+      const int c = (k < nwords) ? __popc(bits[k]) : 0;
+      int chunk;
+      const int ex = wave_excl_scan(c, lane, &chunk);
+      if (k < nwords) rank[k] = total + ex;
+      total += chunk;
     }
     __builtin_amdgcn_wave_barrier();
+    for (int t = lane; t < cnt; t += 64) {
+      const int k = pos[g.hrow[s + t]] - base;
+      if (k >= 0 && k < span) {
+        const int slot = count + rank[k >> 5] + __popc(bits[k >> 5] & ((1u << (k & 31)) - 1u));
+        prow[s + slot] = base + k;
+        pval[s + slot] = g.hval[s + t];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    count += total;
   }
   if (lane == 0) pcnt[q] = count;
 }
