@@ -341,7 +341,6 @@ SolveArgs solve_args(nnls_handle* h, int nF, const int32_t* Flist, const double*
   return a;
 }
 
-double chol_flops(double nF) { return nF * nF * nF / 3.0; }
 // flops of a factor that keeps its leading p0 columns
 double chol_flops_from(double nF, double p0) { return (nF * nF * nF - p0 * p0 * p0) / 3.0; }
 
@@ -1026,7 +1025,7 @@ int nnls_cholesky(nnls_handle* h, int32_t n, const double* S, int32_t lds, doubl
   h->fact_prec = -1;
   FactorArgs fa = factor_args(h, n, nullptr, S, lds, false);
   launch_cholesky(h->stream, fa, fp32);
-  launch_tiles_to_dense(h->stream, n, fa.nb, h->Lt.p, fp32, L, ldl);
+  launch_tiles_to_dense(h->stream, n, h->Lt.p, fp32, L, ldl);
   TRY(sync_read(h, h->h_ctrl, h->ctrl.p, sizeof(Ctrl)));
   const Ctrl c = *h->h_ctrl;
   if (c.status == NNLS_ERR_NOT_PD) {

@@ -94,7 +94,7 @@ __device__ inline void gather_tile(const FactorArgs& a, int tid, int I, int J, T
 // One lower tile (I, J), I >= j0; S, W, s_part, s_rhs are the workgroup's LDS.
 template <typename T>
 __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_ticks, int tid, int I, int J,
-                                          T* S, T* W, double (*s_part)[TILE], double* s_rhs) {
+                                          T* S, T* W, double (*s_part)[TILE]) {
   typedef MF<T> M;
   typedef typename M::acc Acc;
   const int lane = tid & 63, w = tid >> 6;
@@ -293,7 +293,7 @@ __device__ __forceinline__ void lower_update(typename MF<T>::acc (&acc)[3], cons
   }
 }
 template <typename T, int NB, int I0, int J0, int I1, int J1, int I2, int J2>
-__device__ __forceinline__ void lower_store(const typename MF<T>::acc (&acc)[3], T* U, int lane) {
+__device__ __forceinline__ void lower_store(const typename MF<T>::acc (&acc)[3], T* U) {
   constexpr int BI[3] = {I0, I1, I2}, BJ[3] = {J0, J1, J2};
 #pragma unroll
   for (int b = 0; b < NB; ++b) store16<T>(U, 16 * BI[b], 16 * BJ[b], acc[b]);
@@ -394,10 +394,10 @@ __device__ __forceinline__ void walker(const FactorArgs& a, uint64_t wait_ticks,
       }
       __syncthreads();   // U and X fully read
       switch (__builtin_amdgcn_readfirstlane(w)) {
-        case 0: lower_store<T, 3, 0, 0, 3, 0, 3, 1>(acc, U, lane); break;
-        case 1: lower_store<T, 3, 1, 0, 1, 1, 3, 2>(acc, U, lane); break;
-        case 2: lower_store<T, 3, 2, 0, 2, 1, 3, 3>(acc, U, lane); break;
-        default: lower_store<T, 1, 2, 2, 0, 0, 0, 0>(acc, U, lane); break;
+        case 0: lower_store<T, 3, 0, 0, 3, 0, 3, 1>(acc, U); break;
+        case 1: lower_store<T, 3, 1, 0, 1, 1, 3, 2>(acc, U); break;
+        case 2: lower_store<T, 3, 2, 0, 2, 1, 3, 3>(acc, U); break;
+        default: lower_store<T, 1, 2, 2, 0, 0, 0, 0>(acc, U); break;
       }
     }
     if (fwd && tid < TILE) {
@@ -539,7 +539,7 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wa
       return;
     }
     if (t >= ntiles) return;
-    chol_tile<T>(a, wait_ticks, tid, I, J, S, W, s_part, s_rhs);
+    chol_tile<T>(a, wait_ticks, tid, I, J, S, W, s_part);
     __syncthreads();   // LDS is reused by the next tile
   }
 }
@@ -710,7 +710,7 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
 }
 
 template <typename T>
-__global__ void k_tiles_to_dense(int n, int nb, const T* __restrict__ Lt, double* __restrict__ L, int ldl) {
+__global__ void k_tiles_to_dense(int n, const T* __restrict__ Lt, double* __restrict__ L, int ldl) {
   const int64_t total = (int64_t)n * n;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
@@ -751,15 +751,15 @@ void launch_trsv(hipStream_t s, const SolveArgs& a, bool fp32, bool forward) {
   else launch_trsv_td<2>(s, a, fp32, forward);
 }
 
-void launch_tiles_to_dense(hipStream_t s, int n, int nb, const void* Ltiles, bool fp32, double* L, int ldl) {
+void launch_tiles_to_dense(hipStream_t s, int n, const void* Ltiles, bool fp32, double* L, int ldl) {
   const int64_t total = (int64_t)n * n;
   int blocks = (int)((total + 255) / 256);
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
   if (fp32)
-    hipLaunchKernelGGL(k_tiles_to_dense<float>, dim3(blocks), dim3(256), 0, s, n, nb, (const float*)Ltiles, L, ldl);
+    hipLaunchKernelGGL(k_tiles_to_dense<float>, dim3(blocks), dim3(256), 0, s, n, (const float*)Ltiles, L, ldl);
   else
-    hipLaunchKernelGGL(k_tiles_to_dense<double>, dim3(blocks), dim3(256), 0, s, n, nb, (const double*)Ltiles, L, ldl);
+    hipLaunchKernelGGL(k_tiles_to_dense<double>, dim3(blocks), dim3(256), 0, s, n, (const double*)Ltiles, L, ldl);
 }
 
 }  // namespace nnls

@@ -186,8 +186,7 @@ struct SolveArgs {
   int tag;                  // this call's flag value (forward tag, backward tag + 1)
 };
 void launch_trsv(hipStream_t s, const SolveArgs& a, bool fp32, bool forward);
-void launch_tiles_to_dense(hipStream_t s, int n, int nb, const void* Ltiles, bool fp32,
-                           double* L, int ldl);
+void launch_tiles_to_dense(hipStream_t s, int n, const void* Ltiles, bool fp32, double* L, int ldl);
 void launch_reset_tickets(hipStream_t s, Ctrl* ctrl);
 
 // batched dense problems (k_batched.hip): one workgroup per problem
