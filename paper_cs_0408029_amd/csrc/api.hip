@@ -50,6 +50,7 @@ struct nnls_handle {
   DevBuf upcnt, prow, pval, pcnt, Fold, zr;   // F-position Gram lists, order scratch, refinement z
   DevBuf est, ev, exi;                         // condition estimate: state, probe vector, signs
   DevBuf bprobs, border, binfo, bws;   // batched dense problems
+  DevBuf scan;                         // chunk sums of the setup prefix scans
   Ctrl* h_ctrl = nullptr;     // pinned
   int64_t* h_scalar = nullptr;  // pinned scratch for small reads
   int epoch = 0;
@@ -212,8 +213,9 @@ int build_csr(nnls_handle* h, const Problem& P) {
   TRY(ensure(h, h->rowptr, sizeof(int32_t) * ((size_t)P.m + 1)));
   TRY(ensure(h, h->colidx, sizeof(int32_t) * (size_t)P.nnz));
   TRY(ensure(h, h->valr, sizeof(double) * (size_t)P.nnz));
+  TRY(ensure(h, h->scan, sizeof(int64_t) * ((size_t)std::max(P.m, P.n) / 2048 + 1)));
   launch_build_csr(h->stream, P.m, P.n, P.nnz, P.colptr, P.rowidx, P.val, (int32_t*)h->rowcnt.p,
-                   (int32_t*)h->rowptr.p, (int32_t*)h->colidx.p, (double*)h->valr.p);
+                   (int32_t*)h->rowptr.p, (int32_t*)h->colidx.p, (double*)h->valr.p, h->scan.p);
   return NNLS_OK;
 }
 
@@ -240,7 +242,8 @@ GramPos gram_pos_view(nnls_handle* h) {
 int build_gram_sparse(nnls_handle* h, const Problem& P) {
   TRY(build_csr(h, P));
   TRY(ensure(h, h->hptr, sizeof(int64_t) * ((size_t)P.n + 1)));
-  launch_gram_bound(h->stream, P.n, P.colptr, P.rowidx, (const int32_t*)h->rowptr.p, (int64_t*)h->hptr.p);
+  launch_gram_bound(h->stream, P.n, P.colptr, P.rowidx, (const int32_t*)h->rowptr.p, (int64_t*)h->hptr.p,
+                    h->scan.p);
   int64_t ub = 0;
   TRY(sync_read(h, &ub, (int64_t*)h->hptr.p + P.n, sizeof(int64_t)));
   TRY(ensure(h, h->hcnt, sizeof(int32_t) * (size_t)P.n));
@@ -724,7 +727,7 @@ void release_workspace(nnls_handle* h) {
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
                     &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart, &h->spart, &h->spflag,
                     &h->upcnt, &h->prow, &h->pval, &h->pcnt, &h->Fold, &h->zr, &h->est, &h->ev, &h->exi,
-                    &h->bprobs, &h->border, &h->binfo, &h->bws};
+                    &h->bprobs, &h->border, &h->binfo, &h->bws, &h->scan};
   for (DevBuf* b : bufs) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
@@ -804,7 +807,7 @@ int nnls_destroy(nnls_handle* h) {
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
                     &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart, &h->spart, &h->spflag,
                     &h->upcnt, &h->prow, &h->pval, &h->pcnt, &h->Fold, &h->zr, &h->est, &h->ev, &h->exi,
-                    &h->bprobs, &h->border, &h->binfo, &h->bws};
+                    &h->bprobs, &h->border, &h->binfo, &h->bws, &h->scan};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);

@@ -78,55 +78,93 @@ __global__ void k_row_count(int64_t nnz, const int32_t* __restrict__ rowidx, int
     atomicAdd(&rowcnt[rowidx[e]], 1);
 }
 
-// Exclusive scan of count[0..n) into out[0..n], out[n] = total.  One workgroup of 1024
-// threads walks the array in chunks of 1024 * SCAN_PER: each thread loads SCAN_PER
-// consecutive entries (all loads in flight at once), scans them in registers, and the
-// thread totals are scanned across the workgroup; a running carry joins the chunks.
-// Every chunk is read into registers before it is written, so count may alias out.
-constexpr int SCAN_PER = 16;
-template <typename Tin, typename Tout>
-__global__ __launch_bounds__(1024) void k_scan_single(int64_t n, const Tin* count,
-                                                      Tout* out) {
-  __shared__ Tout s_wave[16];
-  __shared__ Tout s_total;
+// Exclusive scan of count[0..n) into out[0..n], out[n] = total, in three launches over
+// chunks of SCAN_CHUNK entries: the chunk sums; one workgroup scans those into chunk
+// offsets; each chunk then stages its entries in LDS with coalesced loads, scans them
+// (SCAN_PER consecutive entries per thread, then the thread totals across the workgroup)
+// and stores the result coalesced.  A chunk is read whole before any of it is written and
+// the sums are taken before any chunk is written, so count may alias out.
+constexpr int SCAN_PER = 8;
+constexpr int SCAN_CHUNK = 256 * SCAN_PER;
+
+template <typename T>
+__device__ inline T block_excl_scan256(T v, T* s_wave, T* total) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  Tout carry = 0;
-  for (int64_t base = 0; base < n; base += 1024 * SCAN_PER) {
-    const int64_t i0 = base + (int64_t)tid * SCAN_PER;
-    Tout v[SCAN_PER];
-#pragma unroll
-    for (int q = 0; q < SCAN_PER; ++q) v[q] = (i0 + q < n) ? (Tout)count[i0 + q] : (Tout)0;
-    Tout local = 0;
-#pragma unroll
-    for (int q = 0; q < SCAN_PER; ++q) local += v[q];
-    // inclusive scan of the thread totals inside the wave
-    Tout t = local;
-    for (int d = 1; d < 64; d <<= 1) {
-      const Tout o = __shfl_up(t, d, 64);
-      if (lane >= d) t += o;
-    }
-    if (lane == 63) s_wave[w] = t;
-    __syncthreads();
-    if (tid == 0) {
-      Tout run = 0;
-      for (int q = 0; q < 16; ++q) {
-        const Tout c = s_wave[q];
-        s_wave[q] = run;
-        run += c;
-      }
-      s_total = run;
-    }
-    __syncthreads();
-    Tout off = carry + s_wave[w] + t - local;
-#pragma unroll
-    for (int q = 0; q < SCAN_PER; ++q) {
-      if (i0 + q < n) out[i0 + q] = off;
-      off += v[q];
-    }
-    carry += s_total;
-    __syncthreads();   // s_wave and s_total are reused by the next chunk
+  T t = v;
+  for (int d = 1; d < 64; d <<= 1) {
+    const T o = __shfl_up(t, d, 64);
+    if (lane >= d) t += o;
   }
-  if (tid == 0) out[n] = carry;
+  if (lane == 63) s_wave[w] = t;
+  __syncthreads();
+  const T before = (w > 0 ? s_wave[0] : 0) + (w > 1 ? s_wave[1] : 0) + (w > 2 ? s_wave[2] : 0);
+  *total = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+  __syncthreads();
+  return before + t - v;
+}
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void k_scan_sums(int64_t n, const Tin* count, Tout* sums) {
+  __shared__ Tout s_wave[4];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
+  Tout v = 0;
+#pragma unroll
+  for (int q = 0; q < SCAN_PER; ++q) {
+    const int64_t i = base + threadIdx.x + 256 * q;
+    if (i < n) v += (Tout)count[i];
+  }
+  Tout total;
+  block_excl_scan256<Tout>(v, s_wave, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Exclusive scan of sums[0..nchunk) in place, one workgroup; *grand = the total.
+template <typename Tout>
+__global__ __launch_bounds__(256) void k_scan_top(int nchunk, Tout* sums, Tout* grand) {
+  __shared__ Tout s_wave[4];
+  Tout carry = 0;
+  for (int c0 = 0; c0 < nchunk; c0 += 256) {
+    const int c = c0 + threadIdx.x;
+    const Tout v = (c < nchunk) ? sums[c] : (Tout)0;
+    Tout total;
+    const Tout ex = block_excl_scan256<Tout>(v, s_wave, &total);
+    if (c < nchunk) sums[c] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) *grand = carry;
+}
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void k_scan_apply(int64_t n, const Tin* count, const Tout* offs, Tout* out) {
+  __shared__ Tout s_val[SCAN_CHUNK];
+  __shared__ Tout s_wave[4];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
+#pragma unroll
+  for (int q = 0; q < SCAN_PER; ++q) {
+    const int64_t i = base + tid + 256 * q;
+    s_val[tid + 256 * q] = (i < n) ? (Tout)count[i] : (Tout)0;
+  }
+  __syncthreads();
+  Tout v[SCAN_PER], local = 0;
+#pragma unroll
+  for (int q = 0; q < SCAN_PER; ++q) {
+    v[q] = s_val[tid * SCAN_PER + q];
+    local += v[q];
+  }
+  Tout total;
+  Tout off = offs[blockIdx.x] + block_excl_scan256<Tout>(local, s_wave, &total);
+#pragma unroll
+  for (int q = 0; q < SCAN_PER; ++q) {
+    s_val[tid * SCAN_PER + q] = off;
+    off += v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < SCAN_PER; ++q) {
+    const int64_t i = base + tid + 256 * q;
+    if (i < n) out[i] = s_val[tid + 256 * q];
+  }
 }
 
 __global__ void k_csr_fill(int n, const int32_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
@@ -500,14 +538,23 @@ void launch_validate_dense(hipStream_t s, int m, int n, const double* A, int lda
                      m, n, A, lda, b, err);
 }
 
+// sums: scratch of ceil(n / SCAN_CHUNK) entries
+template <typename Tin, typename Tout>
+static void launch_scan(hipStream_t s, int64_t n, const Tin* count, Tout* out, Tout* sums) {
+  const int nchunk = (int)((n + SCAN_CHUNK - 1) / SCAN_CHUNK);
+  if (nchunk > 0) hipLaunchKernelGGL((k_scan_sums<Tin, Tout>), dim3(nchunk), dim3(256), 0, s, n, count, sums);
+  hipLaunchKernelGGL((k_scan_top<Tout>), dim3(1), dim3(256), 0, s, nchunk, sums, out + n);
+  if (nchunk > 0)
+    hipLaunchKernelGGL((k_scan_apply<Tin, Tout>), dim3(nchunk), dim3(256), 0, s, n, count, (const Tout*)sums, out);
+}
+
 void launch_build_csr(hipStream_t s, int m, int n, int64_t nnz, const int32_t* colptr,
                       const int32_t* rowidx, const double* val, int32_t* rowcnt, int32_t* rowptr,
-                      int32_t* colidx, double* valr) {
+                      int32_t* colidx, double* valr, void* scan_scratch) {
   launch_fill_i32(s, rowcnt, m, 0);
   if (nnz > 0)
     hipLaunchKernelGGL(k_row_count, dim3(blocks_for(nnz, 256)), dim3(256), 0, s, nnz, rowidx, rowcnt);
-  hipLaunchKernelGGL((k_scan_single<int32_t, int32_t>), dim3(1), dim3(1024), 0, s, (int64_t)m,
-                     (const int32_t*)rowcnt, rowptr);
+  launch_scan<int32_t, int32_t>(s, (int64_t)m, (const int32_t*)rowcnt, rowptr, (int32_t*)scan_scratch);
   launch_fill_i32(s, rowcnt, m, 0);
   hipLaunchKernelGGL(k_csr_fill, dim3(blocks_for(n, 256, 1 << 30)), dim3(256), 0, s, n, colptr, rowidx,
                      val, (const int32_t*)rowptr, rowcnt, colidx, valr);
@@ -516,12 +563,11 @@ void launch_build_csr(hipStream_t s, int m, int n, int64_t nnz, const int32_t* c
 }
 
 void launch_gram_bound(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx,
-                       const int32_t* rowptr, int64_t* hptr) {
+                       const int32_t* rowptr, int64_t* hptr, void* scan_scratch) {
   // ub into hptr[0..n), then an in-place exclusive scan into hptr[0..n]
   hipLaunchKernelGGL(k_gram_bound, dim3(blocks_for(n, 256, 1 << 30)), dim3(256), 0, s, n, colptr,
                      rowidx, rowptr, hptr);
-  hipLaunchKernelGGL((k_scan_single<int64_t, int64_t>), dim3(1), dim3(1024), 0, s, (int64_t)n,
-                     (const int64_t*)hptr, hptr);
+  launch_scan<int64_t, int64_t>(s, (int64_t)n, (const int64_t*)hptr, hptr, (int64_t*)scan_scratch);
 }
 
 void launch_gram_lower(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx,

@@ -74,11 +74,12 @@ void launch_validate_csc(hipStream_t s, int m, int n, int64_t nnz, const int32_t
                          const int32_t* rowidx, const double* val, const double* b, int32_t* err);
 void launch_validate_dense(hipStream_t s, int m, int n, const double* A, int lda, const double* b,
                            int32_t* err);
+// scan_scratch: 8 * ceil(max(m, n) / 2048) bytes of device scratch for the prefix sums
 void launch_build_csr(hipStream_t s, int m, int n, int64_t nnz, const int32_t* colptr,
                       const int32_t* rowidx, const double* val, int32_t* rowcnt, int32_t* rowptr,
-                      int32_t* colidx, double* valr);
+                      int32_t* colidx, double* valr, void* scan_scratch);
 void launch_gram_bound(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx,
-                       const int32_t* rowptr, int64_t* hptr);
+                       const int32_t* rowptr, int64_t* hptr, void* scan_scratch);
 void launch_gram_lower(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx,
                        const double* val, const int32_t* rowptr, const int32_t* colidx,
                        const double* valr, const int64_t* hptr, int32_t* hcnt, int32_t* hrow,
