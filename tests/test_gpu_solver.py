@@ -75,6 +75,22 @@ def test_sparse_large_full_size(h):
     assert nx == 0 and ny == 0 and comp == 0 and dres < 1e-9
 
 
+def test_sparse_large_f_block_beyond_one_window(h):
+    """m = 200000, n = 44000 of the same recipe: the first F-block has 35163 positions, so
+    the F-position lists span two 32768-position windows and the Gram columns two row
+    windows.  Checked against the planted answer and the KKT conditions (the oracle is too
+    slow at this size)."""
+    inst = W.sparse_large(1006, m=200000, n=44000)
+    st, info, x, y, trace = solve_csc(h, inst.A, inst.b)
+    assert st == N.NNLS_OK
+    assert trace[0][4] == 35163
+    assert np.array_equal(x > 0, inst.active)
+    assert np.abs(x - inst.x_star).max() <= 1e-10
+    assert np.abs(y - inst.y_star).max() <= 1e-10
+    nx, ny, comp, dres = kkt_residuals(inst.A, inst.b, x, y)
+    assert nx == 0 and ny == 0 and comp == 0 and dres < 1e-9
+
+
 @pytest.mark.parametrize("m,n,seed", [(40, 16, 1), (300, 100, 2), (700, 256, 3), (1100, 520, 4)])
 def test_dense_planted(h, m, n, seed):
     inst = W.dense_planted(seed, m, n)
