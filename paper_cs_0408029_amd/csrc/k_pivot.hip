@@ -62,6 +62,7 @@ __device__ inline int wave_max(int v) {
 }
 
 constexpr int NBUCKET = 64;    // exponent classes of the reordered part of F
+constexpr int CTRL_BATCH = 8;  // entries per thread fetched together by the classify and exchange
 
 // Exponent class of x >= 0 relative to the largest exponent emax: 0 holds the largest
 // values, NBUCKET - 1 holds zero, subnormals and anything NBUCKET - 2 binades below.
@@ -99,21 +100,35 @@ __global__ __launch_bounds__(CTRL_THREADS) void k_pivot_control(
   // 1. classify + zero + count
   int cnt = 0, rmax = -1;
   double mar = INFINITY;
-  for (int i0 = 0; i0 < n; i0 += CTRL_THREADS) {
-    const int i = i0 + tid;
-    bool bad = false;
-    if (i < n) {
-      const bool f = flags[i] != 0;
-      const double v = f ? x[i] : y[i];
-      if (fabs(v) < tau) {
-        if (f) x[i] = 0.0; else y[i] = 0.0;
-      } else {
-        mar = fmin(mar, fabs(v));
-        bad = v < 0.0;
-      }
-      if (bad) rmax = i;
+  // CTRL_BATCH entries per thread are fetched together (flag, x and y alike, so no load
+  // waits for another), then tested in the same order as one at a time
+  for (int i0 = 0; i0 < n; i0 += CTRL_THREADS * CTRL_BATCH) {
+    uint8_t fb[CTRL_BATCH];
+    double xb[CTRL_BATCH], yb[CTRL_BATCH];
+#pragma unroll
+    for (int u = 0; u < CTRL_BATCH; ++u) {
+      const int i = i0 + u * CTRL_THREADS + tid;
+      fb[u] = (i < n) ? flags[i] : (uint8_t)0;
+      xb[u] = (i < n) ? x[i] : 0.0;
+      yb[u] = (i < n) ? y[i] : 0.0;
     }
-    cnt += __popcll(__ballot(bad));
+#pragma unroll
+    for (int u = 0; u < CTRL_BATCH; ++u) {
+      const int i = i0 + u * CTRL_THREADS + tid;
+      bool bad = false;
+      if (i < n) {
+        const bool f = fb[u] != 0;
+        const double v = f ? xb[u] : yb[u];
+        if (fabs(v) < tau) {
+          if (f) x[i] = 0.0; else y[i] = 0.0;
+        } else {
+          mar = fmin(mar, fabs(v));
+          bad = v < 0.0;
+        }
+        if (bad) rmax = i;
+      }
+      cnt += __popcll(__ballot(bad));
+    }
   }
   rmax = wave_max(rmax);
   mar = wave_min(mar);
@@ -178,25 +193,37 @@ __global__ __launch_bounds__(CTRL_THREADS) void k_pivot_control(
   //     until the new order is built.
   const int branch = s_branch, rsel = s_rmax;
   int p0 = INT_MAX, emax = 0, nadd = 0, nrem = 0;
-  for (int i0 = 0; i0 < n; i0 += CTRL_THREADS) {
-    const int i = i0 + tid;
-    bool add = false, rem = false;
-    if (i < n) {
-      const uint8_t f = flags[i];
-      const double v = f ? x[i] : y[i];
-      const bool flip = (branch == 2) ? (i == rsel) : (v < 0.0);
-      if (mode == 0) {
-        if (flip) flags[i] = f ^ 1;
-      } else {
-        flags[i] = (uint8_t)((f ^ (flip ? 1 : 0)) | (f << 1));
-        add = flip && !f;
-        rem = flip && f;
-        if (rem && mode == 2) p0 = min(p0, pos[i]);
-        if (f && !flip && v > 0.0) emax = max(emax, (int)((__double_as_longlong(v) >> 52) & 0x7ff));
-      }
+  for (int i0 = 0; i0 < n; i0 += CTRL_THREADS * CTRL_BATCH) {
+    uint8_t fb[CTRL_BATCH];
+    double xb[CTRL_BATCH], yb[CTRL_BATCH];
+#pragma unroll
+    for (int u = 0; u < CTRL_BATCH; ++u) {
+      const int i = i0 + u * CTRL_THREADS + tid;
+      fb[u] = (i < n) ? flags[i] : (uint8_t)0;
+      xb[u] = (i < n) ? x[i] : 0.0;
+      yb[u] = (i < n) ? y[i] : 0.0;
     }
-    nadd += __popcll(__ballot(add));
-    nrem += __popcll(__ballot(rem));
+#pragma unroll
+    for (int u = 0; u < CTRL_BATCH; ++u) {
+      const int i = i0 + u * CTRL_THREADS + tid;
+      bool add = false, rem = false;
+      if (i < n) {
+        const uint8_t f = fb[u];
+        const double v = f ? xb[u] : yb[u];
+        const bool flip = (branch == 2) ? (i == rsel) : (v < 0.0);
+        if (mode == 0) {
+          if (flip) flags[i] = f ^ 1;
+        } else {
+          flags[i] = (uint8_t)((f ^ (flip ? 1 : 0)) | (f << 1));
+          add = flip && !f;
+          rem = flip && f;
+          if (rem && mode == 2) p0 = min(p0, pos[i]);
+          if (f && !flip && v > 0.0) emax = max(emax, (int)((__double_as_longlong(v) >> 52) & 0x7ff));
+        }
+      }
+      nadd += __popcll(__ballot(add));
+      nrem += __popcll(__ballot(rem));
+    }
   }
   if (mode != 0) {
     p0 = -wave_max(-p0);
