@@ -46,7 +46,7 @@ struct nnls_handle {
   int max_wgs = 0;            // the grid cap of the current solve
   // workspace
   DevBuf err, ctrl, rowcnt, rowptr, colidx, valr, hptr, hcnt, hrow, hval, c, r, flags, Flist, pos;
-  DevBuf Lt, Dinv, colcnt, dflag, tflag, z, xF, Hd, gF, rpart, spart, spflag;
+  DevBuf Lt, Dinv, colcnt, dflag, tflag, z, xF, Hd, gF, rpart, spart;
   DevBuf upcnt, prow, pval, pcnt, Fold, zr;   // F-position Gram lists, order scratch, refinement z
   DevBuf est, ev, exi;                         // condition estimate: state, probe vector, signs
   DevBuf bprobs, border, binfo, bws;   // batched dense problems
@@ -54,7 +54,8 @@ struct nnls_handle {
   Ctrl* h_ctrl = nullptr;     // pinned
   int64_t* h_scalar = nullptr;  // pinned scratch for small reads
   int epoch = 0;
-  int trsv_tag = 0;           // flag values of the triangular-solve hand-overs, never reused
+  bool slots_empty = false;   // every hand-over slot of the triangular solves is empty (a
+                              // launch that stopped on an error may leave some filled)
   // precision of the factor tiles that belong to the current F order (and the forward-solve
   // blocks with them): 0 float64, 1 float32, -1 none; the next factor of the same
   // precision may keep their untouched leading columns
@@ -288,8 +289,9 @@ int ensure_factor(nnls_handle* h, int nF, bool fp32, bool* lost = nullptr) {
   TRY(ensure(h, h->z, (size_t)nb * TILE * sizeof(double)));
   TRY(ensure(h, h->zr, (size_t)nb * TILE * sizeof(double)));
   TRY(ensure(h, h->xF, (size_t)nb * TILE * sizeof(double)));
+  const void* slots_before = h->spart.p;
   TRY(ensure(h, h->spart, (size_t)nb * TILE * sizeof(double)));
-  TRY(ensure(h, h->spflag, (size_t)nb * sizeof(int32_t), true));
+  if (h->spart.p != slots_before) h->slots_empty = false;
   if (lost) *lost = before[0] != h->Lt.p || before[1] != h->Dinv.p || before[2] != h->z.p;
   return NNLS_OK;
 }
@@ -334,13 +336,10 @@ SolveArgs solve_args(nnls_handle* h, int nF, const int32_t* Flist, const double*
   a.ctrl = (Ctrl*)h->ctrl.p;
   a.wait_ticks = h->wait_ticks;
   a.part = (double*)h->spart.p;
-  a.pflag = (int32_t*)h->spflag.p;
-  h->trsv_tag += 2;   // forward and backward
-  if (h->trsv_tag > (1 << 30)) {   // values are never reused while flags may hold them
-    launch_fill_i32(h->stream, (int32_t*)h->spflag.p, a.nb, 0);
-    h->trsv_tag = 2;
+  if (!h->slots_empty) {   // each launch empties every slot it fills, unless it stopped early
+    launch_fill_i32(h->stream, (int32_t*)h->spart.p, (int64_t)(h->spart.bytes / 4), SLOT_EMPTY_WORD);
+    h->slots_empty = true;
   }
-  a.tag = h->trsv_tag;
   return a;
 }
 
@@ -708,6 +707,7 @@ int solve_common(nnls_handle* h, const Problem& P, double* x, double* y, const n
   prof_flush(h);
   if (info) info->setup_ms = now_ms() - t0;
   st = pivot_loop(h, P, x, y, o, info);
+  if (st != NNLS_OK) h->slots_empty = false;   // a solve may have stopped with slots filled
   if (info) info->solve_ms = now_ms() - t0;
   h->profiling = h->profile_always;
   return set_info_status(info, st);
@@ -725,7 +725,7 @@ void release_workspace(nnls_handle* h) {
   h->fact_prec = -1;
   DevBuf* bufs[] = {&h->err, &h->ctrl, &h->rowcnt, &h->rowptr, &h->colidx, &h->valr, &h->hptr,
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
-                    &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart, &h->spart, &h->spflag,
+                    &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart, &h->spart,
                     &h->upcnt, &h->prow, &h->pval, &h->pcnt, &h->Fold, &h->zr, &h->est, &h->ev, &h->exi,
                     &h->bprobs, &h->border, &h->binfo, &h->bws, &h->scan};
   for (DevBuf* b : bufs) {
@@ -805,7 +805,7 @@ int nnls_destroy(nnls_handle* h) {
   (void)hipStreamSynchronize(h->stream);
   DevBuf* bufs[] = {&h->err, &h->ctrl, &h->rowcnt, &h->rowptr, &h->colidx, &h->valr, &h->hptr,
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
-                    &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart, &h->spart, &h->spflag,
+                    &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart, &h->spart,
                     &h->upcnt, &h->prow, &h->pval, &h->pcnt, &h->Fold, &h->zr, &h->est, &h->ev, &h->exi,
                     &h->bprobs, &h->border, &h->binfo, &h->bws, &h->scan};
   for (DevBuf* b : bufs)
@@ -1056,7 +1056,9 @@ int nnls_spd_solve(nnls_handle* h, int32_t n, const double* S, int32_t lds, cons
   launch_cholesky(h->stream, fa, false);
   SolveArgs sa = solve_args(h, n, nullptr, rhs, x);
   launch_trsv(h->stream, sa, false, false);
-  TRY(sync_read(h, h->h_ctrl, h->ctrl.p, sizeof(Ctrl)));
+  const int rs = sync_read(h, h->h_ctrl, h->ctrl.p, sizeof(Ctrl));
+  if (rs != NNLS_OK || h->h_ctrl->status != NNLS_OK) h->slots_empty = false;
+  TRY(rs);
   const Ctrl c = *h->h_ctrl;
   if (c.status == NNLS_ERR_NOT_PD && failed) *failed = c.failed_pos;
   return c.status;

@@ -548,14 +548,14 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wa
 // blocks in ascending order; backward: x_I = L_II^-T (z_I - sum_{k>I} L_kI^T x_k), blocks in
 // descending order.  Step s solves block blk(s).  Ticket 0 is the walker: it solves the
 // blocks one after another, adding the TD newest terms itself from an LDS ring of its own
-// outputs (tiles of the next step are loaded during the current one).  Ticket s+1 is the
-// helper of step s: it accumulates every older term as the walker publishes blocks and
-// hands the partial sum over (flag = this launch's tag).  A helper waits only for walker
-// steps that precede its own, and the walker waits for helpers of steps it has reached, so
-// every wait ends; each wait is also bounded in wall time.  TD is 1 for chains of at most
-// TD1_MAX_BLOCKS blocks and 2 above: one own term is cheaper for the walker, and with few
-// helpers polling the frontier their hand-over arrives within one step; longer chains keep
-// a second step of slack (measured at 57..152 and 196..469 blocks).
+// outputs.  Ticket s+1 is the helper of step s: it accumulates every older term as the
+// walker publishes blocks and hands the partial sum over in the block's slots (values that
+// are their own ready flags; the walker empties them as it takes them).  A helper waits
+// only for walker steps that precede its own, and the walker waits for helpers of steps it
+// has reached, so every wait ends; each wait is also bounded in wall time.  TD is 1 for
+// chains of at most TD1_MAX_BLOCKS blocks and 2 above: one own term is cheaper for the
+// walker, and with few helpers polling the frontier their hand-over arrives within one
+// step; longer chains keep a second step of slack (measured at 57..152 and 196..469 blocks).
 constexpr int TD1_MAX_BLOCKS = 160;
 
 template <bool FWD>
@@ -582,11 +582,11 @@ __device__ inline void load_dinv(const T* Dv, int I, int r, int g, T (&v)[16]) {
 }
 
 template <typename T, bool FWD, int TD>
-__global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ticks, int tag) {
+__global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ticks) {
   __shared__ double part[4][TILE];
   __shared__ double srhs[TILE];
   __shared__ double ring[TD][TILE];
-  __shared__ int s_t;
+  __shared__ int s_t, s_known[2];
   const int tid = threadIdx.x, r = tid & (TILE - 1), g = tid >> 6;
   int32_t* ticket = FWD ? &a.ctrl->fwd_ticket : &a.ctrl->bwd_ticket;
   int32_t* done = FWD ? &a.ctrl->fwd_done : &a.ctrl->bwd_done;   // steps 0 .. done-1 are solved
@@ -606,13 +606,20 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
     double accl[16];           // BWD: columns 16 g + q, rows spread over the lanes
 #pragma unroll
     for (int q = 0; q < 16; ++q) accl[q] = 0.0;
-    int known = 0;
+    int known = 0, nfr = 0;
     T tv[16];
     if (last > 0) load_term_tile<T, FWD>(Lt, I, blk<FWD>(0, nb), r, g, tv);
     for (int u = 0; u < last; ++u) {
       if (u >= known) {
-        spin_until(done, u + 1, false, a.ctrl, wait_ticks);
-        known = ld_relaxed(done);
+        // one thread polls the frontier and passes it on through LDS (two entries, so
+        // that one is not overwritten before every wave has read it)
+        if (tid == 0) {
+          spin_until(done, u + 1, false, a.ctrl, wait_ticks);
+          s_known[nfr & 1] = ld_relaxed(done);
+        }
+        __syncthreads();
+        known = s_known[nfr & 1];
+        ++nfr;
         acquire_agent();
       }
       const int K = blk<FWD>(u, nb);
@@ -633,34 +640,41 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
     }
     part[g][r] = acc;
     __syncthreads();
-    if (tid < TILE) a.part[(int64_t)I * TILE + tid] = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
-    publish_store(&a.pflag[I], tag);
+    if (tid < TILE) slot_put(&a.part[(int64_t)I * TILE + tid], ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid]);
     return;
   }
 
-  // the walker.  The tiles of step s+1 (its newest-term tiles of L and its inverted
-  // diagonal tile, two sets of registers) are requested at the start of step s, as soon as
-  // step s has read its own, so that their latency hides behind step s.  Only wave 0 waits
-  // for the helper and reads the hand-over and the right-hand side.
+  // the walker.  What step s+1 reads apart from the chain (its newest-term tiles of L, its
+  // inverted diagonal tile and its right-hand side) is requested during step s.  With one
+  // own term the request follows step s's publication, so that no wait of step s covers
+  // those loads (a wait for any load also waits for every load issued before it) and they
+  // complete while the walker waits for the next hand-over; with two, the tiles are
+  // requested as soon as step s has read its own.  Only wave 0 takes the hand-over.
   T td[TD][16], dv[16], dn[16];
-  {
-    const int I0 = blk<FWD>(0, nb);
-    load_dinv<T, FWD>(Dv, I0, r, g, dv);
-  }
+  double rhs = 0.0, rhs_next = 0.0;
+  auto prefetch = [&](int s1, T (&dinv)[16], double& rhs1) {
+    const int In = blk<FWD>(s1, nb);
+#pragma unroll
+    for (int j = 0; j < TD; ++j) {
+      const int u = s1 - TD + j;
+      if (u >= 0) load_term_tile<T, FWD>(Lt, In, blk<FWD>(u, nb), r, g, td[j]);
+    }
+    load_dinv<T, FWD>(Dv, In, r, g, dinv);
+    if (tid < TILE) {
+      const int p = In * TILE + tid;
+      if (FWD) {
+        rhs1 = 0.0;
+        if (p < a.nF) rhs1 = a.rhs_full ? a.rhs_full[a.Flist ? a.Flist[p] : p] : a.rhs_dense[p];
+      } else {
+        rhs1 = a.z[p];
+      }
+    }
+  };
+  prefetch(0, dv, rhs);
   for (int s = 0; s < nb; ++s) {
     const int I = blk<FWD>(s, nb);
-    double rhs = 0.0, older = 0.0;
-    if (tid < TILE) {
-      spin_until(&a.pflag[I], tag, true, a.ctrl, wait_ticks);
-      acquire_agent();
-      const int p = I * TILE + tid;
-      if (FWD) {
-        if (p < a.nF) rhs = a.rhs_full ? a.rhs_full[a.Flist ? a.Flist[p] : p] : a.rhs_dense[p];
-      } else {
-        rhs = a.z[p];
-      }
-      older = a.part[p];
-    }
+    double older = 0.0;
+    if (tid < TILE) older = slot_take(&a.part[I * TILE + tid], a.ctrl, wait_ticks);
     // newest terms: steps max(0, s-TD) .. s-1, oldest first
     double acc = 0.0;
 #pragma unroll
@@ -672,16 +686,7 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
         for (int q = 0; q < 16; ++q) acc = fma((double)td[j][q], xk[g * 16 + q], acc);
       }
     }
-    // step s+1's tiles: its newest-term tiles (td is free now) and its inverse
-    if (s + 1 < nb) {
-      const int In = blk<FWD>(s + 1, nb);
-#pragma unroll
-      for (int j = 0; j < TD; ++j) {
-        const int u = s + 1 - TD + j;
-        if (u >= 0) load_term_tile<T, FWD>(Lt, In, blk<FWD>(u, nb), r, g, td[j]);
-      }
-      load_dinv<T, FWD>(Dv, In, r, g, dn);
-    }
+    if (TD > 1 && s + 1 < nb) prefetch(s + 1, dn, rhs_next);
     part[g][r] = acc;
     __syncthreads();
     if (tid < TILE)
@@ -690,8 +695,6 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
     double xx = 0.0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) xx = fma((double)dv[q], srhs[g * 16 + q], xx);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) dv[q] = dn[q];
     part[g][r] = xx;
     __syncthreads();
     if (tid < TILE) {
@@ -701,6 +704,15 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
       ring[s % TD][tid] = v;
     }
     publish_store(done, s + 1);
+    if (s + 1 < nb) {
+      if (TD == 1) {
+        prefetch(s + 1, dv, rhs);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) dv[q] = dn[q];
+        rhs = rhs_next;
+      }
+    }
   }
   // x into the caller's vector through the F list, off the chain (this workgroup wrote outv)
   if (!FWD && a.out) {
@@ -737,11 +749,11 @@ template <int TD>
 static void launch_trsv_td(hipStream_t s, const SolveArgs& a, bool fp32, bool forward) {
   const dim3 grid(a.nb + 1);   // the helpers and the walker
   if (fp32) {
-    if (forward) hipLaunchKernelGGL((k_trsv_walk<float, true, TD>), grid, dim3(256), 0, s, a, a.wait_ticks, a.tag);
-    hipLaunchKernelGGL((k_trsv_walk<float, false, TD>), grid, dim3(256), 0, s, a, a.wait_ticks, a.tag + 1);
+    if (forward) hipLaunchKernelGGL((k_trsv_walk<float, true, TD>), grid, dim3(256), 0, s, a, a.wait_ticks);
+    hipLaunchKernelGGL((k_trsv_walk<float, false, TD>), grid, dim3(256), 0, s, a, a.wait_ticks);
   } else {
-    if (forward) hipLaunchKernelGGL((k_trsv_walk<double, true, TD>), grid, dim3(256), 0, s, a, a.wait_ticks, a.tag);
-    hipLaunchKernelGGL((k_trsv_walk<double, false, TD>), grid, dim3(256), 0, s, a, a.wait_ticks, a.tag + 1);
+    if (forward) hipLaunchKernelGGL((k_trsv_walk<double, true, TD>), grid, dim3(256), 0, s, a, a.wait_ticks);
+    hipLaunchKernelGGL((k_trsv_walk<double, false, TD>), grid, dim3(256), 0, s, a, a.wait_ticks);
   }
 }
 

@@ -169,6 +169,11 @@ struct FactorArgs {
 void launch_cholesky(hipStream_t s, const FactorArgs& a, bool fp32);
 // z = L^-1 rhs (rhs gathered through Flist when gather != nullptr); x = L^-T z and
 // scatter x through Flist into out (when out != nullptr) and into xF.
+// Both 32-bit halves of an empty hand-over slot of the triangular solves (a signalling-NaN
+// bit pattern, which no arithmetic result has); a buffer of slots is emptied by filling
+// it with this word.
+constexpr int32_t SLOT_EMPTY_WORD = 0x7FF4A5A5;
+
 struct SolveArgs {
   int nF, nb;
   const int32_t* Flist;
@@ -182,9 +187,8 @@ struct SolveArgs {
   int epoch;
   Ctrl* ctrl;
   uint64_t wait_ticks;
-  double* part;             // nb * TILE: partial sums handed to the walker
-  int32_t* pflag;           // nb flags: partial sum of block I ready when == tag
-  int tag;                  // this call's flag value (forward tag, backward tag + 1)
+  double* part;             // nb * TILE hand-over slots: partial sums for the walker, empty
+                            // (every 32-bit word SLOT_EMPTY_WORD) between launches
 };
 void launch_trsv(hipStream_t s, const SolveArgs& a, bool fp32, bool forward);
 void launch_tiles_to_dense(hipStream_t s, int n, const void* Ltiles, bool fp32, double* L, int ldl);

@@ -68,6 +68,37 @@ __device__ inline bool spin_until(const int32_t* p, int target, bool exact, Ctrl
   }
 }
 
+// A hand-over slot whose value is its own ready flag: empty slots hold SLOT_EMPTY, a
+// signalling NaN, which arithmetic never returns (it quiets NaN operands), so a computed
+// value can never read as empty.  One agent-scope access carries both the data and the
+// readiness, where a flag would need a second round trip through memory after it.
+constexpr uint64_t SLOT_EMPTY = ((uint64_t)(uint32_t)SLOT_EMPTY_WORD << 32) | (uint32_t)SLOT_EMPTY_WORD;
+__device__ inline void slot_put(double* p, double v) {
+  __hip_atomic_store((uint64_t*)p, (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until the slot is filled, take its value and leave the slot empty again.  A wait
+// beyond the bound raises NNLS_ERR_DEVICE and returns 0.
+__device__ inline double slot_take(double* p, Ctrl* ctrl, uint64_t wait_ticks) {
+  uint64_t* q = (uint64_t*)p;
+  uint64_t v = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (v == SLOT_EMPTY) {
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+      __builtin_amdgcn_s_sleep(1);
+      v = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (v != SLOT_EMPTY) break;
+      if (ld_relaxed(&ctrl->abort)) return 0.0;
+      if (wall_clock64() - t0 > wait_ticks) {
+        raise_abort(ctrl);
+        return 0.0;
+      }
+    }
+  }
+  __hip_atomic_store(q, SLOT_EMPTY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __longlong_as_double((long long)v);
+}
+
 // Make every thread's global stores visible at agent scope, then let thread 0 set a flag
 // (and bump a counter).  The barrier completes the workgroup's stores into this XCD's L2
 // (workgroup-scope release); thread 0's agent-scope release fence then writes that L2
