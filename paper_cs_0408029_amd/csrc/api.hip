@@ -290,7 +290,7 @@ int ensure_factor(nnls_handle* h, int nF, bool fp32, bool* lost = nullptr) {
   TRY(ensure(h, h->zr, (size_t)nb * TILE * sizeof(double)));
   TRY(ensure(h, h->xF, (size_t)nb * TILE * sizeof(double)));
   const void* slots_before = h->spart.p;
-  TRY(ensure(h, h->spart, (size_t)nb * TILE * sizeof(double)));
+  TRY(ensure(h, h->spart, 2 * (size_t)nb * TILE * sizeof(double)));
   if (h->spart.p != slots_before) h->slots_empty = false;
   if (lost) *lost = before[0] != h->Lt.p || before[1] != h->Dinv.p || before[2] != h->z.p;
   return NNLS_OK;

@@ -549,14 +549,14 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wa
 // descending order.  Step s solves block blk(s).  Ticket 0 is the walker: it solves the
 // blocks one after another, adding the TD newest terms itself from an LDS ring of its own
 // outputs.  Ticket s+1 is the helper of step s: it accumulates every older term as the
-// walker publishes blocks and hands the partial sum over in the block's slots (values that
-// are their own ready flags; the walker empties them as it takes them).  A helper waits
-// only for walker steps that precede its own, and the walker waits for helpers of steps it
-// has reached, so every wait ends; each wait is also bounded in wall time.  TD is 1 for
-// chains of at most TD1_MAX_BLOCKS blocks and 2 above: one own term is cheaper for the
-// walker, and with few helpers polling the frontier their hand-over arrives within one
-// step; longer chains keep a second step of slack (measured at 57..152 and 196..469 blocks).
-constexpr int TD1_MAX_BLOCKS = 160;
+// walker's outputs appear and hands the partial sum over.  Both directions go through
+// slots whose values are their own ready flags: the walker writes each output block into
+// output slots that the helpers read, and takes (and empties) each helper's partial-sum
+// slots; at its end it empties the output slots.  A helper waits only for walker steps that
+// precede its own, and the walker waits for helpers of steps it has reached, so every wait
+// ends; each wait is also bounded in wall time.  The walker adds TD = 1 own term per step:
+// the helper of step s then has one walker step of slack, which covers its hand-over at
+// every chain length measured (57..469 blocks; a second own term was slower throughout).
 
 template <bool FWD>
 __device__ inline int blk(int s, int nb) { return FWD ? s : nb - 1 - s; }
@@ -586,10 +586,10 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
   __shared__ double part[4][TILE];
   __shared__ double srhs[TILE];
   __shared__ double ring[TD][TILE];
-  __shared__ int s_t, s_known[2];
+  __shared__ double xs[2][TILE];
+  __shared__ int s_t;
   const int tid = threadIdx.x, r = tid & (TILE - 1), g = tid >> 6;
   int32_t* ticket = FWD ? &a.ctrl->fwd_ticket : &a.ctrl->bwd_ticket;
-  int32_t* done = FWD ? &a.ctrl->fwd_done : &a.ctrl->bwd_done;   // steps 0 .. done-1 are solved
   if (tid == 0) s_t = atomicAdd(ticket, 1) - 1;
   __syncthreads();
   const int t = s_t, nb = a.nb;
@@ -597,46 +597,27 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
   const T* Lt = (const T*)a.Ltiles;
   const T* Dv = (const T*)a.Dinv;
   double* outv = FWD ? a.z : a.xF;
+  double* xsl = a.part + (int64_t)nb * TILE;   // the walker's outputs, one slot per row
 
   if (t >= 0) {
     // helper of step t: every term from steps 0 .. t-TD-1
     const int I = blk<FWD>(t, nb);
     const int last = t - TD;   // steps < last
-    double acc = 0.0;          // FWD: row r, columns of group g
-    double accl[16];           // BWD: columns 16 g + q, rows spread over the lanes
-#pragma unroll
-    for (int q = 0; q < 16; ++q) accl[q] = 0.0;
-    int known = 0, nfr = 0;
+    double acc = 0.0;          // row r (FWD) or column r (BWD), terms of group g
     T tv[16];
     if (last > 0) load_term_tile<T, FWD>(Lt, I, blk<FWD>(0, nb), r, g, tv);
     for (int u = 0; u < last; ++u) {
-      if (u >= known) {
-        // one thread polls the frontier and passes it on through LDS (two entries, so
-        // that one is not overwritten before every wave has read it)
-        if (tid == 0) {
-          spin_until(done, u + 1, false, a.ctrl, wait_ticks);
-          s_known[nfr & 1] = ld_relaxed(done);
-        }
-        __syncthreads();
-        known = s_known[nfr & 1];
-        ++nfr;
-        acquire_agent();
-      }
       const int K = blk<FWD>(u, nb);
+      // wave 0 waits for the walker's output of step u in its slots and stages it in LDS
+      // (two buffers: the one step u writes was last read before the previous barrier)
+      if (tid < TILE) xs[u & 1][tid] = slot_wait(&xsl[(int64_t)K * TILE + tid], a.ctrl, wait_ticks);
+      __syncthreads();
       T cur[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) cur[q] = tv[q];
       if (u + 1 < last) load_term_tile<T, FWD>(Lt, I, blk<FWD>(u + 1, nb), r, g, tv);
-      if (FWD) {
-        const double* zk = outv + (int64_t)K * TILE;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc = fma((double)cur[q], zk[g * 16 + q], acc);
-      } else {
-        // the transposed tile: thread (r, g) holds column r of L_KI^T's rows 16 g ..
-        const double* xk = outv + (int64_t)K * TILE;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc = fma((double)cur[q], xk[g * 16 + q], acc);
-      }
+      for (int q = 0; q < 16; ++q) acc = fma((double)cur[q], xs[u & 1][g * 16 + q], acc);
     }
     part[g][r] = acc;
     __syncthreads();
@@ -649,7 +630,8 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
   // own term the request follows step s's publication, so that no wait of step s covers
   // those loads (a wait for any load also waits for every load issued before it) and they
   // complete while the walker waits for the next hand-over; with two, the tiles are
-  // requested as soon as step s has read its own.  Only wave 0 takes the hand-over.
+  // requested as soon as step s has read its own.  Only wave 0 takes the hand-over and
+  // writes the output slots.
   T td[TD][16], dv[16], dn[16];
   double rhs = 0.0, rhs_next = 0.0;
   auto prefetch = [&](int s1, T (&dinv)[16], double& rhs1) {
@@ -702,8 +684,9 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
       const int p = I * TILE + tid;
       outv[p] = v;
       ring[s % TD][tid] = v;
+      slot_put(&xsl[p], v);
     }
-    publish_store(done, s + 1);
+    __syncthreads();   // the LDS partial sums are read before the next step writes them
     if (s + 1 < nb) {
       if (TD == 1) {
         prefetch(s + 1, dv, rhs);
@@ -714,6 +697,9 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
       }
     }
   }
+  // every helper has read its last output slot before handing over its own partial sum, and
+  // every hand-over has been taken: the output slots can be emptied for the next launch
+  for (int i = tid; i < nb * TILE; i += 256) slot_clear(&xsl[i]);
   // x into the caller's vector through the F list, off the chain (this workgroup wrote outv)
   if (!FWD && a.out) {
     __syncthreads();
@@ -759,8 +745,7 @@ static void launch_trsv_td(hipStream_t s, const SolveArgs& a, bool fp32, bool fo
 
 void launch_trsv(hipStream_t s, const SolveArgs& a, bool fp32, bool forward) {
   if (a.nb <= 0) return;
-  if (a.nb <= TD1_MAX_BLOCKS) launch_trsv_td<1>(s, a, fp32, forward);
-  else launch_trsv_td<2>(s, a, fp32, forward);
+  launch_trsv_td<1>(s, a, fp32, forward);
 }
 
 void launch_tiles_to_dense(hipStream_t s, int n, const void* Ltiles, bool fp32, double* L, int ldl) {

@@ -28,8 +28,6 @@ struct Ctrl {
   int32_t chol_ticket; // work-queue counters of the dataflow kernels
   int32_t fwd_ticket;
   int32_t bwd_ticket;
-  int32_t fwd_done;    // frontier of the forward triangular solve (blocks finished)
-  int32_t bwd_done;    // frontier of the backward triangular solve
   int32_t j0;          // leading tile columns of the previous factor that the new F order keeps
   int32_t pad_;
   double min_margin;   // smallest |v| over the tested entries that were not zeroed
@@ -187,8 +185,9 @@ struct SolveArgs {
   int epoch;
   Ctrl* ctrl;
   uint64_t wait_ticks;
-  double* part;             // nb * TILE hand-over slots: partial sums for the walker, empty
-                            // (every 32-bit word SLOT_EMPTY_WORD) between launches
+  double* part;             // 2 * nb * TILE hand-over slots, empty (every 32-bit word
+                            // SLOT_EMPTY_WORD) between launches: [0, nb * TILE) the helpers'
+                            // partial sums, [nb * TILE, 2 nb * TILE) the walker's outputs
 };
 void launch_trsv(hipStream_t s, const SolveArgs& a, bool fp32, bool forward);
 void launch_tiles_to_dense(hipStream_t s, int n, const void* Ltiles, bool fp32, double* L, int ldl);

@@ -99,6 +99,30 @@ __device__ inline double slot_take(double* p, Ctrl* ctrl, uint64_t wait_ticks) {
   return __longlong_as_double((long long)v);
 }
 
+// Wait until the slot is filled and return its value, leaving it filled (for slots that
+// several readers take the same value from).
+__device__ inline double slot_wait(const double* p, Ctrl* ctrl, uint64_t wait_ticks) {
+  const uint64_t* q = (const uint64_t*)p;
+  uint64_t v = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (v == SLOT_EMPTY) {
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+      __builtin_amdgcn_s_sleep(1);
+      v = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (v != SLOT_EMPTY) break;
+      if (ld_relaxed(&ctrl->abort)) return 0.0;
+      if (wall_clock64() - t0 > wait_ticks) {
+        raise_abort(ctrl);
+        return 0.0;
+      }
+    }
+  }
+  return __longlong_as_double((long long)v);
+}
+__device__ inline void slot_clear(double* p) {
+  __hip_atomic_store((uint64_t*)p, SLOT_EMPTY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Make every thread's global stores visible at agent scope, then let thread 0 set a flag
 // (and bump a counter).  The barrier completes the workgroup's stores into this XCD's L2
 // (workgroup-scope release); thread 0's agent-scope release fence then writes that L2
