@@ -140,6 +140,27 @@ def test_spd_solve(h, n):
     assert np.linalg.norm(x.cpu().numpy() - xr) <= 1e3 * 50 * n * EPS * np.linalg.norm(xr)
 
 
+def test_spd_solve_after_failed_call(h):
+    """A call that ends in an error leaves the triangular solves' hand-over slots to be
+    emptied again before the next call; solves after it (same size, then a larger one that
+    reallocates the slots) must be exact."""
+    n = 300
+    rng = np.random.default_rng(11)
+    bad = spd(n, 7, cond=1e2)
+    bad[10, 10] = -1.0
+    x = torch.empty(n, dtype=torch.float64, device=DEV)
+    st, failed = N.nnls_spd_solve(h, colmajor_dev(bad), t(rng.standard_normal(n)), x)
+    assert st == N.NNLS_ERR_NOT_PD and failed == 10
+    for nn in (n, 3 * n + 17, n):
+        S = spd(nn, 8 + nn, cond=1e3)
+        rhs = rng.standard_normal(nn)
+        xx = torch.empty(nn, dtype=torch.float64, device=DEV)
+        st, failed = N.nnls_spd_solve(h, colmajor_dev(S), t(rhs), xx)
+        assert st == N.NNLS_OK and failed == -1
+        xr = np.linalg.solve(S, rhs)
+        assert np.linalg.norm(xx.cpu().numpy() - xr) <= 1e3 * 50 * nn * EPS * np.linalg.norm(xr)
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_dual_step(h, seed):
     inst = W.sparse_small(seed, m=1500, n=500, density=0.03)
