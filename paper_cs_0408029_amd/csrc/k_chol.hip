@@ -626,33 +626,31 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
   }
 
   // the walker.  What step s+1 reads apart from the chain (its newest-term tiles of L, its
-  // inverted diagonal tile and its right-hand side) is requested during step s.  With one
-  // own term the request follows step s's publication, so that no wait of step s covers
-  // those loads (a wait for any load also waits for every load issued before it) and they
-  // complete while the walker waits for the next hand-over; with two, the tiles are
-  // requested as soon as step s has read its own.  Only wave 0 takes the hand-over and
-  // writes the output slots.
-  T td[TD][16], dv[16], dn[16];
-  double rhs = 0.0, rhs_next = 0.0;
-  auto prefetch = [&](int s1, T (&dinv)[16], double& rhs1) {
+  // inverted diagonal tile and its right-hand side) is requested once step s has written
+  // its outputs, so that no wait of step s covers those loads (a wait for any load also
+  // waits for every load issued before it); they complete while the walker waits for the
+  // next hand-over.  Only wave 0 takes the hand-over and writes the output slots.
+  T td[TD][16], dv[16];
+  double rhs = 0.0;
+  auto prefetch = [&](int s1) {
     const int In = blk<FWD>(s1, nb);
 #pragma unroll
     for (int j = 0; j < TD; ++j) {
       const int u = s1 - TD + j;
       if (u >= 0) load_term_tile<T, FWD>(Lt, In, blk<FWD>(u, nb), r, g, td[j]);
     }
-    load_dinv<T, FWD>(Dv, In, r, g, dinv);
+    load_dinv<T, FWD>(Dv, In, r, g, dv);
     if (tid < TILE) {
       const int p = In * TILE + tid;
       if (FWD) {
-        rhs1 = 0.0;
-        if (p < a.nF) rhs1 = a.rhs_full ? a.rhs_full[a.Flist ? a.Flist[p] : p] : a.rhs_dense[p];
+        rhs = 0.0;
+        if (p < a.nF) rhs = a.rhs_full ? a.rhs_full[a.Flist ? a.Flist[p] : p] : a.rhs_dense[p];
       } else {
-        rhs1 = a.z[p];
+        rhs = a.z[p];
       }
     }
   };
-  prefetch(0, dv, rhs);
+  prefetch(0);
   for (int s = 0; s < nb; ++s) {
     const int I = blk<FWD>(s, nb);
     double older = 0.0;
@@ -668,7 +666,6 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
         for (int q = 0; q < 16; ++q) acc = fma((double)td[j][q], xk[g * 16 + q], acc);
       }
     }
-    if (TD > 1 && s + 1 < nb) prefetch(s + 1, dn, rhs_next);
     part[g][r] = acc;
     __syncthreads();
     if (tid < TILE)
@@ -687,15 +684,7 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
       slot_put(&xsl[p], v);
     }
     __syncthreads();   // the LDS partial sums are read before the next step writes them
-    if (s + 1 < nb) {
-      if (TD == 1) {
-        prefetch(s + 1, dv, rhs);
-      } else {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) dv[q] = dn[q];
-        rhs = rhs_next;
-      }
-    }
+    if (s + 1 < nb) prefetch(s + 1);
   }
   // every helper has read its last output slot before handing over its own partial sum, and
   // every hand-over has been taken: the output slots can be emptied for the next launch
