@@ -41,7 +41,9 @@ extern "C" {
 typedef enum {
   NNLS_OK = 0,
   NNLS_ERR_INVALID_ARG = -1,   /* bad size, null pointer, malformed CSC structure       */
-  NNLS_ERR_INVALID_VALUE = -2, /* NaN or Inf in A or b                                   */
+  NNLS_ERR_INVALID_VALUE = -2, /* NaN or Inf in A or b, or a tested entry of an iterate
+                                  (x_i on F, y_i on G) that is not finite, which no sign
+                                  test can decide                                        */
   NNLS_ERR_NOT_PD = -3,        /* Cholesky breakdown: the F-block is not numerically
                                   positive definite (A_F rank deficient, or kappa^2 eps
                                   >= 1 as Sec. 2.1 warns); failed_index names the column */
@@ -321,7 +323,8 @@ int nnls_dual_dense(nnls_handle* h, int32_t m, int32_t n, const double* A, int32
  * in place (x is additionally zeroed on the new G and y on the new F).  state (host,
  * int32[3]) holds {N, p, reserved} in and out; N < 0 stands for infinity.  out (host,
  * int32[4]) receives {k, branch (-1 when k == 0), largest infeasible index, new |F|
- * (-1 when k == 0: nothing is exchanged)}. */
+ * (-1 when k == 0: nothing is exchanged)}.  A tested entry that is NaN or infinite
+ * returns NNLS_ERR_INVALID_VALUE and exchanges nothing. */
 int nnls_pivot_step(nnls_handle* h, int32_t n, double* x, double* y, uint8_t* free_flags,
                     double tau, int32_t p_max, int32_t* state, int32_t* out);
 

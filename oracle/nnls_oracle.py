@@ -10,24 +10,29 @@ least squares problems with non-negative variables" (arXiv cs/0408029):
   * complementarity form: y = A^T A x - A^T b, x >= 0, y >= 0, <x, y> = 0 (Eq. 3);
   * complementary basic solution for a split (F, G): x_F solves the unconstrained least
     squares problem on the columns A_F (Eq. 4) and y_G = A_G^T (A_F x_F - b) (Eq. 5);
-  * the pivoting loop of the algorithm box in Sec. 2 ("Block principal pivoting algorithm,
-    modified for numerically degenerate problems"): exchange all infeasible variables
+  * the pivoting loop of the algorithm box in Sec. 2 (block principal pivoting with the
+    paper's change for numerically degenerate problems): exchange all infeasible variables
     while their count falls, allow three non-improving block exchanges, then exchange only
-    the infeasible variable of largest index; zero variables within 1e-12 of zero;
+    the infeasible variable of largest index; tested entries of magnitude below 1e-12
+    count as zero;
   * Eq. 4 is solved by the normal equations A_F^T A_F x_F = A_F^T b with a Cholesky
     factor (Sec. 2.1), taking A_F^T A_F as the F-principal block of A^T A computed once
     from column dot products (Sec. 3).
 
 Readings where the paper is silent or loose (each also listed in the design notes):
-  * zeroing is |v| < tau -> v = 0 with an absolute tau (the box's literal "x_F < 1e-12"
-    would zero every negative entry; the text of Sec. 2 says "within 1e-12 of zero");
+  * zeroing is |v| < tau -> v = 0 with an absolute tau (a literal reading of the box's
+    inequality would zero every negative entry; the Sec. 2 text bounds the magnitude);
   * the same classify-and-zero step also runs before the first exchange, on y = -A^T b;
   * y_G is formed from the un-zeroed x_F; zeroing happens at the top of the next pass;
-  * "negative" means strictly below zero after zeroing; the paper's count "n" is k here;
-  * indices are 0-based; "largest index" is the largest column number;
+  * negative means strictly below zero after zeroing; the box's count, which shares its
+    name with the problem dimension, is k here;
+  * indices are 0-based; the largest index is the largest column number;
   * an iteration cap of 5n + 100 (the paper gives none) ends the loop with 'maxiter';
   * a non-positive or non-finite Cholesky pivot ends the loop with 'not_pd' (Sec. 2.1
-    expects breakdown once kappa^2 eps >= 1 but prescribes no recovery).
+    expects breakdown once kappa^2 eps >= 1 but prescribes no recovery);
+  * the paper assumes finite data: a non-finite entry of A or b, or a tested entry of an
+    iterate that is not finite (overflow), ends the loop with 'invalid_value', since no
+    sign test can decide it.
 
 Library primitives used as steps: scipy sparse products for A^T A, A^T b and the two
 products of Eq. 5; LAPACK dpotrf for the Cholesky factor; triangular solves.
@@ -66,7 +71,7 @@ class Result:
     y: np.ndarray
     free: np.ndarray          # bool[n]: True on F
     iterations: int
-    status: str               # 'ok' | 'not_pd' | 'maxiter'
+    status: str               # 'ok' | 'not_pd' | 'maxiter' | 'invalid_value'
     failed_index: int = -1
     trace: List[TraceRow] = dataclasses.field(default_factory=list)
     last_ninf: int = 0
@@ -150,6 +155,10 @@ def bpp_solve(A, b, tau: float = TAU, p_max: int = P_MAX, max_iter: Optional[int
     m, n = A.shape
     if max_iter is None:
         max_iter = 5 * n + 100
+    a_vals = A.data if sp.issparse(A) else np.asarray(A)
+    if not (np.all(np.isfinite(a_vals)) and np.all(np.isfinite(b))):
+        return Result(x=np.zeros(n), y=np.zeros(n), free=np.zeros(n, dtype=bool), iterations=0,
+                      status='invalid_value')
     H, c = gram(A, b)
 
     # F = empty, G = everything, x = 0, y = -A^T b, p = 3, N = infinity
@@ -161,6 +170,8 @@ def bpp_solve(A, b, tau: float = TAU, p_max: int = P_MAX, max_iter: Optional[int
     trace: List[TraceRow] = []
     it = 0
     while True:
+        if not np.all(np.isfinite(np.where(free, x, y))):
+            return Result(x=x, y=y, free=free, iterations=it, status='invalid_value', trace=trace)
         infeasible, margin = classify(x, y, free, tau)
         k = int(infeasible.sum())
         if k == 0:

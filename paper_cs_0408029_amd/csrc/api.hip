@@ -19,6 +19,8 @@ namespace {
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  uint64_t gen = 0;   // bumped by every (re)allocation: a new allocation may reuse the
+                      // freed address, so only this tells whether the contents were kept
 };
 
 struct PendingEvent {
@@ -95,6 +97,7 @@ int ensure(nnls_handle* h, DevBuf& b, size_t bytes, bool zero_i32 = false) {
     return NNLS_ERR_NO_MEMORY;
   }
   b.bytes = bytes;
+  b.gen += 1;
   if (zero_i32) launch_fill_i32(h->stream, (int32_t*)b.p, (int64_t)(bytes / 4), 0);
   return NNLS_OK;
 }
@@ -280,7 +283,7 @@ int ensure_factor(nnls_handle* h, int nF, bool fp32, bool* lost = nullptr) {
   const int nb = (nF + TILE - 1) / TILE;
   const size_t w = fp32 ? sizeof(float) : sizeof(double);
   const size_t ntiles = (size_t)tile_count(nb);
-  const void* before[3] = {h->Lt.p, h->Dinv.p, h->z.p};
+  const uint64_t before[3] = {h->Lt.gen, h->Dinv.gen, h->z.gen};
   TRY(ensure(h, h->Lt, ntiles * TILE_ELEMS * w));
   TRY(ensure(h, h->Dinv, (size_t)nb * TILE_ELEMS * w));
   TRY(ensure(h, h->colcnt, (size_t)nb * sizeof(int32_t), true));
@@ -289,10 +292,10 @@ int ensure_factor(nnls_handle* h, int nF, bool fp32, bool* lost = nullptr) {
   TRY(ensure(h, h->z, (size_t)nb * TILE * sizeof(double)));
   TRY(ensure(h, h->zr, (size_t)nb * TILE * sizeof(double)));
   TRY(ensure(h, h->xF, (size_t)nb * TILE * sizeof(double)));
-  const void* slots_before = h->spart.p;
+  const uint64_t slots_before = h->spart.gen;
   TRY(ensure(h, h->spart, 2 * (size_t)nb * TILE * sizeof(double)));
-  if (h->spart.p != slots_before) h->slots_empty = false;
-  if (lost) *lost = before[0] != h->Lt.p || before[1] != h->Dinv.p || before[2] != h->z.p;
+  if (h->spart.gen != slots_before) h->slots_empty = false;   // fresh memory: not emptied yet
+  if (lost) *lost = before[0] != h->Lt.gen || before[1] != h->Dinv.gen || before[2] != h->z.gen;
   return NNLS_OK;
 }
 
@@ -402,7 +405,7 @@ int refine(nnls_handle* h, const Problem& P, int nF, double* x, double* y, const
     }
     if (info) info->ir_steps += 1;
     const double dmax = h->h_ctrl->ir_dmax, xmax = h->h_ctrl->ir_xmax;
-    if (!(dmax <= INFINITY) || !(xmax <= INFINITY)) break;
+    if (!(dmax < INFINITY) || !(xmax < INFINITY)) break;   // NaN or overflow: stalled
     // stop once the last correction, or the corrections still to come, are below the
     // target: with the measured contraction rho = dmax / prev (at most 1/2 here) the rest
     // sum to at most dmax * rho / (1 - rho)
@@ -525,6 +528,13 @@ int solve_free(nnls_handle* h, const Problem& P, int nF, int j0, double* x, doub
     bool lost = false;
     TRY(ensure_factor(h, nF, fp32, &lost));
     h->epoch += 1;
+    if (attempt > 0) {
+      // the control step zeroed the column counters and tickets for the first attempt
+      // only: the first factor left its columns counted complete, and the refinement's
+      // triangular solves used up the solve tickets
+      launch_fill_i32(h->stream, (int32_t*)h->colcnt.p, (nF + TILE - 1) / TILE, 0);
+      launch_reset_tickets(h->stream, (Ctrl*)h->ctrl.p);
+    }
     FactorArgs fa = factor_args(h, nF, Flist, P.sparse ? nullptr : (const double*)h->Hd.p,
                                 P.sparse ? 0 : P.n, P.sparse);
     fa.j0 = (attempt == 0 && !lost && h->fact_prec == (fp32 ? 1 : 0)) ? std::min(j0, fa.nb - 1) : 0;

@@ -434,12 +434,15 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
   int N = INT32_MAX, p = a.p_max, iter = 0, nF = 0, k = 0, result = 0;
   double margin = INFINITY;
   for (;;) {
-    // classify: zero |v| < tau, count negatives, largest infeasible index
-    double cnt = 0.0, rmx = -1.0, mar = INFINITY;
+    // classify: zero |v| < tau, count negatives, largest infeasible index; a tested
+    // entry that is not finite ends the problem with NNLS_ERR_INVALID_VALUE
+    double cnt = 0.0, rmx = -1.0, mar = INFINITY, nonfin = 0.0;
     for (int i = tid; i < n; i += BT) {
       const bool f = flags[i] != 0;
       const double v = f ? x[i] : y[i];
-      if (fabs(v) < a.tau) {
+      if (!isfinite(v)) {
+        nonfin = 1.0;
+      } else if (fabs(v) < a.tau) {
         if (f) x[i] = 0.0; else y[i] = 0.0;
       } else {
         mar = fmin(mar, fabs(v));
@@ -452,6 +455,10 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
     k = (int)wg_sum(cnt, red);
     const int rmax = (int)wg_max(rmx, red);
     margin = wg_min(mar, red);
+    if (wg_max(nonfin, red) > 0.0) {
+      result = NNLS_ERR_INVALID_VALUE;
+      break;
+    }
     if (k == 0) break;
     if (iter >= max_iter) {
       result = NNLS_ERR_MAXITER;
@@ -548,11 +555,12 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
             x[j] = v;
             dm = fmax(dm, fabs(xF[q]));
             xm = fmax(xm, fabs(v));
+            if (!isfinite(xF[q]) || !isfinite(v)) dm = INFINITY;   // fmax drops NaN
           }
           dm = wg_max(dm, red);
           xm = wg_max(xm, red);
           if (tid == 0) info->ir_steps += 1;
-          if (!(dm <= INFINITY) || !(xm <= INFINITY)) break;
+          if (!(dm < INFINITY) || !(xm < INFINITY)) break;
           // as in the single-problem path: the last correction, or the bound dm rho/(1-rho)
           // on the corrections still to come, below the target
           const double rho = dm / prev;   // 0 on the first step

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(CTRL_THREADS) void k_pivot_control(
     int n, double* __restrict__ x, double* __restrict__ y, uint8_t* __restrict__ flags,
     int32_t* __restrict__ Flist, int32_t* __restrict__ pos, Ctrl* ctrl, double tau, int p_max,
     int max_iter, int32_t* __restrict__ colcnt, int ncol, int32_t* __restrict__ Fold, int mode) {
-  __shared__ int s_cnt[16], s_max[16];
+  __shared__ int s_cnt[16], s_max[16], s_bad[16];
   __shared__ double s_mar[16];
   __shared__ int s_branch, s_rmax, s_done;
   __shared__ int s_off[16];
@@ -97,8 +97,10 @@ __global__ __launch_bounds__(CTRL_THREADS) void k_pivot_control(
   // the factorisation and solves of this iteration start from zeroed counters
   for (int i = tid; i < ncol; i += CTRL_THREADS) colcnt[i] = 0;
 
-  // 1. classify + zero + count
+  // 1. classify + zero + count.  A tested entry that is not finite (an iterate that
+  //    overflowed) is no sign test at all: the step stops with NNLS_ERR_INVALID_VALUE.
   int cnt = 0, rmax = -1;
+  bool nonfinite = false;
   double mar = INFINITY;
   // CTRL_BATCH entries per thread are fetched together (flag, x and y alike, so no load
   // waits for another), then tested in the same order as one at a time
@@ -119,7 +121,9 @@ __global__ __launch_bounds__(CTRL_THREADS) void k_pivot_control(
       if (i < n) {
         const bool f = fb[u] != 0;
         const double v = f ? xb[u] : yb[u];
-        if (fabs(v) < tau) {
+        if (!isfinite(v)) {
+          nonfinite = true;
+        } else if (fabs(v) < tau) {
           if (f) x[i] = 0.0; else y[i] = 0.0;
         } else {
           mar = fmin(mar, fabs(v));
@@ -132,27 +136,33 @@ __global__ __launch_bounds__(CTRL_THREADS) void k_pivot_control(
   }
   rmax = wave_max(rmax);
   mar = wave_min(mar);
+  const bool wave_nonfinite = __ballot(nonfinite) != 0;
   if (lane == 0) {
     s_cnt[w] = cnt;
     s_max[w] = rmax;
     s_mar[w] = mar;
+    s_bad[w] = wave_nonfinite ? 1 : 0;
   }
   __syncthreads();
 
   // 2. counter rule (one thread)
   if (tid == 0) {
-    int k = 0, r = -1;
+    int k = 0, r = -1, nonfin = 0;
     double mm = INFINITY;
     for (int q = 0; q < CTRL_THREADS / 64; ++q) {
       k += s_cnt[q];
       r = max(r, s_max[q]);
       mm = fmin(mm, s_mar[q]);
+      nonfin |= s_bad[q];
     }
     ctrl->k = k;
     ctrl->rmax = r;
     ctrl->min_margin = mm;
     int branch = -1, done = 0;
-    if (k == 0) {
+    if (nonfin) {
+      done = 1;
+      ctrl->status = NNLS_ERR_INVALID_VALUE;
+    } else if (k == 0) {
       done = 1;
     } else if (ctrl->iter >= max_iter) {
       done = 1;

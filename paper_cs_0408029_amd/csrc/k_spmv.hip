@@ -59,7 +59,11 @@ __global__ __launch_bounds__(256) void k_dual_csc(int n, const int32_t* __restri
   }
 }
 
+// Maximum that keeps a NaN operand (fmax drops it).
+__device__ inline double max_nan(double a, double b) { return (a > b || a != a) ? a : b; }
+
 // x[Flist[p]] -= d[p]; max |d| and max |x_F| by one workgroup (fixed reduction order).
+// A NaN correction or iterate makes the reported maximum NaN, so the host sees it.
 __global__ __launch_bounds__(1024) void k_ir_update(int nF, const int32_t* __restrict__ Flist,
                                                     const double* __restrict__ d,
                                                     double* __restrict__ x, Ctrl* ctrl) {
@@ -70,12 +74,12 @@ __global__ __launch_bounds__(1024) void k_ir_update(int nF, const int32_t* __res
     const int i = Flist[p];
     const double v = x[i] - d[p];
     x[i] = v;
-    dm = fmax(dm, fabs(d[p]));
-    xm = fmax(xm, fabs(v));
+    dm = max_nan(dm, fabs(d[p]));
+    xm = max_nan(xm, fabs(v));
   }
   for (int o = 32; o >= 1; o >>= 1) {
-    dm = fmax(dm, __shfl_xor(dm, o, 64));
-    xm = fmax(xm, __shfl_xor(xm, o, 64));
+    dm = max_nan(dm, __shfl_xor(dm, o, 64));
+    xm = max_nan(xm, __shfl_xor(xm, o, 64));
   }
   if (lane == 0) {
     s_d[w] = dm;
@@ -85,8 +89,8 @@ __global__ __launch_bounds__(1024) void k_ir_update(int nF, const int32_t* __res
   if (tid == 0) {
     double a = 0.0, b = 0.0;
     for (int q = 0; q < 16; ++q) {
-      a = fmax(a, s_d[q]);
-      b = fmax(b, s_x[q]);
+      a = max_nan(a, s_d[q]);
+      b = max_nan(b, s_x[q]);
     }
     ctrl->ir_dmax = a;
     ctrl->ir_xmax = b;

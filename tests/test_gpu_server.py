@@ -78,6 +78,31 @@ def test_mixed_stream_matches_oracle(stream_small, oracle_small, precision, tol)
     assert 0 < stats["p50_ms"] <= stats["p99_ms"] <= stats["max_ms"]
 
 
+@pytest.fixture(scope="module")
+def stream_full():
+    """The serving recipe across the whole size range of the serving mix, n in [64, 8192]
+    (m = 3n): two requests for the batched lane, five for the concurrent sparse lane."""
+    return W.serving_sizes(1014, [64, 200, 600, 1500, 3000, 5500, 8192])
+
+
+@pytest.fixture(scope="module")
+def oracle_full(stream_full):
+    return [bpp_solve(p.A, p.b) for p in stream_full]
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-8)])
+def test_full_size_range_matches_oracle(stream_full, oracle_full, precision, tol):
+    """Every request of the full size range against the sparse oracle, with several large
+    requests factored at once on their capped persistent grids (128 workgroups each)."""
+    with N.Server(0, opts=N.default_options(precision=precision), workers=4, batch_lanes=1,
+                  batch_max_n=256) as srv:
+        results = run_all(srv, stream_full)
+        stats = N.nnls_server_stats(srv)
+    check_against_oracle(stream_full, results, oracle_full, tol)
+    assert stats["completed"] == len(stream_full)
+    assert stats["max_running"] > 1
+
+
 def test_alone_equals_mix_bitwise(stream_small):
     with N.Server(0, workers=4, batch_lanes=2, batch_max_n=160) as srv:
         alone = []

@@ -276,3 +276,112 @@ def test_predicted_error_bounds_the_fig1_errors():
             err = np.linalg.norm(res.x - xt) / np.linalg.norm(xt)
             pred = predicted_rel_error(Hff)
             assert err <= pred <= 30 * err, (lk, seed, err, pred)
+
+
+# ---- the single exchange of the Sec. 2 algorithm box, worked by hand ----
+#
+# A (4 x 3) and b are small integers, so every step can be done exactly by hand:
+#   H = A^T A = [[23, -1, -2], [-1, 21, 5], [-2, 5, 2]],   c = A^T b = [-3, 4, 4].
+# Start: F = {}, x = 0, y = -c = [3, -4, -4]; the infeasible set is {1, 2}, k = 2 < N = inf:
+#   improving block exchange, N = 2, F = {1, 2}.
+# F = {1, 2}: [[21, 5], [5, 2]] x_F = [4, 4] gives x_1 = -12/17, x_2 = 64/17, and
+#   y_0 = H_01 x_1 + H_02 x_2 - c_0 = 12/17 - 128/17 + 3 = -65/17.
+#   Infeasible: {0 (y_0 < 0), 1 (x_1 < 0)}, k = 2, not below N = 2.
+#   * p_max = 0: the budget is spent, so only the infeasible variable of LARGEST index, 1,
+#     changes side: F = {2}.  (Flipping 0 instead would give F = {0, 1, 2}.)
+#     F = {2}: x_2 = 4 / 2 = 2, y_0 = -4 + 3 = -1, y_1 = 10 - 4 = 6; k = 1 < N: F = {0, 2}.
+#   * p_max = 3: budgeted block exchange, p = 2, both change side: F = {0, 2}.
+# F = {0, 2}: [[23, -2], [-2, 2]] x_F = [-3, 4] gives x_0 = 1/21, x_2 = 43/21, and
+#   y_1 = -1/21 + 5 * 43/21 - 4 = 130/21 > 0: feasible, stop.
+HAND_A = np.array([[2.0, -2.0, 0.0], [3.0, 2.0, 0.0], [-3.0, 2.0, 1.0], [-1.0, -3.0, -1.0]])
+HAND_B = np.array([1.0, -3.0, 0.0, -4.0])
+HAND_X = np.array([1.0 / 21.0, 0.0, 43.0 / 21.0])
+HAND_Y = np.array([0.0, 130.0 / 21.0, 0.0])
+# per iteration: (k, branch, N, p, F after the exchange)
+HAND_TRACE = {
+    0: [(2, BRANCH_BLOCK_IMPROVED, 2, 0, {1, 2}), (2, BRANCH_SINGLE, 2, 0, {2}),
+        (1, BRANCH_BLOCK_IMPROVED, 1, 0, {0, 2})],
+    3: [(2, BRANCH_BLOCK_IMPROVED, 2, 3, {1, 2}), (2, BRANCH_BLOCK_BUDGET, 2, 2, {0, 2})],
+}
+
+
+def test_hand_worked_instance_data():
+    """The Gram matrix and right-hand side used in the hand computation above."""
+    assert np.array_equal(HAND_A.T @ HAND_A, [[23, -1, -2], [-1, 21, 5], [-2, 5, 2]])
+    assert np.array_equal(HAND_A.T @ HAND_B, [-3, 4, 4])
+
+
+@pytest.mark.parametrize("p_max", [0, 3])
+def test_single_exchange_takes_the_largest_index(p_max):
+    """Sec. 2 algorithm box, worked by hand: with the budget spent, of the two infeasible
+    variables {0, 1} only the one of largest index (1) changes side.  The trajectory of
+    free sets is fixed by the hand computation; taking any other index changes the second
+    free set."""
+    r = bpp_solve(HAND_A, HAND_B, p_max=p_max)
+    assert r.status == "ok"
+    want = HAND_TRACE[p_max]
+    assert len(r.trace) == len(want)
+    free_sets = []
+    free = np.zeros(3, dtype=bool)
+    for row, (k, branch, N, p, F) in zip(r.trace, want):
+        assert (row.k, row.branch, row.N, row.p, row.n_free) == (k, branch, N, p, len(F))
+        free_sets.append(F)
+    assert set(np.flatnonzero(r.free)) == want[-1][4]
+    assert np.allclose(r.x, HAND_X, rtol=1e-14, atol=1e-15)
+    assert np.allclose(r.y, HAND_Y, rtol=1e-14, atol=1e-15)
+
+
+def test_single_exchange_free_sets_step_by_step():
+    """The same hand-worked run, one box iteration at a time through the oracle's own
+    steps (classify, exchange rule, solve, dual), checking the free set after each
+    exchange against the hand computation."""
+    from oracle import classify, dual, exchange_rule, solve_free
+    H, c = gram(HAND_A, HAND_B)
+    free = np.zeros(3, dtype=bool)
+    x, y = np.zeros(3), -c.copy()
+    N, p = np.inf, 0
+    for k_want, branch_want, _, _, F_want in HAND_TRACE[0]:
+        infeasible, _ = classify(x, y, free, 1e-12)
+        assert int(infeasible.sum()) == k_want
+        N, p, branch = exchange_rule(int(infeasible.sum()), N, p, 0)
+        assert branch == branch_want
+        if branch == BRANCH_SINGLE:
+            assert set(np.flatnonzero(infeasible)) == {0, 1}
+            free[int(np.flatnonzero(infeasible).max())] ^= True
+        else:
+            free ^= infeasible
+        assert set(np.flatnonzero(free)) == F_want
+        idx_f, idx_g = np.flatnonzero(free), np.flatnonzero(~free)
+        xF, failed = solve_free(H, c, idx_f)
+        assert failed == -1
+        x = np.zeros(3)
+        x[idx_f] = xF
+        y = np.zeros(3)
+        y[idx_g] = dual(HAND_A, HAND_B, idx_f, xF, idx_g)
+    infeasible, _ = classify(x, y, free, 1e-12)
+    assert not infeasible.any()
+
+
+# ---- non-finite values (no sign test can decide them) ----
+
+def test_non_finite_input_is_reported():
+    A, b = W.random_dense(5, 12, 6)
+    b = b.copy()
+    b[3] = np.nan
+    assert bpp_solve(A, b).status == "invalid_value"
+    A2 = A.copy()
+    A2[2, 1] = np.inf
+    assert bpp_solve(A2, W.random_dense(5, 12, 6)[1]).status == "invalid_value"
+
+
+NONFINITE_A = np.array([[1e300, 0.0], [0.0, 1.0], [0.0, 1.0]])
+NONFINITE_B = np.array([1e10, 1.0, 1.0])
+
+
+def test_non_finite_iterate_is_reported():
+    """Finite A and b whose A^T b overflows (1e300 * 1e10): the first tested entry,
+    y_0 = -c_0, is -inf.  No sign test can decide it, so the loop stops with
+    invalid_value instead of exchanging on it."""
+    with np.errstate(over="ignore", invalid="ignore"):
+        r = bpp_solve(NONFINITE_A, NONFINITE_B)
+    assert r.status == "invalid_value" and r.iterations == 0

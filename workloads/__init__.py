@@ -183,12 +183,13 @@ def sparse_small(seed: int = 1001, m: int = 2000, n: int = 400, density: float =
 
 
 def sparse_large(seed: int = 1002, m: int = 60000, n: int = 12000, k: int = 25,
-                 frac: float = 0.3, lo: float = 1e-3) -> Instance:
+                 frac: float = 0.3, lo: float = 1e-3, zero_pairs: int = 0) -> Instance:
     """Single large sparse instance: 25 random N(0,1) rows per column plus a three-wide
-    diagonal band (5, 2.5, 1.25); 30% active, margin 1e-3."""
+    diagonal band (5, 2.5, 1.25); 30% active, margin 1e-3.  ``zero_pairs`` inactive
+    variables get y*_i = 0 as well (a degenerate instance: x stays unique, the split not)."""
     rng = np.random.default_rng(seed)
     A = rows_per_col_band_csc(rng, m, n, k)
-    return _finish(A, rng, frac, lo, f"sparse_large_m{m}_n{n}", seed)
+    return _finish(A, rng, frac, lo, f"sparse_large_m{m}_n{n}", seed, zero_pairs=zero_pairs)
 
 
 def sparse_blockband(seed: int = 1005, m: int = 400000, n: int = 50000, k: int = 20,
@@ -220,6 +221,14 @@ def dense_batch(seed: int = 1003, count: int = 4096, n_lo: int = 16, n_hi: int =
     return out
 
 
+def _serving_problem(rng, n: int, k: int, name: str, seed: int) -> Instance:
+    m = 3 * n
+    s = math.sqrt(k)
+    A = rows_per_col_band_csc(rng, m, n, k, band=(s, s / 2, s / 4))
+    frac = float(rng.uniform(0.3, 0.6))
+    return _finish(A, rng, frac, 1e-3, name, seed)
+
+
 def serving_stream(seed: int = 1004, count: int = 64, rate: float = 2000.0,
                    n_lo: int = 64, n_hi: int = 8192, k: int = 20):
     """Poisson arrival times (exponential gaps, mean 1/rate) and mixed sparse problems:
@@ -232,12 +241,35 @@ def serving_stream(seed: int = 1004, count: int = 64, rate: float = 2000.0,
     for i, ss in enumerate(children[1:]):
         rng = np.random.default_rng(ss)
         n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
-        m = 3 * n
-        s = math.sqrt(k)
-        A = rows_per_col_band_csc(rng, m, n, k, band=(s, s / 2, s / 4))
-        frac = float(rng.uniform(0.3, 0.6))
-        probs.append(_finish(A, rng, frac, 1e-3, f"serve{i}_m{m}_n{n}", seed))
+        probs.append(_serving_problem(rng, n, k, f"serve{i}_m{3 * n}_n{n}", seed))
     return arrivals, probs
+
+
+def serving_sizes(seed: int, ns, k: int = 20) -> List[Instance]:
+    """Problems of the serving recipe at the given sizes n (one child stream each), so that
+    a test can span the whole range [64, 8192] of the serving mix with a few requests."""
+    children = np.random.SeedSequence(seed).spawn(len(ns))
+    return [_serving_problem(np.random.default_rng(ss), int(n), k, f"serve_n{n}", seed)
+            for ss, n in zip(children, ns)]
+
+
+def fig2_matrix(rng, rows: int, density: float):
+    """A matrix of the paper's speed experiment (Sec. 4, Fig. 2): rows x (rows - 10) with
+    N(0,1) values; dense (column-major ndarray) at density 1.0, else a uniform random
+    pattern of that density in CSC (the role MATLAB's sprandn plays in the paper), with a
+    right-hand side b ~ N(0,1)."""
+    m, n = rows, rows - 10
+    if density >= 1.0:
+        A = np.asfortranarray(rng.standard_normal((m, n)))
+    else:
+        A = _canonical_csc(sp.random(m, n, density=density, format="csc", random_state=rng,
+                                     data_rvs=rng.standard_normal))
+    return A, rng.standard_normal(m)
+
+
+# the sizes (rows) of Fig. 2: density 1.0 and density 0.01
+FIG2_DENSE_ROWS = (120, 200, 300, 499, 699, 938)
+FIG2_SPARSE_ROWS = (820, 1000, 1200, 1420)
 
 
 def svd_conditioned(seed: int, kappa: float, m: int = 80, n: int = 70, rep: int = 4):
