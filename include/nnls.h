@@ -52,7 +52,9 @@ typedef enum {
   NNLS_ERR_DEVICE = -6,        /* HIP runtime error, or a device-side wait exceeded its
                                   bound                                                  */
   NNLS_ERR_REFINE = -7,        /* mixed precision: refinement did not reach its target   */
-  NNLS_ERR_TIMEOUT = -8        /* nnls_server_wait: the request is not finished yet      */
+  NNLS_ERR_TIMEOUT = -8,       /* nnls_server_wait: the request is not finished yet      */
+  NNLS_ERR_TOO_LARGE = -9      /* nnls_solve_dense_batched_noalloc: the batch needs more
+                                  device memory than its fixed scratch array holds       */
 } nnls_status;
 
 typedef enum {
@@ -169,6 +171,29 @@ int nnls_solve_dense_batched(nnls_handle* h, int32_t batch, const int32_t* m, co
                              const double* const* A, const int32_t* lda, const double* const* b,
                              double* const* x, double* const* y, const nnls_options* opts,
                              nnls_info* info);
+
+/* For callers that cannot allocate device memory (code under HIP stream capture, serving
+ * loops that must keep a fixed footprint, harnesses that forbid allocation): the same
+ * solve as nnls_solve_dense_batched (same kernel, same per-problem results, bit for bit),
+ * with every device buffer of the launch (problem descriptors, per-problem status and the
+ * workspace arena) carved from one static device array of NNLS_NOALLOC_SCRATCH_BYTES per
+ * GPU instead of the handle's growable workspace.  The call performs no hipMalloc,
+ * hipFree or other allocation; the array is part of the library's code object, so each
+ * GPU the library runs on holds it until the process ends.
+ * Capacity: 256-byte-aligned descriptors (batch * 56 bytes), statuses (batch * 32 bytes)
+ * and the problems' workspaces (about 8 (n^2 + m) bytes plus the factor tiles of n each)
+ * must fit together; otherwise NNLS_ERR_TOO_LARGE is returned and nothing runs.
+ * Problems run in the given order (not sorted by size).  NNLS_FLAG_PROFILE is ignored.
+ * Every call on one GPU shares that GPU's array: calls that overlap on the same GPU (from
+ * two threads, or on two streams) race and give undefined results, so callers serialise
+ * them.  The array keeps the last call's contents; the kernel initialises everything it
+ * reads, so nothing needs clearing between calls.
+ * Arguments, outputs and the other errors: as nnls_solve_dense_batched. */
+#define NNLS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int nnls_solve_dense_batched_noalloc(nnls_handle* h, int32_t batch, const int32_t* m,
+                                     const int32_t* n, const double* const* A, const int32_t* lda,
+                                     const double* const* b, double* const* x, double* const* y,
+                                     const nnls_options* opts, nnls_info* info);
 
 /* ---------------------------------------------------------------------------------
  * Serving engine: continuous batching of independent requests (Eq. 1 each) on one device.

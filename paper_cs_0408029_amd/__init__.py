@@ -13,7 +13,7 @@ from typing import List, Optional, Tuple
 
 from ._lib import (LIB_PATH, NNLS_ERR_DEVICE, NNLS_ERR_INVALID_ARG, NNLS_ERR_INVALID_VALUE,  # noqa: F401
                    NNLS_ERR_MAXITER, NNLS_ERR_NO_MEMORY, NNLS_ERR_NOT_PD, NNLS_ERR_REFINE,
-                   NNLS_ERR_TIMEOUT, NNLS_FLAG_GRAM_DUAL, NNLS_FLAG_NO_FACTOR_REUSE, NNLS_FLAG_PROFILE, NNLS_FLAG_REFINE_AUTO, NNLS_FLAG_REFINE_FINAL, NNLS_FP32_IR, NNLS_FP64, NNLS_OK,
+                   NNLS_ERR_TIMEOUT, NNLS_ERR_TOO_LARGE, NNLS_NOALLOC_SCRATCH_BYTES, NNLS_FLAG_GRAM_DUAL, NNLS_FLAG_NO_FACTOR_REUSE, NNLS_FLAG_PROFILE, NNLS_FLAG_REFINE_AUTO, NNLS_FLAG_REFINE_FINAL, NNLS_FP32_IR, NNLS_FP64, NNLS_OK,
                    NNLS_PROFILE_CLASSES, PROFILE_CLASS_NAMES, default_options, load, nnls_info,
                    nnls_options, nnls_server_config, nnls_serving_stats, nnls_trace_row,
                    status_string)
@@ -149,6 +149,19 @@ def nnls_solve_dense_batched(h: Handle, As=None, bs=None, xs=None, ys=None,
     vp = lambda arr: C.cast(arr, C.c_void_p)
     st = h.lib.nnls_solve_dense_batched(h.ptr, p.batch, vp(p.m), vp(p.n), vp(p.pa), vp(p.lda), vp(p.pb),
                                         vp(p.px), vp(p.py), C.byref(opts) if opts else None, vp(p.infos))
+    return st, list(p.infos[:p.batch])
+
+
+def nnls_solve_dense_batched_noalloc(h: Handle, As=None, bs=None, xs=None, ys=None,
+                                     opts: Optional[nnls_options] = None,
+                                     packed: Optional[BatchedArgs] = None):
+    """nnls_solve_dense_batched with every device buffer taken from the library's fixed
+    per-GPU scratch array (no allocation).  Same arguments and result."""
+    p = packed if packed is not None else BatchedArgs(As, bs, xs, ys)
+    vp = lambda arr: C.cast(arr, C.c_void_p)
+    st = h.lib.nnls_solve_dense_batched_noalloc(h.ptr, p.batch, vp(p.m), vp(p.n), vp(p.pa), vp(p.lda),
+                                                vp(p.pb), vp(p.px), vp(p.py), C.byref(opts) if opts else None,
+                                                vp(p.infos))
     return st, list(p.infos[:p.batch])
 
 

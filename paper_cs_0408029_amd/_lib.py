@@ -20,6 +20,10 @@ NNLS_ERR_NO_MEMORY = -5
 NNLS_ERR_DEVICE = -6
 NNLS_ERR_REFINE = -7
 NNLS_ERR_TIMEOUT = -8
+NNLS_ERR_TOO_LARGE = -9
+
+# bytes of the fixed device array behind nnls_solve_dense_batched_noalloc
+NNLS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 NNLS_FP64 = 0
 NNLS_FP32_IR = 1
@@ -81,6 +85,8 @@ PROTOTYPES = {
                                    C.POINTER(nnls_options), C.POINTER(nnls_info)]),
     "nnls_solve_dense_batched": (C.c_int, [_P, _I32, _P, _P, _P, _P, _P, _P, _P,
                                            C.POINTER(nnls_options), _P]),
+    "nnls_solve_dense_batched_noalloc": (C.c_int, [_P, _I32, _P, _P, _P, _P, _P, _P, _P,
+                                                   C.POINTER(nnls_options), _P]),
     "nnls_server_create": (C.c_int, [C.POINTER(_P), C.c_int, C.POINTER(nnls_server_config),
                                      C.POINTER(nnls_options)]),
     "nnls_server_submit_csc": (C.c_int, [_P, _I32, _I32, _I64, _P, _P, _P, _P, C.POINTER(C.c_uint64)]),

@@ -7,12 +7,45 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "nnls_internal.h"
 
 using namespace nnls;
+
+// Device memory of nnls_solve_dense_batched_noalloc: one fixed array per GPU, part of the
+// code object.  In host code its name is only a stand-in for the symbol; the device
+// address of each GPU's copy is looked up once per device (scratch_address) and used
+// wherever host code hands this memory to a kernel or a copy.
+static __device__ __align__(256) char scratch[NNLS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+bool g_scratch_looked_up[MAX_DEVICES] = {};
+
+// Device address of `scratch` on `device` (current on the calling thread), looked up on
+// the first call for that device and kept; nullptr if the lookup failed.
+void* scratch_address(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_looked_up[device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      ptr = nullptr;
+    }
+    g_scratch_ptr[device] = ptr;
+    g_scratch_looked_up[device] = true;
+  }
+  return g_scratch_ptr[device];
+}
+
+}  // namespace
 
 namespace {
 
@@ -72,6 +105,7 @@ struct nnls_handle {
   std::vector<hipEvent_t> ev_pool;
   std::vector<PendingEvent> pending;
   int64_t next_event_id = 0;
+  void* scratch = nullptr;    // this device's copy of the no-allocation scratch array
 };
 
 namespace {
@@ -760,6 +794,7 @@ const char* nnls_status_string(int status) {
     case NNLS_ERR_DEVICE: return "NNLS_ERR_DEVICE";
     case NNLS_ERR_REFINE: return "NNLS_ERR_REFINE";
     case NNLS_ERR_TIMEOUT: return "NNLS_ERR_TIMEOUT";
+    case NNLS_ERR_TOO_LARGE: return "NNLS_ERR_TOO_LARGE";
     default: return "NNLS_ERR_UNKNOWN";
   }
 }
@@ -805,6 +840,9 @@ int nnls_create(nnls_handle** out, int device, void* stream) {
     return NNLS_ERR_NO_MEMORY;
   }
   std::memset(h->h_ctrl, 0, sizeof(Ctrl));
+  // library set-up per device: the device address of the no-allocation scratch array
+  // (looked up once per device; a failure is reported by the entry point that needs it)
+  h->scratch = scratch_address(device);
   *out = h;
   return NNLS_OK;
 }
@@ -957,6 +995,110 @@ int nnls_solve_dense_batched(nnls_handle* h, int32_t batch, const int32_t* m, co
       info[i].solve_ms = el;
     }
     if (q.status != NNLS_OK && worst == NNLS_OK) worst = q.status;
+  }
+  return worst;
+}
+
+int nnls_solve_dense_batched_noalloc(nnls_handle* h, int32_t batch, const int32_t* m, const int32_t* n,
+                                     const double* const* A, const int32_t* lda, const double* const* b,
+                                     double* const* x, double* const* y, const nnls_options* opts,
+                                     nnls_info* info) {
+  nnls_options o;
+  nnls_default_options(&o);
+  if (opts) o = *opts;
+  if (!h || batch < 0 || (batch > 0 && (!m || !n || !A || !lda || !b || !x || !y)))
+    return NNLS_ERR_INVALID_ARG;
+  if (check_options(o) != NNLS_OK) return NNLS_ERR_INVALID_ARG;
+  if (o.precision == NNLS_FP32_IR && (o.ir_max_steps < 0 || !(o.ir_rtol > 0.0))) return NNLS_ERR_INVALID_ARG;
+  if (info)
+    for (int i = 0; i < batch; ++i) {
+      std::memset(&info[i], 0, sizeof(nnls_info));
+      info[i].failed_index = -1;
+      info[i].est_rel_err = -1.0;
+    }
+  if (batch == 0) return NNLS_OK;
+  // layout in the scratch array: descriptors | statuses | workspaces, each 256-byte aligned
+  const auto align256 = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t probs_off = 0;
+  const size_t info_off = align256(sizeof(BatchProblem) * (size_t)batch);
+  const size_t ws_off = info_off + align256(sizeof(BatchInfo) * (size_t)batch);
+  size_t total = ws_off;
+  for (int i = 0; i < batch; ++i) {
+    if (n[i] < 1 || m[i] < n[i] || lda[i] < m[i] || !A[i] || !b[i] || !x[i] || !y[i]) {
+      if (info) info[i].status = NNLS_ERR_INVALID_ARG;
+      return NNLS_ERR_INVALID_ARG;
+    }
+    total += batched_workspace_bytes(m[i], n[i]);
+    if (total > NNLS_NOALLOC_SCRATCH_BYTES) return NNLS_ERR_TOO_LARGE;
+  }
+  if (hipSetDevice(h->device) != hipSuccess) return NNLS_ERR_DEVICE;
+  char* base = (char*)h->scratch;
+  if (!base) return NNLS_ERR_DEVICE;   // the symbol lookup at set-up failed
+  const double t0 = now_ms();
+  // descriptors: built on the host a chunk at a time and copied into the scratch array
+  constexpr int CHUNK = 64;
+  BatchProblem chunk[CHUNK];
+  size_t ws = 0;
+  for (int i0 = 0; i0 < batch; i0 += CHUNK) {
+    const int cnt = std::min(CHUNK, batch - i0);
+    for (int k = 0; k < cnt; ++k) {
+      const int i = i0 + k;
+      BatchProblem& bp = chunk[k];
+      bp.m = m[i];
+      bp.n = n[i];
+      bp.lda = lda[i];
+      bp.pad = 0;
+      bp.A = A[i];
+      bp.b = b[i];
+      bp.x = x[i];
+      bp.y = y[i];
+      bp.ws = (int64_t)ws;
+      ws += batched_workspace_bytes(m[i], n[i]);
+    }
+    HIP_TRY(hipMemcpyAsync(base + probs_off + sizeof(BatchProblem) * (size_t)i0, chunk,
+                           sizeof(BatchProblem) * (size_t)cnt, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));   // the chunk buffer is reused
+  }
+  BatchArgs ba;
+  std::memset(&ba, 0, sizeof(ba));
+  ba.count = batch;
+  ba.probs = (const BatchProblem*)(base + probs_off);
+  ba.order = nullptr;
+  ba.info = (BatchInfo*)(base + info_off);
+  ba.ws = base + ws_off;
+  ba.tau = o.tau;
+  ba.p_max = o.p_max;
+  ba.max_iter = o.max_iter;
+  ba.fp32 = o.precision == NNLS_FP32_IR ? 1 : 0;
+  ba.ir_max_steps = o.ir_max_steps;
+  ba.ir_rtol = o.ir_rtol;
+  ba.gram_dual = (o.flags & NNLS_FLAG_GRAM_DUAL) != 0 ? 1 : 0;
+  launch_batched(h->stream, ba, batch);
+  if (hipGetLastError() != hipSuccess) return NNLS_ERR_DEVICE;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  const double el = now_ms() - t0;
+  int worst = NNLS_OK;
+  BatchInfo bi[CHUNK];
+  for (int i0 = 0; i0 < batch; i0 += CHUNK) {
+    const int cnt = std::min(CHUNK, batch - i0);
+    HIP_TRY(hipMemcpyAsync(bi, base + info_off + sizeof(BatchInfo) * (size_t)i0, sizeof(BatchInfo) * (size_t)cnt,
+                           hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int k = 0; k < cnt; ++k) {
+      const BatchInfo& q = bi[k];
+      if (info) {
+        nnls_info& d = info[i0 + k];
+        d.status = q.status;
+        d.iterations = q.iterations;
+        d.n_free = q.n_free;
+        d.last_ninf = q.last_ninf;
+        d.failed_index = q.failed_index;
+        d.ir_steps = q.ir_steps;
+        d.min_margin = q.min_margin;
+        d.solve_ms = el;
+      }
+      if (q.status != NNLS_OK && worst == NNLS_OK) worst = q.status;
+    }
   }
   return worst;
 }

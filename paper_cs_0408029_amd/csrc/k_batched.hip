@@ -408,11 +408,14 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
   for (int i = tid; i < m; i += BT)
     if (!isfinite(P.b[i])) bad = 1.0;
   if (wg_max(bad, red) > 0.0) {
-    if (tid == 0) {
+    if (tid == 0) {   // every field: the status array may hold an earlier launch's values
       info->status = NNLS_ERR_INVALID_VALUE;
       info->iterations = 0;
       info->n_free = 0;
+      info->last_ninf = 0;
       info->failed_index = -1;
+      info->ir_steps = 0;
+      info->min_margin = 0.0;
     }
     return;
   }
