@@ -60,7 +60,11 @@ typedef enum {
 typedef enum {
   NNLS_FP64 = 0,     /* factor and every vector in float64                               */
   NNLS_FP32_IR = 1   /* F-block factor in float32, float64 iterative refinement of the
-                        normal equations; residual, y_G and sign tests in float64        */
+                        normal equations; residual, y_G and sign tests in float64.  The
+                        solve of an intermediate split is refined only until every tested
+                        sign (|v| >= tau) is certified by an error bound (Sec. 3: the
+                        pivot rule needs correct signs only); the feasible split's x_F is
+                        refined to ir_rtol                                               */
 } nnls_precision;
 
 /* flags */
@@ -81,6 +85,8 @@ typedef enum {
                                      which reads |G| x |F| of H instead of A twice (Eq. 5,
                                      the default); the sparse path ignores it, refinement
                                      and the final recomputation keep Eq. 5               */
+#define NNLS_FLAG_REFINE_ALL 32u /* NNLS_FP32_IR: refine the solve of every split to ir_rtol
+                                     instead of stopping once the tested signs are certified */
 #define NNLS_FLAG_NO_FACTOR_REUSE 4u /* refactor the whole F-block in every pivot
                                      iteration.  By default F is ordered so that the leading
                                      tile columns no exchange touched come first, and their
@@ -92,9 +98,9 @@ typedef struct {
   int32_t max_iter;     /* pivot iteration cap; <= 0 means 5 n + 100 (paper gives none)  */
   int32_t precision;    /* nnls_precision                                                */
   int32_t ir_max_steps; /* NNLS_FP32_IR: refinement steps per pivot iteration            */
-  double ir_rtol;       /* NNLS_FP32_IR: stop when the last correction of x_F, or the
-                           bound on the corrections still to come, is below ir_rtol
-                           max|x_F|                                                     */
+  double ir_rtol;       /* NNLS_FP32_IR: the final x_F is refined until the last
+                           correction is below ir_rtol max|x_F| (while the refinement
+                           contracts by 1/2 or better, that bounds the error left)       */
   uint32_t flags;       /* NNLS_FLAG_*                                                   */
   uint32_t max_workgroups; /* cap on the factor kernel's grid: above it, a persistent grid
                               of this many workgroups takes the tiles from a queue (so
@@ -112,9 +118,16 @@ typedef struct {
   double min_margin;    /* smallest |v| over the final sign tests that were not zeroed   */
   double setup_ms;      /* host wall time of validation + Gram formation                 */
   double solve_ms;      /* host wall time of the whole call                              */
-  double est_rel_err;   /* NNLS_FLAG_REFINE_AUTO: predicted relative error of the final
-                           normal-equations solution, 0.1 kappa_1(A_F^T A_F) 2^-52 with the
-                           1-norm condition estimated from the factor; -1 when not formed */
+  double est_rel_err;   /* NNLS_FP32_IR: bound on max|x_F - exact| / max|x_F| of the
+                           returned x (exact: the least-squares solution on the final F):
+                           the last refinement correction, which bounds the error left
+                           while the refinement contracts by 1/2 or better, plus the
+                           rounding of x_F itself (the refinement residual is summed with
+                           compensation, so its own rounding is far below both); 0 when F
+                           is empty, -1 when not measured.  NNLS_FLAG_REFINE_AUTO:
+                           predicted relative error of the final normal-equations solution,
+                           0.1 kappa_1(A_F^T A_F) 2^-52 with the 1-norm condition estimated
+                           from the factor.  Otherwise -1                                  */
 } nnls_info;
 
 /* One row of the per-iteration trace recorded by the last solve on a handle. */
@@ -126,6 +139,8 @@ typedef struct {
   int32_t n_free;   /* |F| after the exchange                                            */
   int32_t n_reused; /* leading F positions whose factor tiles were kept from the previous
                        iteration's factor (a multiple of 64; 0 when refactored whole)      */
+  int32_t ir_steps; /* NNLS_FP32_IR: refinement steps of this iteration's solve (the last
+                       row also counts the final refinement of the feasible split)       */
 } nnls_trace_row;
 
 typedef struct nnls_handle nnls_handle;

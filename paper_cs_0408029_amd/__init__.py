@@ -13,7 +13,7 @@ from typing import List, Optional, Tuple
 
 from ._lib import (LIB_PATH, NNLS_ERR_DEVICE, NNLS_ERR_INVALID_ARG, NNLS_ERR_INVALID_VALUE,  # noqa: F401
                    NNLS_ERR_MAXITER, NNLS_ERR_NO_MEMORY, NNLS_ERR_NOT_PD, NNLS_ERR_REFINE,
-                   NNLS_ERR_TIMEOUT, NNLS_ERR_TOO_LARGE, NNLS_NOALLOC_SCRATCH_BYTES, NNLS_FLAG_GRAM_DUAL, NNLS_FLAG_NO_FACTOR_REUSE, NNLS_FLAG_PROFILE, NNLS_FLAG_REFINE_AUTO, NNLS_FLAG_REFINE_FINAL, NNLS_FP32_IR, NNLS_FP64, NNLS_OK,
+                   NNLS_ERR_TIMEOUT, NNLS_ERR_TOO_LARGE, NNLS_NOALLOC_SCRATCH_BYTES, NNLS_FLAG_GRAM_DUAL, NNLS_FLAG_NO_FACTOR_REUSE, NNLS_FLAG_PROFILE, NNLS_FLAG_REFINE_ALL, NNLS_FLAG_REFINE_AUTO, NNLS_FLAG_REFINE_FINAL, NNLS_FP32_IR, NNLS_FP64, NNLS_OK,
                    NNLS_PROFILE_CLASSES, PROFILE_CLASS_NAMES, default_options, load, nnls_info,
                    nnls_options, nnls_server_config, nnls_serving_stats, nnls_trace_row,
                    status_string)
@@ -165,12 +165,15 @@ def nnls_solve_dense_batched_noalloc(h: Handle, As=None, bs=None, xs=None, ys=No
     return st, list(p.infos[:p.batch])
 
 
-def nnls_get_trace(h: Handle, reused: bool = False) -> List[Tuple[int, ...]]:
+def nnls_get_trace(h: Handle, reused: bool = False, ir_steps: bool = False) -> List[Tuple[int, ...]]:
     """Per-iteration (k, branch, N, p, |F|); with reused=True also the count of leading F
-    positions whose factor tiles were kept from the previous iteration."""
+    positions whose factor tiles were kept from the previous iteration; with ir_steps=True
+    (instead) the refinement steps of each iteration's solve."""
     cnt = h.lib.nnls_get_trace(h.ptr, None, 0)
     rows = (nnls_trace_row * max(cnt, 1))()
     h.lib.nnls_get_trace(h.ptr, rows, cnt)
+    if ir_steps:
+        return [(r.k, r.branch, r.N, r.p, r.n_free, r.ir_steps) for r in rows[:cnt]]
     if reused:
         return [(r.k, r.branch, r.N, r.p, r.n_free, r.n_reused) for r in rows[:cnt]]
     return [(r.k, r.branch, r.N, r.p, r.n_free) for r in rows[:cnt]]

@@ -33,6 +33,7 @@ NNLS_FLAG_REFINE_FINAL = 2
 NNLS_FLAG_NO_FACTOR_REUSE = 4
 NNLS_FLAG_REFINE_AUTO = 8
 NNLS_FLAG_GRAM_DUAL = 16
+NNLS_FLAG_REFINE_ALL = 32
 
 NNLS_PROFILE_CLASSES = 8
 PROFILE_CLASS_NAMES = ["gram", "control", "cholesky", "trsv", "residual", "refine", "batched", "dual"]
@@ -53,7 +54,7 @@ class nnls_info(C.Structure):
 
 class nnls_trace_row(C.Structure):
     _fields_ = [("k", C.c_int32), ("branch", C.c_int32), ("N", C.c_int32), ("p", C.c_int32),
-                ("n_free", C.c_int32), ("n_reused", C.c_int32)]
+                ("n_free", C.c_int32), ("n_reused", C.c_int32), ("ir_steps", C.c_int32)]
 
 
 class nnls_server_config(C.Structure):

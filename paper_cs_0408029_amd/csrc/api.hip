@@ -83,6 +83,8 @@ struct nnls_handle {
   DevBuf err, ctrl, rowcnt, rowptr, colidx, valr, hptr, hcnt, hrow, hval, c, r, flags, Flist, pos;
   DevBuf Lt, Dinv, colcnt, dflag, tflag, z, xF, Hd, gF, rpart, spart;
   DevBuf upcnt, prow, pval, pcnt, Fold, zr;   // F-position Gram lists, order scratch, refinement z
+  DevBuf wr, bw, bb;                   // sign-certificate bounds of the mixed path
+  DevBuf rlo;                          // low part of the compensated refinement residual
   DevBuf est, ev, exi;                         // condition estimate: state, probe vector, signs
   DevBuf bprobs, border, binfo, bws;   // batched dense problems
   DevBuf scan;                         // chunk sums of the setup prefix scans
@@ -95,6 +97,11 @@ struct nnls_handle {
   // blocks with them): 0 float64, 1 float32, -1 none; the next factor of the same
   // precision may keep their untouched leading columns
   int fact_prec = -1;
+  // mixed path: the current split's x_F is only sign-certified (not refined to ir_rtol),
+  // and the bound on the relative error of the last refined x_F
+  bool certified_only = false;
+  double err_rel = INFINITY;
+  double err_xmax = 0.0;      // max|x_F| that err_rel is relative to
   std::vector<nnls_trace_row> trace;
   // profiling
   bool profiling = false;
@@ -383,6 +390,15 @@ SolveArgs solve_args(nnls_handle* h, int nF, const int32_t* Flist, const double*
 // flops of a factor that keeps its leading p0 columns
 double chol_flops_from(double nF, double p0) { return (nF * nF * nF - p0 * p0 * p0) / 3.0; }
 
+// Eq. 5 for the refinement, compensated: r = A x - b, y_G = A_G^T r, gfree = A_F^T r.
+int residual_dual_dd(nnls_handle* h, const Problem& P, const double* x, double* y, double* gfree) {
+  TRY(ensure(h, h->rlo, sizeof(double) * (size_t)P.m));
+  launch_residual_dual_dd(h->stream, P.m, P.n, P.nnz, (const int32_t*)h->rowptr.p, (const int32_t*)h->colidx.p,
+                          (const double*)h->valr.p, P.colptr, P.rowidx, P.val, P.sparse ? nullptr : P.A, P.lda, x,
+                          P.b, (const uint8_t*)h->flags.p, (double*)h->r.p, (double*)h->rlo.p, y, gfree);
+  return NNLS_OK;
+}
+
 // Eq. 5: r = A x - b, then y_G = A_G^T r (y_F = 0); with gfree also A_F^T r on F.
 void residual_dual(nnls_handle* h, const Problem& P, const double* x, double* y, double* gfree) {
   double* r = (double*)h->r.p;
@@ -398,25 +414,50 @@ void residual_dual(nnls_handle* h, const Problem& P, const double* x, double* y,
 }
 
 // Float64 iterative refinement of x_F against the residual from A with the factor in the
-// handle (float32 when fp32):  g_F = A_F^T (A x - b),  x_F <- x_F - (L L^T)^-1 g_F,  until the
-// last correction, or the bound on the corrections still to come, is below ir_rtol
-// max|x_F|; it stops early when the corrections do not contract or the float32 factor
-// breaks down.  *outcome: REFINED (target reached; y_G was formed from the final x),
-// STALLED (not reached: redo or keep), or REPORT (the control block holds an error status
-// for the next control step to report).
-enum RefineOutcome { REFINED = 0, STALLED = 1, REPORT = 2 };
+// handle (float32 when fp32):  g_F = A_F^T (A x - b),  x_F <- x_F - (L L^T)^-1 g_F.
+// It stops when the last correction is below ir_rtol max|x_F| (CONVERGE), or -- with certify, for the solve of an intermediate
+// split -- as soon as every tested sign is certified by the error bounds of
+// launch_ir_certify, since the pivot rule needs only correct signs of x_F and y_G (Sec. 3).
+// It stops early when the corrections do not contract or the float32 factor breaks down.
+// *outcome: REFINED (target reached; y_G was formed from the final x), CERTIFIED (signs
+// certified; y_G was formed from the iterate before the last correction, x is the
+// corrected one), STALLED (neither: redo or keep), or REPORT (the control block holds an
+// error status for the next control step to report).  *err_rel: bound on the relative
+// max-norm error of the final x_F (INF when not measured).
+enum RefineOutcome { REFINED = 0, STALLED = 1, REPORT = 2, CERTIFIED = 3 };
 int refine(nnls_handle* h, const Problem& P, int nF, double* x, double* y, const nnls_options& o,
-           double spmv_bytes, bool fp32, double l_bytes, nnls_info* info, int* outcome) {
+           double spmv_bytes, bool fp32, double l_bytes, nnls_info* info, int* outcome, bool certify,
+           double* err_rel, double* xmax_out = nullptr) {
   const int32_t* Flist = (const int32_t*)h->Flist.p;
+  const uint8_t* flags = (const uint8_t*)h->flags.p;
   Ctrl* ctrl = (Ctrl*)h->ctrl.p;
   *outcome = STALLED;
+  *err_rel = INFINITY;
   TRY(ensure(h, h->gF, sizeof(double) * (size_t)P.n));
   double* gF = (double*)h->gF.p;
+  double gamma = 0.0;
+  if (certify) {
+    // per split: the sensitivity of y_G to an error in x_F and the rounding scale of y_G
+    TRY(ensure(h, h->bw, sizeof(double) * (size_t)P.n));
+    TRY(ensure(h, h->bb, sizeof(double) * (size_t)P.n));
+    TRY(ensure(h, h->wr, sizeof(double) * (size_t)P.m));
+    if (P.sparse)
+      launch_sign_bounds_csr(h->stream, P.m, P.n, P.nnz, (const int32_t*)h->rowptr.p, (const int32_t*)h->colidx.p,
+                             (const double*)h->valr.p, P.colptr, P.rowidx, P.val, flags, P.b,
+                             (double*)h->wr.p, (double*)h->bw.p, (double*)h->bb.p);
+    else
+      launch_sign_bounds_dense(h->stream, P.m, P.n, P.A, P.lda, Flist, nF, flags, P.b, (double*)h->wr.p,
+                               (double*)h->bw.p, (double*)h->bb.p);
+    // 2 gamma_k^2, gamma_k = k u / (1 - k u) for compensated dot products of length
+    // k <= m + n + 2 (both products of y_j = a_j^T (A_F x_F - b))
+    const double ku = (double)(P.m + P.n + 2) * 1.1102230246251565e-16;
+    gamma = 2.0 * (ku / (1.0 - ku)) * (ku / (1.0 - ku));
+  }
   bool converged = false;
   double prev = INFINITY;
   for (int step = 0;; ++step) {
     int64_t pe = prof_begin(h, NNLS_PROF_RESIDUAL);
-    residual_dual(h, P, x, y, gF);
+    TRY(residual_dual_dd(h, P, x, y, gF));
     prof_end(h, pe, spmv_bytes);
     if (converged) break;
     if (step >= o.ir_max_steps) break;
@@ -425,7 +466,10 @@ int refine(nnls_handle* h, const Problem& P, int nF, double* x, double* y, const
     SolveArgs ca = solve_args(h, nF, Flist, gF, nullptr);
     ca.z = (double*)h->zr.p;   // the factor's own forward-solve blocks stay for the next factor
     launch_trsv(h->stream, ca, fp32, true);
-    launch_ir_update(h->stream, nF, Flist, (const double*)h->xF.p, x, ctrl);
+    launch_ir_update(h->stream, nF, Flist, (const double*)h->xF.p, x, ctrl, step == 0 ? 1 : 0);
+    if (certify)
+      launch_ir_certify(h->stream, P.n, flags, x, y, (const double*)h->bw.p, (const double*)h->bb.p, o.tau, gamma,
+                        ctrl);
     prof_end(h, pe, 2.0 * l_bytes);
     TRY(sync_read(h, h->h_ctrl, ctrl, sizeof(Ctrl)));
     if (h->h_ctrl->status == NNLS_ERR_NOT_PD && fp32) {   // float32 breakdown: the caller redoes it
@@ -440,16 +484,23 @@ int refine(nnls_handle* h, const Problem& P, int nF, double* x, double* y, const
     if (info) info->ir_steps += 1;
     const double dmax = h->h_ctrl->ir_dmax, xmax = h->h_ctrl->ir_xmax;
     if (!(dmax < INFINITY) || !(xmax < INFINITY)) break;   // NaN or overflow: stalled
-    // stop once the last correction, or the corrections still to come, are below the
-    // target: with the measured contraction rho = dmax / prev (at most 1/2 here) the rest
-    // sum to at most dmax * rho / (1 - rho)
+    // While the iteration contracts by 1/2 or better per step (checked on consecutive
+    // corrections, rho = dmax / prev), the error left after a step is at most its
+    // correction: stop once that is below the target.  (The ratio of consecutive
+    // corrections can understate the contraction of the slowest error component, so it
+    // only gates the iteration and does not shrink the bound.)
     const double rho = dmax / prev;                 // 0 on the first step
+    const double scale = xmax > 0.0 ? xmax : 1.0;
+    if (xmax_out) *xmax_out = scale;
     if (dmax <= o.ir_rtol * xmax) {
       converged = true;
+      *err_rel = dmax / scale;
     } else if (rho > 0.5) {
       break;                                        // not contracting
-    } else if (prev < INFINITY && dmax * rho / (1.0 - rho) <= o.ir_rtol * xmax) {
-      converged = true;
+    } else if (certify && h->h_ctrl->ir_uncert == 0) {
+      *err_rel = h->h_ctrl->ir_err / scale;
+      *outcome = CERTIFIED;
+      return NNLS_OK;
     }
     prev = dmax;
   }
@@ -542,18 +593,21 @@ int estimate_rel_err(nnls_handle* h, const Problem& P, int nF, double* out) {
 // the forward solve fused, then the backward solve scattered into x.  In NNLS_FP32_IR the
 // factor is float32 and x_F is refined in float64 against the residual from A,
 //   g_F = A_F^T (A x - b),  x_F <- x_F - (L L^T)^-1 g_F,
-// until the correction, or the bound on the corrections still to come, is below ir_rtol
-// relative to x_F; if it stalls or the step cap is reached, the iteration is redone with a
-// float64 factor (and refined with it).  *y_done is set when the last refinement pass
-// already left y_G for the final x.
+// until every tested sign is certified (certify: an intermediate split, Sec. 3) or the
+// correction is below ir_rtol relative to x_F; if it stalls or the step cap is reached, the iteration is redone with a float64
+// factor (and refined with it).  force64 starts with the float64 factor.  *y_done is set
+// when the last refinement pass already left y_G (for the final x, or certified).
 // j0: leading tile columns the control step kept from the previous factor (the first
 // attempt may use them; *j0_used reports what it did).
 int solve_free(nnls_handle* h, const Problem& P, int nF, int j0, double* x, double* y, const nnls_options& o,
-               double spmv_bytes, bool* y_done, int* j0_used, nnls_info* info) {
+               double spmv_bytes, bool* y_done, int* j0_used, nnls_info* info, bool certify, bool force64) {
   const int32_t* Flist = (const int32_t*)h->Flist.p;
-  bool fp32 = o.precision == NNLS_FP32_IR;
+  const bool mixed = o.precision == NNLS_FP32_IR;
+  bool fp32 = mixed && !force64;
   *y_done = false;
   *j0_used = 0;
+  h->certified_only = false;
+  h->err_rel = INFINITY;
   if (P.sparse)
     launch_gram_positions(h->stream, nF, gram_view(h), (const int32_t*)h->upcnt.p, Flist,
                           (const int32_t*)h->pos.p, (int32_t*)h->pcnt.p, (int32_t*)h->prow.p,
@@ -562,7 +616,7 @@ int solve_free(nnls_handle* h, const Problem& P, int nF, int j0, double* x, doub
     bool lost = false;
     TRY(ensure_factor(h, nF, fp32, &lost));
     h->epoch += 1;
-    if (attempt > 0) {
+    if (attempt > 0 || force64) {
       // the control step zeroed the column counters and tickets for the first attempt
       // only: the first factor left its columns counted complete, and the refinement's
       // triangular solves used up the solve tickets
@@ -571,7 +625,7 @@ int solve_free(nnls_handle* h, const Problem& P, int nF, int j0, double* x, doub
     }
     FactorArgs fa = factor_args(h, nF, Flist, P.sparse ? nullptr : (const double*)h->Hd.p,
                                 P.sparse ? 0 : P.n, P.sparse);
-    fa.j0 = (attempt == 0 && !lost && h->fact_prec == (fp32 ? 1 : 0)) ? std::min(j0, fa.nb - 1) : 0;
+    fa.j0 = (attempt == 0 && !force64 && !lost && h->fact_prec == (fp32 ? 1 : 0)) ? std::min(j0, fa.nb - 1) : 0;
     if (attempt == 0) *j0_used = fa.j0;
     fa.rhs = (const double*)h->c.p;
     fa.z = (double*)h->z.p;
@@ -584,15 +638,20 @@ int solve_free(nnls_handle* h, const Problem& P, int nF, int j0, double* x, doub
     pe = prof_begin(h, NNLS_PROF_TRSV);
     launch_trsv(h->stream, sa, fp32, false);
     prof_end(h, pe, l_bytes);
-    if (o.precision != NNLS_FP32_IR) return NNLS_OK;
+    if (!mixed) return NNLS_OK;
 
     // refined against the residual from A; after a float64 redo as well, so that the mixed
     // path is never less accurate than the refined float64 solution
     int outcome = STALLED;
-    TRY(refine(h, P, nF, x, y, o, spmv_bytes, fp32, l_bytes, info, &outcome));
+    double err = INFINITY;
+    double xm = 0.0;
+    TRY(refine(h, P, nF, x, y, o, spmv_bytes, fp32, l_bytes, info, &outcome, certify, &err, &xm));
     if (outcome == REPORT) return NNLS_OK;          // reported by the next control step
-    if (outcome == REFINED) {
+    if (outcome == REFINED || outcome == CERTIFIED) {
       *y_done = true;
+      h->certified_only = outcome == CERTIFIED;
+      h->err_rel = err;
+      h->err_xmax = xm;
       return NNLS_OK;
     }
     if (!fp32) return NNLS_OK;   // the float64 factor does not contract either: keep x_F
@@ -633,8 +692,12 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
   // residual from A with the split's own factor, and classify the refined x and y again
   const bool auto_refine = (o.flags & NNLS_FLAG_REFINE_AUTO) != 0 && o.precision == NNLS_FP64;
   const bool final_refine = ((o.flags & NNLS_FLAG_REFINE_FINAL) != 0 || auto_refine) && o.precision == NNLS_FP64;
+  const bool mixed = o.precision == NNLS_FP32_IR;
+  const bool certify = mixed && (o.flags & NNLS_FLAG_REFINE_ALL) == 0;   // intermediate splits
   bool refined = false;
   int last_nF = 0;
+  h->certified_only = false;
+  h->err_rel = INFINITY;
   for (;;) {
     int64_t pe = prof_begin(h, NNLS_PROF_CONTROL);
     // ordered F; the previous factor's untouched leading tiles are kept when its
@@ -647,6 +710,38 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
     const Ctrl c = *h->h_ctrl;
     if (c.status != 0) break;
     if (c.done) {
+      if (mixed && h->certified_only && !refined && last_nF > 0) {
+        // the feasible split's x_F was refined only until its signs were certified:
+        // refine it to ir_rtol with the split's factor, then classify again
+        int outcome = STALLED;
+        double err = INFINITY;
+        const int ir_before = info ? info->ir_steps : 0;
+        const bool f32 = h->fact_prec == 1;
+        const double l_bytes = (f32 ? 4.0 : 8.0) * (double)tile_count((last_nF + TILE - 1) / TILE) * TILE_ELEMS;
+        double xm = 0.0;
+        TRY(refine(h, P, last_nF, x, y, o, spmv_bytes, f32, l_bytes, info, &outcome, false, &err, &xm));
+        refined = true;
+        if (!h->trace.empty() && info) h->trace.back().ir_steps += info->ir_steps - ir_before;
+        if (outcome == REPORT) continue;
+        if (outcome == REFINED) {
+          h->certified_only = false;
+          h->err_rel = err;
+          h->err_xmax = xm;
+          continue;
+        }
+        // not contracting to the target: this split again with a float64 factor
+        bool yd = false;
+        int j0u = 0;
+        const int ir_mid = info ? info->ir_steps : 0;
+        TRY(solve_free(h, P, last_nF, 0, x, y, o, spmv_bytes, &yd, &j0u, info, false, true));
+        if (!h->trace.empty() && info) h->trace.back().ir_steps += info->ir_steps - ir_mid;
+        if (!yd) {
+          pe = prof_begin(h, NNLS_PROF_RESIDUAL);
+          residual_dual(h, P, x, y, nullptr);
+          prof_end(h, pe, spmv_bytes);
+        }
+        continue;
+      }
       if (!final_refine || refined || last_nF == 0) break;
       if (auto_refine && !(o.flags & NNLS_FLAG_REFINE_FINAL)) {
         // refine only when the split's predicted error misses the target
@@ -659,7 +754,8 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
       }
       int outcome = STALLED;
       const double l_bytes = 8.0 * (double)tile_count((last_nF + TILE - 1) / TILE) * TILE_ELEMS;
-      TRY(refine(h, P, last_nF, x, y, o, spmv_bytes, false, l_bytes, info, &outcome));
+      double err_unused = INFINITY;
+      TRY(refine(h, P, last_nF, x, y, o, spmv_bytes, false, l_bytes, info, &outcome, false, &err_unused));
       if (outcome == REPORT) {       // keep the split; the control step reports the status
         refined = true;
         continue;
@@ -680,12 +776,14 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
     row.p = c.p;
     row.n_free = c.n_free;
     row.n_reused = 0;
+    const int ir_before = info ? info->ir_steps : 0;
     const int nF = c.n_free;
     last_nF = nF;
     bool y_done = false;
     int j0_used = 0;
-    if (nF > 0) TRY(solve_free(h, P, nF, c.j0, x, y, o, spmv_bytes, &y_done, &j0_used, info));
+    if (nF > 0) TRY(solve_free(h, P, nF, c.j0, x, y, o, spmv_bytes, &y_done, &j0_used, info, certify, false));
     row.n_reused = j0_used * TILE;
+    row.ir_steps = info ? info->ir_steps - ir_before : 0;
     h->trace.push_back(row);
     if (!y_done && gram_dual) {
       pe = prof_begin(h, NNLS_PROF_DUAL);
@@ -705,6 +803,16 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
     info->last_ninf = c.k;
     info->min_margin = c.min_margin;
     info->failed_index = -1;
+    if (mixed) info->est_rel_err = -1.0;
+    if (mixed && c.status == NNLS_OK) {
+      if (last_nF == 0) {
+        info->est_rel_err = 0.0;
+      } else if (h->err_rel < INFINITY && !h->certified_only) {
+        // the remaining correction plus the rounding of x_F itself (the compensated
+        // residual leaves an error far below both)
+        info->est_rel_err = h->err_rel + 2.220446049250313e-16;
+      }
+    }
   }
   if (c.status == NNLS_ERR_NOT_PD) {
     int32_t col = -1;
@@ -721,6 +829,8 @@ int solve_common(nnls_handle* h, const Problem& P, double* x, double* y, const n
   nnls_options o;
   nnls_default_options(&o);
   if (opts) o = *opts;
+  nnls_info local;   // the loop records its counts (refinement steps per trace row) in info
+  if (!info) info = &local;
   if (info) {
     std::memset(info, 0, sizeof(*info));
     info->failed_index = -1;
@@ -771,7 +881,7 @@ void release_workspace(nnls_handle* h) {
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
                     &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart, &h->spart,
                     &h->upcnt, &h->prow, &h->pval, &h->pcnt, &h->Fold, &h->zr, &h->est, &h->ev, &h->exi,
-                    &h->bprobs, &h->border, &h->binfo, &h->bws, &h->scan};
+                    &h->bprobs, &h->border, &h->binfo, &h->bws, &h->scan, &h->wr, &h->bw, &h->bb, &h->rlo};
   for (DevBuf* b : bufs) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
@@ -855,7 +965,7 @@ int nnls_destroy(nnls_handle* h) {
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
                     &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart, &h->spart,
                     &h->upcnt, &h->prow, &h->pval, &h->pcnt, &h->Fold, &h->zr, &h->est, &h->ev, &h->exi,
-                    &h->bprobs, &h->border, &h->binfo, &h->bws, &h->scan};
+                    &h->bprobs, &h->border, &h->binfo, &h->bws, &h->scan, &h->wr, &h->bw, &h->bb, &h->rlo};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);

@@ -564,12 +564,11 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
           xm = wg_max(xm, red);
           if (tid == 0) info->ir_steps += 1;
           if (!(dm < INFINITY) || !(xm < INFINITY)) break;
-          // as in the single-problem path: the last correction, or the bound dm rho/(1-rho)
-          // on the corrections still to come, below the target
+          // as in the single-problem path: while the corrections contract by 1/2 or better,
+          // the last one bounds the error left; stop once it is below the target
           const double rho = dm / prev;   // 0 on the first step
           if (dm <= a.ir_rtol * xm) converged = true;
           else if (rho > 0.5) break;
-          else if (prev < INFINITY && dm * rho / (1.0 - rho) <= a.ir_rtol * xm) converged = true;
           prev = dm;
         }
         if (!y_done) use32 = false;   // not refined to the target: redo in float64

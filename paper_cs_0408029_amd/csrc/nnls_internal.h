@@ -33,6 +33,12 @@ struct Ctrl {
   double min_margin;   // smallest |v| over the tested entries that were not zeroed
   double ir_dmax;      // mixed precision: max |correction| of the last refinement step
   double ir_xmax;      //                  max |x_F| after it
+  double ir_dprev;     //                  max |correction| of the step before (INF: none)
+  double ir_err;       //                  bound on max |x_F - exact| after the last step
+                       //                  (INF while the contraction is not measured)
+  int32_t ir_uncert;   //                  tested entries whose sign the bounds do not
+                       //                  certify (-1: no bound yet)
+  int32_t pad2_;
 };
 
 // Lower-triangle Gram matrix in padded CSC: column j occupies
@@ -125,9 +131,39 @@ void launch_dual_dense(hipStream_t s, int m, int n, const double* A, int lda, co
 void launch_dual_gram_dense(hipStream_t s, int n, const double* H, int64_t ldh, const double* c,
                             const uint8_t* flags, const int32_t* Flist, int nF, const double* x,
                             double* y);
-// x[Flist[p]] -= d[p] for p < nF; writes max |d| and max |x_F| into ctrl (one workgroup)
+// Eq. 5 for the refinement, with compensated sums: r = A x - b kept as r_hi + r_lo, then
+// y_j = a_j^T r on G and gfree_j = a_j^T r on F, each exact up to one rounding and an
+// O((k u)^2) term.  Dense A when A != nullptr (lda), else the CSR copy and the CSC input.
+void launch_residual_dual_dd(hipStream_t s, int m, int n, int64_t nnz, const int32_t* rowptr,
+                             const int32_t* colidx, const double* valr, const int32_t* colptr,
+                             const int32_t* rowidx, const double* val, const double* A, int lda,
+                             const double* x, const double* b, const uint8_t* flags, double* rh,
+                             double* rl, double* y, double* gfree);
+// x[Flist[p]] -= d[p] for p < nF; writes max |d| and max |x_F| into ctrl (one workgroup);
+// first: the first step of a refinement (ir_dprev becomes INF, else the previous ir_dmax)
 void launch_ir_update(hipStream_t s, int nF, const int32_t* Flist, const double* d, double* x,
-                      Ctrl* ctrl);
+                      Ctrl* ctrl, int first);
+// Sign certificates of a refinement step (the Sec. 3 remark that intermediate solves need
+// only correct signs).  Per pivot iteration, with w_r = sum_{j in F} |a_rj|:
+//   bw_j = sum_r |a_rj| w_r  and  bb_j = sum_r |a_rj| |b_r|   for j in G
+// (bounds of y_j's sensitivity to an error in x_F and of its rounding error).
+void launch_sign_bounds_csr(hipStream_t s, int m, int n, int64_t nnz, const int32_t* rowptr,
+                            const int32_t* colidx, const double* valr, const int32_t* colptr,
+                            const int32_t* rowidx, const double* val, const uint8_t* flags,
+                            const double* b, double* w, double* bw, double* bb);
+void launch_sign_bounds_dense(hipStream_t s, int m, int n, const double* A, int lda,
+                              const int32_t* Flist, int nF, const uint8_t* flags, const double* b,
+                              double* w, double* bw, double* bb);
+
+// After launch_ir_update: while the refinement contracts by 1/2 or better (rho =
+// ir_dmax / ir_dprev, measured), the error of x_F is at most e = ir_dmax and that of the x
+// the step's y_G was formed from at most 2 ir_dmax.  Counts the tested entries v (x_i on
+// F, y_i on G) with |v| >= tau whose distance to the zeroing band does not exceed their
+// bound: e (+ rounding) on F; 2 ir_dmax bw_j + 2 u |y_j| + gamma2 (xmax bw_j + bb_j) on G
+// (the compensated y_j's rounding).
+// Writes ctrl->ir_err and ctrl->ir_uncert (-1 when rho is unknown or above 1/2).
+void launch_ir_certify(hipStream_t s, int n, const uint8_t* flags, const double* x, const double* y,
+                       const double* bw, const double* bb, double tau, double gamma2, Ctrl* ctrl);
 
 // condition estimate of the final F-block (k_cond.hip)
 struct CondEst {

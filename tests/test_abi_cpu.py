@@ -55,10 +55,23 @@ def test_status_strings(lib):
     assert N.status_string(-99) == "NNLS_ERR_UNKNOWN"
 
 
-def test_struct_sizes_match_header(lib):
-    assert C.sizeof(N.nnls_options) == 40
-    assert C.sizeof(N.nnls_info) == 56
-    assert C.sizeof(N.nnls_trace_row) == 24
+def test_struct_sizes_match_header(lib, tmp_path):
+    """The ctypes mirrors have the sizes a C compiler gives the header's structs."""
+    import shutil
+    import subprocess
+    names = ["nnls_options", "nnls_info", "nnls_trace_row", "nnls_server_config", "nnls_serving_stats"]
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "sizes.c"
+    inc = os.path.join(ROOT, "include")
+    src.write_text('#include <stdio.h>\n#include "nnls.h"\nint main(void) {\n' +
+                   "".join(f'  printf("%zu\\n", sizeof({t}));\n' for t in names) + "  return 0;\n}\n")
+    exe = tmp_path / "sizes"
+    subprocess.run([cc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    sizes = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                            text=True).stdout.split()]
+    assert sizes == [C.sizeof(getattr(N, t)) for t in names]
 
 
 def test_null_arguments_rejected_without_device(lib):

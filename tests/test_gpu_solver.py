@@ -4,6 +4,7 @@ relative (FP64 path); the per-iteration trace (k, branch, N, p, |F|) must be ide
 whenever every sign test of the run was certified (no tested value within 1e-8 relative
 of the zeroing threshold)."""
 import numpy as np
+import scipy.linalg as sla
 import pytest
 
 import workloads as W
@@ -363,3 +364,73 @@ def test_mixed_ill_scaled_falls_back(h, seed):
     assert st == st64 == N.NNLS_OK
     assert np.array_equal(x != 0, x64 != 0)
     assert relerr(x, x64) <= 1e-6
+
+
+def _ls_reference(A, b, free, steps=3):
+    """x on F of the least-squares problem on the columns A_F: float64 normal equations,
+    then refinement whose residual A_F^T (A_F x - b) is formed exactly in rational
+    arithmetic (every float is a dyadic rational), so the result is the float64 vector
+    nearest the exact solution up to the last correction's rounding."""
+    from fractions import Fraction
+    AF = np.asarray(A)[:, free]
+    cf = sla.cho_factor(AF.T @ AF, lower=True)
+    x = sla.cho_solve(cf, AF.T @ b)
+    Af = [[Fraction(v) for v in row] for row in AF.tolist()]
+    bf = [Fraction(v) for v in np.asarray(b).tolist()]
+    m, k = AF.shape
+    for _ in range(steps):
+        xf = [Fraction(v) for v in x.tolist()]
+        r = [sum((a * xv for a, xv in zip(row, xf)), Fraction(0)) - bi for row, bi in zip(Af, bf)]
+        g = np.array([float(sum((Af[i][j] * r[i] for i in range(m)), Fraction(0))) for j in range(k)])
+        x = x - sla.cho_solve(cf, g)
+    return x
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_mixed_certifies_intermediate_signs(h, seed):
+    """The planted F-block has condition 1e6, so refinement with the float32 factor gains
+    only two to three digits per step.  Intermediate splits stop refining once every tested
+    sign is certified (fewer steps than refining each to ir_rtol), the feasible split is
+    refined to ir_rtol; free sets and trajectory match the oracle, and x matches a reference
+    computed with exact residuals far beyond the float64 normal equations (kappa^2 u ~ 1e-10
+    here), within the error bound the solve reports."""
+    inst = W.conditioned_planted(seed, 600, 300, 1e3)
+    res = bpp_solve(inst.A, inst.b)
+    st, info, x, y, trace = solve_dense(h, inst.A, inst.b, precision=N.NNLS_FP32_IR)
+    steps = [r[5] for r in N.nnls_get_trace(h, ir_steps=True)]
+    print(f"seed {seed}: iterations {info.iterations}, refinement steps per iteration {steps}, "
+          f"est_rel_err {info.est_rel_err:.2e}", flush=True)
+    assert st == N.NNLS_OK and res.status == "ok"
+    assert np.array_equal(x > 0, inst.active) and np.array_equal(res.free, inst.active)
+    if certified(res, 1.0, rel=1e-6):
+        assert trace == oracle_trace(res)
+    assert sum(steps) == info.ir_steps and len(steps) == info.iterations >= 3
+    # every split refined to ir_rtol: the same trajectory and free set, more steps
+    st_a, info_a, x_a, y_a, trace_a = solve_dense(h, inst.A, inst.b, precision=N.NNLS_FP32_IR,
+                                                  flags=N.NNLS_FLAG_REFINE_ALL)
+    steps_a = [r[5] for r in N.nnls_get_trace(h, ir_steps=True)]
+    print(f"  refined to ir_rtol at every split: {steps_a}", flush=True)
+    assert st_a == N.NNLS_OK and trace_a == trace and np.array_equal(x_a > 0, x > 0)
+    assert sum(steps[:-1]) < sum(steps_a[:-1])
+    assert info.ir_steps < info_a.ir_steps
+    xr = _ls_reference(inst.A, inst.b, inst.active)
+    xf = x[inst.active]
+    actual = np.max(np.abs(xf - xr)) / np.max(np.abs(xf))
+    assert 0 < info.est_rel_err <= N.default_options().ir_rtol
+    assert actual <= info.est_rel_err + 4e-16
+    assert actual <= 1e-12
+    assert np.all(x >= 0) and np.all(y >= 0) and np.dot(x, y) == 0.0
+
+
+def test_mixed_error_bound_sparse(h):
+    """The mixed path states a bound on the error of every result: on a sparse problem
+    the bound is at most ir_rtol and covers the distance to the oracle's x (whose own
+    error is far below it)."""
+    inst = W.sparse_small(1002)
+    res = bpp_solve(inst.A, inst.b)
+    st, info, x, y, trace = solve_csc(h, inst.A, inst.b, precision=N.NNLS_FP32_IR)
+    check_mixed(res, st, info, x, y, trace)
+    f = res.free
+    actual = np.max(np.abs(x[f] - res.x[f])) / np.max(np.abs(x[f]))
+    assert 0 < info.est_rel_err <= 1e-12
+    assert actual <= info.est_rel_err + 1e-14   # the oracle's own error is below 1e-14 here

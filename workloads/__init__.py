@@ -289,6 +289,26 @@ def svd_conditioned(seed: int, kappa: float, m: int = 80, n: int = 70, rep: int 
     return A, x_true, A @ x_true
 
 
+def conditioned_planted(seed: int, m: int, n: int, kappa: float, frac: float = 0.4,
+                        lo: float = 0.1) -> Instance:
+    """Dense m x n problem whose planted free block is ill conditioned: the active columns
+    are U diag(s) V^T with singular values geometric from 1 down to 1/kappa (so the final
+    F-block of A^T A has condition kappa^2), the others N(0,1)/sqrt(m); planted
+    complementary x*, y* as for every instance.  A float32 factor of that F-block
+    contracts slowly under refinement."""
+    rng = np.random.default_rng(seed)
+    active, x_star, y_star = _plant_values(rng, n, frac, lo)
+    A = rng.standard_normal((m, n)) / np.sqrt(m)
+    k = int(active.sum())
+    U, _ = np.linalg.qr(rng.standard_normal((m, k)))
+    V, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    A[:, active] = (U * np.geomspace(1.0, 1.0 / kappa, k)) @ V.T
+    A = np.asfortranarray(A)
+    b, dinf = _plant_rhs_dense(A, x_star, y_star)
+    return Instance(A=A, b=np.ascontiguousarray(b), x_star=x_star, y_star=y_star, active=active,
+                    delta_inf=dinf, name=f"conditioned_m{m}_n{n}_k{kappa:g}", seed=seed)
+
+
 def csc_arrays(A: sp.csc_matrix):
     """(colptr int32[n+1], rowidx int32[nnz], val float64[nnz]) of a CSC matrix."""
     return (np.ascontiguousarray(A.indptr, dtype=np.int32),
