@@ -1,13 +1,17 @@
-"""Benchmark: NNLS solves/s of the plain FP64 GPU path on one MI355X.
+"""Benchmark: NNLS solves/s on one MI355X, mixed precision against the plain FP64 GPU path.
 
 One step = one complete solve (validation, Gram matrix and A^T b, the whole pivot loop)
 of a seeded synthetic instance whose inputs are already resident in device memory.
-Default workload: sparse m = 60000, n = 12000, 25 N(0,1) entries per column at random
-rows plus a three-wide diagonal band, 30% of variables active with margin 1e-3 (seed 1002).
+Default workload: sparse m = 400000, n = 50000, 20 N(0,1) entries per column at random
+rows plus a block band (rows [8j, 8j+64) N(0,1), A[8j, j] += sqrt(84)), 25% of variables
+active with margin 1e-3 (seed 1005), solved by the mixed path (float32 factor, float64
+refinement, float64 y_G and sign tests) and by the plain float64 path in the same process.
 
-Prints one JSON line with solves/s, p50/p99 latency, the roofline of the dominant kernel
-(the tiled Cholesky, timed with HIP events on the solver's stream during the timed
-steps) and the CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line: the mixed path's solves/s and p50/p99 latency, the plain path's
+beside it, accuracy against the planted solution and between the paths, the roofline of
+the dominant kernel (the tiled Cholesky, timed with HIP events on the solver's stream
+during the timed steps), the 60000 x 12000 instance's pair, and the CPU oracle timed on a
+bounded sample of the same workload.  Other workloads: --workload (see --help).
 """
 from __future__ import annotations
 
@@ -26,6 +30,9 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix) peak
 PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 (matrix) peak
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E peak
 CHOL_SOURCES = ("paper_cs_0408029_amd/csrc/k_chol.hip", "paper_cs_0408029_amd/csrc/tile_ops.h")
+# committed counter summaries (HBM bytes per launch of the factor) by (workload, precision)
+TRAFFIC_SUMMARY = {("sparse_large", "fp64"): "profiles/k_chol_tiles_sparse_large_m60000_n12000.md",
+                   ("sparse_xl", "fp32ir"): "profiles/k_chol_tiles_float_sparse_xl_m400000_n50000.md"}
 METRIC = "NNLS solves/s + p50/p99 latency vs plain FP64 GPU path at ≤1e-8 rel err"
 
 
@@ -59,9 +66,9 @@ def profiled_traffic(kernel_srcs, summary: str):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(inst, budget_s: float):
+def cpu_baseline(inst, budget_s: float, max_solves: int = 5, what: str = "whole solve(s) of the benchmark instance"):
     """The oracle as it stands, on this host, over whole solves of the same instance until
-    budget_s of CPU work has been spent (at least one solve)."""
+    budget_s of CPU work has been spent (at least one solve, at most max_solves)."""
     from oracle import bpp_solve
     try:
         from threadpoolctl import threadpool_info
@@ -74,11 +81,11 @@ def cpu_baseline(inst, budget_s: float):
         res = bpp_solve(inst.A, inst.b)
         count += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or count >= 5:
+        if el >= budget_s or count >= max_solves:
             break
     return {"value": count / el, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{count} whole solve(s) of the benchmark instance, {el:.1f} s",
-            "status": res.status}
+            "sample": f"{count} {what}, {el:.1f} s", "status": res.status,
+            "free_set_match": bool(np.array_equal(res.free, inst.active))}
 
 
 def bench_batch(args):
@@ -649,7 +656,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="sparse_large")
+    ap.add_argument("--workload", default="metric",
+                    help="metric (default): mixed vs plain FP64 on the 400000 x 50000 instance; or "
+                         "sparse_large, sparse_xl, sparse_small, dense_batch, serve, spmv, kappa, fig2")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="metric: skip the 60000 x 12000 pair")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -704,6 +715,9 @@ def main():
     if not os.path.exists(N.LIB_PATH):
         from paper_cs_0408029_amd.build import build
         build()
+    if args.workload == "metric":
+        bench_metric(args)
+        return
     if args.workload == "dense_batch":
         bench_batch(args)
         return
@@ -721,74 +735,26 @@ def main():
         return
     inst, desc = make_instance(args.workload)
     dev = torch.device("cuda:0")
-    A = inst.A
-    colptr = torch.from_numpy(A.indptr.astype(np.int32)).to(dev)
-    rowidx = torch.from_numpy(A.indices.astype(np.int32)).to(dev)
-    val = torch.from_numpy(A.data).to(dev)
-    b = torch.from_numpy(inst.b).to(dev)
-    x = torch.empty(inst.n, dtype=torch.float64, device=dev)
-    y = torch.empty_like(x)
+    arrays = device_arrays(inst, dev)
     h = N.Handle(0)
-    prec = N.NNLS_FP64 if args.precision == "fp64" else N.NNLS_FP32_IR
-    opts = N.default_options(precision=prec)
-    popts = N.default_options(precision=prec, flags=N.NNLS_FLAG_PROFILE)
-
-    def step(o):
-        st, info = N.nnls_solve_csc(h, inst.m, inst.n, colptr, rowidx, val, b, x, y, o)
-        if st != N.NNLS_OK:
-            raise RuntimeError(f"solve failed: {N.status_string(st)}")
-        return info
-
-    for _ in range(args.warmup):
-        step(opts)
-    N.nnls_reset_profile(h)
-    torch.cuda.synchronize()
-    lat = []
-    iters = 0
-    ir_steps = 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s0 = time.perf_counter()
-        info = step(opts if args.no_profile else popts)
-        lat.append((time.perf_counter() - s0) * 1e3)
-        iters += info.iterations
-        ir_steps += info.ir_steps
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    prof = N.nnls_get_profile(h)
-
-    xh, yh = x.cpu().numpy(), y.cpu().numpy()
-    rel = float(np.linalg.norm(xh - inst.x_star) / np.linalg.norm(inst.x_star))
-    fmatch = bool(np.array_equal(xh > 0, inst.active))
-
-    chol = prof["cholesky"]
-    roof = None
     fp32 = args.precision == "fp32ir"
-    peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
-    if chol["launches"] > 0 and chol["ms"] > 0:
-        achieved = chol["work"] / (chol["ms"] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "kernel": "k_chol_tiles<float>" if fp32 else "k_chol_tiles<double>",
-                "achieved": round(achieved, 3),
-                "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": profiled_traffic(CHOL_SOURCES, "profiles/k_chol_tiles_sparse_large_m60000_n12000.md")
-                if args.workload == "sparse_large" and not fp32 else None,
-                "launches": chol["launches"],
-                "avg_launch_ms": round(chol["ms"] / chol["launches"], 4),
-                "work_per_launch": "(nF^3 - p^3)/3 flops: the F-block factor less its kept leading p columns"}
-    breakdown = {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in prof.items()
-                 if v["launches"]}
+    leg = measure_single(h, inst, arrays, N.NNLS_FP32_IR if fp32 else N.NNLS_FP64, args.steps, args.warmup,
+                         profile=not args.no_profile)
+    h.close()
+    traffic_src = (CHOL_SOURCES, TRAFFIC_SUMMARY.get((args.workload, args.precision)))
+    roof = chol_roofline(leg, fp32, traffic_src)
     out = {
         "metric": METRIC,
-        "value": round(args.steps / total, 4),
+        "value": leg["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(total / args.steps * 1e3, 3),
-        "p50_ms": round(float(np.percentile(lat, 50)), 3),
-        "p99_ms": round(float(np.percentile(lat, 99)), 3),
-        "pivot_iters_per_s": round(iters / total, 2),
-        "refinement_steps_per_solve": round(ir_steps / args.steps, 2),
+        "ms_per_step": leg["ms_per_step"],
+        "p50_ms": leg["p50_ms"],
+        "p99_ms": leg["p99_ms"],
+        "pivot_iters_per_s": leg["pivot_iters_per_s"],
+        "refinement_steps_per_solve": leg["refinement_steps_per_solve"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -797,18 +763,181 @@ def main():
         "config": {"workload": desc,
                    "path": "plain FP64 GPU path, one problem per call" if not fp32 else
                            "float32 factor, float64 refinement, one problem per call",
-                   "m": inst.m, "n": inst.n, "nnz": int(A.nnz)},
-        "rel_err_vs_planted": rel,
-        "free_set_match": fmatch,
-        "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in breakdown.items()},
+                   "m": inst.m, "n": inst.n, "nnz": int(inst.A.nnz)},
+        "rel_err_vs_planted": leg["rel_err_vs_planted"],
+        "free_set_match": leg["free_set_match"],
+        "est_rel_err": leg["est_rel_err"],
+        "kernel_ms_per_step": leg["kernel_ms_per_step"],
+        "factor_launches": leg["factor_launches"],
         "roofline": roof,
         "cpu_baseline": None,
     }
-    h.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_budget)
     print(json.dumps(out), flush=True)
 
+
+def device_arrays(inst, dev):
+    import torch
+    A = inst.A
+    return {"colptr": torch.from_numpy(A.indptr.astype(np.int32)).to(dev),
+            "rowidx": torch.from_numpy(A.indices.astype(np.int32)).to(dev),
+            "val": torch.from_numpy(A.data).to(dev),
+            "b": torch.from_numpy(inst.b).to(dev),
+            "x": torch.empty(inst.n, dtype=torch.float64, device=dev),
+            "y": torch.empty(inst.n, dtype=torch.float64, device=dev)}
+
+
+def measure_single(h, inst, arr, precision, steps, warmup, profile=True):
+    """Whole solves of one sparse instance whose inputs are resident on the device: warm-up,
+    then `steps` timed solves (HIP-event kernel timings on the solver's stream when profile).
+    Returns throughput, latency percentiles, accuracy and the factor launches of the last
+    solve (|F| and the leading positions kept from the previous factor)."""
+    import torch
+    import paper_cs_0408029_amd as N
+    opts = N.default_options(precision=precision)
+    popts = N.default_options(precision=precision, flags=N.NNLS_FLAG_PROFILE)
+
+    def step(o):
+        st, info = N.nnls_solve_csc(h, inst.m, inst.n, arr["colptr"], arr["rowidx"], arr["val"], arr["b"],
+                                    arr["x"], arr["y"], o)
+        if st != N.NNLS_OK:
+            raise RuntimeError(f"solve failed: {N.status_string(st)}")
+        return info
+
+    for _ in range(warmup):
+        step(opts)
+    N.nnls_reset_profile(h)
+    torch.cuda.synchronize()
+    lat, iters, ir_steps, est = [], 0, 0, []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        info = step(popts if profile else opts)
+        lat.append((time.perf_counter() - s0) * 1e3)
+        iters += info.iterations
+        ir_steps += info.ir_steps
+        est.append(info.est_rel_err)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    prof = N.nnls_get_profile(h)
+    trace = N.nnls_get_trace(h, reused=True)
+    xh, yh = arr["x"].cpu().numpy(), arr["y"].cpu().numpy()
+    return {
+        "solves_per_s": round(steps / total, 4),
+        "ms_per_step": round(total / steps * 1e3, 3),
+        "p50_ms": round(float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "pivot_iters_per_s": round(iters / total, 2),
+        "refinement_steps_per_solve": round(ir_steps / steps, 2),
+        "rel_err_vs_planted": float(np.linalg.norm(xh - inst.x_star) / np.linalg.norm(inst.x_star)),
+        "free_set_match": bool(np.array_equal(xh > 0, inst.active)),
+        "est_rel_err": max(est) if precision != N.NNLS_FP64 else None,
+        "kernel_ms_per_step": {k: round(v["ms"] / steps, 3) for k, v in prof.items() if v["launches"]},
+        "factor_launches": [[r[4], r[5]] for r in trace],
+        "_prof": prof, "_x": xh,
+    }
+
+
+def chol_roofline(leg, fp32, traffic_src):
+    """Roofline of the dominant kernel (the tiled F-block factor) from the HIP-event
+    timings of the timed solves: sum over launches of (|F|^3 - p^3)/3 flops (p = kept
+    leading positions) over the summed launch durations."""
+    chol = leg["_prof"]["cholesky"]
+    if not (chol["launches"] > 0 and chol["ms"] > 0):
+        return None
+    achieved = chol["work"] / (chol["ms"] * 1e-3) / 1e12
+    peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
+    srcs, summary = traffic_src
+    return {"bound": "mfma", "kernel": "k_chol_tiles<float>" if fp32 else "k_chol_tiles<double>",
+            "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+            "traffic": profiled_traffic(srcs, summary) if summary else None,
+            "launches": chol["launches"], "avg_launch_ms": round(chol["ms"] / chol["launches"], 4),
+            "work_per_launch": "(nF^3 - p^3)/3 flops: the F-block factor less its kept leading p columns "
+                               "(nF, p per launch of one solve in factor_launches)"}
+
+
+def public(leg):
+    return {k: v for k, v in leg.items() if not k.startswith("_")}
+
+
+def bench_metric(args):
+    """The metric on the largest single-GPU configuration: the sparse 400000 x 50000
+    block-band instance solved by the plain float64 path and by the mixed path (float32
+    factor, float64 refinement, float64 y_G and sign tests) in one process on the same
+    device-resident inputs.  `value` is the mixed path's solves/s; the plain path, the
+    mixed/plain ratio, both paths' accuracy and the 60000 x 12000 instance's pair go beside
+    it."""
+    import torch
+    import paper_cs_0408029_amd as N
+    t0 = time.perf_counter()
+    inst, desc = make_instance("sparse_xl")
+    gen_s = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    arr = device_arrays(inst, dev)
+    h = N.Handle(0)
+    plain = measure_single(h, inst, arr, N.NNLS_FP64, args.steps, args.warmup, profile=not args.no_profile)
+    mixed = measure_single(h, inst, arr, N.NNLS_FP32_IR, args.steps, args.warmup, profile=not args.no_profile)
+    roof = chol_roofline(mixed, True, (CHOL_SOURCES, TRAFFIC_SUMMARY.get(("sparse_xl", "fp32ir"))))
+    x64, x32 = plain["_x"], mixed["_x"]
+    mixed_vs_plain = float(np.linalg.norm(x32 - x64) / np.linalg.norm(x64))
+    same_free = bool(np.array_equal(x32 > 0, x64 > 0))
+    secondary = None
+    if not args.no_secondary:
+        inst2, desc2 = make_instance("sparse_large")
+        arr2 = device_arrays(inst2, dev)
+        k2, w2 = max(args.steps, 10), max(args.warmup, 2)
+        p2 = measure_single(h, inst2, arr2, N.NNLS_FP64, k2, w2, profile=False)
+        m2 = measure_single(h, inst2, arr2, N.NNLS_FP32_IR, k2, w2, profile=False)
+        secondary = {"workload": desc2, "steps": k2,
+                     "plain_fp64": {k: public(p2)[k] for k in ("solves_per_s", "p50_ms", "p99_ms",
+                                                               "rel_err_vs_planted", "free_set_match")},
+                     "mixed": {k: public(m2)[k] for k in ("solves_per_s", "p50_ms", "p99_ms", "rel_err_vs_planted",
+                                                          "free_set_match", "est_rel_err",
+                                                          "refinement_steps_per_solve")},
+                     "mixed_vs_plain_fp64": round(m2["solves_per_s"] / p2["solves_per_s"], 3)}
+    h.close()
+    out = {
+        "metric": METRIC,
+        "value": mixed["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["ms_per_step"],
+        "p50_ms": mixed["p50_ms"],
+        "p99_ms": mixed["p99_ms"],
+        "pivot_iters_per_s": mixed["pivot_iters_per_s"],
+        "refinement_steps_per_solve": mixed["refinement_steps_per_solve"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "vs_plain_fp64": round(mixed["solves_per_s"] / plain["solves_per_s"], 3),
+        "dtype": "f32-factor+f64-refinement",
+        "data": "synthetic",
+        "config": {"workload": desc,
+                   "path": "mixed: float32 F-block factor on MFMA, float64 refinement (compensated residual), "
+                           "float64 y_G and sign tests; one problem per call",
+                   "baseline_path": "plain FP64 GPU path, one problem per call, same process and inputs",
+                   "m": inst.m, "n": inst.n, "nnz": int(inst.A.nnz)},
+        "rel_err_vs_planted": mixed["rel_err_vs_planted"],
+        "rel_err_vs_plain_fp64": mixed_vs_plain,
+        "est_rel_err": mixed["est_rel_err"],
+        "free_set_match": mixed["free_set_match"] and plain["free_set_match"] and same_free,
+        "plain_fp64": {k: public(plain)[k] for k in ("solves_per_s", "ms_per_step", "p50_ms", "p99_ms",
+                                                      "pivot_iters_per_s", "rel_err_vs_planted", "free_set_match",
+                                                      "kernel_ms_per_step")},
+        "kernel_ms_per_step": mixed["kernel_ms_per_step"],
+        "factor_launches": mixed["factor_launches"],
+        "roofline": roof,
+        "secondary": secondary,
+        "generation_s": round(gen_s, 1),
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_budget, max_solves=1,
+                                           what="whole solve(s) of the 400000 x 50000 instance")
+    print(json.dumps(out), flush=True)
 
 if __name__ == "__main__":
     main()
