@@ -664,7 +664,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--precision", choices=["fp64", "fp32ir"], default="fp64",
+    ap.add_argument("--precision", choices=["fp64", "fp32ir", "bf16ir"], default="fp64",
                     help="fp64: the plain FP64 path (the metric's reference); fp32ir: float32 factor "
                          "with float64 refinement")
     ap.add_argument("--batch", type=int, default=4096, help="dense_batch: number of problems")
@@ -737,9 +737,9 @@ def main():
     dev = torch.device("cuda:0")
     arrays = device_arrays(inst, dev)
     h = N.Handle(0)
-    fp32 = args.precision == "fp32ir"
-    leg = measure_single(h, inst, arrays, N.NNLS_FP32_IR if fp32 else N.NNLS_FP64, args.steps, args.warmup,
-                         profile=not args.no_profile)
+    fp32 = args.precision in ("fp32ir", "bf16ir")
+    prec = {"fp64": N.NNLS_FP64, "fp32ir": N.NNLS_FP32_IR, "bf16ir": N.NNLS_BF16_IR}[args.precision]
+    leg = measure_single(h, inst, arrays, prec, args.steps, args.warmup, profile=not args.no_profile)
     h.close()
     traffic_src = (CHOL_SOURCES, TRAFFIC_SUMMARY.get((args.workload, args.precision)))
     roof = chol_roofline(leg, fp32, traffic_src)
@@ -758,11 +758,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if not fp32 else "f32-factor+f64-refinement",
+        "dtype": {"fp64": "f64", "fp32ir": "f32-factor+f64-refinement",
+                  "bf16ir": "f32-factor(bf16-input updates)+f64-refinement"}[args.precision],
         "data": "synthetic",
         "config": {"workload": desc,
-                   "path": "plain FP64 GPU path, one problem per call" if not fp32 else
-                           "float32 factor, float64 refinement, one problem per call",
+                   "path": {"fp64": "plain FP64 GPU path, one problem per call",
+                            "fp32ir": "float32 factor, float64 refinement, one problem per call",
+                            "bf16ir": "float32 factor with bfloat16-input updates, float64 refinement, "
+                                      "one problem per call"}[args.precision],
                    "m": inst.m, "n": inst.n, "nnz": int(inst.A.nnz)},
         "rel_err_vs_planted": leg["rel_err_vs_planted"],
         "free_set_match": leg["free_set_match"],

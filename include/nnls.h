@@ -59,12 +59,20 @@ typedef enum {
 
 typedef enum {
   NNLS_FP64 = 0,     /* factor and every vector in float64                               */
-  NNLS_FP32_IR = 1   /* F-block factor in float32, float64 iterative refinement of the
+  NNLS_FP32_IR = 1,  /* F-block factor in float32, float64 iterative refinement of the
                         normal equations; residual, y_G and sign tests in float64.  The
                         solve of an intermediate split is refined only until every tested
                         sign (|v| >= tau) is certified by an error bound (Sec. 3: the
                         pivot rule needs correct signs only); the feasible split's x_F is
                         refined to ir_rtol                                               */
+  NNLS_BF16_IR = 2   /* as NNLS_FP32_IR, with the factor's left-looking updates on MFMA
+                        from bfloat16 copies of the finished tiles (float32 accumulation;
+                        the diagonal tiles, their inverses and the triangular solves stay
+                        float32).  Refinement recovers the float64 accuracy while
+                        kappa(A_F^T A_F) 2^-8 stays well below 1; an F-block beyond that
+                        is redone in float32, then float64.  Sparse and dense
+                        single-problem solves and nnls_cholesky; the batched solves and
+                        the serving engine return NNLS_ERR_INVALID_ARG for it           */
 } nnls_precision;
 
 /* flags */
@@ -332,8 +340,9 @@ int nnls_gram_csc(nnls_handle* h, int32_t m, int32_t n, int64_t nnz, const int32
 /* Cholesky factor of the symmetric positive definite n x n matrix S (device, column-major,
  * lower triangle read) into L (device, column-major, ldl >= n; the strict upper triangle
  * is written as zero).  This is the factor of Sec. 2.1, run by the tiled MFMA kernel the
- * solver uses on its F-block.  precision: NNLS_FP64 or NNLS_FP32_IR (float32 factor,
- * returned widened to double).  *failed (host) is -1, or the first column whose pivot was
+ * solver uses on its F-block.  precision: NNLS_FP64, NNLS_FP32_IR (float32 factor,
+ * returned widened to double) or NNLS_BF16_IR (float32 factor whose updates read bfloat16
+ * tile copies).  *failed (host) is -1, or the first column whose pivot was
  * non-positive or non-finite (then the status is NNLS_ERR_NOT_PD). */
 int nnls_cholesky(nnls_handle* h, int32_t n, const double* S, int32_t lds, double* L,
                   int32_t ldl, int32_t precision, int32_t* failed);

@@ -13,7 +13,7 @@ from typing import List, Optional, Tuple
 
 from ._lib import (LIB_PATH, NNLS_ERR_DEVICE, NNLS_ERR_INVALID_ARG, NNLS_ERR_INVALID_VALUE,  # noqa: F401
                    NNLS_ERR_MAXITER, NNLS_ERR_NO_MEMORY, NNLS_ERR_NOT_PD, NNLS_ERR_REFINE,
-                   NNLS_ERR_TIMEOUT, NNLS_ERR_TOO_LARGE, NNLS_NOALLOC_SCRATCH_BYTES, NNLS_FLAG_GRAM_DUAL, NNLS_FLAG_NO_FACTOR_REUSE, NNLS_FLAG_PROFILE, NNLS_FLAG_REFINE_ALL, NNLS_FLAG_REFINE_AUTO, NNLS_FLAG_REFINE_FINAL, NNLS_FP32_IR, NNLS_FP64, NNLS_OK,
+                   NNLS_ERR_TIMEOUT, NNLS_ERR_TOO_LARGE, NNLS_NOALLOC_SCRATCH_BYTES, NNLS_FLAG_GRAM_DUAL, NNLS_FLAG_NO_FACTOR_REUSE, NNLS_FLAG_PROFILE, NNLS_FLAG_REFINE_ALL, NNLS_FLAG_REFINE_AUTO, NNLS_FLAG_REFINE_FINAL, NNLS_BF16_IR, NNLS_FP32_IR, NNLS_FP64, NNLS_OK,
                    NNLS_PROFILE_CLASSES, PROFILE_CLASS_NAMES, default_options, load, nnls_info,
                    nnls_options, nnls_server_config, nnls_serving_stats, nnls_trace_row,
                    status_string)

@@ -27,6 +27,7 @@ NNLS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 NNLS_FP64 = 0
 NNLS_FP32_IR = 1
+NNLS_BF16_IR = 2
 
 NNLS_FLAG_PROFILE = 1
 NNLS_FLAG_REFINE_FINAL = 2

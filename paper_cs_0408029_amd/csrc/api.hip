@@ -85,6 +85,7 @@ struct nnls_handle {
   DevBuf upcnt, prow, pval, pcnt, Fold, zr;   // F-position Gram lists, order scratch, refinement z
   DevBuf wr, bw, bb;                   // sign-certificate bounds of the mixed path
   DevBuf rlo;                          // low part of the compensated refinement residual
+  DevBuf Lbf;                          // bfloat16 copies of the factor tiles (NNLS_BF16_IR)
   DevBuf est, ev, exi;                         // condition estimate: state, probe vector, signs
   DevBuf bprobs, border, binfo, bws;   // batched dense problems
   DevBuf scan;                         // chunk sums of the setup prefix scans
@@ -222,8 +223,18 @@ int sync_read(nnls_handle* h, void* dst, const void* src, size_t bytes) {
 int check_options(const nnls_options& o) {
   if (!(o.tau >= 0.0) || !std::isfinite(o.tau)) return NNLS_ERR_INVALID_ARG;
   if (o.p_max < 0) return NNLS_ERR_INVALID_ARG;
-  if (o.precision != NNLS_FP64 && o.precision != NNLS_FP32_IR) return NNLS_ERR_INVALID_ARG;
+  if (o.precision != NNLS_FP64 && o.precision != NNLS_FP32_IR && o.precision != NNLS_BF16_IR)
+    return NNLS_ERR_INVALID_ARG;
+  if (o.precision != NNLS_FP64 && (o.ir_max_steps < 0 || !(o.ir_rtol > 0.0))) return NNLS_ERR_INVALID_ARG;
   return NNLS_OK;
+}
+
+// Factor precisions, from the most accurate: 0 float64; 1 float32; 2 float32 with the
+// left-looking updates on bfloat16 copies of the tiles.  Mixed solves start at their
+// option's level and step towards 0 when a factor breaks down or refinement stalls.
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
+int prec_level(int precision) {
+  return precision == NNLS_BF16_IR ? PREC_BF16 : precision == NNLS_FP32_IR ? PREC_F32 : PREC_F64;
 }
 
 // Problem description shared by the sparse and dense drivers.
@@ -318,14 +329,16 @@ int build_gram_dense(nnls_handle* h, const Problem& P) {
   return NNLS_OK;
 }
 
-// Factor-and-solve workspace for an F-block of order nF.  *lost (optional) is set when the
-// tiles, inverted diagonal tiles or forward-solve blocks had to be reallocated.
-int ensure_factor(nnls_handle* h, int nF, bool fp32, bool* lost = nullptr) {
+// Factor-and-solve workspace for an F-block of order nF at precision level prec.  *lost
+// (optional) is set when the tiles, inverted diagonal tiles, forward-solve blocks or
+// (bfloat16 level) tile copies had to be reallocated.
+int ensure_factor(nnls_handle* h, int nF, int prec, bool* lost = nullptr) {
   const int nb = (nF + TILE - 1) / TILE;
-  const size_t w = fp32 ? sizeof(float) : sizeof(double);
+  const size_t w = prec >= PREC_F32 ? sizeof(float) : sizeof(double);
   const size_t ntiles = (size_t)tile_count(nb);
-  const uint64_t before[3] = {h->Lt.gen, h->Dinv.gen, h->z.gen};
+  const uint64_t before[4] = {h->Lt.gen, h->Dinv.gen, h->z.gen, h->Lbf.gen};
   TRY(ensure(h, h->Lt, ntiles * TILE_ELEMS * w));
+  if (prec == PREC_BF16) TRY(ensure(h, h->Lbf, ntiles * TILE_ELEMS * sizeof(uint16_t)));
   TRY(ensure(h, h->Dinv, (size_t)nb * TILE_ELEMS * w));
   TRY(ensure(h, h->colcnt, (size_t)nb * sizeof(int32_t), true));
   TRY(ensure(h, h->dflag, (size_t)nb * sizeof(int32_t), true));
@@ -336,7 +349,9 @@ int ensure_factor(nnls_handle* h, int nF, bool fp32, bool* lost = nullptr) {
   const uint64_t slots_before = h->spart.gen;
   TRY(ensure(h, h->spart, 2 * (size_t)nb * TILE * sizeof(double)));
   if (h->spart.gen != slots_before) h->slots_empty = false;   // fresh memory: not emptied yet
-  if (lost) *lost = before[0] != h->Lt.gen || before[1] != h->Dinv.gen || before[2] != h->z.gen;
+  if (lost)
+    *lost = before[0] != h->Lt.gen || before[1] != h->Dinv.gen || before[2] != h->z.gen ||
+            (prec == PREC_BF16 && before[3] != h->Lbf.gen);
   return NNLS_OK;
 }
 
@@ -590,20 +605,23 @@ int estimate_rel_err(nnls_handle* h, const Problem& P, int nF, double* out) {
 }
 
 // x_F for the current split (Eq. 4 by the normal equations, Sec. 2.1): factor H_FF with
-// the forward solve fused, then the backward solve scattered into x.  In NNLS_FP32_IR the
-// factor is float32 and x_F is refined in float64 against the residual from A,
+// the forward solve fused, then the backward solve scattered into x.  In the mixed
+// precisions the factor is float32 (NNLS_BF16_IR: its updates from bfloat16 tile copies)
+// and x_F is refined in float64 against the residual from A,
 //   g_F = A_F^T (A x - b),  x_F <- x_F - (L L^T)^-1 g_F,
 // until every tested sign is certified (certify: an intermediate split, Sec. 3) or the
-// correction is below ir_rtol relative to x_F; if it stalls or the step cap is reached, the iteration is redone with a float64
-// factor (and refined with it).  force64 starts with the float64 factor.  *y_done is set
-// when the last refinement pass already left y_G (for the final x, or certified).
+// correction is below ir_rtol relative to x_F; if the factor breaks down, refinement stalls
+// or the step cap is reached, the iteration is redone one precision level up (bfloat16
+// updates -> float32 -> float64) and refined again.  force64 starts with the float64
+// factor.  *y_done is set when the last refinement pass already left y_G (for the final
+// x, or certified).
 // j0: leading tile columns the control step kept from the previous factor (the first
 // attempt may use them; *j0_used reports what it did).
 int solve_free(nnls_handle* h, const Problem& P, int nF, int j0, double* x, double* y, const nnls_options& o,
                double spmv_bytes, bool* y_done, int* j0_used, nnls_info* info, bool certify, bool force64) {
   const int32_t* Flist = (const int32_t*)h->Flist.p;
-  const bool mixed = o.precision == NNLS_FP32_IR;
-  bool fp32 = mixed && !force64;
+  const bool mixed = o.precision != NNLS_FP64;
+  int prec = force64 ? PREC_F64 : prec_level(o.precision);
   *y_done = false;
   *j0_used = 0;
   h->certified_only = false;
@@ -612,9 +630,10 @@ int solve_free(nnls_handle* h, const Problem& P, int nF, int j0, double* x, doub
     launch_gram_positions(h->stream, nF, gram_view(h), (const int32_t*)h->upcnt.p, Flist,
                           (const int32_t*)h->pos.p, (int32_t*)h->pcnt.p, (int32_t*)h->prow.p,
                           (double*)h->pval.p);
-  for (int attempt = 0; attempt < 2; ++attempt) {
+  for (int attempt = 0;; ++attempt) {
+    const bool fp32 = prec >= PREC_F32;
     bool lost = false;
-    TRY(ensure_factor(h, nF, fp32, &lost));
+    TRY(ensure_factor(h, nF, prec, &lost));
     h->epoch += 1;
     if (attempt > 0 || force64) {
       // the control step zeroed the column counters and tickets for the first attempt
@@ -625,14 +644,15 @@ int solve_free(nnls_handle* h, const Problem& P, int nF, int j0, double* x, doub
     }
     FactorArgs fa = factor_args(h, nF, Flist, P.sparse ? nullptr : (const double*)h->Hd.p,
                                 P.sparse ? 0 : P.n, P.sparse);
-    fa.j0 = (attempt == 0 && !force64 && !lost && h->fact_prec == (fp32 ? 1 : 0)) ? std::min(j0, fa.nb - 1) : 0;
+    fa.j0 = (attempt == 0 && !force64 && !lost && h->fact_prec == prec) ? std::min(j0, fa.nb - 1) : 0;
     if (attempt == 0) *j0_used = fa.j0;
     fa.rhs = (const double*)h->c.p;
     fa.z = (double*)h->z.p;
+    fa.Lbf = prec == PREC_BF16 ? h->Lbf.p : nullptr;
     int64_t pe = prof_begin(h, NNLS_PROF_CHOLESKY);
     launch_cholesky(h->stream, fa, fp32);
     prof_end(h, pe, chol_flops_from(nF, (double)fa.j0 * TILE));
-    h->fact_prec = fp32 ? 1 : 0;
+    h->fact_prec = prec;
     const double l_bytes = (fp32 ? 4.0 : 8.0) * (double)tile_count(fa.nb) * TILE_ELEMS;
     SolveArgs sa = solve_args(h, nF, Flist, (const double*)h->c.p, x);
     pe = prof_begin(h, NNLS_PROF_TRSV);
@@ -654,10 +674,9 @@ int solve_free(nnls_handle* h, const Problem& P, int nF, int j0, double* x, doub
       h->err_xmax = xm;
       return NNLS_OK;
     }
-    if (!fp32) return NNLS_OK;   // the float64 factor does not contract either: keep x_F
-    fp32 = false;
+    if (prec == PREC_F64) return NNLS_OK;   // the float64 factor does not contract either: keep x_F
+    prec -= 1;
   }
-  return NNLS_OK;
 }
 
 // The pivot loop on a problem whose Gram matrix and c are built.
@@ -672,7 +691,7 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
   TRY(ensure(h, h->ctrl, sizeof(Ctrl)));
   const int ncol = (n + TILE - 1) / TILE;
   h->fact_prec = -1;
-  const int want_prec = o.precision == NNLS_FP32_IR ? 1 : 0;
+  const int want_prec = prec_level(o.precision);
   const bool reuse = (o.flags & NNLS_FLAG_NO_FACTOR_REUSE) == 0;
   const bool gram_dual = (o.flags & NNLS_FLAG_GRAM_DUAL) != 0 && !P.sparse;   // Eq. 3 for y_G
   TRY(ensure(h, h->colcnt, sizeof(int32_t) * (size_t)ncol, true));
@@ -692,7 +711,7 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
   // residual from A with the split's own factor, and classify the refined x and y again
   const bool auto_refine = (o.flags & NNLS_FLAG_REFINE_AUTO) != 0 && o.precision == NNLS_FP64;
   const bool final_refine = ((o.flags & NNLS_FLAG_REFINE_FINAL) != 0 || auto_refine) && o.precision == NNLS_FP64;
-  const bool mixed = o.precision == NNLS_FP32_IR;
+  const bool mixed = o.precision != NNLS_FP64;
   const bool certify = mixed && (o.flags & NNLS_FLAG_REFINE_ALL) == 0;   // intermediate splits
   bool refined = false;
   int last_nF = 0;
@@ -716,7 +735,7 @@ int pivot_loop(nnls_handle* h, const Problem& P, double* x, double* y, const nnl
         int outcome = STALLED;
         double err = INFINITY;
         const int ir_before = info ? info->ir_steps : 0;
-        const bool f32 = h->fact_prec == 1;
+        const bool f32 = h->fact_prec >= PREC_F32;
         const double l_bytes = (f32 ? 4.0 : 8.0) * (double)tile_count((last_nF + TILE - 1) / TILE) * TILE_ELEMS;
         double xm = 0.0;
         TRY(refine(h, P, last_nF, x, y, o, spmv_bytes, f32, l_bytes, info, &outcome, false, &err, &xm));
@@ -839,8 +858,6 @@ int solve_common(nnls_handle* h, const Problem& P, double* x, double* y, const n
   if (!h) return set_info_status(info, NNLS_ERR_INVALID_ARG);
   h->trace.clear();
   if (check_options(o) != NNLS_OK) return set_info_status(info, NNLS_ERR_INVALID_ARG);
-  if (o.precision == NNLS_FP32_IR && (o.ir_max_steps < 0 || !(o.ir_rtol > 0.0)))
-    return set_info_status(info, NNLS_ERR_INVALID_ARG);
   if (P.n < 1 || P.m < P.n || !P.b || !x || !y) return set_info_status(info, NNLS_ERR_INVALID_ARG);
   if (P.sparse) {
     if (P.nnz < 0 || P.nnz > INT32_MAX || !P.colptr || (P.nnz > 0 && (!P.rowidx || !P.val)))
@@ -881,7 +898,7 @@ void release_workspace(nnls_handle* h) {
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
                     &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart, &h->spart,
                     &h->upcnt, &h->prow, &h->pval, &h->pcnt, &h->Fold, &h->zr, &h->est, &h->ev, &h->exi,
-                    &h->bprobs, &h->border, &h->binfo, &h->bws, &h->scan, &h->wr, &h->bw, &h->bb, &h->rlo};
+                    &h->bprobs, &h->border, &h->binfo, &h->bws, &h->scan, &h->wr, &h->bw, &h->bb, &h->rlo, &h->Lbf};
   for (DevBuf* b : bufs) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
@@ -1017,8 +1034,7 @@ int nnls_solve_dense_batched(nnls_handle* h, int32_t batch, const int32_t* m, co
   if (opts) o = *opts;
   if (!h || batch < 0 || (batch > 0 && (!m || !n || !A || !lda || !b || !x || !y)))
     return NNLS_ERR_INVALID_ARG;
-  if (check_options(o) != NNLS_OK) return NNLS_ERR_INVALID_ARG;
-  if (o.precision == NNLS_FP32_IR && (o.ir_max_steps < 0 || !(o.ir_rtol > 0.0))) return NNLS_ERR_INVALID_ARG;
+  if (check_options(o) != NNLS_OK || o.precision == NNLS_BF16_IR) return NNLS_ERR_INVALID_ARG;
   if (info)
     for (int i = 0; i < batch; ++i) {
       std::memset(&info[i], 0, sizeof(nnls_info));
@@ -1118,8 +1134,7 @@ int nnls_solve_dense_batched_noalloc(nnls_handle* h, int32_t batch, const int32_
   if (opts) o = *opts;
   if (!h || batch < 0 || (batch > 0 && (!m || !n || !A || !lda || !b || !x || !y)))
     return NNLS_ERR_INVALID_ARG;
-  if (check_options(o) != NNLS_OK) return NNLS_ERR_INVALID_ARG;
-  if (o.precision == NNLS_FP32_IR && (o.ir_max_steps < 0 || !(o.ir_rtol > 0.0))) return NNLS_ERR_INVALID_ARG;
+  if (check_options(o) != NNLS_OK || o.precision == NNLS_BF16_IR) return NNLS_ERR_INVALID_ARG;
   if (info)
     for (int i = 0; i < batch; ++i) {
       std::memset(&info[i], 0, sizeof(nnls_info));
@@ -1277,18 +1292,20 @@ int nnls_cholesky(nnls_handle* h, int32_t n, const double* S, int32_t lds, doubl
                   int32_t precision, int32_t* failed) {
   if (failed) *failed = -1;
   if (!h || n < 1 || !S || !L || lds < n || ldl < n ||
-      (precision != NNLS_FP64 && precision != NNLS_FP32_IR))
+      (precision != NNLS_FP64 && precision != NNLS_FP32_IR && precision != NNLS_BF16_IR))
     return NNLS_ERR_INVALID_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return NNLS_ERR_DEVICE;
-  const bool fp32 = precision == NNLS_FP32_IR;
+  const int prec = prec_level(precision);
+  const bool fp32 = prec >= PREC_F32;
   TRY(ensure(h, h->ctrl, sizeof(Ctrl)));
-  TRY(ensure_factor(h, n, fp32));
+  TRY(ensure_factor(h, n, prec));
   launch_ctrl_set_state(h->stream, (Ctrl*)h->ctrl.p, INT32_MAX, 0, 0, 0);
   launch_fill_i32(h->stream, (int32_t*)h->colcnt.p, (n + TILE - 1) / TILE, 0);
   h->epoch += 1;
   h->max_wgs = h->default_wgs;
   h->fact_prec = -1;
   FactorArgs fa = factor_args(h, n, nullptr, S, lds, false);
+  fa.Lbf = prec == PREC_BF16 ? h->Lbf.p : nullptr;
   launch_cholesky(h->stream, fa, fp32);
   launch_tiles_to_dense(h->stream, n, h->Lt.p, fp32, L, ldl);
   TRY(sync_read(h, h->h_ctrl, h->ctrl.p, sizeof(Ctrl)));
@@ -1306,7 +1323,7 @@ int nnls_spd_solve(nnls_handle* h, int32_t n, const double* S, int32_t lds, cons
   if (!h || n < 1 || !S || !rhs || !x || lds < n) return NNLS_ERR_INVALID_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return NNLS_ERR_DEVICE;
   TRY(ensure(h, h->ctrl, sizeof(Ctrl)));
-  TRY(ensure_factor(h, n, false));
+  TRY(ensure_factor(h, n, PREC_F64));
   launch_ctrl_set_state(h->stream, (Ctrl*)h->ctrl.p, INT32_MAX, 0, 0, 0);
   launch_fill_i32(h->stream, (int32_t*)h->colcnt.p, (n + TILE - 1) / TILE, 0);
   h->epoch += 1;

@@ -91,8 +91,35 @@ __device__ inline void gather_tile(const FactorArgs& a, int tid, int I, int J, T
   __syncthreads();
 }
 
+// ---------------------------------------------------------------- bfloat16 operand copies
+// NNLS_BF16_IR: every finished off-diagonal tile is also stored rounded to bfloat16, row by
+// row (element (r, c) at r * TILE + c, 8 KB a tile), and the left-looking updates read
+// these copies: half the bytes of the float32 tiles, and v_mfma_f32_16x16x32_bf16 with
+// float32 accumulation.  The diagonal chain (the walker's last term, the diagonal factor,
+// the triangular solves with the inverted diagonal tiles) stays in float32.  Diagonal tiles
+// never enter an update as operands, so they have no copy.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int LDK = TILE + 8;   // LDS row stride (elements) of a staged bfloat16 tile
+
+__device__ inline uint32_t pack_bf16x2(float lo, float hi) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)lo) |
+         ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)hi) << 16);
+}
+
+// Row-major bfloat16 copy of an LDS tile (column-major float, leading dimension LDT):
+// thread t writes row t / 4, columns 16 (t % 4) .. 16 (t % 4) + 15.
+__device__ __forceinline__ void bf16_copy_to_global(uint16_t* __restrict__ g, const float* X, int tid) {
+  const int r = tid >> 2, c0 = (tid & 3) * 16;
+  uint32_t w[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) w[q] = pack_bf16x2(X[r + (c0 + 2 * q) * LDT], X[r + (c0 + 2 * q + 1) * LDT]);
+  uint4* dst = (uint4*)(g + r * TILE + c0);
+  dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+  dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+}
+
 // One lower tile (I, J), I >= j0; S, W, s_part, s_rhs are the workgroup's LDS.
-template <typename T>
+template <typename T, bool BF>
 __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_ticks, int tid, int I, int J,
                                           T* S, T* W, double (*s_part)[TILE]) {
   typedef MF<T> M;
@@ -133,7 +160,13 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
   // frontier its loads wait until step k's products are issued.
   T* SA = S;
   T* SB = (I == J) ? S : W;
-  T ra[TILE_ELEMS / 256], rb[TILE_ELEMS / 256];
+  T ra[BF ? 1 : TILE_ELEMS / 256], rb[BF ? 1 : TILE_ELEMS / 256];
+  // bfloat16 operands: 16 values a thread (row tid / 4, columns 16 (tid % 4) ..), staged in
+  // LDS row-major with row stride LDK
+  uint4 ha[2], hb[2];
+  uint16_t* HA = (uint16_t*)S;
+  uint16_t* HB = (I == J) ? HA : (uint16_t*)W;
+  const uint16_t* Lb = (const uint16_t*)a.Lbf;
   int known = 0;                             // leading columns this thread knows are complete
   // column k is complete when its nb - max(k, j0) computed tiles are
   auto ready = [&](int k1, bool block) -> bool {
@@ -153,13 +186,24 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
     return true;
   };
   auto load = [&](int k1) {
-    const T* gi = Lt + tile_index(I, k1) * TILE_ELEMS;
+    if constexpr (BF) {
+      const uint4* gi = (const uint4*)(Lb + tile_index(I, k1) * TILE_ELEMS) + 2 * tid;
+      ha[0] = gi[0];
+      ha[1] = gi[1];
+      if (I != J) {
+        const uint4* gj = (const uint4*)(Lb + tile_index(J, k1) * TILE_ELEMS) + 2 * tid;
+        hb[0] = gj[0];
+        hb[1] = gj[1];
+      }
+    } else {
+      const T* gi = Lt + tile_index(I, k1) * TILE_ELEMS;
 #pragma unroll
-    for (int q = 0; q < TILE_ELEMS / 256; ++q) ra[q] = gi[tid + q * 256];
-    if (I != J) {
-      const T* gj = Lt + tile_index(J, k1) * TILE_ELEMS;
+      for (int q = 0; q < TILE_ELEMS / 256; ++q) ra[q] = gi[tid + q * 256];
+      if (I != J) {
+        const T* gj = Lt + tile_index(J, k1) * TILE_ELEMS;
 #pragma unroll
-      for (int q = 0; q < TILE_ELEMS / 256; ++q) rb[q] = gj[tid + q * 256];
+        for (int q = 0; q < TILE_ELEMS / 256; ++q) rb[q] = gj[tid + q * 256];
+      }
     }
   };
   if (kend > 0) {
@@ -168,11 +212,21 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
   }
   for (int k = 0; k < kend; ++k) {
     __syncthreads();   // the previous step's products (or the accumulator set-up) have read LDS
+    if constexpr (BF) {
+      const int o = (tid >> 2) * LDK + (tid & 3) * 16;
+      ((uint4*)(HA + o))[0] = ha[0];
+      ((uint4*)(HA + o))[1] = ha[1];
+      if (I != J) {
+        ((uint4*)(HB + o))[0] = hb[0];
+        ((uint4*)(HB + o))[1] = hb[1];
+      }
+    } else {
 #pragma unroll
-    for (int q = 0; q < TILE_ELEMS / 256; ++q) {
-      const int e = tid + q * 256, o = (e & (TILE - 1)) + (e >> 6) * LDT;
-      SA[o] = ra[q];
-      if (I != J) SB[o] = rb[q];
+      for (int q = 0; q < TILE_ELEMS / 256; ++q) {
+        const int e = tid + q * 256, o = (e & (TILE - 1)) + (e >> 6) * LDT;
+        SA[o] = ra[q];
+        if (I != J) SB[o] = rb[q];
+      }
     }
     __syncthreads();
     bool pre = false;
@@ -185,19 +239,45 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int cc = w * 16 + q;
-        tacc = fma((double)SB[lane + cc * LDT], zk[cc], tacc);
+        double l;
+        if constexpr (BF)
+          l = (double)(float)__builtin_bit_cast(__bf16, HB[lane * LDK + cc]);
+        else
+          l = (double)SB[lane + cc * LDT];
+        tacc = fma(l, zk[cc], tacc);
       }
     }
     if (!skip) {
+      if constexpr (BF) {
+        // lane l: row l % 16 of its 16 x 16 block, k = kh + 8 (l / 16) .. + 7, for both operands
 #pragma unroll
-      for (int kk = 0; kk < TILE; kk += 4) {
-        const int col = (kk + lk) * LDT;
-        const T a0 = -SA[col + qr + lr], a1 = -SA[col + qr + 16 + lr];
-        const T b0 = SB[col + qc + lr], b1 = SB[col + qc + 16 + lr];
-        acc[0][0] = M::op(a0, b0, acc[0][0]);
-        acc[0][1] = M::op(a0, b1, acc[0][1]);
-        acc[1][0] = M::op(a1, b0, acc[1][0]);
-        acc[1][1] = M::op(a1, b1, acc[1][1]);
+        for (int kh = 0; kh < TILE; kh += 32) {
+          const int kofs = kh + 8 * lk;
+          uint4 x0 = *(const uint4*)(HA + (qr + lr) * LDK + kofs);
+          uint4 x1 = *(const uint4*)(HA + (qr + 16 + lr) * LDK + kofs);
+          const uint4 y0 = *(const uint4*)(HB + (qc + lr) * LDK + kofs);
+          const uint4 y1 = *(const uint4*)(HB + (qc + 16 + lr) * LDK + kofs);
+          const uint32_t neg = 0x80008000u;   // S -= L_Ik L_Jk^T: negate the L_Ik operand
+          x0 = make_uint4(x0.x ^ neg, x0.y ^ neg, x0.z ^ neg, x0.w ^ neg);
+          x1 = make_uint4(x1.x ^ neg, x1.y ^ neg, x1.z ^ neg, x1.w ^ neg);
+          const bf16x8 a0 = __builtin_bit_cast(bf16x8, x0), a1 = __builtin_bit_cast(bf16x8, x1);
+          const bf16x8 b0 = __builtin_bit_cast(bf16x8, y0), b1 = __builtin_bit_cast(bf16x8, y1);
+          acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+        }
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < TILE; kk += 4) {
+          const int col = (kk + lk) * LDT;
+          const T a0 = -SA[col + qr + lr], a1 = -SA[col + qr + 16 + lr];
+          const T b0 = SB[col + qc + lr], b1 = SB[col + qc + 16 + lr];
+          acc[0][0] = M::op(a0, b0, acc[0][0]);
+          acc[0][1] = M::op(a0, b1, acc[0][1]);
+          acc[1][0] = M::op(a1, b0, acc[1][0]);
+          acc[1][1] = M::op(a1, b1, acc[1][1]);
+        }
       }
     }
     if (k + 1 < kend && !pre) {
@@ -264,6 +344,7 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
         S[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT] = o[bi][bj][v];
   __syncthreads();
   for (int e = tid; e < TILE_ELEMS; e += 256) dst[e] = S[(e & (TILE - 1)) + (e >> 6) * LDT];
+  if constexpr (BF) bf16_copy_to_global((uint16_t*)a.Lbf + ti * TILE_ELEMS, (const float*)S, tid);
   publish_tile(&a.tflag[ti], &a.colcnt[J], a.epoch);
 }
 
@@ -348,7 +429,7 @@ __device__ __forceinline__ void tile_to_global(T* __restrict__ g, const T* X, in
 // LDS (S_{J+1,J} being fully updated by its own workgroup meanwhile).  It then prefetches
 // the next diagonal partial sum into the buffer the inverse leaves free.  Per column the
 // chain keeps one hand-over from another workgroup (S_{J+1,J}) instead of three.
-template <typename T>
+template <typename T, bool BF>
 __device__ __forceinline__ void walker(const FactorArgs& a, uint64_t wait_ticks, T* Pbuf, T* Qbuf,
                                        double (*s_part)[TILE], double* s_rhs, double* s_z, double* s_tp) {
   typedef MF<T> M;
@@ -472,6 +553,7 @@ __device__ __forceinline__ void walker(const FactorArgs& a, uint64_t wait_ticks,
     for (int bj = 0; bj < 4; ++bj) store16<T>(U, 16 * w, 16 * bj, o[bj]);
     __syncthreads();
     tile_to_global<T>(dsub, U, tid);
+    if constexpr (BF) bf16_copy_to_global((uint16_t*)a.Lbf + ts * TILE_ELEMS, (const float*)U, tid);
     // one release covers L_JJ and L_{J+1,J}
     __syncthreads();
     if (tid == 0) {
@@ -511,7 +593,7 @@ __device__ inline void decode_ticket(int t, int nb, int j0, int* I, int* J) {
 // workgroups by default, fewer when concurrent solves share the device).  A workgroup
 // holds one ticket at a time and only waits for smaller tickets, which running workgroups
 // hold, so the lowest unfinished ticket always progresses.
-template <typename T>
+template <typename T, bool BF>
 __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wait_ticks) {
   __shared__ T S[TILE * LDT];
   __shared__ T W[TILE * LDT];
@@ -535,11 +617,11 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wa
     const int t = s_t, I = s_I, J = s_J;
     __syncthreads();   // every thread has its ticket before thread 0 may take the next
     if (t < 0) {
-      walker<T>(a, wait_ticks, S, W, s_part, s_rhs, s_z, s_tp);
+      walker<T, BF>(a, wait_ticks, S, W, s_part, s_rhs, s_z, s_tp);
       return;
     }
     if (t >= ntiles) return;
-    chol_tile<T>(a, wait_ticks, tid, I, J, S, W, s_part);
+    chol_tile<T, BF>(a, wait_ticks, tid, I, J, S, W, s_part);
     __syncthreads();   // LDS is reused by the next tile
   }
 }
@@ -714,10 +796,12 @@ void launch_cholesky(hipStream_t s, const FactorArgs& a, bool fp32) {
   if (a.nb <= 0 || a.j0 < 0 || a.j0 >= a.nb) return;
   int64_t grid = tile_count_from(a.nb, a.j0) + 1;   // the tiles and the walker
   if (a.max_wgs > 0 && grid > a.max_wgs) grid = a.max_wgs < 2 ? 2 : a.max_wgs;   // walker + >= 1 worker
-  if (fp32)
-    hipLaunchKernelGGL(k_chol_tiles<float>, dim3((unsigned)grid), dim3(256), 0, s, a, a.wait_ticks);
+  if (fp32 && a.Lbf)
+    hipLaunchKernelGGL((k_chol_tiles<float, true>), dim3((unsigned)grid), dim3(256), 0, s, a, a.wait_ticks);
+  else if (fp32)
+    hipLaunchKernelGGL((k_chol_tiles<float, false>), dim3((unsigned)grid), dim3(256), 0, s, a, a.wait_ticks);
   else
-    hipLaunchKernelGGL(k_chol_tiles<double>, dim3((unsigned)grid), dim3(256), 0, s, a, a.wait_ticks);
+    hipLaunchKernelGGL((k_chol_tiles<double, false>), dim3((unsigned)grid), dim3(256), 0, s, a, a.wait_ticks);
 }
 
 template <int TD>

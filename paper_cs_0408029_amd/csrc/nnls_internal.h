@@ -199,6 +199,9 @@ struct FactorArgs {
   const double* rhs;      // optional: forward-solve L z = rhs_F during the factorisation
   double* z;              // nb * TILE, written when rhs != nullptr
   int max_wgs;            // cap on the persistent grid (0: one workgroup per tile and the walker)
+  void* Lbf;              // float factor only: bfloat16 row-major copies of the off-diagonal
+                          // tiles, which the left-looking updates then read (NNLS_BF16_IR);
+                          // nullptr: the updates read the float tiles
 };
 void launch_cholesky(hipStream_t s, const FactorArgs& a, bool fp32);
 // z = L^-1 rhs (rhs gathered through Flist when gather != nullptr); x = L^-T z and

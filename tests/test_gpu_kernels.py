@@ -118,6 +118,27 @@ def test_cholesky_fp32(h, n):
     assert np.linalg.norm(Lg @ Lg.T - S) <= 4 * n * e32 * np.linalg.norm(S)
 
 
+@pytest.mark.parametrize("n", [130, 257, 513, 700])
+def test_cholesky_bf16_updates(h, n):
+    """NNLS_BF16_IR: the left-looking updates take bfloat16 copies of the finished tiles
+    (u = 2^-8) with float32 accumulation, so every entry of L L^T - S is within
+    2u sqrt(S_ii S_jj) (each product of two rounded entries is within 2u, and the products
+    of a row pair sum to at most sqrt(S_ii S_jj) in magnitude), well above what float32
+    updates leave: the bfloat16 path is the one that ran.  (It runs from three tile
+    columns on: the walker applies each diagonal tile's last term in float32.)"""
+    S = spd(n, 20 + n)
+    L = colmajor_dev(np.zeros((n, n)))
+    st, failed = N.nnls_cholesky(h, colmajor_dev(S), L, N.NNLS_BF16_IR)
+    assert st == N.NNLS_OK and failed == -1
+    Lg = L.cpu().numpy()
+    assert np.all(np.triu(Lg, 1) == 0)
+    d = np.sqrt(np.diag(S))
+    rel = np.abs(Lg @ Lg.T - S) / np.outer(d, d)
+    u = 2.0 ** -8
+    assert rel.max() <= 2 * u * 1.05
+    assert rel.max() > 1e-5
+
+
 @pytest.mark.parametrize("n,k", [(10, 3), (100, 70), (130, 128), (64, 0)])
 def test_cholesky_breakdown_position(h, n, k):
     """A negative pivot at position k: the factor reports k, as LAPACK's info does."""

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 import paper_cs_0408029_amd as N  # noqa: E402
-from _gpu_util import certified, oracle_trace, solve_csc, solve_dense  # noqa: E402
+from _gpu_util import DEV, certified, colmajor_dev, oracle_trace, solve_csc, solve_dense, t  # noqa: E402
 
 RTOL = 1e-10
 
@@ -340,7 +340,7 @@ def blockband():
     return W.sparse_blockband(1005)
 
 
-@pytest.mark.parametrize("precision,tol", [(N.NNLS_FP64, 1e-10), (N.NNLS_FP32_IR, 1e-8)])
+@pytest.mark.parametrize("precision,tol", [(N.NNLS_FP64, 1e-10), (N.NNLS_FP32_IR, 1e-8), (N.NNLS_BF16_IR, 1e-8)])
 def test_large_blockband_full_size(h, blockband, precision, tol):
     """The large sparse instance (m = 400000, n = 50000, block band, 25% active) at full
     size: the free set is the planted one and x is the planted x* (an exact NNLS solution
@@ -434,3 +434,53 @@ def test_mixed_error_bound_sparse(h):
     actual = np.max(np.abs(x[f] - res.x[f])) / np.max(np.abs(x[f]))
     assert 0 < info.est_rel_err <= 1e-12
     assert actual <= info.est_rel_err + 1e-14   # the oracle's own error is below 1e-14 here
+
+
+# ------------------------------------------------------------------ bfloat16 updates
+@pytest.mark.parametrize("seed", [1001, 1002, 1003])
+def test_bf16_sparse_small(h, seed):
+    inst = W.sparse_small(seed)
+    res = bpp_solve(inst.A, inst.b)
+    st, info, x, y, trace = solve_csc(h, inst.A, inst.b, precision=N.NNLS_BF16_IR)
+    check_mixed(res, st, info, x, y, trace)
+    assert 0 < info.est_rel_err <= 1e-12
+
+
+def test_bf16_sparse_large_full_size(h):
+    inst = W.sparse_large(1002)
+    res = bpp_solve(inst.A, inst.b)
+    st, info, x, y, trace = solve_csc(h, inst.A, inst.b, precision=N.NNLS_BF16_IR)
+    assert np.array_equal(x > 0, inst.active)
+    check_mixed(res, st, info, x, y, trace)
+
+
+@pytest.mark.parametrize("m,n,seed", [(300, 100, 2), (1100, 520, 4)])
+def test_bf16_dense_planted(h, m, n, seed):
+    inst = W.dense_planted(seed, m, n)
+    res = bpp_solve(inst.A, inst.b)
+    st, info, x, y, trace = solve_dense(h, inst.A, inst.b, precision=N.NNLS_BF16_IR)
+    check_mixed(res, st, info, x, y, trace)
+
+
+def test_bf16_ill_conditioned_climbs_the_ladder(h):
+    """kappa(H_FF) = 1e6 is far beyond what bfloat16 updates can refine (kappa 2^-8 >> 1):
+    those factors are redone in float32 (then float64 if needed) and the result is still
+    the planted free set with x within the reported bound of an exact-residual reference."""
+    inst = W.conditioned_planted(1, 600, 300, 1e3)
+    st, info, x, y, trace = solve_dense(h, inst.A, inst.b, precision=N.NNLS_BF16_IR)
+    assert st == N.NNLS_OK
+    assert np.array_equal(x > 0, inst.active)
+    xr = _ls_reference(inst.A, inst.b, inst.active)
+    xf = x[inst.active]
+    actual = np.max(np.abs(xf - xr)) / np.max(np.abs(xf))
+    assert 0 < info.est_rel_err <= 1e-12 and actual <= info.est_rel_err + 4e-16
+
+
+def test_bf16_rejected_where_not_offered(h):
+    A = np.random.default_rng(0).standard_normal((40, 20))
+    b = np.ones(40)
+    x = torch.empty(20, dtype=torch.float64, device=DEV)
+    y = torch.empty_like(x)
+    st, _ = N.nnls_solve_dense_batched(h, [colmajor_dev(A)], [t(b)], [x], [y],
+                                       N.default_options(precision=N.NNLS_BF16_IR))
+    assert st == N.NNLS_ERR_INVALID_ARG
