@@ -32,6 +32,8 @@
 // every dependency.
 #include <climits>
 
+#include <type_traits>
+
 #include "tile_ops.h"
 
 namespace nnls {
@@ -99,6 +101,8 @@ __device__ inline void gather_tile(const FactorArgs& a, int tid, int I, int J, T
 // the triangular solves with the inverted diagonal tiles) stays in float32.  Diagonal tiles
 // never enter an update as operands, so they have no copy.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+// 16 bytes as a native vector (HIP's uint4 class type keeps arrays of it out of registers)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr int LDK = TILE + 8;   // LDS row stride (elements) of a staged bfloat16 tile
 
 __device__ inline uint32_t pack_bf16x2(float lo, float hi) {
@@ -113,9 +117,9 @@ __device__ __forceinline__ void bf16_copy_to_global(uint16_t* __restrict__ g, co
   uint32_t w[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) w[q] = pack_bf16x2(X[r + (c0 + 2 * q) * LDT], X[r + (c0 + 2 * q + 1) * LDT]);
-  uint4* dst = (uint4*)(g + r * TILE + c0);
-  dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
-  dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+  u32x4* dst = (u32x4*)(g + r * TILE + c0);
+  dst[0] = u32x4{w[0], w[1], w[2], w[3]};
+  dst[1] = u32x4{w[4], w[5], w[6], w[7]};
 }
 
 // One lower tile (I, J), I >= j0; S, W, s_part, s_rhs are the workgroup's LDS.
@@ -163,7 +167,6 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
   T ra[BF ? 1 : TILE_ELEMS / 256], rb[BF ? 1 : TILE_ELEMS / 256];
   // bfloat16 operands: 16 values a thread (row tid / 4, columns 16 (tid % 4) ..), staged in
   // LDS row-major with row stride LDK
-  uint4 ha[2], hb[2];
   uint16_t* HA = (uint16_t*)S;
   uint16_t* HB = (I == J) ? HA : (uint16_t*)W;
   const uint16_t* Lb = (const uint16_t*)a.Lbf;
@@ -186,80 +189,83 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
     return true;
   };
   auto load = [&](int k1) {
-    if constexpr (BF) {
-      const uint4* gi = (const uint4*)(Lb + tile_index(I, k1) * TILE_ELEMS) + 2 * tid;
-      ha[0] = gi[0];
-      ha[1] = gi[1];
-      if (I != J) {
-        const uint4* gj = (const uint4*)(Lb + tile_index(J, k1) * TILE_ELEMS) + 2 * tid;
-        hb[0] = gj[0];
-        hb[1] = gj[1];
-      }
-    } else {
-      const T* gi = Lt + tile_index(I, k1) * TILE_ELEMS;
+    const T* gi = Lt + tile_index(I, k1) * TILE_ELEMS;
 #pragma unroll
-      for (int q = 0; q < TILE_ELEMS / 256; ++q) ra[q] = gi[tid + q * 256];
-      if (I != J) {
-        const T* gj = Lt + tile_index(J, k1) * TILE_ELEMS;
+    for (int q = 0; q < TILE_ELEMS / 256; ++q) ra[q] = gi[tid + q * 256];
+    if (I != J) {
+      const T* gj = Lt + tile_index(J, k1) * TILE_ELEMS;
 #pragma unroll
-        for (int q = 0; q < TILE_ELEMS / 256; ++q) rb[q] = gj[tid + q * 256];
-      }
+      for (int q = 0; q < TILE_ELEMS / 256; ++q) rb[q] = gj[tid + q * 256];
     }
   };
-  if (kend > 0) {
-    ready(0, true);
-    load(0);
-  }
-  for (int k = 0; k < kend; ++k) {
-    __syncthreads();   // the previous step's products (or the accumulator set-up) have read LDS
-    if constexpr (BF) {
-      const int o = (tid >> 2) * LDK + (tid & 3) * 16;
-      ((uint4*)(HA + o))[0] = ha[0];
-      ((uint4*)(HA + o))[1] = ha[1];
+  if constexpr (BF) {
+    // Up to PD steps' operand copies in flight: step s is loaded into the registers of slot
+    // s % PD as soon as its tiles are known final and its slot is free (step s - PD has
+    // been staged), so the loads of later steps overlap the short bfloat16 MFMA steps.  A
+    // step whose tiles were not final when its slot freed is loaded, waiting, at its turn.
+    constexpr int PD = 4;
+    u32x4 rg[PD][4];
+    int held[PD];   // the step each slot holds (-1: none)
+    auto fetch = [&](auto slot, int s1) __attribute__((always_inline)) {
+      constexpr int d = decltype(slot)::value;
+      const u32x4* gi = (const u32x4*)(Lb + tile_index(I, s1) * TILE_ELEMS) + 2 * tid;
+      rg[d][0] = gi[0];
+      rg[d][1] = gi[1];
       if (I != J) {
-        ((uint4*)(HB + o))[0] = hb[0];
-        ((uint4*)(HB + o))[1] = hb[1];
+        const u32x4* gj = (const u32x4*)(Lb + tile_index(J, s1) * TILE_ELEMS) + 2 * tid;
+        rg[d][2] = gj[0];
+        rg[d][3] = gj[1];
       }
-    } else {
+      held[d] = s1;
+    };
+    auto prime = [&](auto slot) __attribute__((always_inline)) {
+      constexpr int d = decltype(slot)::value;
+      held[d] = -1;
+      if (d < kend && ready(d, d == 0)) fetch(slot, d);
+    };
+    prime(std::integral_constant<int, 0>{});
+    prime(std::integral_constant<int, 1>{});
+    prime(std::integral_constant<int, 2>{});
+    prime(std::integral_constant<int, 3>{});
+    auto step = [&](auto slot, int k) __attribute__((always_inline)) {
+      constexpr int d = decltype(slot)::value;
+      if (held[d] != k) {   // at the frontier: wait for this step's tiles
+        ready(k, true);
+        fetch(slot, k);
+      }
+      __syncthreads();   // the previous step's products (or the accumulator set-up) have read LDS
+      {
+        const int o = (tid >> 2) * LDK + (tid & 3) * 16;
+        ((u32x4*)(HA + o))[0] = rg[d][0];
+        ((u32x4*)(HA + o))[1] = rg[d][1];
+        if (I != J) {
+          ((u32x4*)(HB + o))[0] = rg[d][2];
+          ((u32x4*)(HB + o))[1] = rg[d][3];
+        }
+      }
+      __syncthreads();
+      held[d] = -1;
+      if (k + PD < kend && ready(k + PD, false)) fetch(slot, k + PD);
+      if (fwd) {
+        const double* zk = a.z + (int64_t)k * TILE;
 #pragma unroll
-      for (int q = 0; q < TILE_ELEMS / 256; ++q) {
-        const int e = tid + q * 256, o = (e & (TILE - 1)) + (e >> 6) * LDT;
-        SA[o] = ra[q];
-        if (I != J) SB[o] = rb[q];
+        for (int q = 0; q < 16; ++q) {
+          const int cc = w * 16 + q;
+          tacc = fma((double)(float)__builtin_bit_cast(__bf16, HB[lane * LDK + cc]), zk[cc], tacc);
+        }
       }
-    }
-    __syncthreads();
-    bool pre = false;
-    if (k + 1 < kend) {
-      pre = ready(k + 1, false);
-      if (pre) load(k + 1);
-    }
-    if (fwd) {
-      const double* zk = a.z + (int64_t)k * TILE;
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int cc = w * 16 + q;
-        double l;
-        if constexpr (BF)
-          l = (double)(float)__builtin_bit_cast(__bf16, HB[lane * LDK + cc]);
-        else
-          l = (double)SB[lane + cc * LDT];
-        tacc = fma(l, zk[cc], tacc);
-      }
-    }
-    if (!skip) {
-      if constexpr (BF) {
+      if (!skip) {
         // lane l: row l % 16 of its 16 x 16 block, k = kh + 8 (l / 16) .. + 7, for both operands
 #pragma unroll
         for (int kh = 0; kh < TILE; kh += 32) {
           const int kofs = kh + 8 * lk;
-          uint4 x0 = *(const uint4*)(HA + (qr + lr) * LDK + kofs);
-          uint4 x1 = *(const uint4*)(HA + (qr + 16 + lr) * LDK + kofs);
-          const uint4 y0 = *(const uint4*)(HB + (qc + lr) * LDK + kofs);
-          const uint4 y1 = *(const uint4*)(HB + (qc + 16 + lr) * LDK + kofs);
+          u32x4 x0 = *(const u32x4*)(HA + (qr + lr) * LDK + kofs);
+          u32x4 x1 = *(const u32x4*)(HA + (qr + 16 + lr) * LDK + kofs);
+          const u32x4 y0 = *(const u32x4*)(HB + (qc + lr) * LDK + kofs);
+          const u32x4 y1 = *(const u32x4*)(HB + (qc + 16 + lr) * LDK + kofs);
           const uint32_t neg = 0x80008000u;   // S -= L_Ik L_Jk^T: negate the L_Ik operand
-          x0 = make_uint4(x0.x ^ neg, x0.y ^ neg, x0.z ^ neg, x0.w ^ neg);
-          x1 = make_uint4(x1.x ^ neg, x1.y ^ neg, x1.z ^ neg, x1.w ^ neg);
+          x0 ^= neg;
+          x1 ^= neg;
           const bf16x8 a0 = __builtin_bit_cast(bf16x8, x0), a1 = __builtin_bit_cast(bf16x8, x1);
           const bf16x8 b0 = __builtin_bit_cast(bf16x8, y0), b1 = __builtin_bit_cast(bf16x8, y1);
           acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
@@ -267,7 +273,42 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
           acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
           acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
         }
-      } else {
+      }
+    };
+    for (int k0 = 0; k0 < kend; k0 += PD) {
+      step(std::integral_constant<int, 0>{}, k0);
+      if (k0 + 1 < kend) step(std::integral_constant<int, 1>{}, k0 + 1);
+      if (k0 + 2 < kend) step(std::integral_constant<int, 2>{}, k0 + 2);
+      if (k0 + 3 < kend) step(std::integral_constant<int, 3>{}, k0 + 3);
+    }
+  } else {
+    if (kend > 0) {
+      ready(0, true);
+      load(0);
+    }
+    for (int k = 0; k < kend; ++k) {
+      __syncthreads();   // the previous step's products (or the accumulator set-up) have read LDS
+#pragma unroll
+      for (int q = 0; q < TILE_ELEMS / 256; ++q) {
+        const int e = tid + q * 256, o = (e & (TILE - 1)) + (e >> 6) * LDT;
+        SA[o] = ra[q];
+        if (I != J) SB[o] = rb[q];
+      }
+      __syncthreads();
+      bool pre = false;
+      if (k + 1 < kend) {
+        pre = ready(k + 1, false);
+        if (pre) load(k + 1);
+      }
+      if (fwd) {
+        const double* zk = a.z + (int64_t)k * TILE;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int cc = w * 16 + q;
+          tacc = fma((double)SB[lane + cc * LDT], zk[cc], tacc);
+        }
+      }
+      if (!skip) {
 #pragma unroll
         for (int kk = 0; kk < TILE; kk += 4) {
           const int col = (kk + lk) * LDT;
@@ -279,10 +320,10 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
           acc[1][1] = M::op(a1, b1, acc[1][1]);
         }
       }
-    }
-    if (k + 1 < kend && !pre) {
-      ready(k + 1, true);
-      load(k + 1);
+      if (k + 1 < kend && !pre) {
+        ready(k + 1, true);
+        load(k + 1);
+      }
     }
   }
   __syncthreads();   // the last products have read S and W
