@@ -4,14 +4,15 @@ One step = one complete solve (validation, Gram matrix and A^T b, the whole pivo
 of a seeded synthetic instance whose inputs are already resident in device memory.
 Default workload: sparse m = 400000, n = 50000, 20 N(0,1) entries per column at random
 rows plus a block band (rows [8j, 8j+64) N(0,1), A[8j, j] += sqrt(84)), 25% of variables
-active with margin 1e-3 (seed 1005), solved by the mixed path (float32 factor, float64
-refinement, float64 y_G and sign tests) and by the plain float64 path in the same process.
+active with margin 1e-3 (seed 1005), solved by the mixed path (float32 factor whose
+updates run on bfloat16 MFMA, float64 refinement, float64 y_G and sign tests), by the
+float32-factor mixed path and by the plain float64 path in the same process.
 
-Prints one JSON line: the mixed path's solves/s and p50/p99 latency, the plain path's
-beside it, accuracy against the planted solution and between the paths, the roofline of
-the dominant kernel (the tiled Cholesky, timed with HIP events on the solver's stream
-during the timed steps), the 60000 x 12000 instance's pair, and the CPU oracle timed on a
-bounded sample of the same workload.  Other workloads: --workload (see --help).
+Prints one JSON line: the bfloat16-update path's solves/s and p50/p99 latency, the other
+paths beside it, accuracy against the planted solution and between the paths, the
+roofline of the dominant kernel (the tiled Cholesky, timed with HIP events on the solver's
+stream during the timed steps), the 60000 x 12000 instance's legs, and the CPU oracle
+timed on a bounded sample of the same workload.  Other workloads: --workload (see --help).
 """
 from __future__ import annotations
 
@@ -28,11 +29,13 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix) peak
 PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 (matrix) peak
+PEAK_BF16_TFLOPS = 2500.0    # MI355X dense BF16 (matrix) peak
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E peak
 CHOL_SOURCES = ("paper_cs_0408029_amd/csrc/k_chol.hip", "paper_cs_0408029_amd/csrc/tile_ops.h")
 # committed counter summaries (HBM bytes per launch of the factor) by (workload, precision)
 TRAFFIC_SUMMARY = {("sparse_large", "fp64"): "profiles/k_chol_tiles_sparse_large_m60000_n12000.md",
-                   ("sparse_xl", "fp32ir"): "profiles/k_chol_tiles_float_sparse_xl_m400000_n50000.md"}
+                   ("sparse_xl", "fp32ir"): "profiles/k_chol_tiles_float_sparse_xl_m400000_n50000.md",
+                   ("sparse_xl", "bf16ir"): "profiles/k_chol_tiles_bf16_sparse_xl_m400000_n50000.md"}
 METRIC = "NNLS solves/s + p50/p99 latency vs plain FP64 GPU path at ≤1e-8 rel err"
 
 
@@ -742,7 +745,7 @@ def main():
     leg = measure_single(h, inst, arrays, prec, args.steps, args.warmup, profile=not args.no_profile)
     h.close()
     traffic_src = (CHOL_SOURCES, TRAFFIC_SUMMARY.get((args.workload, args.precision)))
-    roof = chol_roofline(leg, fp32, traffic_src)
+    roof = chol_roofline(leg, {"fp64": "fp64", "fp32ir": "fp32", "bf16ir": "bf16"}[args.precision], traffic_src)
     out = {
         "metric": METRIC,
         "value": leg["solves_per_s"],
@@ -842,17 +845,21 @@ def measure_single(h, inst, arr, precision, steps, warmup, profile=True):
     }
 
 
-def chol_roofline(leg, fp32, traffic_src):
+def chol_roofline(leg, kind, traffic_src):
     """Roofline of the dominant kernel (the tiled F-block factor) from the HIP-event
     timings of the timed solves: sum over launches of (|F|^3 - p^3)/3 flops (p = kept
-    leading positions) over the summed launch durations."""
+    leading positions) over the summed launch durations.  kind: fp64, fp32, or bf16 (the
+    float32 factor whose updates -- all but a fraction of a percent of its flops -- run on
+    bfloat16 MFMA, so the bfloat16 peak applies)."""
     chol = leg["_prof"]["cholesky"]
     if not (chol["launches"] > 0 and chol["ms"] > 0):
         return None
     achieved = chol["work"] / (chol["ms"] * 1e-3) / 1e12
-    peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
+    peak = {"fp64": PEAK_FP64_TFLOPS, "fp32": PEAK_FP32_TFLOPS, "bf16": PEAK_BF16_TFLOPS}[kind]
+    name = {"fp64": "k_chol_tiles<double>", "fp32": "k_chol_tiles<float>",
+            "bf16": "k_chol_tiles<float, bf16 updates>"}[kind]
     srcs, summary = traffic_src
-    return {"bound": "mfma", "kernel": "k_chol_tiles<float>" if fp32 else "k_chol_tiles<double>",
+    return {"bound": "mfma", "kernel": name,
             "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
             "traffic": profiled_traffic(srcs, summary) if summary else None,
             "launches": chol["launches"], "avg_launch_ms": round(chol["ms"] / chol["launches"], 4),
@@ -866,10 +873,11 @@ def public(leg):
 
 def bench_metric(args):
     """The metric on the largest single-GPU configuration: the sparse 400000 x 50000
-    block-band instance solved by the plain float64 path and by the mixed path (float32
-    factor, float64 refinement, float64 y_G and sign tests) in one process on the same
-    device-resident inputs.  `value` is the mixed path's solves/s; the plain path, the
-    mixed/plain ratio, both paths' accuracy and the 60000 x 12000 instance's pair go beside
+    block-band instance solved by the plain float64 path and by the two mixed paths
+    (float32 factor; float32 factor with bfloat16-input updates; both with float64
+    refinement, y_G and sign tests) in one process on the same device-resident inputs.
+    `value` is the bfloat16-update path's solves/s; the plain path, the float32-factor
+    path, the ratios, every path's accuracy and the 60000 x 12000 instance's legs go beside
     it."""
     import torch
     import paper_cs_0408029_amd as N
@@ -879,26 +887,36 @@ def bench_metric(args):
     dev = torch.device("cuda:0")
     arr = device_arrays(inst, dev)
     h = N.Handle(0)
-    plain = measure_single(h, inst, arr, N.NNLS_FP64, args.steps, args.warmup, profile=not args.no_profile)
-    mixed = measure_single(h, inst, arr, N.NNLS_FP32_IR, args.steps, args.warmup, profile=not args.no_profile)
-    roof = chol_roofline(mixed, True, (CHOL_SOURCES, TRAFFIC_SUMMARY.get(("sparse_xl", "fp32ir"))))
-    x64, x32 = plain["_x"], mixed["_x"]
-    mixed_vs_plain = float(np.linalg.norm(x32 - x64) / np.linalg.norm(x64))
-    same_free = bool(np.array_equal(x32 > 0, x64 > 0))
+    prof = not args.no_profile
+    plain = measure_single(h, inst, arr, N.NNLS_FP64, args.steps, args.warmup, profile=prof)
+    mixed32 = measure_single(h, inst, arr, N.NNLS_FP32_IR, args.steps, args.warmup, profile=prof)
+    mixed = measure_single(h, inst, arr, N.NNLS_BF16_IR, args.steps, args.warmup, profile=prof)
+    roof = chol_roofline(mixed, "bf16", (CHOL_SOURCES, TRAFFIC_SUMMARY.get(("sparse_xl", "bf16ir"))))
+    roof32 = chol_roofline(mixed32, "fp32", (CHOL_SOURCES, TRAFFIC_SUMMARY.get(("sparse_xl", "fp32ir"))))
+    roof64 = chol_roofline(plain, "fp64", (CHOL_SOURCES, None))
+    x64 = plain["_x"]
+
+    def vs64(leg):
+        return float(np.linalg.norm(leg["_x"] - x64) / np.linalg.norm(x64))
+
+    same_free = bool(np.array_equal(mixed["_x"] > 0, x64 > 0) and np.array_equal(mixed32["_x"] > 0, x64 > 0))
+    keys = ("solves_per_s", "ms_per_step", "p50_ms", "p99_ms", "pivot_iters_per_s", "rel_err_vs_planted",
+            "free_set_match", "kernel_ms_per_step")
     secondary = None
     if not args.no_secondary:
         inst2, desc2 = make_instance("sparse_large")
         arr2 = device_arrays(inst2, dev)
         k2, w2 = max(args.steps, 10), max(args.warmup, 2)
-        p2 = measure_single(h, inst2, arr2, N.NNLS_FP64, k2, w2, profile=False)
-        m2 = measure_single(h, inst2, arr2, N.NNLS_FP32_IR, k2, w2, profile=False)
-        secondary = {"workload": desc2, "steps": k2,
-                     "plain_fp64": {k: public(p2)[k] for k in ("solves_per_s", "p50_ms", "p99_ms",
-                                                               "rel_err_vs_planted", "free_set_match")},
-                     "mixed": {k: public(m2)[k] for k in ("solves_per_s", "p50_ms", "p99_ms", "rel_err_vs_planted",
-                                                          "free_set_match", "est_rel_err",
-                                                          "refinement_steps_per_solve")},
-                     "mixed_vs_plain_fp64": round(m2["solves_per_s"] / p2["solves_per_s"], 3)}
+        legs = {name: measure_single(h, inst2, arr2, prec, k2, w2, profile=False)
+                for name, prec in (("plain_fp64", N.NNLS_FP64), ("fp32_factor", N.NNLS_FP32_IR),
+                                   ("bf16_updates", N.NNLS_BF16_IR))}
+        secondary = {"workload": desc2, "steps": k2}
+        for name, leg in legs.items():
+            secondary[name] = {k: public(leg)[k] for k in ("solves_per_s", "p50_ms", "p99_ms", "rel_err_vs_planted",
+                                                            "free_set_match", "est_rel_err",
+                                                            "refinement_steps_per_solve")}
+        for name in ("fp32_factor", "bf16_updates"):
+            secondary[name + "_vs_plain_fp64"] = round(legs[name]["solves_per_s"] / legs["plain_fp64"]["solves_per_s"], 3)
     h.close()
     out = {
         "metric": METRIC,
@@ -916,20 +934,26 @@ def bench_metric(args):
         "scaling": "weak",
         "vs_baseline": None,
         "vs_plain_fp64": round(mixed["solves_per_s"] / plain["solves_per_s"], 3),
-        "dtype": "f32-factor+f64-refinement",
+        "dtype": "f32-factor(bf16-input updates)+f64-refinement",
         "data": "synthetic",
         "config": {"workload": desc,
-                   "path": "mixed: float32 F-block factor on MFMA, float64 refinement (compensated residual), "
-                           "float64 y_G and sign tests; one problem per call",
+                   "path": "mixed: float32 F-block factor whose left-looking updates run on bfloat16 MFMA "
+                           "(float32 accumulation), float64 refinement with a compensated residual, float64 "
+                           "y_G and sign tests; one problem per call",
                    "baseline_path": "plain FP64 GPU path, one problem per call, same process and inputs",
                    "m": inst.m, "n": inst.n, "nnz": int(inst.A.nnz)},
         "rel_err_vs_planted": mixed["rel_err_vs_planted"],
-        "rel_err_vs_plain_fp64": mixed_vs_plain,
+        "rel_err_vs_plain_fp64": vs64(mixed),
         "est_rel_err": mixed["est_rel_err"],
-        "free_set_match": mixed["free_set_match"] and plain["free_set_match"] and same_free,
-        "plain_fp64": {k: public(plain)[k] for k in ("solves_per_s", "ms_per_step", "p50_ms", "p99_ms",
-                                                      "pivot_iters_per_s", "rel_err_vs_planted", "free_set_match",
-                                                      "kernel_ms_per_step")},
+        "free_set_match": mixed["free_set_match"] and plain["free_set_match"] and mixed32["free_set_match"]
+                          and same_free,
+        "plain_fp64": {k: public(plain)[k] for k in keys},
+        "fp32_factor": dict({k: public(mixed32)[k] for k in keys},
+                            refinement_steps_per_solve=mixed32["refinement_steps_per_solve"],
+                            est_rel_err=mixed32["est_rel_err"], rel_err_vs_plain_fp64=vs64(mixed32),
+                            vs_plain_fp64=round(mixed32["solves_per_s"] / plain["solves_per_s"], 3),
+                            roofline=roof32),
+        "plain_fp64_roofline": roof64,
         "kernel_ms_per_step": mixed["kernel_ms_per_step"],
         "factor_launches": mixed["factor_launches"],
         "roofline": roof,
@@ -941,6 +965,7 @@ def bench_metric(args):
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_budget, max_solves=1,
                                            what="whole solve(s) of the 400000 x 50000 instance")
     print(json.dumps(out), flush=True)
+
 
 if __name__ == "__main__":
     main()
