@@ -17,6 +17,8 @@ timed on a bounded sample of the same workload.  Other workloads: --workload (se
 from __future__ import annotations
 
 import argparse
+import contextlib
+import gc
 import json
 import os
 import sys
@@ -37,6 +39,19 @@ TRAFFIC_SUMMARY = {("sparse_large", "fp64"): "profiles/k_chol_tiles_sparse_large
                    ("sparse_xl", "fp32ir"): "profiles/k_chol_tiles_float_sparse_xl_m400000_n50000.md",
                    ("sparse_xl", "bf16ir"): "profiles/k_chol_tiles_bf16_sparse_xl_m400000_n50000.md"}
 METRIC = "NNLS solves/s + p50/p99 latency vs plain FP64 GPU path at ≤1e-8 rel err"
+
+
+@contextlib.contextmanager
+def no_gc():
+    """Timed regions run with Python's cyclic garbage collector paused (collected first):
+    a full collection over this process's objects takes tens of ms and lands inside a
+    step's wall-clock latency, not in the library."""
+    gc.collect()
+    gc.disable()
+    try:
+        yield
+    finally:
+        gc.enable()
 
 
 def make_instance(name: str):
@@ -126,13 +141,14 @@ def bench_batch(args):
     N.nnls_reset_profile(h)
     torch.cuda.synchronize()
     lat = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s0 = time.perf_counter()
-        infos = step(popts)
-        lat.append((time.perf_counter() - s0) * 1e3)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
+    with no_gc():
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            s0 = time.perf_counter()
+            infos = step(popts)
+            lat.append((time.perf_counter() - s0) * 1e3)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
     prof = N.nnls_get_profile(h)["batched"]
     # accuracy against the planted solutions and the free sets
     errs, match = [], 0
@@ -262,6 +278,8 @@ def bench_serve(args):
                 first[i % len(pool)] = x
 
     col = threading.Thread(target=collector)
+    gc.collect()
+    gc.disable()   # as in no_gc(): a collection pause would land in request latencies
     col.start()
     start = time.perf_counter()
     timed_start = None
@@ -288,6 +306,7 @@ def bench_serve(args):
     ev = threading.Event()
     collect(sat_tickets, ev)
     sat_wall = time.perf_counter() - s0
+    gc.enable()
     sat = N.nnls_server_stats(srv)
     srv.close()
 
@@ -816,16 +835,17 @@ def measure_single(h, inst, arr, precision, steps, warmup, profile=True):
     N.nnls_reset_profile(h)
     torch.cuda.synchronize()
     lat, iters, ir_steps, est = [], 0, 0, []
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        s0 = time.perf_counter()
-        info = step(popts if profile else opts)
-        lat.append((time.perf_counter() - s0) * 1e3)
-        iters += info.iterations
-        ir_steps += info.ir_steps
-        est.append(info.est_rel_err)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
+    with no_gc():
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s0 = time.perf_counter()
+            info = step(popts if profile else opts)
+            lat.append((time.perf_counter() - s0) * 1e3)
+            iters += info.iterations
+            ir_steps += info.ir_steps
+            est.append(info.est_rel_err)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
     prof = N.nnls_get_profile(h)
     trace = N.nnls_get_trace(h, reused=True)
     xh, yh = arr["x"].cpu().numpy(), arr["y"].cpu().numpy()

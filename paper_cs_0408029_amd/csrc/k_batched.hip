@@ -1,13 +1,14 @@
 // Batched dense NNLS: one launch solves many independent problems; each workgroup owns
 // one problem and runs its whole block principal pivoting loop (Sec. 2 algorithm box of
 // the tsnnls paper) on the device, with no host round trip per iteration:
-//   Gram H = A^T A and c = A^T b (Sec. 3, Sec. 2.1), then per iteration the classify /
+//   one pass over A for c = A^T b and the finiteness check, the Gram matrix H = A^T A
+//   (Sec. 3, Sec. 2.1) streamed through LDS on MFMA, then per iteration the classify /
 //   count / exchange step, the left-looking tiled Cholesky of H_FF on MFMA (one tile after
 //   another inside the workgroup, with the same in-LDS diagonal factor as the large-problem
 //   kernel), the two triangular solves, r = A_F x_F - b and y_G = A_G^T r (Eq. 5).
-// The factor is float64, or float32 followed by float64 refinement of x_F against the
-// residual from A.  A problem's arithmetic never depends on the other problems in the
-// launch, so every result is the same alone or in any batch.
+// The factor is float64, or float32 (from a float32 Gram matrix) followed by float64
+// refinement of x_F against the residual from A.  A problem's arithmetic never depends on
+// the other problems in the launch, so every result is the same alone or in any batch.
 #include <climits>
 
 #include "tile_ops.h"
@@ -69,11 +70,11 @@ __device__ inline double wg_min(double v, double* red) {
 }
 
 // ------------------------------------------------------------ Gram matrix
-// H = A^T A (full symmetric, column-major n x n) and c = A^T b.  Lower 64 x 64 tiles on
-// MFMA float64; rows of A are staged in LDS 64 at a time (both column blocks of the tile),
-// so every H_ij is summed over rows in a fixed order.
-__device__ __noinline__ void wg_gram(const double* __restrict__ A, int lda, int m, int n, const double* __restrict__ b,
-                        double* __restrict__ H, double* __restrict__ c, double* Sa, double* Sb) {
+// H = A^T A (full symmetric, column-major n x n) for n > GS_MAXN: lower 64 x 64 tiles on
+// MFMA float64, one tile at a time; rows of A are staged in LDS 64 at a time (both column
+// blocks of the tile), so every H_ij is summed over rows in a fixed order.
+__device__ __noinline__ void wg_gram(const double* __restrict__ A, int lda, int m, int n,
+                                     double* __restrict__ H, double* Sa, double* Sb) {
   typedef MF<double> M;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int qr = (w & 1) * 32, qc = (w >> 1) * 32, lr = lane & 15, lk = lane >> 4;
@@ -120,13 +121,161 @@ __device__ __noinline__ void wg_gram(const double* __restrict__ A, int lda, int 
             }
           }
     }
-  // c_j = a_j^T b: one wave per column, lane-stride partials and a fixed tree
-  for (int j = w; j < n; j += 4) {
-    const double* col = A + (int64_t)j * lda;
-    double s = 0.0;
-    for (int q = lane; q < m; q += 64) s = fma(col[q], b[q], s);
-    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
-    if (lane == 0) c[j] = s;
+  __syncthreads();
+}
+
+// Problem data arrive through descriptors in memory, so the compiler cannot tell that
+// their pointers are global: say so, so the loads are global loads (a flat load also
+// counts as an LDS access, and every LDS wait would then wait for it too).
+typedef const __attribute__((address_space(1))) double* gcdp;
+__device__ inline gcdp gl(const double* p) { return (gcdp)p; }
+
+// H = A^T A for n <= GS_MAXN, in T (float64, or float32 from float32-rounded A), streamed:
+// 16 rows of every column are staged in LDS per step (double-buffered, the next rows in
+// registers while the MFMA work on the current ones runs).  H is cut into 32 x 32
+// rectangles on and below the diagonal; each wave keeps Q of them (2 x 2 MFMA blocks each,
+// four products per four LDS reads) in its accumulators for a whole pass over the rows.
+// When the rectangles exceed 4 QMAX the rows are streamed again for the rest (spread
+// evenly over the passes).  Every H_ij is summed over rows in a fixed order.  The code is
+// specialised on NR = ceil(n / 32), so that every loop has a fixed trip count.
+constexpr int GS_MAXN = 256;
+constexpr int GS_KR = 16;                   // rows per step
+constexpr int GS_CSTEP = BT / GS_KR;        // columns moved per thread step
+template <typename T> struct GS;
+template <> struct GS<double> { static constexpr int QMAX = 7; };
+template <> struct GS<float> { static constexpr int QMAX = 12; };
+template <typename T, int NR> struct GSPlan {
+  static constexpr int nrect = NR * (NR + 1) / 2;
+  static constexpr int passes = (nrect + 4 * GS<T>::QMAX - 1) / (4 * GS<T>::QMAX);
+  static constexpr int per = (nrect + passes - 1) / passes;   // rectangles per pass
+  static constexpr int Q = (per + 3) / 4;                     // per wave
+  static constexpr int EPT = 32 * NR / GS_CSTEP;              // staged values per thread
+};
+// LDS row stride (elements) of the staged rows: 16 columns of one row group start half a
+// bank cycle apart from the next group's for 8-byte reads, a quarter for 4-byte reads
+template <typename T> __host__ __device__ constexpr int gs_stride(int npad) {
+  return sizeof(T) == 8 ? npad + ((16 - npad % 32) + 32) % 32 : npad + ((16 - npad % 64) + 64) % 64;
+}
+constexpr size_t GS_LDS_BYTES = 2 * GS_KR * (size_t)gs_stride<double>(GS_MAXN) * 8;
+
+// One pass: wave w accumulates the rectangles t0 + w + 4 q (q < Q) below tend; slots past
+// tend compute on rectangle (0, 0) and are not stored, so the MFMA sequence has no
+// branches.  Staged values past m or n are read clamped into A and multiplied by zero (A
+// is finite here), so the loads have no branches either.
+template <typename T, int NR>
+__device__ __noinline__ void gram_pass(const double* __restrict__ A, int lda, int m, int n, T* __restrict__ H,
+                                       T* St, int t0, int tend) {
+  typedef MF<T> M;
+  typedef typename M::acc Acc;
+  typedef GSPlan<T, NR> PL;
+  constexpr int KR = GS_KR, CSTEP = GS_CSTEP, EPT = PL::EPT, Q = PL::Q;
+  constexpr int npad = 32 * NR, SR = gs_stride<T>(npad);
+  const int tid = threadIdx.x, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nch = (m + KR - 1) / KR;
+  int ra[Q], rb[Q];   // first row and column of slot q's rectangle
+  bool on[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    int t = t0 + w + 4 * q, c = 0;
+    on[q] = t < tend;
+    if (!on[q]) t = 0;
+    while (t >= NR - c) {   // rectangles column by column: column c holds rows c .. NR-1
+      t -= NR - c;
+      ++c;
+    }
+    ra[q] = (c + t) * 32;
+    rb[q] = c * 32;
+  }
+  Acc acc[Q][2][2];
+#pragma unroll
+  for (int q = 0; q < Q; ++q)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[q][bi][bj][v] = (T)0;
+  // staging: thread tid moves row srow of columns scol + CSTEP u
+  const int srow = tid % KR, scol = tid / KR;
+  const gcdp Ag = gl(A);
+  double pre[EPT];   // raw loads: nothing waits for them before the next step's stores
+  auto fetch = [&](int ch) __attribute__((always_inline)) {
+    const gcdp src = Ag + min(ch * KR + srow, m - 1);
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) pre[u] = src[(int64_t)min(scol + CSTEP * u, n - 1) * lda];
+  };
+  fetch(0);
+  for (int ch = 0; ch < nch; ++ch) {
+    T* B = St + (ch & 1) * (KR * SR);
+    T* dst = B + srow * SR + scol;
+    const bool rin = ch * KR + srow < m;
+#pragma unroll
+    for (int u = 0; u < EPT; ++u)
+      dst[CSTEP * u] = (T)(pre[u] * ((rin && scol + CSTEP * u < n) ? 1.0 : 0.0));
+    __syncthreads();   // also: every wave is done with the buffer written next step
+    if (ch + 1 < nch) fetch(ch + 1);
+    // (k step, rectangle) pairs in order, the operands of the next pair read from LDS
+    // while the four products of the current one run
+    const T* rowp = B + lk * SR + lr;
+    T op[2][4];
+    constexpr int NS = (KR / 4) * Q;
+    auto ld = [&](int st, T* o) __attribute__((always_inline)) {
+      const T* pr = rowp + (st / Q) * 4 * SR;
+      const int q = st % Q;
+      o[0] = pr[ra[q]];
+      o[1] = pr[ra[q] + 16];
+      o[2] = pr[rb[q]];
+      o[3] = pr[rb[q] + 16];
+    };
+    ld(0, op[0]);
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+      if (st + 1 < NS) ld(st + 1, op[(st + 1) & 1]);
+      const int q = st % Q;
+      const T* o = op[st & 1];
+      acc[q][0][0] = M::op(o[0], o[2], acc[q][0][0]);
+      acc[q][0][1] = M::op(o[0], o[3], acc[q][0][1]);
+      acc[q][1][0] = M::op(o[1], o[2], acc[q][1][0]);
+      acc[q][1][1] = M::op(o[1], o[3], acc[q][1][1]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < Q; ++q)
+    if (on[q])
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = ra[q] + 16 * bi + M::row(lane, v), j = rb[q] + 16 * bj + lr;
+            // on the diagonal only the lower half is stored, so each entry has one writer
+            if (i < n && j < n && (ra[q] != rb[q] || i >= j)) {
+              H[i + (int64_t)j * n] = acc[q][bi][bj][v];
+              H[j + (int64_t)i * n] = acc[q][bi][bj][v];
+            }
+          }
+}
+
+template <typename T, int NR>
+__device__ inline void gram_passes(const double* A, int lda, int m, int n, T* H, T* St) {
+  typedef GSPlan<T, NR> PL;
+  for (int t0 = 0; t0 < PL::nrect; t0 += PL::per) gram_pass<T, NR>(A, lda, m, n, H, St, t0, min(PL::nrect, t0 + PL::per));
+}
+
+template <typename T>
+__device__ void wg_gram_stream(const double* A, int lda, int m, int n, T* H, T* St) {
+  switch ((n + 31) >> 5) {
+    case 1: gram_passes<T, 1>(A, lda, m, n, H, St); break;
+    case 2: gram_passes<T, 2>(A, lda, m, n, H, St); break;
+    case 3: gram_passes<T, 3>(A, lda, m, n, H, St); break;
+    case 4: gram_passes<T, 4>(A, lda, m, n, H, St); break;
+    case 5: gram_passes<T, 5>(A, lda, m, n, H, St); break;
+    case 6: gram_passes<T, 6>(A, lda, m, n, H, St); break;
+    case 7: gram_passes<T, 7>(A, lda, m, n, H, St); break;
+    default: gram_passes<T, 8>(A, lda, m, n, H, St); break;
   }
   __syncthreads();
 }
@@ -138,10 +287,11 @@ __device__ __noinline__ void diag_tile(T* S, T* W, PivotReport rep) {
   factor_invert_tile<T>(S, W, rep);
 }
 
-// Left-looking tiled Cholesky of H_FF inside one workgroup (tiles one after another).
-// Tiles (column-major packed) and inverted diagonal tiles go to the problem's workspace.
-template <typename T>
-__device__ __noinline__ void wg_factor(const double* __restrict__ H, int n, const int32_t* __restrict__ Flist, int nF,
+// Left-looking tiled Cholesky of H_FF inside one workgroup (tiles one after another), from
+// a Gram matrix held in TH.  Tiles (column-major packed) and inverted diagonal tiles go to
+// the problem's workspace.
+template <typename T, typename TH>
+__device__ __noinline__ void wg_factor(const TH* __restrict__ H, int n, const int32_t* __restrict__ Flist, int nF,
                           T* Lt, T* Dv, T* S, T* W, const PivotReport& rep0) {
   typedef MF<T> M;
   typedef typename M::acc Acc;
@@ -155,9 +305,9 @@ __device__ __noinline__ void wg_factor(const double* __restrict__ H, int n, cons
       for (int e = tid; e < TILE_ELEMS; e += BT) {
         const int rr = e & (TILE - 1), cc = e >> 6;
         const int p = I * TILE + rr, q = J * TILE + cc;
-        double v = (p == q) ? 1.0 : 0.0;
-        if (p < nF && q < nF) v = H[Flist[p] + (int64_t)Flist[q] * n];
-        S[rr + cc * LDT] = (T)v;
+        T v = (p == q) ? (T)1 : (T)0;
+        if (p < nF && q < nF) v = (T)H[Flist[p] + (int64_t)Flist[q] * n];
+        S[rr + cc * LDT] = v;
       }
       __syncthreads();
       Acc acc[2][2];
@@ -303,50 +453,171 @@ __device__ __noinline__ void wg_solve(const T* Lt, const T* Dv, int nF, const do
   }
 }
 
-// r = A x - b over the free columns (ascending), then y_j = a_j^T r on G and, with g,
-// g_p = a_{F[p]}^T r on F.
-__device__ __noinline__ void wg_residual_dual(const double* __restrict__ A, int lda, int m, int n, const double* __restrict__ b,
-                                 const uint8_t* flags, const int32_t* Flist, int nF, const double* x,
-                                 double* r, double* y, double* g) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int i = tid; i < m; i += BT) {
-    double s = 0.0;
-    for (int p = 0; p < nF; ++p) {
-      const int j = Flist[p];
-      s = fma(A[i + (int64_t)j * lda], x[j], s);
+// r = A_F x_F - b: thread t owns rows t + BT u (u < U); the free columns (ascending) and
+// their x values are staged in LDS in chunks of CH, and K columns are loaded per step, so
+// U K loads are in flight per thread.  Each r_i is summed over F positions in order.
+constexpr int CH = 2048;
+template <int U, int K>
+__device__ __noinline__ void wg_resid_rows(const double* __restrict__ A, int lda, int m, const double* __restrict__ b,
+                                           const int32_t* Flist, int nF, const double* x, double* r,
+                                           int32_t* sF, double* sX) {
+  const int tid = threadIdx.x;
+  for (int i0 = 0; i0 < m; i0 += BT * U) {
+    double acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = 0.0;
+    int rows[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) rows[u] = min(i0 + tid + BT * u, m - 1);   // in bounds; unused past m
+    for (int p0 = 0; p0 < nF; p0 += CH) {
+      const int cnt = min(CH, nF - p0);
+      __syncthreads();
+      for (int q = tid; q < cnt; q += BT) {
+        const int j = Flist[p0 + q];
+        sF[q] = j;
+        sX[q] = x[j];
+      }
+      __syncthreads();
+      int p = 0;
+      for (; p + K <= cnt; p += K) {
+        double v[K][U];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const double* col = A + (int64_t)sF[p + k] * lda;
+#pragma unroll
+          for (int u = 0; u < U; ++u) v[k][u] = col[rows[u]];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const double xv = sX[p + k];
+#pragma unroll
+          for (int u = 0; u < U; ++u) acc[u] = fma(v[k][u], xv, acc[u]);
+        }
+      }
+      for (; p < cnt; ++p) {
+        const double* col = A + (int64_t)sF[p] * lda;
+        const double xv = sX[p];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] = fma(col[rows[u]], xv, acc[u]);
+      }
     }
-    r[i] = s - b[i];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + tid + BT * u;
+      if (i < m) r[i] = acc[u] - b[i];
+    }
   }
   __syncthreads();
-  for (int j = w; j < n; j += 4) {
-    const bool f = flags[j] != 0;
-    if (f && !g) {
-      if (lane == 0) y[j] = 0.0;
+}
+
+__device__ inline void wg_resid(const double* A, int lda, int m, const double* b, const int32_t* Flist, int nF,
+                                const double* x, double* r, int32_t* sF, double* sX) {
+  if (m <= BT) wg_resid_rows<1, 16>(A, lda, m, b, Flist, nF, x, r, sF, sX);
+  else if (m <= 2 * BT) wg_resid_rows<2, 8>(A, lda, m, b, Flist, nF, x, r, sF, sX);
+  else wg_resid_rows<4, 4>(A, lda, m, b, Flist, nF, x, r, sF, sX);
+}
+
+// Column dot products a_j^T v, one wave per column, for:
+//   ATR_ALL  every column j: out[j]; also reports (return value 1) a non-finite entry of A
+//            or of v (the input check, with v = b)
+//   ATR_DUAL out[j] for j not free (y_G), 0 for free j (y_F = 0)
+//   ATR_FREE out[p] for the free column at position p (p < nF)
+// Lane l takes rows l + 64 t: with m <= 64 RQ the lane's entries of v sit in registers and
+// all RQ loads of a column are in flight at once; longer columns loop over rows.  Each dot
+// product is summed in a fixed order (four interleaved partial sums, then a fixed tree).
+enum { ATR_ALL = 0, ATR_DUAL = 1, ATR_FREE = 2 };
+
+__device__ inline double wave_tree(double s) {
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+  return s;
+}
+
+template <int RQ>
+__device__ __noinline__ int wg_atr_reg(const double* __restrict__ A, int lda, int m, int n, const double* v,
+                                       const uint8_t* flags, const int32_t* Flist, int nF, double* out, int mode) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double vr[RQ];
+  int rows[RQ];
+  bool bad = false;
+#pragma unroll
+  for (int t = 0; t < RQ; ++t) {
+    const int q = lane + 64 * t;
+    rows[t] = min(q, m - 1);
+    vr[t] = q < m ? v[q] : 0.0;
+    if (mode == ATR_ALL && !isfinite(vr[t])) bad = true;
+  }
+  const int cnt = mode == ATR_FREE ? nF : n;
+  for (int k = w; k < cnt; k += BT / 64) {
+    const int j = mode == ATR_FREE ? Flist[k] : k;
+    if (mode == ATR_DUAL && flags[j]) {
+      if (lane == 0) out[j] = 0.0;
       continue;
     }
     const double* col = A + (int64_t)j * lda;
-    double s = 0.0;
-    for (int q = lane; q < m; q += 64) s = fma(col[q], r[q], s);
-    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
-    if (lane == 0) y[j] = f ? 0.0 : s;
-  }
-  if (g) {
-    __syncthreads();
-    for (int p = tid; p < nF; p += BT) {
-      // g is indexed by position: recompute from the column (cheap next to the sweep above)
-      const int j = Flist[p];
-      const double* col = A + (int64_t)j * lda;
-      double s0 = 0.0, s1 = 0.0;
-      int q = 0;
-      for (; q + 1 < m; q += 2) {
-        s0 = fma(col[q], r[q], s0);
-        s1 = fma(col[q + 1], r[q + 1], s1);
-      }
-      if (q < m) s0 = fma(col[q], r[q], s0);
-      g[p] = s0 + s1;
+    double a[RQ];
+#pragma unroll
+    for (int t = 0; t < RQ; ++t) a[t] = col[rows[t]];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < RQ; ++t) {
+      if (mode == ATR_ALL && !isfinite(a[t])) bad = true;
+      s[t & 3] = fma(a[t], vr[t], s[t & 3]);   // vr = 0 past m
     }
+    const double tot = wave_tree((s[0] + s[1]) + (s[2] + s[3]));
+    if (lane == 0) out[mode == ATR_FREE ? k : j] = tot;
   }
   __syncthreads();
+  return bad ? 1 : 0;
+}
+
+__device__ __noinline__ int wg_atr_loop(const double* __restrict__ A, int lda, int m, int n, const double* v,
+                                        const uint8_t* flags, const int32_t* Flist, int nF, double* out, int mode) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  bool bad = false;
+  if (mode == ATR_ALL)
+    for (int q = threadIdx.x; q < m; q += BT)
+      if (!isfinite(v[q])) bad = true;
+  const int cnt = mode == ATR_FREE ? nF : n;
+  for (int k = w; k < cnt; k += BT / 64) {
+    const int j = mode == ATR_FREE ? Flist[k] : k;
+    if (mode == ATR_DUAL && flags[j]) {
+      if (lane == 0) out[j] = 0.0;
+      continue;
+    }
+    const double* col = A + (int64_t)j * lda;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    int q = lane;
+    for (; q + 192 < m; q += 256) {
+      double a[4], vv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        a[t] = col[q + 64 * t];
+        vv[t] = v[q + 64 * t];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (mode == ATR_ALL && !isfinite(a[t])) bad = true;
+        s[t] = fma(a[t], vv[t], s[t]);
+      }
+    }
+    for (; q < m; q += 64) {
+      const double a = col[q];
+      if (mode == ATR_ALL && !isfinite(a)) bad = true;
+      s[0] = fma(a, v[q], s[0]);
+    }
+    const double tot = wave_tree((s[0] + s[1]) + (s[2] + s[3]));
+    if (lane == 0) out[mode == ATR_FREE ? k : j] = tot;
+  }
+  __syncthreads();
+  return bad ? 1 : 0;
+}
+
+__device__ inline int wg_atr(const double* A, int lda, int m, int n, const double* v, const uint8_t* flags,
+                             const int32_t* Flist, int nF, double* out, int mode) {
+  if (m <= 256) return wg_atr_reg<4>(A, lda, m, n, v, flags, Flist, nF, out, mode);
+  if (m <= 512) return wg_atr_reg<8>(A, lda, m, n, v, flags, Flist, nF, out, mode);
+  if (m <= 1024) return wg_atr_reg<16>(A, lda, m, n, v, flags, Flist, nF, out, mode);
+  return wg_atr_loop(A, lda, m, n, v, flags, Flist, nF, out, mode);
 }
 
 // Eq. 3 on G: y_j = sum_p H[F_p, j] x[F_p] - c_j (H symmetric: column j), y_F = 0.
@@ -371,13 +642,60 @@ __device__ __noinline__ void wg_dual_gram(const double* __restrict__ H, int n, c
   __syncthreads();
 }
 
+// First kernel of a batched solve, one workgroup per problem: c = A^T b in one pass over
+// A, which also rejects a non-finite entry of A or b (the problem's status says which),
+// then for n <= GS_MAXN the Gram matrix streamed on MFMA (float32 for the mixed path).
+// On its own, so that the Gram passes get the whole register file (one workgroup per CU)
+// while the pivoting kernel keeps two per CU.
+__global__ __launch_bounds__(BT, 1) void k_batched_gram(BatchArgs a) {
+  __shared__ __attribute__((aligned(16))) char smem[GS_LDS_BYTES];
+  __shared__ double red[8];
+  const int tid = threadIdx.x;
+  const int pi = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
+  if (pi >= a.count) return;
+  const BatchProblem P = a.probs[pi];
+  const int m = P.m, n = P.n;
+  const WsLayout Lw = ws_layout(m, n);
+  char* base = a.ws + P.ws;
+  BatchInfo* info = a.info + pi;
+  const int bad = wg_atr(P.A, P.lda, m, n, P.b, nullptr, nullptr, 0, (double*)(base + Lw.c), ATR_ALL);
+  if (wg_max((double)bad, red) > 0.0) {
+    if (tid == 0) {   // every field: the status array may hold an earlier launch's values
+      info->status = NNLS_ERR_INVALID_VALUE;
+      info->iterations = 0;
+      info->n_free = 0;
+      info->last_ninf = 0;
+      info->failed_index = -1;
+      info->ir_steps = 0;
+      info->min_margin = 0.0;
+    }
+    return;
+  }
+  if (n <= GS_MAXN) {
+    if (a.fp32) wg_gram_stream<float>(P.A, P.lda, m, n, (float*)(base + Lw.H), (float*)smem);
+    else wg_gram_stream<double>(P.A, P.lda, m, n, (double*)(base + Lw.H), (double*)smem);
+  }
+  if (tid == 0) {
+    info->status = 0;
+    info->failed_index = INT32_MAX;
+    info->ir_steps = 0;
+  }
+}
+
+constexpr size_t SMEM_BYTES = GS_LDS_BYTES > 2 * TILE * LDT * 8 ? GS_LDS_BYTES : 2 * TILE * LDT * 8;
+
 __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
-  __shared__ double S64[TILE * LDT];
-  __shared__ double W64[TILE * LDT];
+  // staged rows of the streamed Gram matrix, or two staged 64 x 64 tiles, or the staged F
+  // columns and x values of the residual
+  __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];
   __shared__ double red[8];
   __shared__ double part[4 * TILE];
   __shared__ double vec[TILE];
   __shared__ int s_int[8];
+  double* S64 = (double*)smem;
+  double* W64 = S64 + TILE * LDT;
+  int32_t* sF = (int32_t*)W64;
+  double* sX = S64;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int pi = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
   if (pi >= a.count) return;
@@ -399,37 +717,15 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
   int32_t* status = &info->status;
   int32_t* failed_pos = &info->failed_index;
 
-  // validation: non-finite A or b
-  double bad = 0.0;
-  for (int64_t e = tid; e < (int64_t)m * n; e += BT) {
-    const int64_t j = e / m, i = e - j * m;
-    if (!isfinite(P.A[i + j * P.lda])) bad = 1.0;
-  }
-  for (int i = tid; i < m; i += BT)
-    if (!isfinite(P.b[i])) bad = 1.0;
-  if (wg_max(bad, red) > 0.0) {
-    if (tid == 0) {   // every field: the status array may hold an earlier launch's values
-      info->status = NNLS_ERR_INVALID_VALUE;
-      info->iterations = 0;
-      info->n_free = 0;
-      info->last_ninf = 0;
-      info->failed_index = -1;
-      info->ir_steps = 0;
-      info->min_margin = 0.0;
-    }
-    return;
-  }
-
-  wg_gram(P.A, P.lda, m, n, P.b, H, c, S64, W64);
+  // k_batched_gram has computed c and, for n <= GS_MAXN, the Gram matrix (float32 for
+  // the mixed path), or rejected the problem
+  if (*status != 0) return;
+  bool h64 = !(a.fp32 && n <= GS_MAXN);
+  if (n > GS_MAXN) wg_gram(P.A, P.lda, m, n, H, S64, W64);
   for (int i = tid; i < n; i += BT) {
     x[i] = 0.0;
     y[i] = -c[i];
     flags[i] = 0;
-  }
-  if (tid == 0) {
-    info->status = 0;
-    info->failed_index = INT32_MAX;
-    info->ir_steps = 0;
   }
   __syncthreads();
 
@@ -512,12 +808,19 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
       const PivotReport rep = {0, nF, failed_pos, status};
       bool use32 = a.fp32 != 0;
       for (int attempt = 0; attempt < 2 && !y_done; ++attempt) {
-        if (use32) {
-          wg_factor<float>(H, n, Flist, nF, (float*)(base + Lw.Lt), (float*)(base + Lw.Dv),
-                           (float*)S64, (float*)W64, rep);
-        } else {
-          wg_factor<double>(H, n, Flist, nF, (double*)(base + Lw.Lt), (double*)(base + Lw.Dv), S64, W64, rep);
+        if (!use32 && !h64) {   // float64 factor after a float32 failure: float64 Gram first
+          wg_gram(P.A, P.lda, m, n, H, S64, W64);
+          h64 = true;
         }
+        if (use32 && h64)
+          wg_factor<float, double>(H, n, Flist, nF, (float*)(base + Lw.Lt), (float*)(base + Lw.Dv),
+                                   (float*)S64, (float*)W64, rep);
+        else if (use32)
+          wg_factor<float, float>((const float*)H, n, Flist, nF, (float*)(base + Lw.Lt), (float*)(base + Lw.Dv),
+                                  (float*)S64, (float*)W64, rep);
+        else
+          wg_factor<double, double>(H, n, Flist, nF, (double*)(base + Lw.Lt), (double*)(base + Lw.Dv), S64, W64,
+                                    rep);
         __syncthreads();
         if (use32 && *status == NNLS_ERR_NOT_PD) {   // float32 breakdown: float64 instead
           __syncthreads();
@@ -540,16 +843,13 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
         for (int q = tid; q < nF; q += BT) x[Flist[q]] = xF[q];
         __syncthreads();
         if (!use32) break;
-        // float64 refinement of x_F against the residual from A
+        // float64 refinement of x_F against the residual from A: r = A_F x_F - b and
+        // g = A_F^T r over the free columns only, the correction from the float32 factor
         bool converged = false;
         double prev = INFINITY;
-        for (int step = 0;; ++step) {
-          wg_residual_dual(P.A, P.lda, m, n, P.b, flags, Flist, nF, x, r, y, gpos);
-          if (converged) {
-            y_done = true;
-            break;
-          }
-          if (step >= a.ir_max_steps) break;
+        for (int step = 0; step < a.ir_max_steps; ++step) {
+          wg_resid(P.A, P.lda, m, P.b, Flist, nF, x, r, sF, sX);
+          wg_atr(P.A, P.lda, m, n, r, flags, Flist, nF, gpos, ATR_FREE);
           wg_solve<float>((float*)(base + Lw.Lt), (float*)(base + Lw.Dv), nF, gpos, z, xF, part, vec);
           double dm = 0.0, xm = 0.0;
           for (int q = tid; q < nF; q += BT) {
@@ -567,11 +867,20 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
           // as in the single-problem path: while the corrections contract by 1/2 or better,
           // the last one bounds the error left; stop once it is below the target
           const double rho = dm / prev;   // 0 on the first step
-          if (dm <= a.ir_rtol * xm) converged = true;
-          else if (rho > 0.5) break;
+          if (dm <= a.ir_rtol * xm) {
+            converged = true;
+            break;
+          }
+          if (rho > 0.5) break;
           prev = dm;
         }
-        if (!y_done) use32 = false;   // not refined to the target: redo in float64
+        if (converged) {   // y_G from the refined x (Eq. 5)
+          wg_resid(P.A, P.lda, m, P.b, Flist, nF, x, r, sF, sX);
+          wg_atr(P.A, P.lda, m, n, r, flags, Flist, nF, y, ATR_DUAL);
+          y_done = true;
+        } else {
+          use32 = false;   // not refined to the target: redo in float64
+        }
       }
       __syncthreads();
       if (*status != 0) {
@@ -580,8 +889,12 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
       }
     }
     if (!y_done) {
-      if (a.gram_dual) wg_dual_gram(H, n, c, flags, Flist, nF, x, y);
-      else wg_residual_dual(P.A, P.lda, m, n, P.b, flags, Flist, nF, x, r, y, nullptr);
+      if (a.gram_dual) {   // H is float64 here: the mixed path reaches this only after a float64 factor
+        wg_dual_gram(H, n, c, flags, Flist, nF, x, y);
+      } else {
+        wg_resid(P.A, P.lda, m, P.b, Flist, nF, x, r, sF, sX);
+        wg_atr(P.A, P.lda, m, n, r, flags, Flist, nF, y, ATR_DUAL);
+      }
     }
   }
   __syncthreads();
@@ -607,6 +920,7 @@ size_t batched_workspace_bytes(int m, int n) { return ws_layout(m, n).total; }
 
 void launch_batched(hipStream_t s, const BatchArgs& a, int grid) {
   if (grid <= 0) return;
+  hipLaunchKernelGGL(k_batched_gram, dim3(grid), dim3(BT), 0, s, a);
   hipLaunchKernelGGL(k_batched, dim3(grid), dim3(BT), 0, s, a);
 }
 
