@@ -130,25 +130,29 @@ __device__ __noinline__ void wg_gram(const double* __restrict__ A, int lda, int 
 typedef const __attribute__((address_space(1))) double* gcdp;
 __device__ inline gcdp gl(const double* p) { return (gcdp)p; }
 
-// H = A^T A for n <= GS_MAXN, in T (float64, or float32 from float32-rounded A), streamed:
-// 16 rows of every column are staged in LDS per step (double-buffered, the next rows in
-// registers while the MFMA work on the current ones runs).  H is cut into 32 x 32
-// rectangles on and below the diagonal; each wave keeps Q of them (2 x 2 MFMA blocks each,
-// four products per four LDS reads) in its accumulators for a whole pass over the rows.
-// When the rectangles exceed 4 QMAX the rows are streamed again for the rest (spread
-// evenly over the passes).  Every H_ij is summed over rows in a fixed order.  The code is
-// specialised on NR = ceil(n / 32), so that every loop has a fixed trip count.
+// H = A^T A for n <= GS_MAXN, in T (float64, or float32 from float32-rounded A), streamed
+// by a workgroup of GT threads (eight waves, two per SIMD): 16 rows of every column are
+// staged in LDS per step (double-buffered, the next rows in registers while the MFMA work
+// on the current ones runs).  H is cut into 32 x 32 rectangles on and below the diagonal;
+// each wave keeps Q of them (2 x 2 MFMA blocks each, four products per four LDS reads) in
+// its accumulators for a whole pass over the rows.  When the rectangles exceed 8 QMAX the
+// rows are streamed again for the rest (spread evenly over the passes).  The first pass
+// also forms c = A^T b in float64 from the staged values (each thread's rows, then a fixed
+// tree over the 16 threads of a column) and checks every entry of A and b for finiteness.
+// Every H_ij and c_j is summed over rows in a fixed order.  The code is specialised on
+// NR = ceil(n / 32), so that every loop has a fixed trip count.
+constexpr int GT = 512;                     // threads of the Gram workgroup
 constexpr int GS_MAXN = 256;
 constexpr int GS_KR = 16;                   // rows per step
-constexpr int GS_CSTEP = BT / GS_KR;        // columns moved per thread step
+constexpr int GS_CSTEP = GT / GS_KR;        // columns moved per thread step
 template <typename T> struct GS;
-template <> struct GS<double> { static constexpr int QMAX = 7; };
-template <> struct GS<float> { static constexpr int QMAX = 12; };
+template <> struct GS<double> { static constexpr int QMAX = 3; };
+template <> struct GS<float> { static constexpr int QMAX = 6; };
 template <typename T, int NR> struct GSPlan {
   static constexpr int nrect = NR * (NR + 1) / 2;
-  static constexpr int passes = (nrect + 4 * GS<T>::QMAX - 1) / (4 * GS<T>::QMAX);
+  static constexpr int passes = (nrect + 8 * GS<T>::QMAX - 1) / (8 * GS<T>::QMAX);
   static constexpr int per = (nrect + passes - 1) / passes;   // rectangles per pass
-  static constexpr int Q = (per + 3) / 4;                     // per wave
+  static constexpr int Q = (per + 7) / 8;                     // per wave
   static constexpr int EPT = 32 * NR / GS_CSTEP;              // staged values per thread
 };
 // LDS row stride (elements) of the staged rows: 16 columns of one row group start half a
@@ -158,34 +162,38 @@ template <typename T> __host__ __device__ constexpr int gs_stride(int npad) {
 }
 constexpr size_t GS_LDS_BYTES = 2 * GS_KR * (size_t)gs_stride<double>(GS_MAXN) * 8;
 
-// One pass: wave w accumulates the rectangles t0 + w + 4 q (q < Q) below tend; slots past
+// One pass: wave w accumulates the rectangles t0 + w + 8 q (q < Q) below tend; slots past
 // tend compute on rectangle (0, 0) and are not stored, so the MFMA sequence has no
-// branches.  Staged values past m or n are read clamped into A and multiplied by zero (A
-// is finite here), so the loads have no branches either.
+// branches.  Staged values past m or n are read clamped into A and multiplied by zero, so
+// the loads have no branches either.  Returns nonzero when the first pass met a value of
+// A or b that is not finite (H and c are then not meaningful).
 template <typename T, int NR>
-__device__ __noinline__ void gram_pass(const double* __restrict__ A, int lda, int m, int n, T* __restrict__ H,
-                                       T* St, int t0, int tend) {
+__device__ __noinline__ int gram_pass(const double* __restrict__ A, int lda, int m, int n,
+                                      const double* __restrict__ b, T* __restrict__ H, double* __restrict__ c,
+                                      T* St, int t0, int tend) {
   typedef MF<T> M;
   typedef typename M::acc Acc;
   typedef GSPlan<T, NR> PL;
   constexpr int KR = GS_KR, CSTEP = GS_CSTEP, EPT = PL::EPT, Q = PL::Q;
   constexpr int npad = 32 * NR, SR = gs_stride<T>(npad);
+  static_assert(CSTEP * EPT == npad, "staging covers the padded columns");
   const int tid = threadIdx.x, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const bool first = t0 == 0;
   const int nch = (m + KR - 1) / KR;
   int ra[Q], rb[Q];   // first row and column of slot q's rectangle
   bool on[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    int t = t0 + w + 4 * q, c = 0;
+    int t = t0 + w + 8 * q, cc = 0;
     on[q] = t < tend;
     if (!on[q]) t = 0;
-    while (t >= NR - c) {   // rectangles column by column: column c holds rows c .. NR-1
-      t -= NR - c;
-      ++c;
+    while (t >= NR - cc) {   // rectangles column by column: column cc holds rows cc .. NR-1
+      t -= NR - cc;
+      ++cc;
     }
-    ra[q] = (c + t) * 32;
-    rb[q] = c * 32;
+    ra[q] = (cc + t) * 32;
+    rb[q] = cc * 32;
   }
   Acc acc[Q][2][2];
 #pragma unroll
@@ -198,18 +206,33 @@ __device__ __noinline__ void gram_pass(const double* __restrict__ A, int lda, in
         for (int v = 0; v < 4; ++v) acc[q][bi][bj][v] = (T)0;
   // staging: thread tid moves row srow of columns scol + CSTEP u
   const int srow = tid % KR, scol = tid / KR;
-  const gcdp Ag = gl(A);
-  double pre[EPT];   // raw loads: nothing waits for them before the next step's stores
+  const gcdp Ag = gl(A), bg = gl(b);
+  double pre[EPT], bpre;   // raw loads: nothing waits for them before the next step's stores
+  double cpart[EPT];
+  bool bad = false;
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) cpart[u] = 0.0;
   auto fetch = [&](int ch) __attribute__((always_inline)) {
-    const gcdp src = Ag + min(ch * KR + srow, m - 1);
+    const int row = min(ch * KR + srow, m - 1);
+    const gcdp src = Ag + row;
 #pragma unroll
     for (int u = 0; u < EPT; ++u) pre[u] = src[(int64_t)min(scol + CSTEP * u, n - 1) * lda];
+    bpre = bg[row];
   };
   fetch(0);
   for (int ch = 0; ch < nch; ++ch) {
     T* B = St + (ch & 1) * (KR * SR);
     T* dst = B + srow * SR + scol;
     const bool rin = ch * KR + srow < m;
+    if (first) {
+      const double bv = rin ? bpre : 0.0;
+      bad |= !isfinite(bpre);
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) {
+        bad |= !isfinite(pre[u]);
+        cpart[u] = fma(pre[u], bv, cpart[u]);   // bv = 0 past m; columns past n are not stored
+      }
+    }
 #pragma unroll
     for (int u = 0; u < EPT; ++u)
       dst[CSTEP * u] = (T)(pre[u] * ((rin && scol + CSTEP * u < n) ? 1.0 : 0.0));
@@ -240,7 +263,16 @@ __device__ __noinline__ void gram_pass(const double* __restrict__ A, int lda, in
       acc[q][1][1] = M::op(o[1], o[3], acc[q][1][1]);
     }
   }
-  __syncthreads();
+  if (first) {   // c_j: the 16 threads of column j are lanes 16 g .. 16 g + 15 of one wave
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      double v = cpart[u];
+      for (int d = 1; d < 16; d <<= 1) v += __shfl_xor(v, d, 64);
+      const int col = scol + CSTEP * u;
+      if (srow == 0 && col < n) c[col] = v;
+    }
+  }
+  const int any_bad = __syncthreads_or(bad ? 1 : 0);
 #pragma unroll
   for (int q = 0; q < Q; ++q)
     if (on[q])
@@ -257,27 +289,30 @@ __device__ __noinline__ void gram_pass(const double* __restrict__ A, int lda, in
               H[j + (int64_t)i * n] = acc[q][bi][bj][v];
             }
           }
+  return any_bad;
 }
 
 template <typename T, int NR>
-__device__ inline void gram_passes(const double* A, int lda, int m, int n, T* H, T* St) {
+__device__ inline int gram_passes(const double* A, int lda, int m, int n, const double* b, T* H, double* c, T* St) {
   typedef GSPlan<T, NR> PL;
-  for (int t0 = 0; t0 < PL::nrect; t0 += PL::per) gram_pass<T, NR>(A, lda, m, n, H, St, t0, min(PL::nrect, t0 + PL::per));
+  int bad = 0;
+  for (int t0 = 0; t0 < PL::nrect && !bad; t0 += PL::per)
+    bad = gram_pass<T, NR>(A, lda, m, n, b, H, c, St, t0, min(PL::nrect, t0 + PL::per));
+  return bad;
 }
 
 template <typename T>
-__device__ void wg_gram_stream(const double* A, int lda, int m, int n, T* H, T* St) {
+__device__ int wg_gram_stream(const double* A, int lda, int m, int n, const double* b, T* H, double* c, T* St) {
   switch ((n + 31) >> 5) {
-    case 1: gram_passes<T, 1>(A, lda, m, n, H, St); break;
-    case 2: gram_passes<T, 2>(A, lda, m, n, H, St); break;
-    case 3: gram_passes<T, 3>(A, lda, m, n, H, St); break;
-    case 4: gram_passes<T, 4>(A, lda, m, n, H, St); break;
-    case 5: gram_passes<T, 5>(A, lda, m, n, H, St); break;
-    case 6: gram_passes<T, 6>(A, lda, m, n, H, St); break;
-    case 7: gram_passes<T, 7>(A, lda, m, n, H, St); break;
-    default: gram_passes<T, 8>(A, lda, m, n, H, St); break;
+    case 1: return gram_passes<T, 1>(A, lda, m, n, b, H, c, St);
+    case 2: return gram_passes<T, 2>(A, lda, m, n, b, H, c, St);
+    case 3: return gram_passes<T, 3>(A, lda, m, n, b, H, c, St);
+    case 4: return gram_passes<T, 4>(A, lda, m, n, b, H, c, St);
+    case 5: return gram_passes<T, 5>(A, lda, m, n, b, H, c, St);
+    case 6: return gram_passes<T, 6>(A, lda, m, n, b, H, c, St);
+    case 7: return gram_passes<T, 7>(A, lda, m, n, b, H, c, St);
+    default: return gram_passes<T, 8>(A, lda, m, n, b, H, c, St);
   }
-  __syncthreads();
 }
 
 // ------------------------------------------------------------ factor and solves
@@ -642,14 +677,15 @@ __device__ __noinline__ void wg_dual_gram(const double* __restrict__ H, int n, c
   __syncthreads();
 }
 
-// First kernel of a batched solve, one workgroup per problem: c = A^T b in one pass over
-// A, which also rejects a non-finite entry of A or b (the problem's status says which),
-// then for n <= GS_MAXN the Gram matrix streamed on MFMA (float32 for the mixed path).
-// On its own, so that the Gram passes get the whole register file (one workgroup per CU)
-// while the pivoting kernel keeps two per CU.
-__global__ __launch_bounds__(BT, 1) void k_batched_gram(BatchArgs a) {
+// First kernel of a batched solve, one workgroup of GT threads per problem: for
+// n <= GS_MAXN the Gram matrix streamed on MFMA (float32 for the mixed path) with
+// c = A^T b and the finiteness check of A and b in the same pass; the problem's status
+// says whether it was rejected.  Larger problems only get their status cleared here: the
+// pivoting kernel forms their c and Gram matrix itself.  On its own, so that the Gram
+// passes run eight waves per CU with their own register budget while the pivoting kernel
+// keeps two workgroups of four waves.
+__global__ __launch_bounds__(GT, 1) void k_batched_gram(BatchArgs a) {
   __shared__ __attribute__((aligned(16))) char smem[GS_LDS_BYTES];
-  __shared__ double red[8];
   const int tid = threadIdx.x;
   const int pi = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
   if (pi >= a.count) return;
@@ -658,27 +694,20 @@ __global__ __launch_bounds__(BT, 1) void k_batched_gram(BatchArgs a) {
   const WsLayout Lw = ws_layout(m, n);
   char* base = a.ws + P.ws;
   BatchInfo* info = a.info + pi;
-  const int bad = wg_atr(P.A, P.lda, m, n, P.b, nullptr, nullptr, 0, (double*)(base + Lw.c), ATR_ALL);
-  if (wg_max((double)bad, red) > 0.0) {
-    if (tid == 0) {   // every field: the status array may hold an earlier launch's values
-      info->status = NNLS_ERR_INVALID_VALUE;
-      info->iterations = 0;
-      info->n_free = 0;
-      info->last_ninf = 0;
-      info->failed_index = -1;
-      info->ir_steps = 0;
-      info->min_margin = 0.0;
-    }
-    return;
-  }
+  int bad = 0;
   if (n <= GS_MAXN) {
-    if (a.fp32) wg_gram_stream<float>(P.A, P.lda, m, n, (float*)(base + Lw.H), (float*)smem);
-    else wg_gram_stream<double>(P.A, P.lda, m, n, (double*)(base + Lw.H), (double*)smem);
+    double* c = (double*)(base + Lw.c);
+    if (a.fp32) bad = wg_gram_stream<float>(P.A, P.lda, m, n, P.b, (float*)(base + Lw.H), c, (float*)smem);
+    else bad = wg_gram_stream<double>(P.A, P.lda, m, n, P.b, (double*)(base + Lw.H), c, (double*)smem);
   }
-  if (tid == 0) {
-    info->status = 0;
-    info->failed_index = INT32_MAX;
+  if (tid == 0) {   // every field: the status array may hold an earlier launch's values
+    info->status = bad ? NNLS_ERR_INVALID_VALUE : 0;
+    info->iterations = 0;
+    info->n_free = 0;
+    info->last_ninf = 0;
+    info->failed_index = bad ? -1 : INT32_MAX;
     info->ir_steps = 0;
+    info->min_margin = 0.0;
   }
 }
 
@@ -717,11 +746,21 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
   int32_t* status = &info->status;
   int32_t* failed_pos = &info->failed_index;
 
-  // k_batched_gram has computed c and, for n <= GS_MAXN, the Gram matrix (float32 for
-  // the mixed path), or rejected the problem
+  // for n <= GS_MAXN k_batched_gram has formed c and the Gram matrix (float32 for the
+  // mixed path), or rejected the problem; larger problems do both here, the check too
   if (*status != 0) return;
   bool h64 = !(a.fp32 && n <= GS_MAXN);
-  if (n > GS_MAXN) wg_gram(P.A, P.lda, m, n, H, S64, W64);
+  if (n > GS_MAXN) {
+    const int bad = wg_atr(P.A, P.lda, m, n, P.b, nullptr, nullptr, 0, c, ATR_ALL);
+    if (wg_max((double)bad, red) > 0.0) {
+      if (tid == 0) {
+        info->status = NNLS_ERR_INVALID_VALUE;
+        info->failed_index = -1;
+      }
+      return;
+    }
+    wg_gram(P.A, P.lda, m, n, H, S64, W64);
+  }
   for (int i = tid; i < n; i += BT) {
     x[i] = 0.0;
     y[i] = -c[i];
@@ -920,7 +959,7 @@ size_t batched_workspace_bytes(int m, int n) { return ws_layout(m, n).total; }
 
 void launch_batched(hipStream_t s, const BatchArgs& a, int grid) {
   if (grid <= 0) return;
-  hipLaunchKernelGGL(k_batched_gram, dim3(grid), dim3(BT), 0, s, a);
+  hipLaunchKernelGGL(k_batched_gram, dim3(grid), dim3(GT), 0, s, a);
   hipLaunchKernelGGL(k_batched, dim3(grid), dim3(BT), 0, s, a);
 }
 

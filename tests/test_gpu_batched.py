@@ -112,6 +112,45 @@ def test_failures_stay_in_their_problem(h):
     assert relerr(xs[0], res.x) <= 1e-10
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_gram_column_groups_and_edges(h, precision):
+    """Sizes on both sides of each 32-column group of the streamed Gram matrix, m not a
+    multiple of its 16-row steps, and n past its limit (the in-kernel tiled Gram)."""
+    ns = [1, 2, 31, 32, 33, 63, 64, 65, 96, 97, 128, 129, 160, 193, 224, 225, 255, 256, 257, 300]
+    insts = [W.dense_planted(500 + k, max(n + 1, 2 * n + 7 * k % 13), n) for k, n in enumerate(ns)]
+    st, infos, xs, ys = run_batch(h, [(i.A, i.b) for i in insts], precision=precision)
+    assert st == N.NNLS_OK
+    for inst, info, x in zip(insts, infos, xs):
+        res = bpp_solve(inst.A, inst.b)
+        assert info.iterations == res.iterations
+        assert np.array_equal(x > 0, res.x > 0)
+        assert relerr(x, res.x) <= 1e-10, (inst.m, inst.n)
+
+
+@pytest.mark.parametrize("n", [40, 300])
+def test_non_finite_entries_rejected(h, n):
+    """A NaN or an infinity anywhere in A (first and last row and column) or b is reported
+    for its own problem only, on both sides of the streamed Gram matrix's size limit."""
+    good = W.dense_planted(21, 2 * n + 5, n)
+    m = good.A.shape[0]
+    cases = []
+    for (i, j, v) in [(0, 0, np.nan), (m - 1, n - 1, np.inf), (m - 1, 0, -np.inf), (0, n - 1, np.nan)]:
+        A = good.A.copy()
+        A[i, j] = v
+        cases.append((A, good.b))
+    for i in (0, m - 1):
+        b = good.b.copy()
+        b[i] = np.nan
+        cases.append((good.A, b))
+    problems = [(good.A, good.b)] + cases + [(good.A, good.b)]
+    for precision in (0, 1):
+        st, infos, xs, ys = run_batch(h, problems, precision=precision)
+        assert st == N.NNLS_ERR_INVALID_VALUE
+        assert [i.status for i in infos] == [N.NNLS_OK] + [N.NNLS_ERR_INVALID_VALUE] * len(cases) + [N.NNLS_OK]
+        assert all(i.failed_index == -1 and i.iterations == 0 for i in infos[1:-1])
+        assert np.array_equal(xs[0], xs[-1])
+
+
 def test_empty_and_invalid(h):
     st, infos, xs, ys = run_batch(h, [])
     assert st == N.NNLS_OK and infos == []
