@@ -21,7 +21,7 @@ constexpr int BT = 256;   // threads per workgroup
 
 // Workspace layout of one problem (byte offsets from its base).
 struct WsLayout {
-  size_t H, c, r, flags, Flist, Lt, Dv, z, xF, g, total;
+  size_t H, c, r, flags, Flist, Glist, Lt, Dv, z, xF, g, total;
 };
 
 __host__ __device__ inline WsLayout ws_layout(int m, int n) {
@@ -34,6 +34,7 @@ __host__ __device__ inline WsLayout ws_layout(int m, int n) {
   L.r = o;     o += ((size_t)m * 8 + 255) & ~(size_t)255;
   L.flags = o; o += ((size_t)n + 255) & ~(size_t)255;
   L.Flist = o; o += ((size_t)n * 4 + 255) & ~(size_t)255;
+  L.Glist = o; o += ((size_t)n * 4 + 255) & ~(size_t)255;
   L.Lt = o;    o += nt * TILE_ELEMS * 8;              // sized for float64 tiles
   L.Dv = o;    o += (size_t)nb * TILE_ELEMS * 8;
   L.z = o;     o += (size_t)nb * TILE * 8;
@@ -328,6 +329,7 @@ __device__ __noinline__ void diag_tile(T* S, T* W, PivotReport rep) {
 template <typename T, typename TH>
 __device__ __noinline__ void wg_factor(const TH* __restrict__ H, int n, const int32_t* __restrict__ Flist, int nF,
                           T* Lt, T* Dv, T* S, T* W, const PivotReport& rep0) {
+  __shared__ int32_t sidx[2 * TILE];
   typedef MF<T> M;
   typedef typename M::acc Acc;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -335,14 +337,30 @@ __device__ __noinline__ void wg_factor(const TH* __restrict__ H, int n, const in
   const int nb = (nF + TILE - 1) / TILE;
   for (int J = 0; J < nb; ++J)
     for (int I = J; I < nb; ++I) {
-      // gather tile (I, J) of H_FF; positions past nF are identity padding
+      // gather tile (I, J) of H_FF (positions past nF are identity padding): the tile's
+      // row and column indices staged in LDS, then every thread's 16 loads at once
       __syncthreads();
-      for (int e = tid; e < TILE_ELEMS; e += BT) {
-        const int rr = e & (TILE - 1), cc = e >> 6;
-        const int p = I * TILE + rr, q = J * TILE + cc;
-        T v = (p == q) ? (T)1 : (T)0;
-        if (p < nF && q < nF) v = (T)H[Flist[p] + (int64_t)Flist[q] * n];
-        S[rr + cc * LDT] = v;
+      if (tid < 2 * TILE) {
+        const int p = (tid < TILE ? I : J) * TILE + (tid & (TILE - 1));
+        sidx[tid] = p < nF ? Flist[p] : -1;
+      }
+      __syncthreads();
+      constexpr int GH = TILE_ELEMS / BT / 2;   // loads in flight per thread
+#pragma unroll
+      for (int k0 = 0; k0 < TILE_ELEMS / BT; k0 += GH) {
+        TH hv[GH];
+#pragma unroll
+        for (int k = 0; k < GH; ++k) {
+          const int e = tid + BT * (k0 + k), rr = e & (TILE - 1), cc = e >> 6;
+          const int fi = sidx[rr], fj = sidx[TILE + cc];
+          hv[k] = H[(fi < 0 ? 0 : fi) + (int64_t)(fj < 0 ? 0 : fj) * n];
+        }
+#pragma unroll
+        for (int k = 0; k < GH; ++k) {
+          const int e = tid + BT * (k0 + k), rr = e & (TILE - 1), cc = e >> 6;
+          const bool in = sidx[rr] >= 0 && sidx[TILE + cc] >= 0;
+          S[rr + cc * LDT] = in ? (T)hv[k] : ((I * TILE + rr == J * TILE + cc) ? (T)1 : (T)0);
+        }
       }
       __syncthreads();
       Acc acc[2][2];
@@ -547,30 +565,27 @@ __device__ __noinline__ void wg_resid_rows(const double* __restrict__ A, int lda
 
 __device__ inline void wg_resid(const double* A, int lda, int m, const double* b, const int32_t* Flist, int nF,
                                 const double* x, double* r, int32_t* sF, double* sX) {
-  if (m <= BT) wg_resid_rows<1, 16>(A, lda, m, b, Flist, nF, x, r, sF, sX);
-  else if (m <= 2 * BT) wg_resid_rows<2, 8>(A, lda, m, b, Flist, nF, x, r, sF, sX);
-  else wg_resid_rows<4, 4>(A, lda, m, b, Flist, nF, x, r, sF, sX);
+  if (m <= BT) wg_resid_rows<1, 32>(A, lda, m, b, Flist, nF, x, r, sF, sX);
+  else if (m <= 2 * BT) wg_resid_rows<2, 16>(A, lda, m, b, Flist, nF, x, r, sF, sX);
+  else wg_resid_rows<4, 8>(A, lda, m, b, Flist, nF, x, r, sF, sX);
 }
 
-// Column dot products a_j^T v, one wave per column, for:
-//   ATR_ALL  every column j: out[j]; also reports (return value 1) a non-finite entry of A
-//            or of v (the input check, with v = b)
-//   ATR_DUAL out[j] for j not free (y_G), 0 for free j (y_F = 0)
-//   ATR_FREE out[p] for the free column at position p (p < nF)
-// Lane l takes rows l + 64 t: with m <= 64 RQ the lane's entries of v sit in registers and
-// all RQ loads of a column are in flight at once; longer columns loop over rows.  Each dot
-// product is summed in a fixed order (four interleaved partial sums, then a fixed tree).
-enum { ATR_ALL = 0, ATR_DUAL = 1, ATR_FREE = 2 };
-
+// Column dot products out_k = a_j^T v over a list of columns j = list[k] (k < cnt; the
+// identity when list is null), one wave per CW columns at a time: lane l takes rows
+// l + 64 t, and with m <= 64 RQ the lane's entries of v sit in registers and all RQ CW
+// loads of a group are in flight at once; longer columns loop over rows.  With check, a
+// non-finite entry of A or v is reported (return value 1).  Each dot product is summed
+// in a fixed order (four interleaved partial sums, then a fixed tree).
 __device__ inline double wave_tree(double s) {
   for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
   return s;
 }
 
-template <int RQ>
-__device__ __noinline__ int wg_atr_reg(const double* __restrict__ A, int lda, int m, int n, const double* v,
-                                       const uint8_t* flags, const int32_t* Flist, int nF, double* out, int mode) {
+template <int RQ, int CW>
+__device__ __noinline__ int wg_atr_reg(const double* __restrict__ A, int lda, int m, const double* v,
+                                       const int32_t* list, int cnt, double* out, bool check) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const gcdp Ag = gl(A);
   double vr[RQ];
   int rows[RQ];
   bool bad = false;
@@ -579,47 +594,47 @@ __device__ __noinline__ int wg_atr_reg(const double* __restrict__ A, int lda, in
     const int q = lane + 64 * t;
     rows[t] = min(q, m - 1);
     vr[t] = q < m ? v[q] : 0.0;
-    if (mode == ATR_ALL && !isfinite(vr[t])) bad = true;
+    if (check && !isfinite(vr[t])) bad = true;
   }
-  const int cnt = mode == ATR_FREE ? nF : n;
-  for (int k = w; k < cnt; k += BT / 64) {
-    const int j = mode == ATR_FREE ? Flist[k] : k;
-    if (mode == ATR_DUAL && flags[j]) {
-      if (lane == 0) out[j] = 0.0;
-      continue;
-    }
-    const double* col = A + (int64_t)j * lda;
-    double a[RQ];
+  for (int k0 = w * CW; k0 < cnt; k0 += (BT / 64) * CW) {
+    int js[CW];
 #pragma unroll
-    for (int t = 0; t < RQ; ++t) a[t] = col[rows[t]];
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int t = 0; t < RQ; ++t) {
-      if (mode == ATR_ALL && !isfinite(a[t])) bad = true;
-      s[t & 3] = fma(a[t], vr[t], s[t & 3]);   // vr = 0 past m
+    for (int c = 0; c < CW; ++c) {
+      const int k = min(k0 + c, cnt - 1);   // past cnt: a repeat of the last column, not stored
+      js[c] = list ? list[k] : k;
     }
-    const double tot = wave_tree((s[0] + s[1]) + (s[2] + s[3]));
-    if (lane == 0) out[mode == ATR_FREE ? k : j] = tot;
+    double a[CW][RQ];
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+      const gcdp col = Ag + (int64_t)js[c] * lda;
+#pragma unroll
+      for (int t = 0; t < RQ; ++t) a[c][t] = col[rows[t]];
+    }
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+      double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < RQ; ++t) {
+        if (check && !isfinite(a[c][t])) bad = true;
+        s[t & 3] = fma(a[c][t], vr[t], s[t & 3]);   // vr = 0 past m
+      }
+      const double tot = wave_tree((s[0] + s[1]) + (s[2] + s[3]));
+      if (lane == 0 && k0 + c < cnt) out[k0 + c] = tot;
+    }
   }
   __syncthreads();
   return bad ? 1 : 0;
 }
 
-__device__ __noinline__ int wg_atr_loop(const double* __restrict__ A, int lda, int m, int n, const double* v,
-                                        const uint8_t* flags, const int32_t* Flist, int nF, double* out, int mode) {
+__device__ __noinline__ int wg_atr_loop(const double* __restrict__ A, int lda, int m, const double* v,
+                                        const int32_t* list, int cnt, double* out, bool check) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   bool bad = false;
-  if (mode == ATR_ALL)
+  if (check)
     for (int q = threadIdx.x; q < m; q += BT)
       if (!isfinite(v[q])) bad = true;
-  const int cnt = mode == ATR_FREE ? nF : n;
   for (int k = w; k < cnt; k += BT / 64) {
-    const int j = mode == ATR_FREE ? Flist[k] : k;
-    if (mode == ATR_DUAL && flags[j]) {
-      if (lane == 0) out[j] = 0.0;
-      continue;
-    }
-    const double* col = A + (int64_t)j * lda;
+    const double* col = A + (int64_t)(list ? list[k] : k) * lda;
     double s[4] = {0.0, 0.0, 0.0, 0.0};
     int q = lane;
     for (; q + 192 < m; q += 256) {
@@ -631,28 +646,39 @@ __device__ __noinline__ int wg_atr_loop(const double* __restrict__ A, int lda, i
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        if (mode == ATR_ALL && !isfinite(a[t])) bad = true;
+        if (check && !isfinite(a[t])) bad = true;
         s[t] = fma(a[t], vv[t], s[t]);
       }
     }
     for (; q < m; q += 64) {
       const double a = col[q];
-      if (mode == ATR_ALL && !isfinite(a)) bad = true;
+      if (check && !isfinite(a)) bad = true;
       s[0] = fma(a, v[q], s[0]);
     }
     const double tot = wave_tree((s[0] + s[1]) + (s[2] + s[3]));
-    if (lane == 0) out[mode == ATR_FREE ? k : j] = tot;
+    if (lane == 0) out[k] = tot;
   }
   __syncthreads();
   return bad ? 1 : 0;
 }
 
-__device__ inline int wg_atr(const double* A, int lda, int m, int n, const double* v, const uint8_t* flags,
-                             const int32_t* Flist, int nF, double* out, int mode) {
-  if (m <= 256) return wg_atr_reg<4>(A, lda, m, n, v, flags, Flist, nF, out, mode);
-  if (m <= 512) return wg_atr_reg<8>(A, lda, m, n, v, flags, Flist, nF, out, mode);
-  if (m <= 1024) return wg_atr_reg<16>(A, lda, m, n, v, flags, Flist, nF, out, mode);
-  return wg_atr_loop(A, lda, m, n, v, flags, Flist, nF, out, mode);
+__device__ inline int wg_atr(const double* A, int lda, int m, const double* v, const int32_t* list, int cnt,
+                             double* out, bool check) {
+  if (m <= 256) return wg_atr_reg<4, 8>(A, lda, m, v, list, cnt, out, check);
+  if (m <= 512) return wg_atr_reg<8, 4>(A, lda, m, v, list, cnt, out, check);
+  if (m <= 1024) return wg_atr_reg<16, 2>(A, lda, m, v, list, cnt, out, check);
+  return wg_atr_loop(A, lda, m, v, list, cnt, out, check);
+}
+
+// y_G = A_G^T r over the G list into gpos (by G position), then scattered to y; y_F = 0
+__device__ inline void wg_dual(const double* A, int lda, int m, int n, const double* r, const uint8_t* flags,
+                               const int32_t* Glist, int nF, double* gpos, double* y) {
+  const int nG = n - nF;
+  wg_atr(A, lda, m, r, Glist, nG, gpos, false);
+  for (int k = threadIdx.x; k < nG; k += BT) y[Glist[k]] = gpos[k];
+  for (int i = threadIdx.x; i < n; i += BT)
+    if (flags[i]) y[i] = 0.0;
+  __syncthreads();
 }
 
 // Eq. 3 on G: y_j = sum_p H[F_p, j] x[F_p] - c_j (H symmetric: column j), y_F = 0.
@@ -737,6 +763,7 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
   double* r = (double*)(base + Lw.r);
   uint8_t* flags = (uint8_t*)(base + Lw.flags);
   int32_t* Flist = (int32_t*)(base + Lw.Flist);
+  int32_t* Glist = (int32_t*)(base + Lw.Glist);
   double* z = (double*)(base + Lw.z);
   double* xF = (double*)(base + Lw.xF);
   double* gpos = (double*)(base + Lw.g);
@@ -751,7 +778,7 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
   if (*status != 0) return;
   bool h64 = !(a.fp32 && n <= GS_MAXN);
   if (n > GS_MAXN) {
-    const int bad = wg_atr(P.A, P.lda, m, n, P.b, nullptr, nullptr, 0, c, ATR_ALL);
+    const int bad = wg_atr(P.A, P.lda, m, P.b, nullptr, n, c, true);
     if (wg_max((double)bad, red) > 0.0) {
       if (tid == 0) {
         info->status = NNLS_ERR_INVALID_VALUE;
@@ -833,6 +860,7 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
       int pre = 0;
       for (int q = 0; q < w; ++q) pre += s_int[q];
       if (in) Flist[off + pre + below] = i;
+      else if (i < n) Glist[i - (off + pre + below)] = i;   // i minus the free indices below it
       off += (s_int[0] + s_int[1]) + (s_int[2] + s_int[3]);
       __syncthreads();
     }
@@ -888,7 +916,7 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
         double prev = INFINITY;
         for (int step = 0; step < a.ir_max_steps; ++step) {
           wg_resid(P.A, P.lda, m, P.b, Flist, nF, x, r, sF, sX);
-          wg_atr(P.A, P.lda, m, n, r, flags, Flist, nF, gpos, ATR_FREE);
+          wg_atr(P.A, P.lda, m, r, Flist, nF, gpos, false);
           wg_solve<float>((float*)(base + Lw.Lt), (float*)(base + Lw.Dv), nF, gpos, z, xF, part, vec);
           double dm = 0.0, xm = 0.0;
           for (int q = tid; q < nF; q += BT) {
@@ -915,7 +943,7 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
         }
         if (converged) {   // y_G from the refined x (Eq. 5)
           wg_resid(P.A, P.lda, m, P.b, Flist, nF, x, r, sF, sX);
-          wg_atr(P.A, P.lda, m, n, r, flags, Flist, nF, y, ATR_DUAL);
+          wg_dual(P.A, P.lda, m, n, r, flags, Glist, nF, gpos, y);
           y_done = true;
         } else {
           use32 = false;   // not refined to the target: redo in float64
@@ -932,7 +960,7 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
         wg_dual_gram(H, n, c, flags, Flist, nF, x, y);
       } else {
         wg_resid(P.A, P.lda, m, P.b, Flist, nF, x, r, sF, sX);
-        wg_atr(P.A, P.lda, m, n, r, flags, Flist, nF, y, ATR_DUAL);
+        wg_dual(P.A, P.lda, m, n, r, flags, Glist, nF, gpos, y);
       }
     }
   }
