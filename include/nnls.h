@@ -225,10 +225,12 @@ int nnls_solve_dense_batched_noalloc(nnls_handle* h, int32_t batch, const int32_
  * ticket at once.  Requests are admitted in arrival order as soon as the device memory
  * they need (A, Gram matrix, factor at |F| = n, vectors; estimated on the host from the
  * CSC) fits next to the requests already running; a request that is alone is always
- * admitted.  Requests with n <= batch_max_n are gathered into batched launches (one
- * workgroup per request, the whole pivoting loop on the device, as in
- * nnls_solve_dense_batched); larger ones run the sparse solver of nnls_solve_csc, several
- * at once on separate streams.  Which path a request takes depends on its n only, and both
+ * admitted.  Requests with n <= batch_max_n go to batched lanes, which step at the level
+ * of pivot iterations: each step admits queued requests (their dense A, Gram matrix,
+ * factor and (F, G) state then stay in device memory), advances every live request by
+ * batch_step_iters iterations of the Sec. 2 loop in one launch (one workgroup per request,
+ * as in nnls_solve_dense_batched) and retires the ones that finished.  Larger requests run
+ * the sparse solver of nnls_solve_csc, several at once on separate streams.  Which path a request takes depends on its n only, and both
  * paths give results that do not depend on the other requests, so a result is the same
  * whether the request ran alone or among others.  x and y are available in host memory
  * when the request is reported done; latency is measured from submit to that point.
@@ -244,7 +246,11 @@ typedef struct {
   int32_t batch_lanes;      /* batched launches in flight at once; 0: 2                  */
   int32_t batch_max_n;      /* n <= batch_max_n goes to batched launches; 0: 256; < 0:
                                never                                                     */
-  int32_t batch_max_count;  /* requests per batched launch; 0: 1024                      */
+  int32_t batch_max_count;  /* live requests per batched lane; 0: 1024                   */
+  int32_t batch_step_iters; /* pivot iterations every live request of a batched lane takes
+                               per step (admission and retirement happen between steps);
+                               0: 1; < 0: whole solves, a step ends when all have finished */
+  int32_t pad;
 } nnls_server_config;
 
 typedef struct {

@@ -60,7 +60,8 @@ class nnls_trace_row(C.Structure):
 
 class nnls_server_config(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("workers", C.c_int32), ("batch_lanes", C.c_int32),
-                ("batch_max_n", C.c_int32), ("batch_max_count", C.c_int32)]
+                ("batch_max_n", C.c_int32), ("batch_max_count", C.c_int32), ("batch_step_iters", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class nnls_serving_stats(C.Structure):

@@ -1063,7 +1063,8 @@ int nnls_solve_dense_batched(nnls_handle* h, int32_t batch, const int32_t* m, co
     bp.b = b[i];
     bp.x = x[i];
     bp.y = y[i];
-    bp.ws = (int64_t)total;
+    bp.info = nullptr;   // set below, once the device arrays exist
+    bp.ws = (char*)(uintptr_t)total;
     total += batched_workspace_bytes(m[i], n[i]);
     order[(size_t)i] = i;
   }
@@ -1077,6 +1078,10 @@ int nnls_solve_dense_batched(nnls_handle* h, int32_t batch, const int32_t* m, co
   TRY(ensure(h, h->border, sizeof(int32_t) * (size_t)batch));
   TRY(ensure(h, h->binfo, sizeof(BatchInfo) * (size_t)batch));
   TRY(ensure(h, h->bws, total));
+  for (int i = 0; i < batch; ++i) {
+    probs[(size_t)i].info = (BatchInfo*)h->binfo.p + i;
+    probs[(size_t)i].ws = (char*)h->bws.p + (uintptr_t)probs[(size_t)i].ws;
+  }
   HIP_TRY(hipMemcpyAsync(h->bprobs.p, probs.data(), sizeof(BatchProblem) * (size_t)batch,
                          hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipMemcpyAsync(h->border.p, order.data(), sizeof(int32_t) * (size_t)batch,
@@ -1086,8 +1091,6 @@ int nnls_solve_dense_batched(nnls_handle* h, int32_t batch, const int32_t* m, co
   ba.count = batch;
   ba.probs = (const BatchProblem*)h->bprobs.p;
   ba.order = (const int32_t*)h->border.p;
-  ba.info = (BatchInfo*)h->binfo.p;
-  ba.ws = (char*)h->bws.p;
   ba.tau = o.tau;
   ba.p_max = o.p_max;
   ba.max_iter = o.max_iter;
@@ -1177,7 +1180,8 @@ int nnls_solve_dense_batched_noalloc(nnls_handle* h, int32_t batch, const int32_
       bp.b = b[i];
       bp.x = x[i];
       bp.y = y[i];
-      bp.ws = (int64_t)ws;
+      bp.info = (BatchInfo*)(base + info_off) + i;
+      bp.ws = base + ws_off + ws;
       ws += batched_workspace_bytes(m[i], n[i]);
     }
     HIP_TRY(hipMemcpyAsync(base + probs_off + sizeof(BatchProblem) * (size_t)i0, chunk,
@@ -1189,8 +1193,6 @@ int nnls_solve_dense_batched_noalloc(nnls_handle* h, int32_t batch, const int32_
   ba.count = batch;
   ba.probs = (const BatchProblem*)(base + probs_off);
   ba.order = nullptr;
-  ba.info = (BatchInfo*)(base + info_off);
-  ba.ws = base + ws_off;
   ba.tau = o.tau;
   ba.p_max = o.p_max;
   ba.max_iter = o.max_iter;

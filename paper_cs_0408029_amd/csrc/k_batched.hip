@@ -21,7 +21,7 @@ constexpr int BT = 256;   // threads per workgroup
 
 // Workspace layout of one problem (byte offsets from its base).
 struct WsLayout {
-  size_t H, c, r, flags, Flist, Glist, Lt, Dv, z, xF, g, total;
+  size_t state, H, c, r, flags, Flist, Glist, Lt, Dv, z, xF, g, total;
 };
 
 __host__ __device__ inline WsLayout ws_layout(int m, int n) {
@@ -29,6 +29,7 @@ __host__ __device__ inline WsLayout ws_layout(int m, int n) {
   const size_t nt = (size_t)nb * (nb + 1) / 2;
   WsLayout L;
   size_t o = 0;
+  L.state = o; o += 256;
   L.H = o;     o += ((size_t)n * n * 8 + 255) & ~(size_t)255;
   L.c = o;     o += ((size_t)n * 8 + 255) & ~(size_t)255;
   L.r = o;     o += ((size_t)m * 8 + 255) & ~(size_t)255;
@@ -43,6 +44,13 @@ __host__ __device__ inline WsLayout ws_layout(int m, int n) {
   L.total = o;
   return L;
 }
+
+// Pivot state of a problem between launches (a launch may stop after a number of pivot
+// iterations and the next one resumes at the classify step): the Sec. 2 counters N and p,
+// the iterations taken, |F| of the last exchange and the precision of the Gram matrix.
+struct BatchState {
+  int32_t started, N, p, iter, nF, h64, pad0, pad1;
+};
 
 // ------------------------------------------------------------ workgroup reductions
 __device__ inline double wg_sum(double v, double* red) {
@@ -718,8 +726,8 @@ __global__ __launch_bounds__(GT, 1) void k_batched_gram(BatchArgs a) {
   const BatchProblem P = a.probs[pi];
   const int m = P.m, n = P.n;
   const WsLayout Lw = ws_layout(m, n);
-  char* base = a.ws + P.ws;
-  BatchInfo* info = a.info + pi;
+  char* base = P.ws;
+  BatchInfo* info = P.info;
   int bad = 0;
   if (n <= GS_MAXN) {
     double* c = (double*)(base + Lw.c);
@@ -733,15 +741,16 @@ __global__ __launch_bounds__(GT, 1) void k_batched_gram(BatchArgs a) {
     info->last_ninf = 0;
     info->failed_index = bad ? -1 : INT32_MAX;
     info->ir_steps = 0;
+    info->done = bad ? 1 : 0;
     info->min_margin = 0.0;
+    ((BatchState*)(base + Lw.state))->started = 0;
   }
 }
 
-constexpr size_t SMEM_BYTES = GS_LDS_BYTES > 2 * TILE * LDT * 8 ? GS_LDS_BYTES : 2 * TILE * LDT * 8;
+constexpr size_t SMEM_BYTES = 2 * TILE * LDT * 8;
 
 __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
-  // staged rows of the streamed Gram matrix, or two staged 64 x 64 tiles, or the staged F
-  // columns and x values of the residual
+  // two staged 64 x 64 tiles, or the staged F columns and x values of the residual
   __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];
   __shared__ double red[8];
   __shared__ double part[4 * TILE];
@@ -755,9 +764,11 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
   const int pi = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
   if (pi >= a.count) return;
   const BatchProblem P = a.probs[pi];
+  BatchInfo* info = P.info;
+  if (info->done) return;   // finished in an earlier launch, or rejected by k_batched_gram
   const int m = P.m, n = P.n;
   const WsLayout Lw = ws_layout(m, n);
-  char* base = a.ws + P.ws;
+  char* base = P.ws;
   double* H = (double*)(base + Lw.H);
   double* c = (double*)(base + Lw.c);
   double* r = (double*)(base + Lw.r);
@@ -767,36 +778,50 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
   double* z = (double*)(base + Lw.z);
   double* xF = (double*)(base + Lw.xF);
   double* gpos = (double*)(base + Lw.g);
+  BatchState* state = (BatchState*)(base + Lw.state);
   double* x = P.x;
   double* y = P.y;
-  BatchInfo* info = a.info + pi;
   int32_t* status = &info->status;
   int32_t* failed_pos = &info->failed_index;
 
-  // for n <= GS_MAXN k_batched_gram has formed c and the Gram matrix (float32 for the
-  // mixed path), or rejected the problem; larger problems do both here, the check too
-  if (*status != 0) return;
-  bool h64 = !(a.fp32 && n <= GS_MAXN);
-  if (n > GS_MAXN) {
-    const int bad = wg_atr(P.A, P.lda, m, P.b, nullptr, n, c, true);
-    if (wg_max((double)bad, red) > 0.0) {
-      if (tid == 0) {
-        info->status = NNLS_ERR_INVALID_VALUE;
-        info->failed_index = -1;
-      }
-      return;
-    }
-    wg_gram(P.A, P.lda, m, n, H, S64, W64);
-  }
-  for (int i = tid; i < n; i += BT) {
-    x[i] = 0.0;
-    y[i] = -c[i];
-    flags[i] = 0;
-  }
-  __syncthreads();
-
   const int max_iter = a.max_iter > 0 ? a.max_iter : 5 * n + 100;
-  int N = INT32_MAX, p = a.p_max, iter = 0, nF = 0, k = 0, result = 0;
+  int N, p, iter, nF, k = 0, result = 0;
+  bool h64;
+  if (!state->started) {
+    // for n <= GS_MAXN k_batched_gram has formed c and the Gram matrix (float32 for the
+    // mixed path); larger problems do both here, the finiteness check too
+    h64 = !(a.fp32 && n <= GS_MAXN);
+    if (n > GS_MAXN) {
+      const int bad = wg_atr(P.A, P.lda, m, P.b, nullptr, n, c, true);
+      if (wg_max((double)bad, red) > 0.0) {
+        if (tid == 0) {
+          info->status = NNLS_ERR_INVALID_VALUE;
+          info->failed_index = -1;
+          info->done = 1;
+        }
+        return;
+      }
+      wg_gram(P.A, P.lda, m, n, H, S64, W64);
+    }
+    for (int i = tid; i < n; i += BT) {
+      x[i] = 0.0;
+      y[i] = -c[i];
+      flags[i] = 0;
+    }
+    __syncthreads();
+    N = INT32_MAX;
+    p = a.p_max;
+    iter = 0;
+    nF = 0;
+  } else {
+    N = state->N;
+    p = state->p;
+    iter = state->iter;
+    nF = state->nF;
+    h64 = state->h64 != 0;
+  }
+  int steps = 0;
+  bool finished = true;
   double margin = INFINITY;
   for (;;) {
     // classify: zero |v| < tau, count negatives, largest infeasible index; a tested
@@ -829,6 +854,11 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
       result = NNLS_ERR_MAXITER;
       break;
     }
+    if (a.max_steps > 0 && steps >= a.max_steps) {   // suspend here; the next launch classifies again
+      finished = false;
+      break;
+    }
+    ++steps;
     int branch;
     if (k < N) {
       N = k;
@@ -966,17 +996,27 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
   }
   __syncthreads();
   if (tid == 0) {
-    if (result == 0) result = *status;
-    info->status = result;
-    info->iterations = iter;
-    info->n_free = nF;
-    info->last_ninf = k;
-    info->min_margin = margin;
-    if (result == NNLS_ERR_NOT_PD) {
-      const int fp = *failed_pos;
-      info->failed_index = (fp >= 0 && fp < nF) ? Flist[fp] : -1;
+    if (!finished) {
+      state->started = 1;
+      state->N = N;
+      state->p = p;
+      state->iter = iter;
+      state->nF = nF;
+      state->h64 = h64 ? 1 : 0;
     } else {
-      info->failed_index = -1;
+      if (result == 0) result = *status;
+      info->status = result;
+      info->iterations = iter;
+      info->n_free = nF;
+      info->last_ninf = k;
+      info->min_margin = margin;
+      if (result == NNLS_ERR_NOT_PD) {
+        const int fp = *failed_pos;
+        info->failed_index = (fp >= 0 && fp < nF) ? Flist[fp] : -1;
+      } else {
+        info->failed_index = -1;
+      }
+      info->done = 1;
     }
   }
 }
@@ -985,10 +1025,21 @@ __global__ __launch_bounds__(BT, 2) void k_batched(BatchArgs a) {
 
 size_t batched_workspace_bytes(int m, int n) { return ws_layout(m, n).total; }
 
-void launch_batched(hipStream_t s, const BatchArgs& a, int grid) {
+void launch_batched_gram(hipStream_t s, const BatchArgs& a, int grid) {
   if (grid <= 0) return;
   hipLaunchKernelGGL(k_batched_gram, dim3(grid), dim3(GT), 0, s, a);
+}
+
+void launch_batched_steps(hipStream_t s, const BatchArgs& a, int grid) {
+  if (grid <= 0) return;
   hipLaunchKernelGGL(k_batched, dim3(grid), dim3(BT), 0, s, a);
+}
+
+void launch_batched(hipStream_t s, const BatchArgs& a, int grid) {
+  BatchArgs whole = a;
+  whole.max_steps = 0;
+  launch_batched_gram(s, whole, grid);
+  launch_batched_steps(s, whole, grid);
 }
 
 }  // namespace nnls

@@ -485,8 +485,8 @@ __global__ __launch_bounds__(256) void k_gemvT_dense(int m, int n, const double*
   if (lane == 0) out[j] = scale * s;
 }
 
-// One workgroup per packed request, one wave per column: dense[a_off + i + m j] = val
-// for every stored entry (i, j).  The dense blocks are zero-filled beforehand.
+// One workgroup per packed request: the dense block is zeroed, then, one wave per column,
+// dense[a_off + i + m j] = val for every stored entry (i, j).
 __global__ void __launch_bounds__(256) k_csc_scatter(const ScatterDesc* __restrict__ desc,
                                                      const char* __restrict__ packed,
                                                      double* __restrict__ dense) {
@@ -497,6 +497,9 @@ __global__ void __launch_bounds__(256) k_csc_scatter(const ScatterDesc* __restri
   const int32_t* rowidx = (const int32_t*)(base + L.rowidx);
   const double* val = (const double*)(base + L.val);
   double* A = dense + d.a_off;
+  const int64_t total = (int64_t)d.m * d.n;
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) A[e] = 0.0;
+  __syncthreads();   // the zeros land before the nonzeros
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int j = wave; j < d.n; j += 4) {
     const int e1 = colptr[j + 1];

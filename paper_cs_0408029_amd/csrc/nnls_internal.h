@@ -233,24 +233,25 @@ void launch_tiles_to_dense(hipStream_t s, int n, const void* Ltiles, bool fp32, 
 void launch_reset_tickets(hipStream_t s, Ctrl* ctrl);
 
 // batched dense problems (k_batched.hip): one workgroup per problem
+struct BatchInfo {
+  int32_t status, iterations, n_free, last_ninf, failed_index, ir_steps;
+  int32_t done;           // finished (any status); 0 while the pivot loop is suspended
+  int32_t pad;
+  double min_margin;
+};
 struct BatchProblem {
   int32_t m, n, lda, pad;
   const double* A;
   const double* b;
   double* x;
   double* y;
-  int64_t ws;             // byte offset of the problem's workspace in the arena
-};
-struct BatchInfo {
-  int32_t status, iterations, n_free, last_ninf, failed_index, ir_steps;
-  double min_margin;
+  BatchInfo* info;        // the problem's result and status, kept across launches
+  char* ws;               // the problem's workspace (batched_workspace_bytes), 256-byte aligned
 };
 struct BatchArgs {
   int count;
   const BatchProblem* probs;
   const int32_t* order;   // launch order (workgroup b solves problem order[b]); may be null
-  BatchInfo* info;
-  char* ws;
   double tau;
   int p_max;
   int max_iter;           // <= 0: 5 n + 100 per problem
@@ -258,9 +259,16 @@ struct BatchArgs {
   int ir_max_steps;
   double ir_rtol;
   int gram_dual;          // y_G from the cached Gram matrix (Eq. 3) instead of Eq. 5
+  int max_steps;          // pivot iterations per launch of the pivoting kernel; <= 0: all
 };
 size_t batched_workspace_bytes(int m, int n);
+// Whole solves: the Gram kernel, then the pivoting kernel until every problem is done.
 void launch_batched(hipStream_t s, const BatchArgs& a, int grid);
+// The two kernels on their own: the Gram kernel starts problems (c, Gram matrix, status,
+// fresh pivot state); the pivoting kernel runs up to a.max_steps pivot iterations of every
+// problem that is not done yet and suspends the others at their next classify step.
+void launch_batched_gram(hipStream_t s, const BatchArgs& a, int grid);
+void launch_batched_steps(hipStream_t s, const BatchArgs& a, int grid);
 void launch_ctrl_clear_breakdown(hipStream_t s, Ctrl* ctrl);   // NOT_PD -> 0 (mixed retry)
 
 // One request packed into a single block (host staging and device copy share the layout):

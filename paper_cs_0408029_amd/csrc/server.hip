@@ -2,12 +2,14 @@
 //
 // Submit copies a request into one pinned staging block (colptr | rowidx | val | b) taken
 // from a size-class pool and queues it on one of two lanes, chosen by n alone:
-//   - batched lane (n <= batch_max_n): a lane thread takes every admissible queued request
-//     (up to batch_max_count), stages them into one contiguous device block with a single
-//     copy, scatters each CSC into a dense column-major block on the device and runs them
-//     in one launch of the per-problem batched kernel, so all live small problems take
-//     their pivot iterations together; each lane owns a stream and several lanes keep
-//     launches in flight while new requests queue for the next one;
+//   - batched lane (n <= batch_max_n), stepped at pivot-iteration level: a lane thread
+//     keeps a set of live problems whose state (dense A, Gram matrix, factor, (F, G) split,
+//     x, y) stays in device memory.  Each step admits the queued requests that fit (up to
+//     batch_max_count live), scatters their CSC into dense column-major blocks and forms
+//     their Gram matrices, then advances every live problem by batch_step_iters pivot
+//     iterations in one launch (one workgroup per problem) and retires the ones that
+//     finished, so a short request leaves as soon as it converges and a new one joins at
+//     the next step instead of waiting for a whole batch; several lanes step in turn;
 //   - sparse lane: each worker owns a stream and a solver handle and runs one request at a
 //     time through the full sparse path (Gram, tiled factor, triangular solves, residual,
 //     dual), so several large requests overlap on the device.
@@ -121,6 +123,56 @@ struct DevVec {
   }
 };
 
+// Device blocks in power-of-two size classes (64 KiB << c), reused across requests of the
+// batched lane; up to `keep` bytes of free blocks are cached, the rest go back at once.
+class DevPool {
+ public:
+  explicit DevPool(size_t keep) : keep_(keep) {}
+  ~DevPool() { release_all(); }
+  void* get(size_t bytes, int* cls_out) {
+    int c = 0;
+    while (((size_t)65536 << c) < bytes) ++c;
+    *cls_out = c;
+    if ((int)free_.size() > c && !free_[(size_t)c].empty()) {
+      void* p = free_[(size_t)c].back();
+      free_[(size_t)c].pop_back();
+      cached_ -= (size_t)65536 << c;
+      return p;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, (size_t)65536 << c) != hipSuccess) {
+      (void)hipGetLastError();
+      release_all();   // give the cached blocks back and try once more
+      if (hipMalloc(&p, (size_t)65536 << c) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+    }
+    return p;
+  }
+  void put(void* p, int cls) {
+    if (!p) return;
+    const size_t bytes = (size_t)65536 << cls;
+    if (cached_ + bytes > keep_) {
+      (void)hipFree(p);
+      return;
+    }
+    if ((int)free_.size() <= cls) free_.resize((size_t)cls + 1);
+    free_[(size_t)cls].push_back(p);
+    cached_ += bytes;
+  }
+  void release_all() {
+    for (std::vector<void*>& fl : free_)
+      for (void* p : fl) (void)hipFree(p);
+    free_.clear();
+    cached_ = 0;
+  }
+
+ private:
+  size_t keep_, cached_ = 0;
+  std::vector<std::vector<void*>> free_;
+};
+
 struct PinnedVec {
   void* p = nullptr;
   size_t bytes = 0;
@@ -176,9 +228,24 @@ size_t sparse_footprint(int m, int n, int64_t nnz, const int32_t* rowidx) {
   return f;
 }
 
+// Device block of one live request of the batched lane: packed input | dense A | x | y |
+// workspace, each part 256-byte aligned.
+struct LiveLayout {
+  size_t dense, x, y, ws, total;
+};
+LiveLayout live_layout(int m, int n, int64_t nnz) {
+  const auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  LiveLayout L;
+  L.dense = al((size_t)pack_layout(m, n, nnz).total);
+  L.x = L.dense + al((size_t)m * n * 8);
+  L.y = L.x + al((size_t)n * 8);
+  L.ws = L.y + al((size_t)n * 8);
+  L.total = L.ws + batched_workspace_bytes(m, n);
+  return L;
+}
+
 size_t batched_footprint(int m, int n, int64_t nnz) {
-  return (size_t)pack_layout(m, n, nnz).total + (size_t)m * n * 8 + batched_workspace_bytes(m, n) +
-         (size_t)n * 16 + sizeof(ScatterDesc) + sizeof(BatchProblem) + sizeof(BatchInfo) + 8;
+  return live_layout(m, n, nnz).total + sizeof(ScatterDesc) + sizeof(BatchProblem) + sizeof(BatchInfo);
 }
 
 }  // namespace
@@ -334,110 +401,227 @@ void batch_lane(nnls_server* s) {
   const bool ok = open_lane(s, &stream, &h);
   report_start(s, ok);
   if (!ok) return;
-  DevVec dpacked, ddense, dxy, ddesc;
-  PinnedVec hpacked, hxy, hdesc;
-  std::vector<Request*> group;
-  std::vector<int32_t> vm, vn, vlda;
-  std::vector<const double*> vA, vb;
-  std::vector<double*> vx, vy;
-  std::vector<nnls_info> vinfo;
-  std::deque<Request*>& q = s->queue[LANE_BATCHED];
+  struct Live {
+    Request* r;
+    void* blk;
+    int cls;
+    int slot;
+    BatchProblem desc;
+  };
   const int cap = s->cfg.batch_max_count;
-  for (;;) {
-    group.clear();
-    {
-      std::unique_lock<std::mutex> lk(s->mu);
-      s->cv_work.wait(lk, [&] { return s->stop || (!q.empty() && admissible(s, q.front())); });
-      if (s->stop) break;
-      while (!q.empty() && (int)group.size() < cap && admissible(s, q.front())) {
+  DevPool blocks(s->keep_bytes);
+  DevVec dinfo, ddesc, dscat;
+  PinnedVec hinfo, hdesc, hscat;
+  std::vector<Live> live, fresh, leaving;
+  std::vector<int> free_slots;
+  for (int i = cap - 1; i >= 0; --i) free_slots.push_back(i);
+  std::vector<Request*> taken, finished;
+  std::deque<Request*>& q = s->queue[LANE_BATCHED];
+  if (!dinfo.ensure(sizeof(BatchInfo) * (size_t)cap) || !hinfo.ensure(sizeof(BatchInfo) * (size_t)cap) ||
+      !ddesc.ensure(sizeof(BatchProblem) * (size_t)cap) || !hdesc.ensure(sizeof(BatchProblem) * (size_t)cap) ||
+      !dscat.ensure(sizeof(ScatterDesc) * (size_t)cap) || !hscat.ensure(sizeof(ScatterDesc) * (size_t)cap)) {
+    // cannot step at all: every request that reaches this lane fails
+    for (;;) {
+      taken.clear();
+      {
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv_work.wait(lk, [&] { return s->stop || (!q.empty() && admissible(s, q.front())); });
+        if (s->stop) break;
         Request* r = q.front();
         q.pop_front();
         admit(s, r);
-        group.push_back(r);
+        taken.push_back(r);
+      }
+      fail_all(s, taken, NNLS_ERR_NO_MEMORY);
+    }
+    nnls_destroy(h);
+    (void)hipStreamDestroy(stream);
+    return;
+  }
+  BatchInfo* inf = (BatchInfo*)hinfo.p;
+  BatchArgs ba;
+  std::memset(&ba, 0, sizeof(ba));
+  ba.tau = s->opts.tau;
+  ba.p_max = s->opts.p_max;
+  ba.max_iter = s->opts.max_iter;
+  ba.fp32 = s->opts.precision == NNLS_FP32_IR ? 1 : 0;
+  ba.ir_max_steps = s->opts.ir_max_steps;
+  ba.ir_rtol = s->opts.ir_rtol;
+  ba.gram_dual = (s->opts.flags & NNLS_FLAG_GRAM_DUAL) != 0 ? 1 : 0;
+  const int step_iters = s->cfg.batch_step_iters;
+  auto fail_live = [&](std::vector<Live>& v, int st) {
+    taken.clear();
+    for (Live& l : v) {
+      taken.push_back(l.r);
+      blocks.put(l.blk, l.cls);
+      free_slots.push_back(l.slot);
+    }
+    v.clear();
+    fail_all(s, taken, st);
+  };
+  for (;;) {
+    // admission at the step boundary
+    taken.clear();
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      if (live.empty())
+        s->cv_work.wait(lk, [&] { return s->stop || (!q.empty() && admissible(s, q.front())); });
+      if (s->stop && live.empty()) break;
+      while (!s->stop && !q.empty() && (int)(live.size() + taken.size()) < cap && admissible(s, q.front())) {
+        Request* r = q.front();
+        q.pop_front();
+        admit(s, r);
+        taken.push_back(r);
       }
       s->batches += 1;
     }
-    const int count = (int)group.size();
-    size_t packed_bytes = 0, dense_elems = 0, xy_elems = 0;
-    for (Request* r : group) {
-      packed_bytes += (size_t)r->L.total;
-      dense_elems += (size_t)r->m * r->n;
-      xy_elems += (size_t)r->n * 2;
+    // new problems: device block, input copy, dense A, Gram matrix
+    fresh.clear();
+    std::vector<Request*> nomem;
+    for (Request* r : taken) {
+      const LiveLayout L = live_layout(r->m, r->n, r->nnz);
+      Live l;
+      l.r = r;
+      l.blk = blocks.get(L.total, &l.cls);
+      if (!l.blk) {
+        nomem.push_back(r);
+        continue;
+      }
+      l.slot = free_slots.back();
+      free_slots.pop_back();
+      char* base = (char*)l.blk;
+      BatchProblem& d = l.desc;
+      d.m = r->m;
+      d.n = r->n;
+      d.lda = r->m;
+      d.pad = 0;
+      d.A = (const double*)(base + L.dense);
+      d.b = (const double*)(base + r->L.b);
+      d.x = (double*)(base + L.x);
+      d.y = (double*)(base + L.y);
+      d.info = (BatchInfo*)dinfo.p + l.slot;
+      d.ws = base + L.ws;
+      fresh.push_back(l);
     }
-    if (!dpacked.ensure(packed_bytes) || !ddense.ensure(dense_elems * 8) || !dxy.ensure(xy_elems * 8) ||
-        !ddesc.ensure(sizeof(ScatterDesc) * (size_t)count) || !hpacked.ensure(packed_bytes) ||
-        !hxy.ensure(xy_elems * 8) || !hdesc.ensure(sizeof(ScatterDesc) * (size_t)count)) {
-      fail_all(s, group, NNLS_ERR_NO_MEMORY);
-      continue;
-    }
-    vm.resize((size_t)count);
-    vn.resize((size_t)count);
-    vlda.resize((size_t)count);
-    vA.resize((size_t)count);
-    vb.resize((size_t)count);
-    vx.resize((size_t)count);
-    vy.resize((size_t)count);
-    vinfo.resize((size_t)count);
-    ScatterDesc* desc = (ScatterDesc*)hdesc.p;
-    size_t in_off = 0, a_off = 0, xy_off = 0;
-    for (int i = 0; i < count; ++i) {
-      Request* r = group[(size_t)i];
-      std::memcpy((char*)hpacked.p + in_off, r->in, (size_t)r->L.total);
-      desc[i].m = r->m;
-      desc[i].n = r->n;
-      desc[i].nnz = r->nnz;
-      desc[i].in_off = (int64_t)in_off;
-      desc[i].a_off = (int64_t)a_off;
-      vm[(size_t)i] = r->m;
-      vn[(size_t)i] = r->n;
-      vlda[(size_t)i] = r->m;
-      vA[(size_t)i] = (const double*)ddense.p + a_off;
-      vb[(size_t)i] = (const double*)((const char*)dpacked.p + in_off + r->L.b);
-      vx[(size_t)i] = (double*)dxy.p + xy_off;
-      vy[(size_t)i] = (double*)dxy.p + xy_off + r->n;
-      in_off += (size_t)r->L.total;
-      a_off += (size_t)r->m * r->n;
-      xy_off += (size_t)r->n * 2;
-    }
+    if (!nomem.empty()) fail_all(s, nomem, NNLS_ERR_NO_MEMORY);
     int st = NNLS_OK;
-    if (hipMemcpyAsync(dpacked.p, hpacked.p, packed_bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(ddesc.p, hdesc.p, sizeof(ScatterDesc) * (size_t)count, hipMemcpyHostToDevice, stream) !=
-            hipSuccess) {
-      (void)hipGetLastError();
+    if (!fresh.empty()) {
+      ScatterDesc* sd = (ScatterDesc*)hscat.p;
+      BatchProblem* bd = (BatchProblem*)hdesc.p;
+      const char* origin = (const char*)fresh[0].blk;
+      for (size_t i = 0; i < fresh.size(); ++i) {
+        const Live& l = fresh[i];
+        const LiveLayout L = live_layout(l.r->m, l.r->n, l.r->nnz);
+        sd[i].m = l.r->m;
+        sd[i].n = l.r->n;
+        sd[i].nnz = l.r->nnz;
+        sd[i].in_off = (int64_t)((const char*)l.blk - origin);
+        sd[i].a_off = (int64_t)((const char*)l.blk + L.dense - origin) / 8;
+        bd[i] = l.desc;
+        if (hipMemcpyAsync(l.blk, l.r->in, (size_t)l.r->L.total, hipMemcpyHostToDevice, stream) != hipSuccess)
+          st = NNLS_ERR_DEVICE;
+      }
+      if (st == NNLS_OK &&
+          (hipMemcpyAsync(dscat.p, sd, sizeof(ScatterDesc) * fresh.size(), hipMemcpyHostToDevice, stream) !=
+               hipSuccess ||
+           hipMemcpyAsync(ddesc.p, bd, sizeof(BatchProblem) * fresh.size(), hipMemcpyHostToDevice, stream) !=
+               hipSuccess))
+        st = NNLS_ERR_DEVICE;
+      if (st == NNLS_OK) {
+        launch_csc_scatter(stream, (int)fresh.size(), (const ScatterDesc*)dscat.p, origin, (double*)origin);
+        ba.count = (int)fresh.size();
+        ba.probs = (const BatchProblem*)ddesc.p;
+        ba.order = nullptr;
+        launch_batched_gram(stream, ba, (int)fresh.size());
+        if (hipGetLastError() != hipSuccess) st = NNLS_ERR_DEVICE;
+      }
+      // the host descriptor buffers are rewritten below: wait for the copies out of them
+      if (st == NNLS_OK && hipStreamSynchronize(stream) != hipSuccess) st = NNLS_ERR_DEVICE;
+      if (st != NNLS_OK) {
+        (void)hipGetLastError();
+        fail_live(fresh, st);
+        fail_live(live, st);
+        continue;
+      }
+      for (Live& l : fresh) live.push_back(l);
+    }
+    if (live.empty()) continue;
+    // one step of every live problem
+    BatchProblem* bd = (BatchProblem*)hdesc.p;
+    int maxslot = 0;
+    for (size_t i = 0; i < live.size(); ++i) {
+      bd[i] = live[i].desc;
+      maxslot = std::max(maxslot, live[i].slot + 1);
+    }
+    ba.count = (int)live.size();
+    ba.probs = (const BatchProblem*)ddesc.p;
+    ba.order = nullptr;
+    ba.max_steps = step_iters;
+    if (hipMemcpyAsync(ddesc.p, bd, sizeof(BatchProblem) * live.size(), hipMemcpyHostToDevice, stream) !=
+        hipSuccess)
       st = NNLS_ERR_DEVICE;
-    }
     if (st == NNLS_OK) {
-      launch_fill(stream, (double*)ddense.p, (int64_t)dense_elems, 0.0);
-      launch_csc_scatter(stream, count, (const ScatterDesc*)ddesc.p, (const char*)dpacked.p, (double*)ddense.p);
-      if (hipGetLastError() != hipSuccess) st = NNLS_ERR_DEVICE;
+      launch_batched_steps(stream, ba, (int)live.size());
+      if (hipGetLastError() != hipSuccess ||
+          hipMemcpyAsync(inf, dinfo.p, sizeof(BatchInfo) * (size_t)maxslot, hipMemcpyDeviceToHost, stream) !=
+              hipSuccess ||
+          hipStreamSynchronize(stream) != hipSuccess)
+        st = NNLS_ERR_DEVICE;
     }
-    if (st == NNLS_OK) {
-      // per-problem statuses land in vinfo; the call's own status matters only when the
-      // launch itself could not run
-      const int bst = nnls_solve_dense_batched(h, count, vm.data(), vn.data(), vA.data(), vlda.data(), vb.data(),
-                                               vx.data(), vy.data(), &s->opts, vinfo.data());
-      if (bst == NNLS_ERR_DEVICE || bst == NNLS_ERR_NO_MEMORY || bst == NNLS_ERR_INVALID_ARG) st = bst;
-    }
-    if (st == NNLS_OK &&
-        (hipMemcpyAsync(hxy.p, dxy.p, xy_elems * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-         hipStreamSynchronize(stream) != hipSuccess)) {
-      (void)hipGetLastError();
-      st = NNLS_ERR_DEVICE;
-    }
+    ba.max_steps = 0;
     if (st != NNLS_OK) {
-      fail_all(s, group, st);
+      (void)hipGetLastError();
+      fail_live(live, st);
       continue;
     }
-    xy_off = 0;
-    for (int i = 0; i < count; ++i) {
-      Request* r = group[(size_t)i];
-      std::memcpy(r->out, (const double*)hxy.p + xy_off, (size_t)r->n * 16);
-      r->info = vinfo[(size_t)i];
-      xy_off += (size_t)r->n * 2;
+    // retire the problems that finished in this step
+    finished.clear();
+    leaving.clear();
+    size_t keep = 0;
+    for (size_t i = 0; i < live.size(); ++i) {
+      Live& l = live[i];
+      const BatchInfo& qi = inf[l.slot];
+      if (!qi.done) {
+        live[keep++] = l;
+        continue;
+      }
+      Request* r = l.r;
+      if (hipMemcpyAsync(r->out, l.desc.x, (size_t)r->n * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+          hipMemcpyAsync(r->out + r->n, l.desc.y, (size_t)r->n * 8, hipMemcpyDeviceToHost, stream) != hipSuccess) {
+        (void)hipGetLastError();
+        st = NNLS_ERR_DEVICE;
+      }
+      std::memset(&r->info, 0, sizeof(r->info));
+      r->info.status = qi.status;
+      r->info.iterations = qi.iterations;
+      r->info.n_free = qi.n_free;
+      r->info.last_ninf = qi.last_ninf;
+      r->info.failed_index = qi.failed_index;
+      r->info.ir_steps = qi.ir_steps;
+      r->info.min_margin = qi.min_margin;
+      r->info.est_rel_err = -1.0;
+      finished.push_back(r);
+      leaving.push_back(l);   // its block goes back to the pool after the copies out of it
     }
-    retire(s, group.data(), group.size());
+    live.resize(keep);
+    if (!finished.empty()) {
+      if (hipStreamSynchronize(stream) != hipSuccess) {
+        (void)hipGetLastError();
+        st = NNLS_ERR_DEVICE;
+      }
+      for (Live& l : leaving) {
+        blocks.put(l.blk, l.cls);
+        free_slots.push_back(l.slot);
+      }
+      if (st != NNLS_OK)
+        for (Request* r : finished) r->info.status = st;
+      retire(s, finished.data(), finished.size());
+    }
   }
-  for (DevVec* v : {&dpacked, &ddense, &dxy, &ddesc}) v->release();
+  ddesc.release();
+  dinfo.release();
+  dscat.release();
+  blocks.release_all();
   nnls_destroy(h);
   (void)hipStreamDestroy(stream);
 }
@@ -485,6 +669,7 @@ int nnls_server_create(nnls_server** out, int device, const nnls_server_config* 
   if (c.batch_lanes == 0) c.batch_lanes = 2;
   if (c.batch_max_n == 0) c.batch_max_n = 256;
   if (c.batch_max_count == 0) c.batch_max_count = 1024;
+  if (c.batch_step_iters == 0) c.batch_step_iters = 1;
   if (c.workers < 1 || c.workers > 64 || c.batch_lanes < 0 || c.batch_lanes > 16 || c.batch_max_count < 1)
     return NNLS_ERR_INVALID_ARG;
   if (c.batch_max_n < 0) c.batch_lanes = 0;

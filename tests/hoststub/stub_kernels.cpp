@@ -495,7 +495,10 @@ size_t batched_workspace_bytes(int m, int n) {
          (size_t)tile_count((int)nb_of(n)) * TILE_ELEMS * 8;
 }
 
-void launch_batched(hipStream_t s, const BatchArgs& a0, int grid) {
+// The stand-in pivoting takes two iterations per problem: the Gram kernel starts it
+// (its counter lives in the first bytes of the workspace), each step launch advances it by
+// max_steps iterations (all when <= 0) and finishes it with fixed values.
+void launch_batched_gram(hipStream_t s, const BatchArgs& a0, int grid) {
   const BatchArgs a = a0;
   stub_enqueue(s, [=] {
     for (int blk = 0; blk < grid; ++blk) {
@@ -504,12 +507,33 @@ void launch_batched(hipStream_t s, const BatchArgs& a0, int grid) {
       const BatchProblem P = a.probs[pi];
       for (int j = 0; j < P.n; ++j) read_all(P.A + (int64_t)j * P.lda, P.m);
       read_all(P.b, P.m);
-      write_bytes(a.ws + P.ws, (int64_t)batched_workspace_bytes(P.m, P.n));
+      write_bytes(P.ws, (int64_t)batched_workspace_bytes(P.m, P.n));
+      *(int32_t*)P.ws = 0;
+      BatchInfo& q = *P.info;
+      q.status = 0;
+      q.done = 0;
+      q.ir_steps = 0;
+    }
+  });
+}
+
+void launch_batched_steps(hipStream_t s, const BatchArgs& a0, int grid) {
+  const BatchArgs a = a0;
+  stub_enqueue(s, [=] {
+    for (int blk = 0; blk < grid; ++blk) {
+      const int pi = a.order ? a.order[blk] : blk;
+      if (pi >= a.count) continue;
+      const BatchProblem P = a.probs[pi];
+      BatchInfo& q = *P.info;
+      if (q.done) continue;
+      int32_t* it = (int32_t*)P.ws;
+      read_all(P.A, P.m);
+      *it += a.max_steps > 0 ? a.max_steps : 2;
+      if (*it < 2) continue;
       for (int j = 0; j < P.n; ++j) {
         P.x[j] = 0.5;
         P.y[j] = 0.0;
       }
-      BatchInfo& q = a.info[pi];
       q.status = 0;
       q.iterations = 2;
       q.n_free = P.n;
@@ -517,8 +541,16 @@ void launch_batched(hipStream_t s, const BatchArgs& a0, int grid) {
       q.failed_index = -1;
       q.ir_steps = a.fp32 ? 2 : 0;
       q.min_margin = 1.0;
+      q.done = 1;
     }
   });
+}
+
+void launch_batched(hipStream_t s, const BatchArgs& a, int grid) {
+  BatchArgs whole = a;
+  whole.max_steps = 0;
+  launch_batched_gram(s, whole, grid);
+  launch_batched_steps(s, whole, grid);
 }
 
 void launch_csc_scatter(hipStream_t s, int count, const ScatterDesc* desc, const char* packed, double* dense) {
@@ -530,6 +562,7 @@ void launch_csc_scatter(hipStream_t s, int count, const ScatterDesc* desc, const
       const int32_t* colptr = (const int32_t*)(packed + d.in_off);
       const int32_t* rowidx = (const int32_t*)(packed + d.in_off + L.rowidx);
       const double* val = (const double*)(packed + d.in_off + L.val);
+      for (int64_t e = 0; e < (int64_t)d.m * d.n; ++e) dense[d.a_off + e] = 0.0;
       for (int j = 0; j < d.n; ++j)
         for (int32_t e = colptr[j]; e < colptr[j + 1]; ++e)
           dense[d.a_off + rowidx[e] + (int64_t)j * d.m] = val[e];

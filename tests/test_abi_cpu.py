@@ -91,7 +91,7 @@ def test_create_reports_missing_device(lib):
 
 
 def test_server_structs_and_null_arguments(lib):
-    assert C.sizeof(N.nnls_server_config) == 24
+    assert C.sizeof(N.nnls_server_config) == 32
     assert C.sizeof(N.nnls_serving_stats) == 4 * 8 + 2 * 4 + 8 * 8
     assert lib.nnls_server_create(None, 0, None, None) == N.NNLS_ERR_INVALID_ARG
     assert lib.nnls_server_destroy(None) == N.NNLS_ERR_INVALID_ARG

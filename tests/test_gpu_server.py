@@ -156,6 +156,32 @@ def test_sparse_lane_only_matches_batched_lane(stream_small):
         assert relerr(a[1], b[1]) <= 1e-10, p.name
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_iteration_level_steps_equal_whole_solves(stream_small, precision):
+    """The batched lane advances live requests a few pivot iterations per step and admits
+    and retires requests between steps; the pivot state carried from step to step gives
+    bitwise the same result as a whole solve in one launch, for every step size."""
+    sub = [p for p in stream_small if p.A.shape[1] <= 160]
+    opts = N.default_options(precision=precision)
+    runs = {}
+    for iters in (-1, 1, 2):
+        with N.Server(0, opts=opts, workers=1, batch_lanes=1, batch_max_n=160, batch_step_iters=iters) as srv:
+            runs[iters] = run_all(srv, sub)
+            stats = N.nnls_server_stats(srv)
+        if iters == 1:   # a request takes several steps, so there were more steps than requests
+            assert stats["batches"] > 1
+    for k, p in enumerate(sub):
+        ref = runs[-1][k]
+        assert ref[0] == N.NNLS_OK, p.name
+        for iters in (1, 2):
+            got = runs[iters][k]
+            assert got[0] == N.NNLS_OK
+            assert np.array_equal(got[1], ref[1]), (p.name, iters)
+            assert np.array_equal(got[2], ref[2]), (p.name, iters)
+            assert got[3].iterations == ref[3].iterations
+            assert got[3].ir_steps == ref[3].ir_steps
+
+
 def test_bad_requests_fail_alone(stream_small):
     good = stream_small[:6]
     with N.Server(0, workers=2, batch_lanes=1, batch_max_n=160) as srv:
