@@ -311,7 +311,7 @@ int nnls_get_trace(nnls_handle* h, nnls_trace_row* rows, int cap);
  * For class c (see nnls_profile_class), launches[c] and total_ms[c] are written (host
  * arrays of length NNLS_PROFILE_CLASSES), and flops[c] the algorithmic work of those
  * launches (floating-point operations; bytes for the memory-bound classes). */
-#define NNLS_PROFILE_CLASSES 8
+#define NNLS_PROFILE_CLASSES 9
 typedef enum {
   NNLS_PROF_GRAM = 0,      /* A^T A and A^T b (bytes)                                   */
   NNLS_PROF_CONTROL = 1,   /* classify, count, exchange, rebuild F (bytes)              */
@@ -320,9 +320,12 @@ typedef enum {
   NNLS_PROF_RESIDUAL = 4,  /* r = A x - b and y_G = A_G^T r (bytes; in nnls_dual_csc the
                               residual alone, the dual being NNLS_PROF_DUAL)            */
   NNLS_PROF_REFINE = 5,    /* mixed precision refinement (bytes)                        */
-  NNLS_PROF_BATCHED = 6,   /* one batched launch (flops sum n^2 m of the Gram matrices) */
-  NNLS_PROF_DUAL = 7       /* y_G = A_G^T r on its own (bytes); inside NNLS_PROF_RESIDUAL
+  NNLS_PROF_BATCHED = 6,   /* a batched launch's pivoting kernel (the pivot loops of all
+                              problems; work: sum n^2 m, as for the Gram kernel)        */
+  NNLS_PROF_DUAL = 7,      /* y_G = A_G^T r on its own (bytes); inside NNLS_PROF_RESIDUAL
                               when timed as part of a solve                             */
+  NNLS_PROF_BATCHED_GRAM = 8 /* a batched launch's Gram kernel: c, the Gram matrices and
+                              the input check (flops sum n^2 m)                         */
 } nnls_profile_class;
 int nnls_get_profile(nnls_handle* h, int64_t* launches, double* total_ms, double* work);
 int nnls_reset_profile(nnls_handle* h);

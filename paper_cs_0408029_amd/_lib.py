@@ -36,8 +36,9 @@ NNLS_FLAG_REFINE_AUTO = 8
 NNLS_FLAG_GRAM_DUAL = 16
 NNLS_FLAG_REFINE_ALL = 32
 
-NNLS_PROFILE_CLASSES = 8
-PROFILE_CLASS_NAMES = ["gram", "control", "cholesky", "trsv", "residual", "refine", "batched", "dual"]
+NNLS_PROFILE_CLASSES = 9
+PROFILE_CLASS_NAMES = ["gram", "control", "cholesky", "trsv", "residual", "refine", "batched", "dual",
+                       "batched_gram"]
 
 
 class nnls_options(C.Structure):

@@ -1101,8 +1101,11 @@ int nnls_solve_dense_batched(nnls_handle* h, int32_t batch, const int32_t* m, co
   h->profiling = h->profile_always || (o.flags & NNLS_FLAG_PROFILE) != 0;
   double flops = 0.0;
   for (int i = 0; i < batch; ++i) flops += (double)n[i] * n[i] * m[i];
+  const int64_t pg = prof_begin(h, NNLS_PROF_BATCHED_GRAM);
+  launch_batched_gram(h->stream, ba, batch);
+  prof_end(h, pg, flops);
   const int64_t pe = prof_begin(h, NNLS_PROF_BATCHED);
-  launch_batched(h->stream, ba, batch);
+  launch_batched_steps(h->stream, ba, batch);   // max_steps 0: every problem to the end
   prof_end(h, pe, flops);
   std::vector<BatchInfo> bi((size_t)batch);
   const int st = sync_read(h, bi.data(), h->binfo.p, sizeof(BatchInfo) * (size_t)batch);
