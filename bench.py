@@ -159,6 +159,22 @@ def bench_batch(args):
         xh = x.cpu().numpy()
         errs.append(float(np.linalg.norm(xh - inst.x_star) / np.linalg.norm(inst.x_star)))
         match += int(np.array_equal(xh > 0, inst.active))
+    # the same batch prepared once and replayed from its captured graph
+    plan = N.BatchPlan(h, As, bs, xs, ys, opts)
+    for _ in range(args.warmup):
+        plan.execute()
+    glat = []
+    with no_gc():
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        for _ in range(args.steps):
+            s0 = time.perf_counter()
+            st, _ = plan.execute()
+            glat.append((time.perf_counter() - s0) * 1e3)
+            if st != N.NNLS_OK:
+                raise RuntimeError(f"graph replay failed: {N.status_string(st)}")
+        gtotal = time.perf_counter() - g0
+    plan.close()
     # plain float64 path, one problem per call
     k = min(args.plain_sample, len(insts))
     o64 = N.default_options()
@@ -192,6 +208,10 @@ def bench_batch(args):
                                "N(0,1)/sqrt(m), 40% active, seed 1003",
                    "path": "batched, one launch" + (", y_G from the Gram matrix (Eq. 3)" if args.gram_dual else "")},
         "max_rel_err_vs_planted": max(errs), "free_set_matches": f"{match}/{len(insts)}",
+        "graph_replay": {"solves_per_s": round(args.steps * len(insts) / gtotal, 2),
+                         "ms_per_step": round(gtotal / args.steps * 1e3, 3),
+                         "p50_ms": round(float(np.percentile(glat, 50)), 3),
+                         "p99_ms": round(float(np.percentile(glat, 99)), 3)},
         "plain_fp64_solves_per_s": round(plain, 2), "plain_sample": k,
         "roofline": {"bound": "mfma", "kernel": "k_batched_gram" + ("<double>" if prec == N.NNLS_FP64 else "<float>"),
                      "achieved": round(achieved, 4) if achieved else None,

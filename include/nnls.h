@@ -180,11 +180,12 @@ int nnls_solve_dense(nnls_handle* h, int32_t m, int32_t n, const double* A, int3
                      const double* b, double* x, double* y, const nnls_options* opts,
                      nnls_info* info);
 
-/* Solve `batch` independent dense problems in one launch (Eq. 1 for each).  m, n, lda:
+/* Solve `batch` independent dense problems together (Eq. 1 for each).  m, n, lda:
  * host int32[batch]; A, b, x, y: host arrays of `batch` DEVICE pointers (A column-major
- * with lda >= m, b double[m], x and y double[n] outputs).  Each problem runs the whole
- * pivoting loop of the Sec. 2 algorithm box on the device in one workgroup; its result
- * does not depend on the other problems in the batch.  opts applies to every problem
+ * with lda >= m, b double[m], x and y double[n] outputs).  Two launches: one workgroup per
+ * problem forms A^T b and the Gram matrix (and checks the input), then one workgroup per
+ * problem runs the whole pivoting loop of the Sec. 2 algorithm box on the device; a
+ * problem's result does not depend on the other problems in the batch.  opts applies to every problem
  * (NNLS_FP32_IR: float32 factor, float64 refinement).  info: host nnls_info[batch] or
  * NULL.  Returns NNLS_OK when every problem succeeded, otherwise the first failing status
  * (per-problem statuses are in info; a failed problem does not affect the others).
@@ -203,7 +204,7 @@ int nnls_solve_dense_batched(nnls_handle* h, int32_t batch, const int32_t* m, co
  * GPU instead of the handle's growable workspace.  The call performs no hipMalloc,
  * hipFree or other allocation; the array is part of the library's code object, so each
  * GPU the library runs on holds it until the process ends.
- * Capacity: 256-byte-aligned descriptors (batch * 56 bytes), statuses (batch * 32 bytes)
+ * Capacity: 256-byte-aligned descriptors (batch * 64 bytes), statuses (batch * 40 bytes)
  * and the problems' workspaces (about 8 (n^2 + m) bytes plus the factor tiles of n each)
  * must fit together; otherwise NNLS_ERR_TOO_LARGE is returned and nothing runs.
  * Problems run in the given order (not sorted by size).  NNLS_FLAG_PROFILE is ignored.
@@ -217,6 +218,37 @@ int nnls_solve_dense_batched_noalloc(nnls_handle* h, int32_t batch, const int32_
                                      const int32_t* n, const double* const* A, const int32_t* lda,
                                      const double* const* b, double* const* x, double* const* y,
                                      const nnls_options* opts, nnls_info* info);
+
+/* ---------------------------------------------------------------------------------
+ * Prepared batched solves, replayed from a captured HIP graph
+ * For a batch whose shapes and device buffers stay the same over many solves (new values
+ * in A and b each time): nnls_batch_plan_create checks the batch as
+ * nnls_solve_dense_batched does, uploads the problem descriptors, allocates the workspace
+ * and the status array once, and records the two kernels of a batched solve and the copy
+ * of the statuses into pinned host memory in a HIP graph (captured on a private stream);
+ * nnls_batch_plan_execute replays the graph on the handle's stream, with no host-side
+ * preparation.  Each replay reads A and b as they are when it runs and writes x and y; the
+ * results are bitwise those of nnls_solve_dense_batched on the same inputs (same kernels,
+ * same order).  The plan keeps the pointers it was given: the caller keeps those buffers
+ * alive and unmoved until nnls_batch_plan_destroy.  The plan uses the handle's stream and
+ * device; calls on one plan are not thread-safe.  NNLS_FLAG_PROFILE is ignored.
+ * Errors of create: INVALID_ARG (as nnls_solve_dense_batched), NO_MEMORY, DEVICE (the
+ * capture or instantiation failed); nothing is kept on error and *plan is NULL.
+ * --------------------------------------------------------------------------------- */
+typedef struct nnls_batch_plan nnls_batch_plan;
+int nnls_batch_plan_create(nnls_handle* h, int32_t batch, const int32_t* m, const int32_t* n,
+                           const double* const* A, const int32_t* lda, const double* const* b,
+                           double* const* x, double* const* y, const nnls_options* opts,
+                           nnls_batch_plan** plan);
+/* Queue one replay on the handle's stream.  With info (host nnls_info[batch]) the call
+ * waits for it and returns as nnls_solve_dense_batched does; with info NULL it returns
+ * NNLS_OK once the replay is queued, and nnls_batch_plan_info reads the statuses later.
+ * Errors: INVALID_ARG (plan NULL), DEVICE. */
+int nnls_batch_plan_execute(nnls_batch_plan* plan, nnls_info* info);
+/* Wait for the handle's stream and fill info (host nnls_info[batch]) from the last replay;
+ * returns its first failing status, or NNLS_OK. */
+int nnls_batch_plan_info(nnls_batch_plan* plan, nnls_info* info);
+int nnls_batch_plan_destroy(nnls_batch_plan* plan);
 
 /* ---------------------------------------------------------------------------------
  * Serving engine: continuous batching of independent requests (Eq. 1 each) on one device.

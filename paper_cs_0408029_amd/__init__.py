@@ -165,6 +165,48 @@ def nnls_solve_dense_batched_noalloc(h: Handle, As=None, bs=None, xs=None, ys=No
     return st, list(p.infos[:p.batch])
 
 
+class BatchPlan:
+    """A prepared batched solve (nnls_batch_plan): the batch's descriptors and workspace are
+    set up once and one solve is captured in a HIP graph; execute() replays it on the
+    handle's stream with whatever values A and b hold.  The tensors must stay alive and in
+    place while the plan exists (the plan keeps references to them)."""
+
+    def __init__(self, h: Handle, As, bs, xs, ys, opts: Optional[nnls_options] = None):
+        self.h = h
+        self.args = BatchedArgs(As, bs, xs, ys)
+        p = self.args
+        vp = lambda arr: C.cast(arr, C.c_void_p)
+        plan = C.c_void_p()
+        st = h.lib.nnls_batch_plan_create(h.ptr, p.batch, vp(p.m), vp(p.n), vp(p.pa), vp(p.lda), vp(p.pb),
+                                          vp(p.px), vp(p.py), C.byref(opts) if opts else None, C.byref(plan))
+        if st != NNLS_OK:
+            raise RuntimeError(f"nnls_batch_plan_create failed: {status_string(st)}")
+        self._p = plan
+
+    def execute(self, wait: bool = True):
+        """Replay once.  wait=True: returns (status, [nnls_info]); wait=False: returns the
+        status of queueing it (read the results with info())."""
+        if not wait:
+            return self.h.lib.nnls_batch_plan_execute(self._p, None)
+        st = self.h.lib.nnls_batch_plan_execute(self._p, C.cast(self.args.infos, C.c_void_p))
+        return st, list(self.args.infos[:self.args.batch])
+
+    def info(self):
+        st = self.h.lib.nnls_batch_plan_info(self._p, C.cast(self.args.infos, C.c_void_p))
+        return st, list(self.args.infos[:self.args.batch])
+
+    def close(self):
+        if self._p:
+            self.h.lib.nnls_batch_plan_destroy(self._p)
+            self._p = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def nnls_get_trace(h: Handle, reused: bool = False, ir_steps: bool = False) -> List[Tuple[int, ...]]:
     """Per-iteration (k, branch, N, p, |F|); with reused=True also the count of leading F
     positions whose factor tiles were kept from the previous iteration; with ir_steps=True

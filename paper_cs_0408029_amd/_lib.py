@@ -91,6 +91,11 @@ PROTOTYPES = {
                                            C.POINTER(nnls_options), _P]),
     "nnls_solve_dense_batched_noalloc": (C.c_int, [_P, _I32, _P, _P, _P, _P, _P, _P, _P,
                                                    C.POINTER(nnls_options), _P]),
+    "nnls_batch_plan_create": (C.c_int, [_P, _I32, _P, _P, _P, _P, _P, _P, _P, C.POINTER(nnls_options),
+                                         C.POINTER(_P)]),
+    "nnls_batch_plan_execute": (C.c_int, [_P, _P]),
+    "nnls_batch_plan_info": (C.c_int, [_P, _P]),
+    "nnls_batch_plan_destroy": (C.c_int, [_P]),
     "nnls_server_create": (C.c_int, [C.POINTER(_P), C.c_int, C.POINTER(nnls_server_config),
                                      C.POINTER(nnls_options)]),
     "nnls_server_submit_csc": (C.c_int, [_P, _I32, _I32, _I64, _P, _P, _P, _P, C.POINTER(C.c_uint64)]),

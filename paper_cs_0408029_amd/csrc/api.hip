@@ -71,6 +71,21 @@ double now_ms() {
 
 }  // namespace
 
+// A prepared batch: device descriptors, statuses and workspace, and the captured graph of
+// one batched solve (see nnls_batch_plan_create).
+struct nnls_batch_plan {
+  nnls_handle* h = nullptr;
+  int batch = 0;
+  void* d_probs = nullptr;
+  void* d_order = nullptr;
+  void* d_info = nullptr;
+  void* d_ws = nullptr;
+  void* h_info = nullptr;   // pinned copy of the statuses, written by the graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double t0 = 0.0;
+};
+
 struct nnls_handle {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -1231,6 +1246,151 @@ int nnls_solve_dense_batched_noalloc(nnls_handle* h, int32_t batch, const int32_
     }
   }
   return worst;
+}
+
+// ------------------------------------------------------------ prepared batches
+int nnls_batch_plan_create(nnls_handle* h, int32_t batch, const int32_t* m, const int32_t* n,
+                           const double* const* A, const int32_t* lda, const double* const* b,
+                           double* const* x, double* const* y, const nnls_options* opts,
+                           nnls_batch_plan** plan) {
+  if (!plan) return NNLS_ERR_INVALID_ARG;
+  *plan = nullptr;
+  nnls_options o;
+  nnls_default_options(&o);
+  if (opts) o = *opts;
+  if (!h || batch < 1 || !m || !n || !A || !lda || !b || !x || !y) return NNLS_ERR_INVALID_ARG;
+  if (check_options(o) != NNLS_OK || o.precision == NNLS_BF16_IR) return NNLS_ERR_INVALID_ARG;
+  for (int i = 0; i < batch; ++i)
+    if (n[i] < 1 || m[i] < n[i] || lda[i] < m[i] || !A[i] || !b[i] || !x[i] || !y[i]) return NNLS_ERR_INVALID_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return NNLS_ERR_DEVICE;
+  nnls_batch_plan* P = new (std::nothrow) nnls_batch_plan();
+  if (!P) return NNLS_ERR_NO_MEMORY;
+  P->h = h;
+  P->batch = batch;
+  std::vector<BatchProblem> probs((size_t)batch);
+  std::vector<int32_t> order((size_t)batch);
+  size_t total = 0;
+  for (int i = 0; i < batch; ++i) {
+    BatchProblem& bp = probs[(size_t)i];
+    bp.m = m[i];
+    bp.n = n[i];
+    bp.lda = lda[i];
+    bp.pad = 0;
+    bp.A = A[i];
+    bp.b = b[i];
+    bp.x = x[i];
+    bp.y = y[i];
+    bp.ws = (char*)(uintptr_t)total;
+    total += batched_workspace_bytes(m[i], n[i]);
+    order[(size_t)i] = i;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a_, int b_) {   // as nnls_solve_dense_batched
+    const double wa = (double)n[a_] * n[a_] * (m[a_] + n[a_]);
+    const double wb = (double)n[b_] * n[b_] * (m[b_] + n[b_]);
+    return wa > wb;
+  });
+  auto fail = [&](int st) {
+    (void)hipGetLastError();
+    nnls_batch_plan_destroy(P);
+    return st;
+  };
+  if (hipMalloc(&P->d_probs, sizeof(BatchProblem) * (size_t)batch) != hipSuccess ||
+      hipMalloc(&P->d_order, sizeof(int32_t) * (size_t)batch) != hipSuccess ||
+      hipMalloc(&P->d_info, sizeof(BatchInfo) * (size_t)batch) != hipSuccess ||
+      hipMalloc(&P->d_ws, total) != hipSuccess ||
+      hipHostMalloc(&P->h_info, sizeof(BatchInfo) * (size_t)batch, hipHostMallocDefault) != hipSuccess)
+    return fail(NNLS_ERR_NO_MEMORY);
+  for (int i = 0; i < batch; ++i) {
+    probs[(size_t)i].info = (BatchInfo*)P->d_info + i;
+    probs[(size_t)i].ws = (char*)P->d_ws + (uintptr_t)probs[(size_t)i].ws;
+  }
+  if (hipMemcpy(P->d_probs, probs.data(), sizeof(BatchProblem) * (size_t)batch, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(P->d_order, order.data(), sizeof(int32_t) * (size_t)batch, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(NNLS_ERR_DEVICE);
+  BatchArgs ba;
+  std::memset(&ba, 0, sizeof(ba));
+  ba.count = batch;
+  ba.probs = (const BatchProblem*)P->d_probs;
+  ba.order = (const int32_t*)P->d_order;
+  ba.tau = o.tau;
+  ba.p_max = o.p_max;
+  ba.max_iter = o.max_iter;
+  ba.fp32 = o.precision == NNLS_FP32_IR ? 1 : 0;
+  ba.ir_max_steps = o.ir_max_steps;
+  ba.ir_rtol = o.ir_rtol;
+  ba.gram_dual = (o.flags & NNLS_FLAG_GRAM_DUAL) != 0 ? 1 : 0;
+  ba.max_steps = 0;
+  // record: both kernels and the status copy, on a private stream (no memset nodes)
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(NNLS_ERR_DEVICE);
+  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    launch_batched_gram(cs, ba, batch);
+    launch_batched_steps(cs, ba, batch);
+    ok = hipMemcpyAsync(P->h_info, P->d_info, sizeof(BatchInfo) * (size_t)batch, hipMemcpyDeviceToHost, cs) ==
+         hipSuccess;
+    hipGraph_t g = nullptr;
+    const bool ended = hipStreamEndCapture(cs, &g) == hipSuccess;
+    ok = ok && ended && g;
+    P->graph = g;
+  }
+  (void)hipStreamDestroy(cs);
+  if (!ok || hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0) != hipSuccess) return fail(NNLS_ERR_DEVICE);
+  *plan = P;
+  return NNLS_OK;
+}
+
+int nnls_batch_plan_execute(nnls_batch_plan* plan, nnls_info* info) {
+  if (!plan || !plan->exec) return NNLS_ERR_INVALID_ARG;
+  if (hipSetDevice(plan->h->device) != hipSuccess) return NNLS_ERR_DEVICE;
+  plan->t0 = now_ms();
+  if (hipGraphLaunch(plan->exec, plan->h->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return NNLS_ERR_DEVICE;
+  }
+  return info ? nnls_batch_plan_info(plan, info) : NNLS_OK;
+}
+
+int nnls_batch_plan_info(nnls_batch_plan* plan, nnls_info* info) {
+  if (!plan) return NNLS_ERR_INVALID_ARG;
+  if (hipSetDevice(plan->h->device) != hipSuccess || hipStreamSynchronize(plan->h->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return NNLS_ERR_DEVICE;
+  }
+  const double el = now_ms() - plan->t0;
+  const BatchInfo* bi = (const BatchInfo*)plan->h_info;
+  int worst = NNLS_OK;
+  for (int i = 0; i < plan->batch; ++i) {
+    const BatchInfo& q = bi[i];
+    if (info) {
+      nnls_info& d = info[i];
+      std::memset(&d, 0, sizeof(d));
+      d.status = q.status;
+      d.iterations = q.iterations;
+      d.n_free = q.n_free;
+      d.last_ninf = q.last_ninf;
+      d.failed_index = q.failed_index;
+      d.ir_steps = q.ir_steps;
+      d.min_margin = q.min_margin;
+      d.est_rel_err = -1.0;
+      d.solve_ms = el;
+    }
+    if (q.status != NNLS_OK && worst == NNLS_OK) worst = q.status;
+  }
+  return worst;
+}
+
+int nnls_batch_plan_destroy(nnls_batch_plan* plan) {
+  if (!plan) return NNLS_OK;
+  (void)hipSetDevice(plan->h->device);
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  for (void* p : {plan->d_probs, plan->d_order, plan->d_info, plan->d_ws})
+    if (p) (void)hipFree(p);
+  if (plan->h_info) (void)hipHostFree(plan->h_info);
+  delete plan;
+  return NNLS_OK;
 }
 
 int nnls_get_trace(nnls_handle* h, nnls_trace_row* rows, int cap) {

@@ -193,3 +193,49 @@ def test_gram_dual_matches_oracle(h, batch24, precision, tol):
         assert relerr(x, res.x) <= tol
         assert np.linalg.norm(y - res.y) <= tol * max(np.linalg.norm(res.y), 1.0)
         assert np.all(x >= 0) and np.all(y >= 0) and np.dot(x, y) == 0.0
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_plan_replays_match_eager(h, batch24, precision):
+    """A prepared batch replayed from its captured graph: each replay, with the program's own
+    work on the stream and host synchronisations between replays and new values in b, gives
+    bitwise the result of nnls_solve_dense_batched on the same inputs."""
+    problems, insts = batch24
+    opts = N.default_options(precision=precision)
+    As = [colmajor_dev(A) for A, _ in problems]
+    bs = [t(b) for _, b in problems]
+    nan = lambda k: torch.full((k,), np.nan, dtype=torch.float64, device=DEV)
+    xs = [nan(A.shape[1]) for A, _ in problems]
+    ys = [nan(A.shape[1]) for A, _ in problems]
+    xe = [nan(A.shape[1]) for A, _ in problems]
+    ye = [nan(A.shape[1]) for A, _ in problems]
+    plan = N.BatchPlan(h, As, bs, xs, ys, opts)
+    for k, scale in enumerate([1.0, 0.5, 2.0, 1.0, -1.0]):
+        for b, (_, b0) in zip(bs, problems):          # eager work between the replays
+            b.copy_(torch.from_numpy(b0 * scale).to(DEV))
+        for x in xs:
+            x.fill_(np.nan)
+        if k % 2:
+            assert plan.execute(wait=False) == N.NNLS_OK
+            st, infos = plan.info()
+        else:
+            st, infos = plan.execute()
+        ste, infe = N.nnls_solve_dense_batched(h, As, bs, xe, ye, opts)
+        torch.cuda.synchronize()
+        assert st == ste == N.NNLS_OK
+        for i in range(len(problems)):
+            assert torch.equal(xs[i], xe[i]) and torch.equal(ys[i], ye[i]), (k, i)
+            assert infos[i].iterations == infe[i].iterations and infos[i].ir_steps == infe[i].ir_steps
+        if scale == 1.0:
+            for x, inst in zip(xs, insts):
+                assert np.array_equal(x.cpu().numpy() > 0, inst.active)
+    plan.close()
+
+
+def test_plan_rejects_bad_batches(h):
+    with pytest.raises(RuntimeError):
+        N.BatchPlan(h, [], [], [], [])
+    A = torch.zeros((3, 5), dtype=torch.float64, device=DEV).t().contiguous().t()   # m < n
+    with pytest.raises(RuntimeError):
+        N.BatchPlan(h, [A], [torch.zeros(3, dtype=torch.float64, device=DEV)],
+                    [torch.zeros(5, dtype=torch.float64, device=DEV)], [torch.zeros(5, dtype=torch.float64, device=DEV)])
