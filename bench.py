@@ -160,7 +160,10 @@ def bench_batch(args):
         errs.append(float(np.linalg.norm(xh - inst.x_star) / np.linalg.norm(inst.x_star)))
         match += int(np.array_equal(xh > 0, inst.active))
     # the same batch prepared once and replayed from its captured graph
+    pc0 = time.perf_counter()
     plan = N.BatchPlan(h, As, bs, xs, ys, opts)
+    plan_s = time.perf_counter() - pc0
+    shapes = plan.tile_shapes()
     for _ in range(args.warmup):
         plan.execute()
     glat = []
@@ -211,7 +214,9 @@ def bench_batch(args):
         "graph_replay": {"solves_per_s": round(args.steps * len(insts) / gtotal, 2),
                          "ms_per_step": round(gtotal / args.steps * 1e3, 3),
                          "p50_ms": round(float(np.percentile(glat, 50)), 3),
-                         "p99_ms": round(float(np.percentile(glat, 99)), 3)},
+                         "p99_ms": round(float(np.percentile(glat, 99)), 3),
+                         "plan_create_s": round(plan_s, 3),
+                         "autotuned_rects_per_wave": {f"n<={32 * k}": v for k, v in shapes.items()}},
         "plain_fp64_solves_per_s": round(plain, 2), "plain_sample": k,
         "roofline": {"bound": "mfma", "kernel": "k_batched_gram" + ("<double>" if prec == N.NNLS_FP64 else "<float>"),
                      "achieved": round(achieved, 4) if achieved else None,

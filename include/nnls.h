@@ -248,6 +248,13 @@ int nnls_batch_plan_execute(nnls_batch_plan* plan, nnls_info* info);
 /* Wait for the handle's stream and fill info (host nnls_info[batch]) from the last replay;
  * returns its first failing status, or NNLS_OK. */
 int nnls_batch_plan_info(nnls_batch_plan* plan, nnls_info* info);
+/* The Gram kernel's accumulator tile shape that the plan's autotuner chose for each
+ * bucket: shapes (host int32[9]) receives, for k = ceil(n / 32) = 1..8, the number of 32 x
+ * 32 rectangles of the Gram matrix a wave accumulates per pass over A (0 where the batch
+ * has no problem of that bucket; n > 256 is not tuned).  At plan creation every bucket is
+ * timed on its own problems with each shape whose pass plan differs, and the fastest
+ * kept; all shapes sum each entry in the same order, so results do not depend on it. */
+int nnls_batch_plan_tile_shapes(const nnls_batch_plan* plan, int32_t* shapes);
 int nnls_batch_plan_destroy(nnls_batch_plan* plan);
 
 /* ---------------------------------------------------------------------------------

@@ -195,6 +195,12 @@ class BatchPlan:
         st = self.h.lib.nnls_batch_plan_info(self._p, C.cast(self.args.infos, C.c_void_p))
         return st, list(self.args.infos[:self.args.batch])
 
+    def tile_shapes(self) -> dict:
+        """{ceil(n/32): rectangles per wave per pass} as chosen by the autotuner."""
+        out = (C.c_int32 * 9)()
+        self.h.lib.nnls_batch_plan_tile_shapes(self._p, C.cast(out, C.c_void_p))
+        return {k: out[k] for k in range(1, 9) if out[k]}
+
     def close(self):
         if self._p:
             self.h.lib.nnls_batch_plan_destroy(self._p)

@@ -96,6 +96,7 @@ PROTOTYPES = {
     "nnls_batch_plan_execute": (C.c_int, [_P, _P]),
     "nnls_batch_plan_info": (C.c_int, [_P, _P]),
     "nnls_batch_plan_destroy": (C.c_int, [_P]),
+    "nnls_batch_plan_tile_shapes": (C.c_int, [_P, _P]),
     "nnls_server_create": (C.c_int, [C.POINTER(_P), C.c_int, C.POINTER(nnls_server_config),
                                      C.POINTER(nnls_options)]),
     "nnls_server_submit_csc": (C.c_int, [_P, _I32, _I32, _I64, _P, _P, _P, _P, C.POINTER(C.c_uint64)]),

@@ -84,6 +84,7 @@ struct nnls_batch_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   double t0 = 0.0;
+  uint8_t shapes[GS_NR + 1] = {};   // tile shape the autotuner chose per ceil(n / 32) (0: none)
 };
 
 struct nnls_handle {
@@ -1321,6 +1322,61 @@ int nnls_batch_plan_create(nnls_handle* h, int32_t batch, const int32_t* m, cons
   ba.ir_rtol = o.ir_rtol;
   ba.gram_dual = (o.flags & NNLS_FLAG_GRAM_DUAL) != 0 ? 1 : 0;
   ba.max_steps = 0;
+  // Tile-shape autotuner of the Gram kernel: for each 32-column bucket of the batch
+  // (problems with ceil(n / 32) = nr <= GS_NR), time the kernel on that bucket's problems
+  // alone with each accumulator shape whose pass plan differs, and keep the fastest.  The
+  // shapes sum every entry in the same order, so the choice changes no result.
+  {
+    std::vector<std::vector<int32_t>> bucket(GS_NR + 1);
+    for (int i = 0; i < batch; ++i)
+      if (n[i] <= 32 * GS_NR) bucket[(size_t)((n[i] + 31) / 32)].push_back(i);
+    const int qv[2][GS_VARIANTS] = {{2, 3, 4}, {4, 6, 8}};   // rectangles per wave, as in the kernel
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(NNLS_ERR_DEVICE);
+    bool tune_ok = true;
+    for (int nr = 1; nr <= GS_NR && tune_ok; ++nr) {
+      const std::vector<int32_t>& bl = bucket[(size_t)nr];
+      if (bl.empty()) continue;
+      const int nrect = nr * (nr + 1) / 2;
+      int plan_of[GS_VARIANTS];
+      for (int k = 0; k < GS_VARIANTS; ++k) {
+        const int q = qv[ba.fp32 ? 1 : 0][k];
+        const int passes = (nrect + 8 * q - 1) / (8 * q), per = (nrect + passes - 1) / passes;
+        plan_of[k] = passes * 64 + (per + 7) / 8;
+      }
+      tune_ok = hipMemcpy(P->d_order, bl.data(), sizeof(int32_t) * bl.size(), hipMemcpyHostToDevice) == hipSuccess;
+      BatchArgs tb = ba;
+      tb.order = (const int32_t*)P->d_order;
+      int best = -1;
+      float best_ms = 0.0f;
+      for (int k = 0; k < GS_VARIANTS && tune_ok; ++k) {
+        if (k != 1 && plan_of[k] == plan_of[1]) continue;   // the same code as the default
+        tb.gram_variant[nr] = (uint8_t)(1 + k);
+        float t = 0.0f;
+        for (int rep = 0; rep < 3 && tune_ok; ++rep) {   // the first launch warms up
+          tune_ok = hipEventRecord(e0, h->stream) == hipSuccess;
+          launch_batched_gram(h->stream, tb, (int)bl.size());
+          tune_ok = tune_ok && hipEventRecord(e1, h->stream) == hipSuccess &&
+                    hipEventSynchronize(e1) == hipSuccess;
+          float ms = 0.0f;
+          if (tune_ok) tune_ok = hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+          if (rep == 1 || (rep == 2 && ms < t)) t = ms;
+        }
+        if (tune_ok && (best < 0 || t < best_ms)) {
+          best = k;
+          best_ms = t;
+        }
+      }
+      if (best < 0) best = 1;
+      ba.gram_variant[nr] = (uint8_t)(1 + best);
+      P->shapes[nr] = (uint8_t)qv[ba.fp32 ? 1 : 0][best];
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!tune_ok ||
+        hipMemcpy(P->d_order, order.data(), sizeof(int32_t) * (size_t)batch, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(NNLS_ERR_DEVICE);
+  }
   // record: both kernels and the status copy, on a private stream (no memset nodes)
   hipStream_t cs = nullptr;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(NNLS_ERR_DEVICE);
@@ -1379,6 +1435,12 @@ int nnls_batch_plan_info(nnls_batch_plan* plan, nnls_info* info) {
     if (q.status != NNLS_OK && worst == NNLS_OK) worst = q.status;
   }
   return worst;
+}
+
+int nnls_batch_plan_tile_shapes(const nnls_batch_plan* plan, int32_t* shapes) {
+  if (!plan || !shapes) return NNLS_ERR_INVALID_ARG;
+  for (int k = 0; k <= GS_NR; ++k) shapes[k] = plan->shapes[k];
+  return NNLS_OK;
 }
 
 int nnls_batch_plan_destroy(nnls_batch_plan* plan) {

@@ -154,12 +154,17 @@ constexpr int GT = 512;                     // threads of the Gram workgroup
 constexpr int GS_MAXN = 256;
 constexpr int GS_KR = 16;                   // rows per step
 constexpr int GS_CSTEP = GT / GS_KR;        // columns moved per thread step
+// Accumulator tile shapes: the most rectangles a wave holds in one pass, by variant (an
+// argument of the launch, chosen per NR by the autotuner of prepared batches; shape 1 is
+// the default).  Every variant sums each H_ij and c_j in the same order, so the results do
+// not depend on the choice.
 template <typename T> struct GS;
-template <> struct GS<double> { static constexpr int QMAX = 3; };
-template <> struct GS<float> { static constexpr int QMAX = 6; };
-template <typename T, int NR> struct GSPlan {
+template <> struct GS<double> { static constexpr int QV[GS_VARIANTS] = {2, 3, 4}; };
+template <> struct GS<float> { static constexpr int QV[GS_VARIANTS] = {4, 6, 8}; };
+template <typename T, int NR, int V> struct GSPlan {
+  static constexpr int QMAX = GS<T>::QV[V];
   static constexpr int nrect = NR * (NR + 1) / 2;
-  static constexpr int passes = (nrect + 8 * GS<T>::QMAX - 1) / (8 * GS<T>::QMAX);
+  static constexpr int passes = (nrect + 8 * QMAX - 1) / (8 * QMAX);
   static constexpr int per = (nrect + passes - 1) / passes;   // rectangles per pass
   static constexpr int Q = (per + 7) / 8;                     // per wave
   static constexpr int EPT = 32 * NR / GS_CSTEP;              // staged values per thread
@@ -176,13 +181,13 @@ constexpr size_t GS_LDS_BYTES = 2 * GS_KR * (size_t)gs_stride<double>(GS_MAXN) *
 // branches.  Staged values past m or n are read clamped into A and multiplied by zero, so
 // the loads have no branches either.  Returns nonzero when the first pass met a value of
 // A or b that is not finite (H and c are then not meaningful).
-template <typename T, int NR>
+template <typename T, int NR, int V>
 __device__ __noinline__ int gram_pass(const double* __restrict__ A, int lda, int m, int n,
                                       const double* __restrict__ b, T* __restrict__ H, double* __restrict__ c,
                                       T* St, int t0, int tend) {
   typedef MF<T> M;
   typedef typename M::acc Acc;
-  typedef GSPlan<T, NR> PL;
+  typedef GSPlan<T, NR, V> PL;
   constexpr int KR = GS_KR, CSTEP = GS_CSTEP, EPT = PL::EPT, Q = PL::Q;
   constexpr int npad = 32 * NR, SR = gs_stride<T>(npad);
   static_assert(CSTEP * EPT == npad, "staging covers the padded columns");
@@ -301,26 +306,39 @@ __device__ __noinline__ int gram_pass(const double* __restrict__ A, int lda, int
   return any_bad;
 }
 
-template <typename T, int NR>
+template <typename T, int NR, int V>
 __device__ inline int gram_passes(const double* A, int lda, int m, int n, const double* b, T* H, double* c, T* St) {
-  typedef GSPlan<T, NR> PL;
+  typedef GSPlan<T, NR, V> PL;
   int bad = 0;
   for (int t0 = 0; t0 < PL::nrect && !bad; t0 += PL::per)
-    bad = gram_pass<T, NR>(A, lda, m, n, b, H, c, St, t0, min(PL::nrect, t0 + PL::per));
+    bad = gram_pass<T, NR, V>(A, lda, m, n, b, H, c, St, t0, min(PL::nrect, t0 + PL::per));
   return bad;
 }
 
+template <typename T, int NR>
+__device__ inline int gram_variant(int v, const double* A, int lda, int m, int n, const double* b, T* H, double* c,
+                                   T* St) {
+  switch (v) {
+    case 0: return gram_passes<T, NR, 0>(A, lda, m, n, b, H, c, St);
+    case 2: return gram_passes<T, NR, 2>(A, lda, m, n, b, H, c, St);
+    default: return gram_passes<T, NR, 1>(A, lda, m, n, b, H, c, St);
+  }
+}
+
 template <typename T>
-__device__ int wg_gram_stream(const double* A, int lda, int m, int n, const double* b, T* H, double* c, T* St) {
-  switch ((n + 31) >> 5) {
-    case 1: return gram_passes<T, 1>(A, lda, m, n, b, H, c, St);
-    case 2: return gram_passes<T, 2>(A, lda, m, n, b, H, c, St);
-    case 3: return gram_passes<T, 3>(A, lda, m, n, b, H, c, St);
-    case 4: return gram_passes<T, 4>(A, lda, m, n, b, H, c, St);
-    case 5: return gram_passes<T, 5>(A, lda, m, n, b, H, c, St);
-    case 6: return gram_passes<T, 6>(A, lda, m, n, b, H, c, St);
-    case 7: return gram_passes<T, 7>(A, lda, m, n, b, H, c, St);
-    default: return gram_passes<T, 8>(A, lda, m, n, b, H, c, St);
+__device__ int wg_gram_stream(const double* A, int lda, int m, int n, const double* b, T* H, double* c, T* St,
+                              const uint8_t* variant) {
+  const int nr = (n + 31) >> 5;
+  const int v = variant[nr] == 0 ? 1 : variant[nr] - 1;   // 0: the default shape; 1 + k: shape k
+  switch (nr) {
+    case 1: return gram_variant<T, 1>(v, A, lda, m, n, b, H, c, St);
+    case 2: return gram_variant<T, 2>(v, A, lda, m, n, b, H, c, St);
+    case 3: return gram_variant<T, 3>(v, A, lda, m, n, b, H, c, St);
+    case 4: return gram_variant<T, 4>(v, A, lda, m, n, b, H, c, St);
+    case 5: return gram_variant<T, 5>(v, A, lda, m, n, b, H, c, St);
+    case 6: return gram_variant<T, 6>(v, A, lda, m, n, b, H, c, St);
+    case 7: return gram_variant<T, 7>(v, A, lda, m, n, b, H, c, St);
+    default: return gram_variant<T, 8>(v, A, lda, m, n, b, H, c, St);
   }
 }
 
@@ -731,8 +749,10 @@ __global__ __launch_bounds__(GT, 1) void k_batched_gram(BatchArgs a) {
   int bad = 0;
   if (n <= GS_MAXN) {
     double* c = (double*)(base + Lw.c);
-    if (a.fp32) bad = wg_gram_stream<float>(P.A, P.lda, m, n, P.b, (float*)(base + Lw.H), c, (float*)smem);
-    else bad = wg_gram_stream<double>(P.A, P.lda, m, n, P.b, (double*)(base + Lw.H), c, (double*)smem);
+    if (a.fp32)
+      bad = wg_gram_stream<float>(P.A, P.lda, m, n, P.b, (float*)(base + Lw.H), c, (float*)smem, a.gram_variant);
+    else
+      bad = wg_gram_stream<double>(P.A, P.lda, m, n, P.b, (double*)(base + Lw.H), c, (double*)smem, a.gram_variant);
   }
   if (tid == 0) {   // every field: the status array may hold an earlier launch's values
     info->status = bad ? NNLS_ERR_INVALID_VALUE : 0;

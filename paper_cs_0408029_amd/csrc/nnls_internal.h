@@ -248,6 +248,8 @@ struct BatchProblem {
   BatchInfo* info;        // the problem's result and status, kept across launches
   char* ws;               // the problem's workspace (batched_workspace_bytes), 256-byte aligned
 };
+constexpr int GS_NR = 8;         // the streamed Gram kernel takes n <= 32 GS_NR
+constexpr int GS_VARIANTS = 3;   // its accumulator tile shapes (k = 0, 1, 2; 1 the default)
 struct BatchArgs {
   int count;
   const BatchProblem* probs;
@@ -260,6 +262,7 @@ struct BatchArgs {
   double ir_rtol;
   int gram_dual;          // y_G from the cached Gram matrix (Eq. 3) instead of Eq. 5
   int max_steps;          // pivot iterations per launch of the pivoting kernel; <= 0: all
+  uint8_t gram_variant[GS_NR + 1];   // Gram kernel tile shape by ceil(n / 32): 0 default, 1 + k shape k
 };
 size_t batched_workspace_bytes(int m, int n);
 // Whole solves: the Gram kernel, then the pivoting kernel until every problem is done.

@@ -210,6 +210,9 @@ def test_plan_replays_match_eager(h, batch24, precision):
     xe = [nan(A.shape[1]) for A, _ in problems]
     ye = [nan(A.shape[1]) for A, _ in problems]
     plan = N.BatchPlan(h, As, bs, xs, ys, opts)
+    shapes = plan.tile_shapes()   # the autotuner's choice per 32-column bucket
+    assert set(shapes) == {(A.shape[1] + 31) // 32 for A, _ in problems}
+    assert all(v in ((2, 3, 4) if precision == 0 else (4, 6, 8)) for v in shapes.values())
     for k, scale in enumerate([1.0, 0.5, 2.0, 1.0, -1.0]):
         for b, (_, b0) in zip(bs, problems):          # eager work between the replays
             b.copy_(torch.from_numpy(b0 * scale).to(DEV))
