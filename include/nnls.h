@@ -385,6 +385,11 @@ int nnls_gram_csc(nnls_handle* h, int32_t m, int32_t n, int64_t nnz, const int32
                   const int32_t* rowidx, const double* val, const double* b, double* H,
                   int32_t ldh, double* c);
 
+/* The same for a dense A (device, column-major m x n, lda >= m): H on MFMA float64, one
+ * workgroup per 64 x 64 tile of its lower half, mirrored. */
+int nnls_gram_dense(nnls_handle* h, int32_t m, int32_t n, const double* A, int32_t lda, const double* b,
+                    double* H, int32_t ldh, double* c);
+
 /* Cholesky factor of the symmetric positive definite n x n matrix S (device, column-major,
  * lower triangle read) into L (device, column-major, ldl >= n; the strict upper triangle
  * is written as zero).  This is the factor of Sec. 2.1, run by the tiled MFMA kernel the

@@ -255,6 +255,19 @@ def nnls_gram_csc(h: Handle, m: int, n: int, colptr, rowidx, val, b, H, c) -> in
                                H.stride(1) if n > 1 else n, _ptr(c, torch.float64, "c", n))
 
 
+def nnls_gram_dense(h: Handle, A, b, H, c) -> int:
+    """A: column-major float64 device matrix (m, n); H: (n, n) column-major; c: (n,)."""
+    torch = _torch()
+    m, n = A.shape
+    if A.dtype != torch.float64 or not A.is_cuda or A.stride(0) != 1:
+        raise ValueError("A: expected a column-major float64 device matrix")
+    if H.dtype != torch.float64 or not H.is_cuda or H.stride(0) != 1 or H.shape != (n, n):
+        raise ValueError("H: expected an (n, n) column-major float64 device tensor")
+    return h.lib.nnls_gram_dense(h.ptr, m, n, C.c_void_p(A.data_ptr()), A.stride(1) if n > 1 else m,
+                                 _ptr(b, torch.float64, "b", m), C.c_void_p(H.data_ptr()),
+                                 H.stride(1) if n > 1 else n, _ptr(c, torch.float64, "c", n))
+
+
 def _colmajor(M, name):
     torch = _torch()
     if M.dtype != torch.float64 or not M.is_cuda or M.stride(0) != 1 or M.dim() != 2:

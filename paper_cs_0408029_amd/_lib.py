@@ -111,6 +111,7 @@ PROTOTYPES = {
     "nnls_reset_profile": (C.c_int, [_P]),
     "nnls_set_profiling": (C.c_int, [_P, C.c_int]),
     "nnls_gram_csc": (C.c_int, [_P, _I32, _I32, _I64, _P, _P, _P, _P, _P, _I32, _P]),
+    "nnls_gram_dense": (C.c_int, [_P, _I32, _I32, _P, _I32, _P, _P, _I32, _P]),
     "nnls_cholesky": (C.c_int, [_P, _I32, _P, _I32, _P, _I32, _I32, C.POINTER(_I32)]),
     "nnls_spd_solve": (C.c_int, [_P, _I32, _P, _I32, _P, _P, C.POINTER(_I32)]),
     "nnls_dual_csc": (C.c_int, [_P, _I32, _I32, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),

@@ -1515,6 +1515,17 @@ int nnls_gram_csc(nnls_handle* h, int32_t m, int32_t n, int64_t nnz, const int32
   return NNLS_OK;
 }
 
+int nnls_gram_dense(nnls_handle* h, int32_t m, int32_t n, const double* A, int32_t lda, const double* b,
+                    double* H, int32_t ldh, double* c) {
+  if (!h || n < 1 || m < 1 || !A || lda < m || !b || !H || !c || ldh < n) return NNLS_ERR_INVALID_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return NNLS_ERR_DEVICE;
+  launch_gram_dense(h->stream, m, n, A, lda, H, ldh);
+  launch_gemvT_dense(h->stream, m, n, A, lda, b, c, 1.0);
+  if (hipGetLastError() != hipSuccess) return NNLS_ERR_DEVICE;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return NNLS_OK;
+}
+
 int nnls_cholesky(nnls_handle* h, int32_t n, const double* S, int32_t lds, double* L, int32_t ldl,
                   int32_t precision, int32_t* failed) {
   if (failed) *failed = -1;

@@ -8,7 +8,7 @@
 // and for every new F order the F-block is re-indexed into F-position space, each
 // position keeping the entries at or below the diagonal in position order: the factor
 // gathers its tiles from that.
-#include "nnls_internal.h"
+#include "tile_ops.h"
 
 namespace nnls {
 
@@ -450,24 +450,81 @@ __global__ void k_lower_to_dense(int n, GramLower g, double* H, int ldh) {
   }
 }
 
-// Dense H = A^T A, 16 x 16 output tile per workgroup, rows of A staged through LDS in
-// slabs of 16; each entry is summed in ascending row order.
+// Dense H = A^T A on MFMA float64: one workgroup per 64 x 64 tile on or below the
+// diagonal of H (tiles taken column by column).  Rows of A are staged in LDS 16 at a time
+// for the tile's two column blocks (one block on the diagonal), double-buffered, with the
+// next rows' loads in flight while the current ones are multiplied; each of the four waves
+// accumulates a 32 x 32 quadrant as 2 x 2 blocks of 16.  Each H_ij is summed over the rows
+// in a fixed order; the tile is written to both triangles (a diagonal tile from its lower
+// half, so each entry has one writer).
+constexpr int GD_KR = 16, GD_LD = 64 + 4;
 __global__ __launch_bounds__(256) void k_gram_dense(int m, int n, const double* __restrict__ A, int lda,
                                                     double* __restrict__ H, int ldh) {
-  __shared__ double sa[16][17], sb[16][17];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int i = blockIdx.y * 16 + ty, j = blockIdx.x * 16 + tx;
-  const int ci = blockIdx.y * 16 + tx, cj = blockIdx.x * 16 + tx;
-  double s = 0.0;
-  for (int r0 = 0; r0 < m; r0 += 16) {
-    const int r = r0 + ty;
-    sa[ty][tx] = (r < m && ci < n) ? A[r + (int64_t)ci * lda] : 0.0;   // sa[row][col i]
-    sb[ty][tx] = (r < m && cj < n) ? A[r + (int64_t)cj * lda] : 0.0;
-    __syncthreads();
-    for (int q = 0; q < 16; ++q) s = fma(sa[q][ty], sb[q][tx], s);
-    __syncthreads();
+  typedef MF<double> M;
+  __shared__ double Sa[2][GD_KR * GD_LD], Sb[2][GD_KR * GD_LD];
+  const int nb = (n + 63) / 64;
+  int t = blockIdx.x, J = 0;
+  while (t >= nb - J) {
+    t -= nb - J;
+    ++J;
   }
-  if (i < n && j < n) H[i + (int64_t)j * ldh] = s;
+  const int I = J + t;
+  const bool diag = I == J;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, lr = lane & 15, lk = lane >> 4;
+  const int qr = (w & 1) * 32, qc = (w >> 1) * 32;
+  // staging: thread tid moves row srow of columns scol + 16 u (u < 4) of each block
+  const int srow = tid & 15, scol = tid >> 4;
+  const int ci0 = I * 64 + scol, cj0 = J * 64 + scol;
+  double pa[4], pb[4];
+  auto fetch = [&](int r0) __attribute__((always_inline)) {
+    const double* rowp = A + min(r0 + srow, m - 1);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      pa[u] = rowp[(int64_t)min(ci0 + 16 * u, n - 1) * lda];
+      pb[u] = rowp[(int64_t)min(cj0 + 16 * u, n - 1) * lda];   // on the diagonal, a copy of pa
+    }
+  };
+  M::acc acc[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = (M::acc){0.0, 0.0, 0.0, 0.0};
+  const int nch = (m + GD_KR - 1) / GD_KR;
+  fetch(0);
+  for (int ch = 0; ch < nch; ++ch) {
+    double* sa = Sa[ch & 1];
+    double* sb = diag ? sa : Sb[ch & 1];
+    const bool rin = ch * GD_KR + srow < m;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      sa[srow * GD_LD + scol + 16 * u] = (rin && ci0 + 16 * u < n) ? pa[u] : 0.0;
+      if (!diag) sb[srow * GD_LD + scol + 16 * u] = (rin && cj0 + 16 * u < n) ? pb[u] : 0.0;
+    }
+    __syncthreads();   // also: every wave is done with the buffer written next step
+    if (ch + 1 < nch) fetch((ch + 1) * GD_KR);
+#pragma unroll
+    for (int kk = 0; kk < GD_KR; kk += 4) {
+      const double* ra = sa + (kk + lk) * GD_LD + lr;
+      const double* rb = sb + (kk + lk) * GD_LD + lr;
+      const double a0 = ra[qr], a1 = ra[qr + 16], b0 = rb[qc], b1 = rb[qc + 16];
+      acc[0][0] = M::op(a0, b0, acc[0][0]);
+      acc[0][1] = M::op(a0, b1, acc[0][1]);
+      acc[1][0] = M::op(a1, b0, acc[1][0]);
+      acc[1][1] = M::op(a1, b1, acc[1][1]);
+    }
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = I * 64 + qr + 16 * bi + M::row(lane, v), j = J * 64 + qc + 16 * bj + lr;
+        if (i < n && j < n && (!diag || i >= j)) {
+          H[i + (int64_t)j * ldh] = acc[bi][bj][v];
+          H[j + (int64_t)i * ldh] = acc[bi][bj][v];
+        }
+      }
 }
 
 // out_j = scale * sum_r A_rj v_r: one wave per column, fixed lane-stride partial sums and
@@ -604,8 +661,8 @@ void launch_lower_to_dense(hipStream_t s, int n, GramLower g, double* H, int ldh
 }
 
 void launch_gram_dense(hipStream_t s, int m, int n, const double* A, int lda, double* H, int ldh) {
-  dim3 grid((n + 15) / 16, (n + 15) / 16);
-  hipLaunchKernelGGL(k_gram_dense, grid, dim3(256), 0, s, m, n, A, lda, H, ldh);
+  const int nb = (n + 63) / 64;
+  hipLaunchKernelGGL(k_gram_dense, dim3((unsigned)(nb * (nb + 1) / 2)), dim3(256), 0, s, m, n, A, lda, H, ldh);
 }
 
 void launch_gemvT_dense(hipStream_t s, int m, int n, const double* A, int lda, const double* v,

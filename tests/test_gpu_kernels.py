@@ -41,6 +41,28 @@ def test_gram_and_rhs(h, m, n, density, seed):
     assert np.allclose(c.cpu().numpy(), c_or, rtol=1e-13, atol=1e-13 * np.abs(c_or).max())
 
 
+@pytest.mark.parametrize("m,n,seed", [(1, 1, 1), (17, 3, 2), (70, 65, 3), (300, 129, 4), (1000, 257, 5),
+                                      (64, 64, 6), (5003, 100, 7), (130, 130, 8)])
+def test_gram_dense_mfma(h, m, n, seed):
+    """Dense H = A^T A on MFMA (64 x 64 tiles of its lower half, ragged edges, 16-row steps)
+    and c = A^T b, against the oracle's Gram step, within the float64 dot-product bound
+    m eps (|A|^T |A|)_ij; H exactly symmetric."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, n))
+    b = rng.standard_normal(m)
+    H = colmajor_dev(np.full((n, n), np.nan))
+    c = torch.empty(n, dtype=torch.float64, device=DEV)
+    assert N.nnls_gram_dense(h, colmajor_dev(A), t(b), H, c) == N.NNLS_OK
+    H_or, c_or = gram(A, b)
+    H_or = np.asarray(H_or.toarray() if hasattr(H_or, "toarray") else H_or)
+    bound = (np.abs(A).T @ np.abs(A)) * (m * EPS) + 1e-300
+    Hg = H.cpu().numpy()
+    assert np.all(np.abs(Hg - H_or) <= bound)
+    assert np.array_equal(Hg, Hg.T)
+    cb = (np.abs(A).T @ np.abs(b)) * (m * EPS) + 1e-300
+    assert np.all(np.abs(c.cpu().numpy() - c_or) <= cb)
+
+
 def test_gram_windows_sweeps_and_long_rows(h):
     """The Gram kernel's rarer paths: more than one 32768-row window (n = 33000, with one
     row of A meeting columns on both sides of the window edge), columns of H with more than
