@@ -389,6 +389,191 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
   publish_tile(&a.tflag[ti], &a.colcnt[J], a.epoch);
 }
 
+// A strip of cnt <= R off-diagonal tiles (I0 + r, J) of one column (bfloat16 updates):
+// every step k stages L_Jk once and the cnt tiles L_{I0+r,k}, and the four waves each
+// update their 32 x 32 quadrant of every tile of the strip, so one load of L_Jk and one
+// pair of barriers serve R tiles (R + 1 tile loads for R outputs instead of 2 R).  Two
+// steps' operand copies are in flight in registers.  Each tile is finished as in
+// chol_tile: L_IJ = S_IJ (L_JJ^-1)^T, stored, copied to bfloat16 and published.
+// stage: (R + 1) bfloat16 tiles with row stride LDK; S (a float tile) aliases it.
+constexpr size_t STRIP_STAGE_BYTES = (size_t)(CHOL_STRIP + 1) * TILE * LDK * 2;
+
+template <int R>
+__device__ __forceinline__ void chol_strip(const FactorArgs& a, uint64_t wait_ticks, int I0, int cnt, int J,
+                                        char* stage) {
+  typedef MF<float> M;
+  typedef M::acc Acc;
+  const int tid = fresh_tid(), lane = tid & 63, w = tid >> 6;
+  const int nb = a.nb, j0 = a.j0;
+  float* Lt = (float*)a.Ltiles;
+  const float* Dv = (const float*)a.Dinv;
+  const uint16_t* Lb = (const uint16_t*)a.Lbf;
+  float* S = (float*)stage;
+  uint16_t* HB = (uint16_t*)stage;   // L_Jk
+  const int qr = (w & 1) * 32, qc = (w >> 1) * 32, lr = lane & 15, lk = lane >> 4;
+  Acc acc[R][2][2];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[r][bi][bj][v] = 0.0f;
+    if (r < cnt) {
+      gather_tile<float>(a, tid, I0 + r, J, S);
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            acc[r][bi][bj][v] = S[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT];
+      __syncthreads();   // S is overwritten by the next gather or the first step's operands
+    }
+  }
+  const bool needJ = J >= j0;   // L_Jk is computed in this launch
+  int known = 0;                // leading columns this thread knows are complete
+  auto ready = [&](int k1, bool block) -> bool {
+    if (k1 < known) return true;
+    if (ld_relaxed(&a.colcnt[k1]) >= nb - max(k1, j0)) {
+      known = k1 + 1;
+      while (known < J && ld_relaxed(&a.colcnt[known]) >= nb - max(known, j0)) ++known;
+    } else if (!block) {
+      for (int r = 0; r < cnt; ++r)
+        if (ld_relaxed(&a.tflag[tile_index(I0 + r, k1)]) != a.epoch) return false;
+      if (needJ && ld_relaxed(&a.tflag[tile_index(J, k1)]) != a.epoch) return false;
+    } else {
+      for (int r = 0; r < cnt; ++r) spin_until(&a.tflag[tile_index(I0 + r, k1)], a.epoch, true, a.ctrl, wait_ticks);
+      if (needJ) spin_until(&a.tflag[tile_index(J, k1)], a.epoch, true, a.ctrl, wait_ticks);
+    }
+    acquire_agent();
+    return true;
+  };
+  constexpr int PD = 2;
+  u32x4 rg[PD][R + 1][2];
+  int held[PD];
+  auto fetch = [&](auto slot, int s1) __attribute__((always_inline)) {
+    constexpr int d = decltype(slot)::value;
+    const u32x4* gj = (const u32x4*)(Lb + tile_index(J, s1) * TILE_ELEMS) + 2 * tid;
+    rg[d][R][0] = gj[0];
+    rg[d][R][1] = gj[1];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (r < cnt) {
+        const u32x4* gi = (const u32x4*)(Lb + tile_index(I0 + r, s1) * TILE_ELEMS) + 2 * tid;
+        rg[d][r][0] = gi[0];
+        rg[d][r][1] = gi[1];
+      }
+    held[d] = s1;
+  };
+  auto prime = [&](auto slot) __attribute__((always_inline)) {
+    constexpr int d = decltype(slot)::value;
+    held[d] = -1;
+    if (d < J && ready(d, d == 0)) fetch(slot, d);
+  };
+  prime(std::integral_constant<int, 0>{});
+  prime(std::integral_constant<int, 1>{});
+  auto step = [&](auto slot, int k) __attribute__((always_inline)) {
+    constexpr int d = decltype(slot)::value;
+    if (held[d] != k) {   // at the frontier: wait for this step's tiles
+      ready(k, true);
+      fetch(slot, k);
+    }
+    __syncthreads();   // the previous step's products have read the staged operands
+    {
+      const int o = (tid >> 2) * LDK + (tid & 3) * 16;
+      ((u32x4*)(HB + o))[0] = rg[d][R][0];
+      ((u32x4*)(HB + o))[1] = rg[d][R][1];
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (r < cnt) {
+          uint16_t* HA = HB + (r + 1) * TILE * LDK;
+          ((u32x4*)(HA + o))[0] = rg[d][r][0];
+          ((u32x4*)(HA + o))[1] = rg[d][r][1];
+        }
+    }
+    __syncthreads();
+    held[d] = -1;
+    if (k + PD < J && ready(k + PD, false)) fetch(slot, k + PD);
+#pragma unroll
+    for (int kh = 0; kh < TILE; kh += 32) {
+      const int kofs = kh + 8 * lk;
+      const bf16x8 b0 = __builtin_bit_cast(bf16x8, *(const u32x4*)(HB + (qc + lr) * LDK + kofs));
+      const bf16x8 b1 = __builtin_bit_cast(bf16x8, *(const u32x4*)(HB + (qc + 16 + lr) * LDK + kofs));
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (r < cnt) {
+          const uint16_t* HA = HB + (r + 1) * TILE * LDK;
+          u32x4 x0 = *(const u32x4*)(HA + (qr + lr) * LDK + kofs);
+          u32x4 x1 = *(const u32x4*)(HA + (qr + 16 + lr) * LDK + kofs);
+          const uint32_t neg = 0x80008000u;   // S -= L_Ik L_Jk^T: negate the L_Ik operand
+          x0 ^= neg;
+          x1 ^= neg;
+          const bf16x8 a0 = __builtin_bit_cast(bf16x8, x0), a1 = __builtin_bit_cast(bf16x8, x1);
+          acc[r][0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[r][0][0], 0, 0, 0);
+          acc[r][0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[r][0][1], 0, 0, 0);
+          acc[r][1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[r][1][0], 0, 0, 0);
+          acc[r][1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[r][1][1], 0, 0, 0);
+        }
+    }
+  };
+  for (int k0 = 0; k0 < J; k0 += PD) {
+    step(std::integral_constant<int, 0>{}, k0);
+    if (k0 + 1 < J) step(std::integral_constant<int, 1>{}, k0 + 1);
+  }
+  __syncthreads();   // the last products have read the staged operands
+  if (needJ) {
+    spin_until(&a.dflag[J], a.epoch, true, a.ctrl, wait_ticks);
+    acquire_agent();
+  }
+  const float* D = Dv + (int64_t)J * TILE_ELEMS;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (r >= cnt) continue;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          S[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT] = acc[r][bi][bj][v];
+    __syncthreads();
+    Acc o[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[bi][bj][v] = 0.0f;
+#pragma unroll
+    for (int kk = 0; kk < TILE; kk += 4) {
+      const int kc = kk + lk;
+      const float a0 = S[(qr + lr) + kc * LDT], a1 = S[(qr + 16 + lr) + kc * LDT];
+      const float b0 = D[kc * TILE + qc + lr], b1 = D[kc * TILE + qc + 16 + lr];
+      o[0][0] = M::op(a0, b0, o[0][0]);
+      o[0][1] = M::op(a0, b1, o[0][1]);
+      o[1][0] = M::op(a1, b0, o[1][0]);
+      o[1][1] = M::op(a1, b1, o[1][1]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          S[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT] = o[bi][bj][v];
+    __syncthreads();
+    const int64_t ti = tile_index(I0 + r, J);
+    float* dst = Lt + ti * TILE_ELEMS;
+    for (int e = tid; e < TILE_ELEMS; e += 256) dst[e] = S[(e & (TILE - 1)) + (e >> 6) * LDT];
+    bf16_copy_to_global((uint16_t*)a.Lbf + ti * TILE_ELEMS, S, tid);
+    publish_tile(&a.tflag[ti], &a.colcnt[J], a.epoch);
+    __syncthreads();   // S is rewritten by the next tile of the strip
+  }
+}
+
 // The walker's update of the ten lower 16 x 16 blocks of a diagonal tile, U -= X X^T,
 // spread over four waves (three blocks for waves 0..2, one for wave 3).  A wave's blocks
 // (I0, J0), (I1, J1), (I2, J2), the first NB of them, share the block rows of X they read.
@@ -618,15 +803,27 @@ __device__ __forceinline__ void walker(const FactorArgs& a, uint64_t wait_ticks,
   }
 }
 
-// Ticket t -> lower tile (I, J) in column-major order over the rows I >= max(J, j0).
-__device__ inline void decode_ticket(int t, int nb, int j0, int* I, int* J) {
-  int j = 0, start = 0;
-  while (t >= start + (nb - max(j, j0))) {
-    start += nb - max(j, j0);
-    ++j;
-  }
-  *I = max(j, j0) + (t - start);
+// Ticket t -> unit (I, J, cnt): cnt tiles (I .. I + cnt - 1, J) in the order of col_units,
+// column by column (R = 1: single tiles, rows I >= max(J, j0) in order).
+__device__ inline void decode_ticket(int t, int nb, int j0, int R, int* I, int* J, int* cnt) {
+  int j = 0;
+  for (int u = col_units(0, nb, j0, R); t >= u; u = col_units(++j, nb, j0, R)) t -= u;
   *J = j;
+  *cnt = 1;
+  if (j >= j0) {
+    if (t == 0) {
+      *I = j;
+      return;
+    }
+    if (t == 1 && j + 1 < nb) {
+      *I = j + 1;
+      return;
+    }
+    t -= j + 1 < nb ? 2 : 1;
+  }
+  const int first = j >= j0 ? j + 2 : j0;
+  *I = first + t * R;
+  *cnt = min(R, nb - *I);
 }
 
 // A persistent grid: each workgroup takes tickets until none are left, so a launch holds
@@ -636,32 +833,44 @@ __device__ inline void decode_ticket(int t, int nb, int j0, int* I, int* J) {
 // hold, so the lowest unfinished ticket always progresses.
 template <typename T, bool BF>
 __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wait_ticks) {
-  __shared__ T S[TILE * LDT];
-  __shared__ T W[TILE * LDT];
+  // two staged tiles (the walker's and a single tile's buffers), or a strip's operands
+  constexpr size_t TWO = 2 * (size_t)TILE * LDT * sizeof(T);
+  __shared__ __attribute__((aligned(16))) char smem[BF && STRIP_STAGE_BYTES > TWO ? STRIP_STAGE_BYTES : TWO];
+  T* S = (T*)smem;
+  T* W = S + TILE * LDT;
   __shared__ double s_part[4][TILE];
   __shared__ double s_rhs[TILE];
   __shared__ double s_z[TILE];
   __shared__ double s_tp[TILE];
-  __shared__ int s_t, s_I, s_J;
-  const int64_t ntiles = tile_count_from(a.nb, a.j0);
+  __shared__ int s_t, s_I, s_J, s_cnt;
+  constexpr int R = BF ? CHOL_STRIP : 1;
+  const int64_t nunits = unit_count_from(a.nb, a.j0, R);
   for (;;) {
     const int tid = fresh_tid();
     if (tid == 0) {
       const int t = atomicAdd(&a.ctrl->chol_ticket, 1) - 1;   // ticket 0 is the walker
-      int I = 0, J = 0;
-      if (t >= 0 && t < ntiles) decode_ticket(t, a.nb, a.j0, &I, &J);
+      int I = 0, J = 0, cnt = 1;
+      if (t >= 0 && t < nunits) decode_ticket(t, a.nb, a.j0, R, &I, &J, &cnt);
       s_t = t;
       s_I = I;
       s_J = J;
+      s_cnt = cnt;
     }
     __syncthreads();
-    const int t = s_t, I = s_I, J = s_J;
+    const int t = s_t, I = s_I, J = s_J, cnt = s_cnt;
     __syncthreads();   // every thread has its ticket before thread 0 may take the next
     if (t < 0) {
       walker<T, BF>(a, wait_ticks, S, W, s_part, s_rhs, s_z, s_tp);
       return;
     }
-    if (t >= ntiles) return;
+    if (t >= nunits) return;
+    if constexpr (BF) {
+      if (I >= J + 2 || J < a.j0) {   // a strip of plain off-diagonal tiles
+        chol_strip<CHOL_STRIP>(a, wait_ticks, I, cnt, J, smem);
+        __syncthreads();
+        continue;
+      }
+    }
     chol_tile<T, BF>(a, wait_ticks, tid, I, J, S, W, s_part);
     __syncthreads();   // LDS is reused by the next tile
   }
@@ -835,7 +1044,7 @@ __global__ void k_tiles_to_dense(int n, const T* __restrict__ Lt, double* __rest
 
 void launch_cholesky(hipStream_t s, const FactorArgs& a, bool fp32) {
   if (a.nb <= 0 || a.j0 < 0 || a.j0 >= a.nb) return;
-  int64_t grid = tile_count_from(a.nb, a.j0) + 1;   // the tiles and the walker
+  int64_t grid = unit_count_from(a.nb, a.j0, fp32 && a.Lbf ? CHOL_STRIP : 1) + 1;   // the units and the walker
   if (a.max_wgs > 0 && grid > a.max_wgs) grid = a.max_wgs < 2 ? 2 : a.max_wgs;   // walker + >= 1 worker
   if (fp32 && a.Lbf)
     hipLaunchKernelGGL((k_chol_tiles<float, true>), dim3((unsigned)grid), dim3(256), 0, s, a, a.wait_ticks);

@@ -71,6 +71,22 @@ __host__ __device__ inline int64_t tile_count(int nb) { return (int64_t)nb * (nb
 __host__ __device__ inline int64_t tile_count_from(int nb, int j0) {
   return (int64_t)j0 * (nb - j0) + tile_count(nb - j0);
 }
+// Units of work of a factor launch whose off-diagonal tiles are taken in strips of up to R
+// consecutive rows of one column: a computed column J >= j0 gives its diagonal tile, its
+// sub-diagonal tile and the rows J+2 .. nb-1 in strips; a kept column J < j0 gives the rows
+// j0 .. nb-1 in strips.  With R = 1 every unit is one tile, in the order of tile_count_from.
+__host__ __device__ inline int col_units(int J, int nb, int j0, int R) {
+  const int first = J >= j0 ? J + 2 : j0;   // first row taken in strips
+  const int rows = nb - first;
+  const int lead = J >= j0 ? (J + 1 < nb ? 2 : 1) : 0;
+  return lead + (rows > 0 ? (rows + R - 1) / R : 0);
+}
+__host__ __device__ inline int64_t unit_count_from(int nb, int j0, int R) {
+  int64_t u = 0;
+  for (int J = 0; J < nb; ++J) u += col_units(J, nb, j0, R);
+  return u;
+}
+constexpr int CHOL_STRIP = 4;   // rows per strip of the bfloat16-update factor
 
 // ---------------------------------------------------------------- launchers
 // setup (k_setup.hip)
