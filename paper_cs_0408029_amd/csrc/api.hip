@@ -411,6 +411,9 @@ SolveArgs solve_args(nnls_handle* h, int nF, const int32_t* Flist, const double*
   a.ctrl = (Ctrl*)h->ctrl.p;
   a.wait_ticks = h->wait_ticks;
   a.part = (double*)h->spart.p;
+  // a factor with bfloat16 updates also has bfloat16 copies of its off-diagonal tiles: the
+  // solves read those (half the bytes of L; refinement absorbs the rounding)
+  a.Lbf = h->fact_prec == PREC_BF16 ? h->Lbf.p : nullptr;
   if (!h->slots_empty) {   // each launch empties every slot it fills, unless it stopped early
     launch_fill_i32(h->stream, (int32_t*)h->spart.p, (int64_t)(h->spart.bytes / 4), SLOT_EMPTY_WORD);
     h->slots_empty = true;

@@ -906,6 +906,26 @@ __device__ inline void load_term_tile(const T* Lt, int I, int K, int r, int g, T
   }
 }
 
+// The same from the bfloat16 row-major copy of the tile (element (r, c) at r TILE + c).
+template <bool FWD>
+__device__ inline void load_term_tile_bf(const uint16_t* Lb, int I, int K, int r, int g, float (&v)[16]) {
+  if (FWD) {   // row r, columns 16 g .. 16 g + 15: 32 contiguous bytes
+    const u32x4* p = (const u32x4*)(Lb + tile_index(I, K) * TILE_ELEMS + r * TILE + g * 16);
+    const u32x4 w0 = p[0], w1 = p[1];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[2 * q] = __uint_as_float(w0[q] << 16);
+      v[2 * q + 1] = __uint_as_float(w0[q] & 0xFFFF0000u);
+      v[8 + 2 * q] = __uint_as_float(w1[q] << 16);
+      v[8 + 2 * q + 1] = __uint_as_float(w1[q] & 0xFFFF0000u);
+    }
+  } else {     // column r, rows 16 g .. 16 g + 15 of L_KI
+    const uint16_t* tl = Lb + tile_index(K, I) * TILE_ELEMS;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = __uint_as_float((uint32_t)tl[(g * 16 + q) * TILE + r] << 16);
+  }
+}
+
 template <typename T, bool FWD>
 __device__ inline void load_dinv(const T* Dv, int I, int r, int g, T (&v)[16]) {
   const T* D = Dv + (int64_t)I * TILE_ELEMS;
@@ -913,7 +933,7 @@ __device__ inline void load_dinv(const T* Dv, int I, int r, int g, T (&v)[16]) {
   for (int q = 0; q < 16; ++q) v[q] = FWD ? D[(g * 16 + q) * TILE + r] : D[r * TILE + g * 16 + q];
 }
 
-template <typename T, bool FWD, int TD>
+template <typename T, bool FWD, int TD, bool BF>
 __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ticks) {
   __shared__ double part[4][TILE];
   __shared__ double srhs[TILE];
@@ -928,6 +948,11 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
   if (t >= nb) return;   // also covers a counter that was not reset
   const T* Lt = (const T*)a.Ltiles;
   const T* Dv = (const T*)a.Dinv;
+  const uint16_t* Lb = (const uint16_t*)a.Lbf;
+  auto load_term = [&](int I1, int K1, T (&v)[16]) __attribute__((always_inline)) {
+    if constexpr (BF) load_term_tile_bf<FWD>(Lb, I1, K1, r, g, v);
+    else load_term_tile<T, FWD>(Lt, I1, K1, r, g, v);
+  };
   double* outv = FWD ? a.z : a.xF;
   double* xsl = a.part + (int64_t)nb * TILE;   // the walker's outputs, one slot per row
 
@@ -937,7 +962,7 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
     const int last = t - TD;   // steps < last
     double acc = 0.0;          // row r (FWD) or column r (BWD), terms of group g
     T tv[16];
-    if (last > 0) load_term_tile<T, FWD>(Lt, I, blk<FWD>(0, nb), r, g, tv);
+    if (last > 0) load_term(I, blk<FWD>(0, nb), tv);
     for (int u = 0; u < last; ++u) {
       const int K = blk<FWD>(u, nb);
       // wave 0 waits for the walker's output of step u in its slots and stages it in LDS
@@ -947,7 +972,7 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
       T cur[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) cur[q] = tv[q];
-      if (u + 1 < last) load_term_tile<T, FWD>(Lt, I, blk<FWD>(u + 1, nb), r, g, tv);
+      if (u + 1 < last) load_term(I, blk<FWD>(u + 1, nb), tv);
 #pragma unroll
       for (int q = 0; q < 16; ++q) acc = fma((double)cur[q], xs[u & 1][g * 16 + q], acc);
     }
@@ -969,7 +994,7 @@ __global__ __launch_bounds__(256) void k_trsv_walk(SolveArgs a, uint64_t wait_ti
 #pragma unroll
     for (int j = 0; j < TD; ++j) {
       const int u = s1 - TD + j;
-      if (u >= 0) load_term_tile<T, FWD>(Lt, In, blk<FWD>(u, nb), r, g, td[j]);
+      if (u >= 0) load_term(In, blk<FWD>(u, nb), td[j]);
     }
     load_dinv<T, FWD>(Dv, In, r, g, dv);
     if (tid < TILE) {
@@ -1057,12 +1082,15 @@ void launch_cholesky(hipStream_t s, const FactorArgs& a, bool fp32) {
 template <int TD>
 static void launch_trsv_td(hipStream_t s, const SolveArgs& a, bool fp32, bool forward) {
   const dim3 grid(a.nb + 1);   // the helpers and the walker
-  if (fp32) {
-    if (forward) hipLaunchKernelGGL((k_trsv_walk<float, true, TD>), grid, dim3(256), 0, s, a, a.wait_ticks);
-    hipLaunchKernelGGL((k_trsv_walk<float, false, TD>), grid, dim3(256), 0, s, a, a.wait_ticks);
+  if (fp32 && a.Lbf) {
+    if (forward) hipLaunchKernelGGL((k_trsv_walk<float, true, TD, true>), grid, dim3(256), 0, s, a, a.wait_ticks);
+    hipLaunchKernelGGL((k_trsv_walk<float, false, TD, true>), grid, dim3(256), 0, s, a, a.wait_ticks);
+  } else if (fp32) {
+    if (forward) hipLaunchKernelGGL((k_trsv_walk<float, true, TD, false>), grid, dim3(256), 0, s, a, a.wait_ticks);
+    hipLaunchKernelGGL((k_trsv_walk<float, false, TD, false>), grid, dim3(256), 0, s, a, a.wait_ticks);
   } else {
-    if (forward) hipLaunchKernelGGL((k_trsv_walk<double, true, TD>), grid, dim3(256), 0, s, a, a.wait_ticks);
-    hipLaunchKernelGGL((k_trsv_walk<double, false, TD>), grid, dim3(256), 0, s, a, a.wait_ticks);
+    if (forward) hipLaunchKernelGGL((k_trsv_walk<double, true, TD, false>), grid, dim3(256), 0, s, a, a.wait_ticks);
+    hipLaunchKernelGGL((k_trsv_walk<double, false, TD, false>), grid, dim3(256), 0, s, a, a.wait_ticks);
   }
 }
 

@@ -243,6 +243,8 @@ struct SolveArgs {
   double* part;             // 2 * nb * TILE hand-over slots, empty (every 32-bit word
                             // SLOT_EMPTY_WORD) between launches: [0, nb * TILE) the helpers'
                             // partial sums, [nb * TILE, 2 nb * TILE) the walker's outputs
+  const void* Lbf;          // float factor only: the bfloat16 copies of its off-diagonal tiles,
+                            // read instead of the float tiles (nullptr: the float tiles)
 };
 void launch_trsv(hipStream_t s, const SolveArgs& a, bool fp32, bool forward);
 void launch_tiles_to_dense(hipStream_t s, int n, const void* Ltiles, bool fp32, double* L, int ldl);

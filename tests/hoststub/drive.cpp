@@ -143,6 +143,74 @@ void direct_solver(int seed, int rounds) {
   }
 }
 
+// A prepared batch of dense problems replayed from its graph, on the thread's own stream
+// and handle, while the server and the other threads run.
+void plan_user(int seed, int rounds) {
+  std::mt19937 rng(seed);
+  std::uniform_int_distribution<int> size(8, 300);
+  std::normal_distribution<double> val(0.0, 1.0);
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    fail("plan stream", -1);
+    return;
+  }
+  nnls_handle* h = nullptr;
+  int rc = nnls_create(&h, 0, (void*)st);
+  if (rc != NNLS_OK) {
+    fail("plan create handle", rc);
+    hipStreamDestroy(st);
+    return;
+  }
+  for (int r = 0; r < rounds; ++r) {
+    const int batch = 5;
+    std::vector<int32_t> m(batch), n(batch), lda(batch);
+    std::vector<const double*> A(batch), b(batch);
+    std::vector<double*> x(batch), y(batch);
+    std::vector<void*> owned;
+    for (int i = 0; i < batch; ++i) {
+      n[i] = size(rng);
+      m[i] = lda[i] = 2 * n[i] + 3;
+      std::vector<double> ha((size_t)m[i] * n[i]), hb((size_t)m[i]);
+      for (double& v : ha) v = val(rng);
+      for (double& v : hb) v = val(rng);
+      void *da, *db, *dx, *dy;
+      hipMalloc(&da, ha.size() * 8);
+      hipMalloc(&db, hb.size() * 8);
+      hipMalloc(&dx, (size_t)n[i] * 8);
+      hipMalloc(&dy, (size_t)n[i] * 8);
+      hipMemcpyAsync(da, ha.data(), ha.size() * 8, hipMemcpyHostToDevice, st);
+      hipMemcpyAsync(db, hb.data(), hb.size() * 8, hipMemcpyHostToDevice, st);
+      A[i] = (const double*)da;
+      b[i] = (const double*)db;
+      x[i] = (double*)dx;
+      y[i] = (double*)dy;
+      for (void* q : {da, db, dx, dy}) owned.push_back(q);
+    }
+    nnls_options o;
+    nnls_default_options(&o);
+    o.precision = (r % 2) ? NNLS_FP32_IR : NNLS_FP64;
+    nnls_batch_plan* plan = nullptr;
+    rc = nnls_batch_plan_create(h, batch, m.data(), n.data(), A.data(), lda.data(), b.data(), x.data(), y.data(),
+                                &o, &plan);
+    if (rc != NNLS_OK) {
+      fail("plan create", rc);
+    } else {
+      std::vector<nnls_info> info((size_t)batch);
+      for (int k = 0; k < 3; ++k) {
+        rc = (k == 1) ? nnls_batch_plan_execute(plan, nullptr) : nnls_batch_plan_execute(plan, info.data());
+        if (rc == NNLS_OK && k == 1) rc = nnls_batch_plan_info(plan, info.data());
+        if (rc != NNLS_OK) fail("plan execute", rc);
+      }
+      int32_t shapes[9];
+      if (nnls_batch_plan_tile_shapes(plan, shapes) != NNLS_OK) fail("plan shapes", -1);
+      nnls_batch_plan_destroy(plan);
+    }
+    for (void* q : owned) hipFree(q);
+  }
+  nnls_destroy(h);
+  hipStreamDestroy(st);
+}
+
 }  // namespace
 
 int main() {
@@ -165,6 +233,7 @@ int main() {
   std::vector<std::thread> th;
   for (int t = 0; t < 4; ++t) th.emplace_back(submitter, s, 100 + t, 36);
   for (int t = 0; t < 3; ++t) th.emplace_back(direct_solver, 200 + t, 4);
+  th.emplace_back(plan_user, 300, 4);
   std::atomic<bool> stop{false};
   std::thread stats([&] {
     while (!stop) {

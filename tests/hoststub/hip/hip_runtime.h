@@ -59,3 +59,22 @@ hipError_t hipEventDestroy(hipEvent_t e);
 hipError_t hipEventRecord(hipEvent_t e, hipStream_t s);
 hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b);
 hipError_t hipGetSymbolAddress(void** ptr, const void* symbol);
+hipError_t hipMemcpy(void* dst, const void* src, size_t bytes, hipMemcpyKind kind);
+hipError_t hipEventSynchronize(hipEvent_t e);
+
+// Graphs: a stream in capture records its tasks instead of running them; a launched graph
+// enqueues the recorded tasks on the target stream.
+typedef enum { hipStreamCaptureModeGlobal = 0, hipStreamCaptureModeThreadLocal = 1, hipStreamCaptureModeRelaxed = 2 }
+    hipStreamCaptureMode;
+struct ihipGraph_t;
+typedef ihipGraph_t* hipGraph_t;
+struct ihipGraphExec_t;
+typedef ihipGraphExec_t* hipGraphExec_t;
+struct hipGraphNode;
+typedef hipGraphNode* hipGraphNode_t;
+hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode mode);
+hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t* g);
+hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, hipGraphNode_t* err_node, char* log, size_t log_size);
+hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t s);
+hipError_t hipGraphExecDestroy(hipGraphExec_t e);
+hipError_t hipGraphDestroy(hipGraph_t g);

@@ -22,6 +22,8 @@ struct ihipStream_t {
   std::condition_variable cv, idle;
   std::deque<std::function<void()>> q;
   bool stop = false, busy = false;
+  bool capturing = false;                        // tasks go to `captured` instead of q
+  std::vector<std::function<void()>> captured;
   std::thread worker;
   ihipStream_t() { worker = std::thread([this] { run(); }); }
   ~ihipStream_t() {
@@ -54,6 +56,10 @@ struct ihipStream_t {
   void push(std::function<void()> f) {
     {
       std::lock_guard<std::mutex> lk(mu);
+      if (capturing) {
+        captured.push_back(std::move(f));
+        return;
+      }
       q.push_back(std::move(f));
     }
     cv.notify_one();
@@ -64,8 +70,17 @@ struct ihipStream_t {
   }
 };
 
+// An event is a flag that a task on the recording stream sets.
 struct ihipEvent_t {
-  int unused = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  bool done = true;
+};
+struct ihipGraph_t {
+  std::vector<std::function<void()>> tasks;
+};
+struct ihipGraphExec_t {
+  std::vector<std::function<void()>> tasks;
 };
 
 namespace {
@@ -165,7 +180,61 @@ hipError_t hipEventDestroy(hipEvent_t e) {
   delete e;
   return hipSuccess;
 }
-hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t s) {
+  {
+    std::lock_guard<std::mutex> lk(e->mu);
+    e->done = false;
+  }
+  resolve(s)->push([e] {
+    std::lock_guard<std::mutex> lk(e->mu);   // notified under the lock: a waiter may destroy e at once
+    e->done = true;
+    e->cv.notify_all();
+  });
+  return hipSuccess;
+}
+hipError_t hipEventSynchronize(hipEvent_t e) {
+  std::unique_lock<std::mutex> lk(e->mu);
+  e->cv.wait(lk, [&] { return e->done; });
+  return hipSuccess;
+}
+hipError_t hipMemcpy(void* dst, const void* src, size_t bytes, hipMemcpyKind) {
+  sync_all();   // as the HIP runtime's blocking copy: after the work queued before it
+  std::memcpy(dst, src, bytes);
+  return hipSuccess;
+}
+hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode) {
+  ihipStream_t* st = resolve(s);
+  std::lock_guard<std::mutex> lk(st->mu);
+  if (st->capturing) return hipErrorInvalidValue;
+  st->capturing = true;
+  st->captured.clear();
+  return hipSuccess;
+}
+hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t* g) {
+  ihipStream_t* st = resolve(s);
+  std::lock_guard<std::mutex> lk(st->mu);
+  if (!st->capturing) return hipErrorInvalidValue;
+  st->capturing = false;
+  *g = new ihipGraph_t{std::move(st->captured)};
+  st->captured.clear();
+  return hipSuccess;
+}
+hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, hipGraphNode_t*, char*, size_t) {
+  *e = new ihipGraphExec_t{g->tasks};
+  return hipSuccess;
+}
+hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t s) {
+  for (const auto& f : e->tasks) resolve(s)->push(f);
+  return hipSuccess;
+}
+hipError_t hipGraphExecDestroy(hipGraphExec_t e) {
+  delete e;
+  return hipSuccess;
+}
+hipError_t hipGraphDestroy(hipGraph_t g) {
+  delete g;
+  return hipSuccess;
+}
 hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) {
   *ms = 0.f;
   return hipSuccess;
