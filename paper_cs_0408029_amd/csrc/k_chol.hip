@@ -389,18 +389,22 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
   publish_tile(&a.tflag[ti], &a.colcnt[J], a.epoch);
 }
 
-// A strip of cnt <= R off-diagonal tiles (I0 + r, J) of one column (bfloat16 updates):
-// every step k stages L_Jk once and the cnt tiles L_{I0+r,k}, and the four waves each
-// update their 32 x 32 quadrant of every tile of the strip, so one load of L_Jk and one
-// pair of barriers serve R tiles (R + 1 tile loads for R outputs instead of 2 R).  Two
-// steps' operand copies are in flight in registers.  Each tile is finished as in
-// chol_tile: L_IJ = S_IJ (L_JJ^-1)^T, stored, copied to bfloat16 and published.
-// stage: (R + 1) bfloat16 tiles with row stride LDK; S (a float tile) aliases it.
-constexpr size_t STRIP_STAGE_BYTES = (size_t)(CHOL_STRIP + 1) * TILE * LDK * 2;
+// A strip of cnt <= R off-diagonal tiles (I0 + r, J0 + c), r < cnt, c < C, of C = 1 or 2
+// adjacent columns (bfloat16 updates).  Every step k < J0 stages the C tiles L_{J0+c,k} and
+// the cnt tiles L_{I0+r,k} once, and the four waves each update their 32 x 32 quadrant of
+// every tile of the strip: with C = 1 one pair of barriers and one L_Jk load serve R tiles
+// (R + 1 tile loads for R outputs instead of 2 R), with C = 2 each L_Ik also serves both
+// columns (R + 2 loads for 2 R outputs).  Two steps' operand copies are in flight in
+// registers.  Column J0 is then finished as in chol_tile, L_IJ = S_IJ (L_JJ^-1)^T, stored,
+// copied to bfloat16 and published; with C = 2 its new tiles (and the walker's
+// L_{J0+1,J0}) give the last update term of column J0 + 1, which is finished after it.
+// stage: (R + C) bfloat16 tiles with row stride LDK; S (a float tile) aliases it.
+constexpr size_t STRIP_STAGE_BYTES =
+    (size_t)(CHOL_STRIP + 1 > CHOL_PAIR + 2 ? CHOL_STRIP + 1 : CHOL_PAIR + 2) * TILE * LDK * 2;
 
-template <int R>
-__device__ __forceinline__ void chol_strip(const FactorArgs& a, uint64_t wait_ticks, int I0, int cnt, int J,
-                                        char* stage) {
+template <int R, int C>
+__device__ __forceinline__ void chol_strip(const FactorArgs& a, uint64_t wait_ticks, int I0, int cnt, int J0,
+                                           char* stage) {
   typedef MF<float> M;
   typedef M::acc Acc;
   const int tid = fresh_tid(), lane = tid & 63, w = tid >> 6;
@@ -409,55 +413,64 @@ __device__ __forceinline__ void chol_strip(const FactorArgs& a, uint64_t wait_ti
   const float* Dv = (const float*)a.Dinv;
   const uint16_t* Lb = (const uint16_t*)a.Lbf;
   float* S = (float*)stage;
-  uint16_t* HB = (uint16_t*)stage;   // L_Jk
+  uint16_t* HB = (uint16_t*)stage;                  // L_{J0+c,k} at HB + c TILE LDK
+  uint16_t* HA0 = HB + C * TILE * LDK;              // L_{I0+r,k} at HA0 + r TILE LDK
   const int qr = (w & 1) * 32, qc = (w >> 1) * 32, lr = lane & 15, lk = lane >> 4;
-  Acc acc[R][2][2];
+  Acc acc[C][R][2][2];
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
+  for (int c = 0; c < C; ++c)
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[r][bi][bj][v] = 0.0f;
-    if (r < cnt) {
-      gather_tile<float>(a, tid, I0 + r, J, S);
+    for (int r = 0; r < R; ++r) {
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            acc[r][bi][bj][v] = S[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT];
-      __syncthreads();   // S is overwritten by the next gather or the first step's operands
+          for (int v = 0; v < 4; ++v) acc[c][r][bi][bj][v] = 0.0f;
+      if (r < cnt) {
+        gather_tile<float>(a, tid, I0 + r, J0 + c, S);
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              acc[c][r][bi][bj][v] = S[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT];
+        __syncthreads();   // S is overwritten by the next gather or the first step's operands
+      }
     }
-  }
-  const bool needJ = J >= j0;   // L_Jk is computed in this launch
-  int known = 0;                // leading columns this thread knows are complete
+  const bool needJ = J0 >= j0;   // the L_{J0+c,k} are computed in this launch (C = 2: both or neither)
+  int known = 0;                 // leading columns this thread knows are complete
   auto ready = [&](int k1, bool block) -> bool {
     if (k1 < known) return true;
     if (ld_relaxed(&a.colcnt[k1]) >= nb - max(k1, j0)) {
       known = k1 + 1;
-      while (known < J && ld_relaxed(&a.colcnt[known]) >= nb - max(known, j0)) ++known;
+      while (known < J0 && ld_relaxed(&a.colcnt[known]) >= nb - max(known, j0)) ++known;
     } else if (!block) {
       for (int r = 0; r < cnt; ++r)
         if (ld_relaxed(&a.tflag[tile_index(I0 + r, k1)]) != a.epoch) return false;
-      if (needJ && ld_relaxed(&a.tflag[tile_index(J, k1)]) != a.epoch) return false;
+      if (needJ)
+        for (int c = 0; c < C; ++c)
+          if (ld_relaxed(&a.tflag[tile_index(J0 + c, k1)]) != a.epoch) return false;
     } else {
       for (int r = 0; r < cnt; ++r) spin_until(&a.tflag[tile_index(I0 + r, k1)], a.epoch, true, a.ctrl, wait_ticks);
-      if (needJ) spin_until(&a.tflag[tile_index(J, k1)], a.epoch, true, a.ctrl, wait_ticks);
+      if (needJ)
+        for (int c = 0; c < C; ++c) spin_until(&a.tflag[tile_index(J0 + c, k1)], a.epoch, true, a.ctrl, wait_ticks);
     }
     acquire_agent();
     return true;
   };
-  constexpr int PD = 2;
-  u32x4 rg[PD][R + 1][2];
+  constexpr int PD = C == 1 ? 2 : 1;   // a pair's second step in flight would not fit the registers
+  u32x4 rg[PD][R + C][2];
   int held[PD];
   auto fetch = [&](auto slot, int s1) __attribute__((always_inline)) {
     constexpr int d = decltype(slot)::value;
-    const u32x4* gj = (const u32x4*)(Lb + tile_index(J, s1) * TILE_ELEMS) + 2 * tid;
-    rg[d][R][0] = gj[0];
-    rg[d][R][1] = gj[1];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const u32x4* gj = (const u32x4*)(Lb + tile_index(J0 + c, s1) * TILE_ELEMS) + 2 * tid;
+      rg[d][R + c][0] = gj[0];
+      rg[d][R + c][1] = gj[1];
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r)
       if (r < cnt) {
@@ -470,10 +483,44 @@ __device__ __forceinline__ void chol_strip(const FactorArgs& a, uint64_t wait_ti
   auto prime = [&](auto slot) __attribute__((always_inline)) {
     constexpr int d = decltype(slot)::value;
     held[d] = -1;
-    if (d < J && ready(d, d == 0)) fetch(slot, d);
+    if (d < J0 && ready(d, d == 0)) fetch(slot, d);
   };
+  // one update step from the staged operands: acc[c][r] -= L_{I0+r} L_{J0+c}^T over c < nc
+  auto products = [&](int nc) __attribute__((always_inline)) {
+#pragma unroll
+    for (int kh = 0; kh < TILE; kh += 32) {
+      const int kofs = kh + 8 * lk;
+      bf16x8 b0[C], b1[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const uint16_t* hb = HB + c * TILE * LDK;
+        b0[c] = __builtin_bit_cast(bf16x8, *(const u32x4*)(hb + (qc + lr) * LDK + kofs));
+        b1[c] = __builtin_bit_cast(bf16x8, *(const u32x4*)(hb + (qc + 16 + lr) * LDK + kofs));
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (r < cnt) {
+          const uint16_t* HA = HA0 + r * TILE * LDK;
+          u32x4 x0 = *(const u32x4*)(HA + (qr + lr) * LDK + kofs);
+          u32x4 x1 = *(const u32x4*)(HA + (qr + 16 + lr) * LDK + kofs);
+          const uint32_t neg = 0x80008000u;   // S -= L_Ik L_Jk^T: negate the L_Ik operand
+          x0 ^= neg;
+          x1 ^= neg;
+          const bf16x8 a0 = __builtin_bit_cast(bf16x8, x0), a1 = __builtin_bit_cast(bf16x8, x1);
+#pragma unroll
+          for (int c = 0; c < C; ++c)
+            if (c >= C - nc) {
+              acc[c][r][0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0[c], acc[c][r][0][0], 0, 0, 0);
+              acc[c][r][0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1[c], acc[c][r][0][1], 0, 0, 0);
+              acc[c][r][1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0[c], acc[c][r][1][0], 0, 0, 0);
+              acc[c][r][1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1[c], acc[c][r][1][1], 0, 0, 0);
+            }
+        }
+    }
+  };
+  const int o16 = (tid >> 2) * LDK + (tid & 3) * 16;   // this thread's 16 staged values of a tile
   prime(std::integral_constant<int, 0>{});
-  prime(std::integral_constant<int, 1>{});
+  if constexpr (PD > 1) prime(std::integral_constant<int, PD - 1>{});
   auto step = [&](auto slot, int k) __attribute__((always_inline)) {
     constexpr int d = decltype(slot)::value;
     if (held[d] != k) {   // at the frontier: wait for this step's tiles
@@ -481,96 +528,115 @@ __device__ __forceinline__ void chol_strip(const FactorArgs& a, uint64_t wait_ti
       fetch(slot, k);
     }
     __syncthreads();   // the previous step's products have read the staged operands
-    {
-      const int o = (tid >> 2) * LDK + (tid & 3) * 16;
-      ((u32x4*)(HB + o))[0] = rg[d][R][0];
-      ((u32x4*)(HB + o))[1] = rg[d][R][1];
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (r < cnt) {
-          uint16_t* HA = HB + (r + 1) * TILE * LDK;
-          ((u32x4*)(HA + o))[0] = rg[d][r][0];
-          ((u32x4*)(HA + o))[1] = rg[d][r][1];
-        }
+    for (int c = 0; c < C; ++c) {
+      uint16_t* hb = HB + c * TILE * LDK;
+      ((u32x4*)(hb + o16))[0] = rg[d][R + c][0];
+      ((u32x4*)(hb + o16))[1] = rg[d][R + c][1];
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (r < cnt) {
+        uint16_t* HA = HA0 + r * TILE * LDK;
+        ((u32x4*)(HA + o16))[0] = rg[d][r][0];
+        ((u32x4*)(HA + o16))[1] = rg[d][r][1];
+      }
     __syncthreads();
     held[d] = -1;
-    if (k + PD < J && ready(k + PD, false)) fetch(slot, k + PD);
-#pragma unroll
-    for (int kh = 0; kh < TILE; kh += 32) {
-      const int kofs = kh + 8 * lk;
-      const bf16x8 b0 = __builtin_bit_cast(bf16x8, *(const u32x4*)(HB + (qc + lr) * LDK + kofs));
-      const bf16x8 b1 = __builtin_bit_cast(bf16x8, *(const u32x4*)(HB + (qc + 16 + lr) * LDK + kofs));
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (r < cnt) {
-          const uint16_t* HA = HB + (r + 1) * TILE * LDK;
-          u32x4 x0 = *(const u32x4*)(HA + (qr + lr) * LDK + kofs);
-          u32x4 x1 = *(const u32x4*)(HA + (qr + 16 + lr) * LDK + kofs);
-          const uint32_t neg = 0x80008000u;   // S -= L_Ik L_Jk^T: negate the L_Ik operand
-          x0 ^= neg;
-          x1 ^= neg;
-          const bf16x8 a0 = __builtin_bit_cast(bf16x8, x0), a1 = __builtin_bit_cast(bf16x8, x1);
-          acc[r][0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[r][0][0], 0, 0, 0);
-          acc[r][0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[r][0][1], 0, 0, 0);
-          acc[r][1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[r][1][0], 0, 0, 0);
-          acc[r][1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[r][1][1], 0, 0, 0);
-        }
-    }
+    if (k + PD < J0 && ready(k + PD, false)) fetch(slot, k + PD);
+    products(C);
   };
-  for (int k0 = 0; k0 < J; k0 += PD) {
+  for (int k0 = 0; k0 < J0; k0 += PD) {
     step(std::integral_constant<int, 0>{}, k0);
-    if (k0 + 1 < J) step(std::integral_constant<int, 1>{}, k0 + 1);
+    if constexpr (PD > 1)
+      if (k0 + 1 < J0) step(std::integral_constant<int, PD - 1>{}, k0 + 1);
   }
   __syncthreads();   // the last products have read the staged operands
-  if (needJ) {
-    spin_until(&a.dflag[J], a.epoch, true, a.ctrl, wait_ticks);
-    acquire_agent();
-  }
-  const float* D = Dv + (int64_t)J * TILE_ELEMS;
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    if (r >= cnt) continue;
+  for (int c = 0; c < C; ++c) {
+    const int J = J0 + c;
+    if (c > 0) {
+      // the last term of column J: L_{I,J-1} (finished above by this workgroup) times
+      // L_{J,J-1} (the walker's sub-diagonal tile of column J-1, or a kept tile)
+      if (needJ) {
+        spin_until(&a.tflag[tile_index(J, J - 1)], a.epoch, true, a.ctrl, wait_ticks);
+        acquire_agent();
+      }
+      {
+        const u32x4* gj = (const u32x4*)(Lb + tile_index(J, J - 1) * TILE_ELEMS) + 2 * tid;
+        const u32x4 j0v = gj[0], j1v = gj[1];
+        u32x4 iv[R][2];
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+        for (int r = 0; r < R; ++r)
+          if (r < cnt) {
+            const u32x4* gi = (const u32x4*)(Lb + tile_index(I0 + r, J - 1) * TILE_ELEMS) + 2 * tid;
+            iv[r][0] = gi[0];
+            iv[r][1] = gi[1];
+          }
+        uint16_t* hb = HB + (C - 1) * TILE * LDK;   // products(1) reads column C-1's buffer
+        ((u32x4*)(hb + o16))[0] = j0v;
+        ((u32x4*)(hb + o16))[1] = j1v;
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          S[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT] = acc[r][bi][bj][v];
-    __syncthreads();
-    Acc o[2][2];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) o[bi][bj][v] = 0.0f;
-#pragma unroll
-    for (int kk = 0; kk < TILE; kk += 4) {
-      const int kc = kk + lk;
-      const float a0 = S[(qr + lr) + kc * LDT], a1 = S[(qr + 16 + lr) + kc * LDT];
-      const float b0 = D[kc * TILE + qc + lr], b1 = D[kc * TILE + qc + 16 + lr];
-      o[0][0] = M::op(a0, b0, o[0][0]);
-      o[0][1] = M::op(a0, b1, o[0][1]);
-      o[1][0] = M::op(a1, b0, o[1][0]);
-      o[1][1] = M::op(a1, b1, o[1][1]);
+        for (int r = 0; r < R; ++r)
+          if (r < cnt) {
+            uint16_t* HA = HA0 + r * TILE * LDK;
+            ((u32x4*)(HA + o16))[0] = iv[r][0];
+            ((u32x4*)(HA + o16))[1] = iv[r][1];
+          }
+      }
+      __syncthreads();
+      products(1);
+      __syncthreads();   // the products have read the staged operands (S aliases them)
     }
-    __syncthreads();
+    if (needJ) {
+      spin_until(&a.dflag[J], a.epoch, true, a.ctrl, wait_ticks);
+      acquire_agent();
+    }
+    const float* D = Dv + (int64_t)J * TILE_ELEMS;
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int r = 0; r < R; ++r) {
+      if (r >= cnt) continue;
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
+      for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          S[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT] = o[bi][bj][v];
-    __syncthreads();
-    const int64_t ti = tile_index(I0 + r, J);
-    float* dst = Lt + ti * TILE_ELEMS;
-    for (int e = tid; e < TILE_ELEMS; e += 256) dst[e] = S[(e & (TILE - 1)) + (e >> 6) * LDT];
-    bf16_copy_to_global((uint16_t*)a.Lbf + ti * TILE_ELEMS, S, tid);
-    publish_tile(&a.tflag[ti], &a.colcnt[J], a.epoch);
-    __syncthreads();   // S is rewritten by the next tile of the strip
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            S[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT] = acc[c][r][bi][bj][v];
+      __syncthreads();
+      Acc o[2][2];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) o[bi][bj][v] = 0.0f;
+#pragma unroll
+      for (int kk = 0; kk < TILE; kk += 4) {
+        const int kc = kk + lk;
+        const float a0 = S[(qr + lr) + kc * LDT], a1 = S[(qr + 16 + lr) + kc * LDT];
+        const float b0 = D[kc * TILE + qc + lr], b1 = D[kc * TILE + qc + 16 + lr];
+        o[0][0] = M::op(a0, b0, o[0][0]);
+        o[0][1] = M::op(a0, b1, o[0][1]);
+        o[1][0] = M::op(a1, b0, o[1][0]);
+        o[1][1] = M::op(a1, b1, o[1][1]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            S[(qr + 16 * bi + M::row(lane, v)) + (qc + 16 * bj + lr) * LDT] = o[bi][bj][v];
+      __syncthreads();
+      const int64_t ti = tile_index(I0 + r, J);
+      float* dst = Lt + ti * TILE_ELEMS;
+      for (int e = tid; e < TILE_ELEMS; e += 256) dst[e] = S[(e & (TILE - 1)) + (e >> 6) * LDT];
+      bf16_copy_to_global((uint16_t*)a.Lbf + ti * TILE_ELEMS, S, tid);
+      publish_tile(&a.tflag[ti], &a.colcnt[J], a.epoch);
+      __syncthreads();   // S is rewritten by the next tile
+    }
   }
 }
 
@@ -803,29 +869,6 @@ __device__ __forceinline__ void walker(const FactorArgs& a, uint64_t wait_ticks,
   }
 }
 
-// Ticket t -> unit (I, J, cnt): cnt tiles (I .. I + cnt - 1, J) in the order of col_units,
-// column by column (R = 1: single tiles, rows I >= max(J, j0) in order).
-__device__ inline void decode_ticket(int t, int nb, int j0, int R, int* I, int* J, int* cnt) {
-  int j = 0;
-  for (int u = col_units(0, nb, j0, R); t >= u; u = col_units(++j, nb, j0, R)) t -= u;
-  *J = j;
-  *cnt = 1;
-  if (j >= j0) {
-    if (t == 0) {
-      *I = j;
-      return;
-    }
-    if (t == 1 && j + 1 < nb) {
-      *I = j + 1;
-      return;
-    }
-    t -= j + 1 < nb ? 2 : 1;
-  }
-  const int first = j >= j0 ? j + 2 : j0;
-  *I = first + t * R;
-  *cnt = min(R, nb - *I);
-}
-
 // A persistent grid: each workgroup takes tickets until none are left, so a launch holds
 // at most gridDim.x workgroups however large the F-block is (the device's resident
 // workgroups by default, fewer when concurrent solves share the device).  A workgroup
@@ -842,22 +885,23 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wa
   __shared__ double s_rhs[TILE];
   __shared__ double s_z[TILE];
   __shared__ double s_tp[TILE];
-  __shared__ int s_t, s_I, s_J, s_cnt;
-  constexpr int R = BF ? CHOL_STRIP : 1;
-  const int64_t nunits = unit_count_from(a.nb, a.j0, R);
+  __shared__ int s_t, s_kind, s_I, s_J, s_cnt;
+  const UnitPlan plan = {a.nb, a.j0, BF ? CHOL_STRIP : 1, CHOL_PAIR, BF};
+  const int64_t nunits = unit_total(plan);
   for (;;) {
     const int tid = fresh_tid();
     if (tid == 0) {
       const int t = atomicAdd(&a.ctrl->chol_ticket, 1) - 1;   // ticket 0 is the walker
-      int I = 0, J = 0, cnt = 1;
-      if (t >= 0 && t < nunits) decode_ticket(t, a.nb, a.j0, R, &I, &J, &cnt);
+      FactorUnit f = {UNIT_TILE, 0, 0, 1};
+      if (t >= 0 && t < nunits) f = unit_at(t, plan);
       s_t = t;
-      s_I = I;
-      s_J = J;
-      s_cnt = cnt;
+      s_kind = f.kind;
+      s_I = f.I;
+      s_J = f.J;
+      s_cnt = f.cnt;
     }
     __syncthreads();
-    const int t = s_t, I = s_I, J = s_J, cnt = s_cnt;
+    const int t = s_t, kind = s_kind, I = s_I, J = s_J, cnt = s_cnt;
     __syncthreads();   // every thread has its ticket before thread 0 may take the next
     if (t < 0) {
       walker<T, BF>(a, wait_ticks, S, W, s_part, s_rhs, s_z, s_tp);
@@ -865,8 +909,13 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wa
     }
     if (t >= nunits) return;
     if constexpr (BF) {
-      if (I >= J + 2 || J < a.j0) {   // a strip of plain off-diagonal tiles
-        chol_strip<CHOL_STRIP>(a, wait_ticks, I, cnt, J, smem);
+      if (kind == UNIT_STRIP) {
+        chol_strip<CHOL_STRIP, 1>(a, wait_ticks, I, cnt, J, smem);
+        __syncthreads();
+        continue;
+      }
+      if (kind == UNIT_PAIR) {
+        chol_strip<CHOL_PAIR, 2>(a, wait_ticks, I, cnt, J, smem);
         __syncthreads();
         continue;
       }
@@ -1069,7 +1118,9 @@ __global__ void k_tiles_to_dense(int n, const T* __restrict__ Lt, double* __rest
 
 void launch_cholesky(hipStream_t s, const FactorArgs& a, bool fp32) {
   if (a.nb <= 0 || a.j0 < 0 || a.j0 >= a.nb) return;
-  int64_t grid = unit_count_from(a.nb, a.j0, fp32 && a.Lbf ? CHOL_STRIP : 1) + 1;   // the units and the walker
+  const bool bf = fp32 && a.Lbf;
+  const UnitPlan plan = {a.nb, a.j0, bf ? CHOL_STRIP : 1, CHOL_PAIR, bf};
+  int64_t grid = unit_total(plan) + 1;   // the units and the walker
   if (a.max_wgs > 0 && grid > a.max_wgs) grid = a.max_wgs < 2 ? 2 : a.max_wgs;   // walker + >= 1 worker
   if (fp32 && a.Lbf)
     hipLaunchKernelGGL((k_chol_tiles<float, true>), dim3((unsigned)grid), dim3(256), 0, s, a, a.wait_ticks);

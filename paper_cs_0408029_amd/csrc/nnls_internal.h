@@ -71,22 +71,115 @@ __host__ __device__ inline int64_t tile_count(int nb) { return (int64_t)nb * (nb
 __host__ __device__ inline int64_t tile_count_from(int nb, int j0) {
   return (int64_t)j0 * (nb - j0) + tile_count(nb - j0);
 }
-// Units of work of a factor launch whose off-diagonal tiles are taken in strips of up to R
-// consecutive rows of one column: a computed column J >= j0 gives its diagonal tile, its
-// sub-diagonal tile and the rows J+2 .. nb-1 in strips; a kept column J < j0 gives the rows
-// j0 .. nb-1 in strips.  With R = 1 every unit is one tile, in the order of tile_count_from.
-__host__ __device__ inline int col_units(int J, int nb, int j0, int R) {
-  const int first = J >= j0 ? J + 2 : j0;   // first row taken in strips
-  const int rows = nb - first;
-  const int lead = J >= j0 ? (J + 1 < nb ? 2 : 1) : 0;
-  return lead + (rows > 0 ? (rows + R - 1) / R : 0);
+// Units of work of a factor launch.  The diagonal and sub-diagonal tiles of a computed
+// column (the walker's inputs) are single units; the other off-diagonal tiles are taken in
+// strips of RS rows of one column, or -- with pairs -- in strips of RP rows of two adjacent
+// columns, whose second column is finished after the first.  Columns are grouped from the
+// start of the kept (J < j0) and of the computed (J >= j0) range, two at a time with pairs
+// (an odd last column alone).  A group's units, in ticket order:
+//   computed single J:      (J, J), (J+1, J), strips of rows J+2 ..
+//   computed pair (J, J+1): (J, J), (J+1, J), (J+2, J) alone, (J+1, J+1), (J+2, J+1),
+//                           pair strips of rows J+3 ..
+//   kept single or pair:    strips or pair strips of rows j0 ..
+// Every unit waits only for units of earlier groups, earlier units of its own group and the
+// walker (ticket 0), which are running or done.  RS = 1 without pairs is one tile per unit,
+// in the column-major order of tile_count_from.
+enum { UNIT_TILE = 0, UNIT_STRIP = 1, UNIT_PAIR = 2 };
+struct FactorUnit {
+  int kind, I, J, cnt;   // cnt rows I .. I + cnt - 1 of column J (and J + 1 for a pair)
+};
+struct UnitPlan {
+  int nb, j0, RS, RP;
+  bool pairs;
+};
+__host__ __device__ inline int strips_of(int rows, int R) { return rows > 0 ? (rows + R - 1) / R : 0; }
+__host__ __device__ inline int group_span(int J, const UnitPlan& p) {
+  const int end = J < p.j0 ? p.j0 : p.nb;
+  return (p.pairs && J + 1 < end) ? 2 : 1;
 }
-__host__ __device__ inline int64_t unit_count_from(int nb, int j0, int R) {
+__host__ __device__ inline int group_units(int J, int C, const UnitPlan& p) {
+  if (J < p.j0) return strips_of(p.nb - p.j0, C == 2 ? p.RP : p.RS);
+  if (C == 1) return 1 + (J + 1 < p.nb ? 1 : 0) + strips_of(p.nb - J - 2, p.RS);
+  const int third = J + 2 < p.nb ? 1 : 0;
+  return 3 + 2 * third + strips_of(p.nb - J - 3, p.RP);
+}
+__host__ __device__ inline int64_t unit_total(const UnitPlan& p) {
   int64_t u = 0;
-  for (int J = 0; J < nb; ++J) u += col_units(J, nb, j0, R);
+  for (int J = 0; J < p.nb;) {
+    const int C = group_span(J, p);
+    u += group_units(J, C, p);
+    J += C;
+  }
   return u;
 }
-constexpr int CHOL_STRIP = 4;   // rows per strip of the bfloat16-update factor
+__host__ __device__ inline FactorUnit unit_at(int64_t t, const UnitPlan& p) {
+  int J = 0, C = group_span(0, p);
+  for (int64_t u = group_units(0, C, p); t >= u; u = group_units(J, C, p)) {
+    t -= u;
+    J += C;
+    C = group_span(J, p);
+  }
+  FactorUnit f;
+  f.J = J;
+  f.cnt = 1;
+  if (J < p.j0) {
+    const int R = C == 2 ? p.RP : p.RS;
+    f.kind = C == 2 ? UNIT_PAIR : UNIT_STRIP;
+    f.I = p.j0 + (int)t * R;
+    f.cnt = p.nb - f.I < R ? p.nb - f.I : R;
+    return f;
+  }
+  f.kind = UNIT_TILE;
+  if (C == 1) {
+    if (t == 0) {
+      f.I = J;
+      return f;
+    }
+    if (t == 1 && J + 1 < p.nb) {
+      f.I = J + 1;
+      return f;
+    }
+    t -= J + 1 < p.nb ? 2 : 1;
+    f.kind = UNIT_STRIP;
+    f.I = J + 2 + (int)t * p.RS;
+    f.cnt = p.nb - f.I < p.RS ? p.nb - f.I : p.RS;
+    return f;
+  }
+  const bool third = J + 2 < p.nb;
+  if (t < 2) {   // (J, J), (J+1, J)
+    f.I = J + (int)t;
+    return f;
+  }
+  t -= 2;
+  if (third) {
+    if (t == 0) {   // (J+2, J) alone: the next column's sub-diagonal tile reads it
+      f.kind = UNIT_STRIP;
+      f.I = J + 2;
+      return f;
+    }
+    t -= 1;
+  }
+  if (t == 0) {   // (J+1, J+1)
+    f.I = J + 1;
+    f.J = J + 1;
+    return f;
+  }
+  t -= 1;
+  if (third) {
+    if (t == 0) {   // (J+2, J+1)
+      f.I = J + 2;
+      f.J = J + 1;
+      return f;
+    }
+    t -= 1;
+  }
+  f.kind = UNIT_PAIR;
+  f.I = J + 3 + (int)t * p.RP;
+  f.cnt = p.nb - f.I < p.RP ? p.nb - f.I : p.RP;
+  return f;
+}
+constexpr int CHOL_STRIP = 4;   // rows per one-column strip of the bfloat16-update factor
+constexpr int CHOL_PAIR = 3;    // rows per two-column strip
 
 // ---------------------------------------------------------------- launchers
 // setup (k_setup.hip)
