@@ -102,6 +102,7 @@ struct nnls_handle {
   DevBuf wr, bw, bb;                   // sign-certificate bounds of the mixed path
   DevBuf rlo;                          // low part of the compensated refinement residual
   DevBuf Lbf;                          // bfloat16 copies of the factor tiles (NNLS_BF16_IR)
+  DevBuf Mc;                           // coupling tiles of the triangular solves' walker
   DevBuf est, ev, exi;                         // condition estimate: state, probe vector, signs
   DevBuf bprobs, border, binfo, bws;   // batched dense problems
   DevBuf scan;                         // chunk sums of the setup prefix scans
@@ -356,6 +357,7 @@ int ensure_factor(nnls_handle* h, int nF, int prec, bool* lost = nullptr) {
   TRY(ensure(h, h->Lt, ntiles * TILE_ELEMS * w));
   if (prec == PREC_BF16) TRY(ensure(h, h->Lbf, ntiles * TILE_ELEMS * sizeof(uint16_t)));
   TRY(ensure(h, h->Dinv, (size_t)nb * TILE_ELEMS * w));
+  TRY(ensure(h, h->Mc, walk_coupling_bytes(nb, prec >= PREC_F32)));
   TRY(ensure(h, h->colcnt, (size_t)nb * sizeof(int32_t), true));
   TRY(ensure(h, h->dflag, (size_t)nb * sizeof(int32_t), true));
   TRY(ensure(h, h->tflag, ntiles * sizeof(int32_t), true));
@@ -383,6 +385,7 @@ FactorArgs factor_args(nnls_handle* h, int nF, const int32_t* Flist, const doubl
   a.dense = dense;
   a.ldd = ldd;
   a.Ltiles = h->Lt.p;
+  a.Mc = h->Mc.p;   // the walker's coupling tiles, formed after the factor
   a.Dinv = h->Dinv.p;
   a.colcnt = (int32_t*)h->colcnt.p;
   a.dflag = (int32_t*)h->dflag.p;
@@ -401,6 +404,7 @@ SolveArgs solve_args(nnls_handle* h, int nF, const int32_t* Flist, const double*
   a.nb = (nF + TILE - 1) / TILE;
   a.Flist = Flist;
   a.Ltiles = h->Lt.p;
+  a.Mc = h->Mc.p;
   a.Dinv = h->Dinv.p;
   a.rhs_full = rhs;
   a.rhs_dense = nullptr;
@@ -917,7 +921,8 @@ void release_workspace(nnls_handle* h) {
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
                     &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart, &h->spart,
                     &h->upcnt, &h->prow, &h->pval, &h->pcnt, &h->Fold, &h->zr, &h->est, &h->ev, &h->exi,
-                    &h->bprobs, &h->border, &h->binfo, &h->bws, &h->scan, &h->wr, &h->bw, &h->bb, &h->rlo, &h->Lbf};
+                    &h->bprobs, &h->border, &h->binfo, &h->bws, &h->scan, &h->wr, &h->bw, &h->bb, &h->rlo, &h->Lbf,
+                    &h->Mc};
   for (DevBuf* b : bufs) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
@@ -1001,7 +1006,8 @@ int nnls_destroy(nnls_handle* h) {
                     &h->hcnt, &h->hrow, &h->hval, &h->c, &h->r, &h->flags, &h->Flist, &h->pos,
                     &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart, &h->spart,
                     &h->upcnt, &h->prow, &h->pval, &h->pcnt, &h->Fold, &h->zr, &h->est, &h->ev, &h->exi,
-                    &h->bprobs, &h->border, &h->binfo, &h->bws, &h->scan, &h->wr, &h->bw, &h->bb, &h->rlo};
+                    &h->bprobs, &h->border, &h->binfo, &h->bws, &h->scan, &h->wr, &h->bw, &h->bb, &h->rlo, &h->Lbf,
+                    &h->Mc};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
@@ -1547,6 +1553,7 @@ int nnls_cholesky(nnls_handle* h, int32_t n, const double* S, int32_t lds, doubl
   h->fact_prec = -1;
   FactorArgs fa = factor_args(h, n, nullptr, S, lds, false);
   fa.Lbf = prec == PREC_BF16 ? h->Lbf.p : nullptr;
+  fa.Mc = nullptr;   // no triangular solves follow
   launch_cholesky(h->stream, fa, fp32);
   launch_tiles_to_dense(h->stream, n, h->Lt.p, fp32, L, ldl);
   TRY(sync_read(h, h->h_ctrl, h->ctrl.p, sizeof(Ctrl)));

@@ -188,6 +188,8 @@ __global__ __launch_bounds__(CTRL_THREADS) void k_pivot_control(
     ctrl->chol_ticket = 0;
     ctrl->fwd_ticket = 0;
     ctrl->bwd_ticket = 0;
+    ctrl->fwd_walked = 0;
+    ctrl->bwd_walked = 0;
     s_branch = branch;
     s_rmax = r;
     s_done = done;
@@ -419,6 +421,8 @@ __global__ void k_reset_tickets(Ctrl* ctrl) {
   ctrl->chol_ticket = 0;
   ctrl->fwd_ticket = 0;
   ctrl->bwd_ticket = 0;
+  ctrl->fwd_walked = 0;
+  ctrl->bwd_walked = 0;
 }
 
 __global__ void k_ctrl_clear_breakdown(Ctrl* ctrl) {

@@ -29,7 +29,7 @@ struct Ctrl {
   int32_t fwd_ticket;
   int32_t bwd_ticket;
   int32_t j0;          // leading tile columns of the previous factor that the new F order keeps
-  int32_t pad_;
+  int32_t fwd_walked;  // steps the forward-solve walker has finished (a hint for its helpers)
   double min_margin;   // smallest |v| over the tested entries that were not zeroed
   double ir_dmax;      // mixed precision: max |correction| of the last refinement step
   double ir_xmax;      //                  max |x_F| after it
@@ -38,7 +38,7 @@ struct Ctrl {
                        //                  (INF while the contraction is not measured)
   int32_t ir_uncert;   //                  tested entries whose sign the bounds do not
                        //                  certify (-1: no bound yet)
-  int32_t pad2_;
+  int32_t bwd_walked;  // the same for the backward solve
 };
 
 // Lower-triangle Gram matrix in padded CSC: column j occupies
@@ -311,7 +311,18 @@ struct FactorArgs {
   void* Lbf;              // float factor only: bfloat16 row-major copies of the off-diagonal
                           // tiles, which the left-looking updates then read (NNLS_BF16_IR);
                           // nullptr: the updates read the float tiles
+  void* Mc;               // optional: the triangular solves' coupling tiles, formed after the
+                          // factor (walk_coupling_bytes; nullptr: not formed)
 };
+// Newest terms the walker of the triangular solves adds itself each step.  The factor's
+// coupling tiles hold them premultiplied by the inverted diagonal tile, row-major in the
+// factor's precision: forward D_I L_{I,I-j}, backward D_I^T L_{I+j,I}^T, j = 1 .. TD, at
+// ((dir * nb + I) * TD + j - 1) * TILE_ELEMS (dir 0 forward, 1 backward).
+template <typename T> struct WalkTD { static constexpr int value = sizeof(T) == 4 ? 3 : 2; };
+inline size_t walk_coupling_bytes(int nb, bool fp32) {
+  return fp32 ? 2 * (size_t)WalkTD<float>::value * nb * TILE_ELEMS * sizeof(float)
+              : 2 * (size_t)WalkTD<double>::value * nb * TILE_ELEMS * sizeof(double);
+}
 void launch_cholesky(hipStream_t s, const FactorArgs& a, bool fp32);
 // z = L^-1 rhs (rhs gathered through Flist when gather != nullptr); x = L^-T z and
 // scatter x through Flist into out (when out != nullptr) and into xF.
@@ -338,6 +349,7 @@ struct SolveArgs {
                             // partial sums, [nb * TILE, 2 nb * TILE) the walker's outputs
   const void* Lbf;          // float factor only: the bfloat16 copies of its off-diagonal tiles,
                             // read instead of the float tiles (nullptr: the float tiles)
+  const void* Mc;           // the factor's coupling tiles (FactorArgs::Mc), formed after it
 };
 void launch_trsv(hipStream_t s, const SolveArgs& a, bool fp32, bool forward);
 void launch_tiles_to_dense(hipStream_t s, int n, const void* Ltiles, bool fp32, double* L, int ldl);
