@@ -315,9 +315,10 @@ struct FactorArgs {
                           // factor (walk_coupling_bytes; nullptr: not formed)
 };
 // Newest terms the walker of the triangular solves adds itself each step.  The factor's
-// coupling tiles hold them premultiplied by the inverted diagonal tile, row-major in the
-// factor's precision: forward D_I L_{I,I-j}, backward D_I^T L_{I+j,I}^T, j = 1 .. TD, at
-// ((dir * nb + I) * TD + j - 1) * TILE_ELEMS (dir 0 forward, 1 backward).
+// coupling tiles hold them premultiplied by the inverted diagonal tile, in the factor's
+// precision and in the walker's thread order: forward D_I L_{I,I-j}, backward
+// D_I^T L_{I+j,I}^T, j = 1 .. TD, at ((dir * nb + I) * TD + j - 1) * TILE_ELEMS (dir 0
+// forward, 1 backward).
 template <typename T> struct WalkTD { static constexpr int value = sizeof(T) == 4 ? 3 : 2; };
 inline size_t walk_coupling_bytes(int nb, bool fp32) {
   return fp32 ? 2 * (size_t)WalkTD<float>::value * nb * TILE_ELEMS * sizeof(float)
@@ -352,6 +353,10 @@ struct SolveArgs {
   const void* Mc;           // the factor's coupling tiles (FactorArgs::Mc), formed after it
 };
 void launch_trsv(hipStream_t s, const SolveArgs& a, bool fp32, bool forward);
+// The coupling tiles of a factor (FactorArgs::Mc), in bfloat16 for a factor with bfloat16
+// updates; launch_cholesky calls it after the factor when Mc is set.
+void launch_walk_couplings(hipStream_t s, int nb, const void* Ltiles, const void* Dinv, void* Mc, bool fp32,
+                           bool bf16);
 void launch_tiles_to_dense(hipStream_t s, int n, const void* Ltiles, bool fp32, double* L, int ldl);
 void launch_reset_tickets(hipStream_t s, Ctrl* ctrl);
 

@@ -38,6 +38,8 @@ template <> struct MF<float> {
 };
 
 constexpr int LDT = TILE + 1;    // LDS leading dimension of a column-major staged tile
+// 16 bytes as a native vector (HIP's uint4 class type keeps arrays of it out of registers)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline int32_t ld_relaxed(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
