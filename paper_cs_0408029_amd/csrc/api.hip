@@ -353,7 +353,7 @@ int ensure_factor(nnls_handle* h, int nF, int prec, bool* lost = nullptr) {
   const int nb = (nF + TILE - 1) / TILE;
   const size_t w = prec >= PREC_F32 ? sizeof(float) : sizeof(double);
   const size_t ntiles = (size_t)tile_count(nb);
-  const uint64_t before[4] = {h->Lt.gen, h->Dinv.gen, h->z.gen, h->Lbf.gen};
+  const uint64_t before[5] = {h->Lt.gen, h->Dinv.gen, h->z.gen, h->Lbf.gen, h->Mc.gen};
   TRY(ensure(h, h->Lt, ntiles * TILE_ELEMS * w));
   if (prec == PREC_BF16) TRY(ensure(h, h->Lbf, ntiles * TILE_ELEMS * sizeof(uint16_t)));
   TRY(ensure(h, h->Dinv, (size_t)nb * TILE_ELEMS * w));
@@ -369,7 +369,7 @@ int ensure_factor(nnls_handle* h, int nF, int prec, bool* lost = nullptr) {
   if (h->spart.gen != slots_before) h->slots_empty = false;   // fresh memory: not emptied yet
   if (lost)
     *lost = before[0] != h->Lt.gen || before[1] != h->Dinv.gen || before[2] != h->z.gen ||
-            (prec == PREC_BF16 && before[3] != h->Lbf.gen);
+            (prec == PREC_BF16 && (before[3] != h->Lbf.gen || before[4] != h->Mc.gen));
   return NNLS_OK;
 }
 

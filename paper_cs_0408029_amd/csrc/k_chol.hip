@@ -398,10 +398,18 @@ __device__ __forceinline__ void chol_tile(const FactorArgs& a, uint64_t wait_tic
 // stage: (R + C) bfloat16 tiles with row stride LDK; S (a float tile) aliases it.
 constexpr size_t STRIP_STAGE_BYTES =
     (size_t)(CHOL_STRIP + 1 > CHOL_PAIR + 2 ? CHOL_STRIP + 1 : CHOL_PAIR + 2) * TILE * LDK * 2;
+// The row walkers of a kept block apply the ROW_TD newest terms from the forward coupling
+// tiles (the same TD as the triangular solves'): a ring of ROW_TD + 1 outputs and ROW_TD
+// staged couplings, bfloat16 row-major.
+constexpr int ROW_TD = WalkTD<float>::value;
+constexpr size_t ROW_STAGE_BYTES = (size_t)(2 * ROW_TD + 1) * TILE * LDK * sizeof(uint16_t);
 
+// rw (one column of a kept block, with row walkers): the strip stops ROW_TD terms short and
+// hands over Y = S L_JJ^-T, the partial tile of the row walker, in the float tile (flag
+// -epoch, no bfloat16 copy, not counted in colcnt).
 template <int R, int C>
 __device__ __forceinline__ void chol_strip(const FactorArgs& a, uint64_t wait_ticks, int I0, int cnt, int J0,
-                                           char* stage) {
+                                           char* stage, bool rw = false) {
   typedef MF<float> M;
   typedef M::acc Acc;
   const int tid = fresh_tid(), lane = tid & 63, w = tid >> 6;
@@ -458,6 +466,7 @@ __device__ __forceinline__ void chol_strip(const FactorArgs& a, uint64_t wait_ti
     return true;
   };
   constexpr int PD = C == 1 ? 2 : 1;   // a pair's second step in flight would not fit the registers
+  const int kend = rw ? max(J0 - ROW_TD, 0) : J0;   // update steps k < kend
   u32x4 rg[PD][R + C][2];
   int held[PD];
   auto fetch = [&](auto slot, int s1) __attribute__((always_inline)) {
@@ -480,7 +489,7 @@ __device__ __forceinline__ void chol_strip(const FactorArgs& a, uint64_t wait_ti
   auto prime = [&](auto slot) __attribute__((always_inline)) {
     constexpr int d = decltype(slot)::value;
     held[d] = -1;
-    if (d < J0 && ready(d, d == 0)) fetch(slot, d);
+    if (d < kend && ready(d, d == 0)) fetch(slot, d);
   };
   // one update step from the staged operands: acc[c][r] -= L_{I0+r} L_{J0+c}^T over c < nc
   auto products = [&](int nc) __attribute__((always_inline)) {
@@ -540,13 +549,13 @@ __device__ __forceinline__ void chol_strip(const FactorArgs& a, uint64_t wait_ti
       }
     __syncthreads();
     held[d] = -1;
-    if (k + PD < J0 && ready(k + PD, false)) fetch(slot, k + PD);
+    if (k + PD < kend && ready(k + PD, false)) fetch(slot, k + PD);
     products(C);
   };
-  for (int k0 = 0; k0 < J0; k0 += PD) {
+  for (int k0 = 0; k0 < kend; k0 += PD) {
     step(std::integral_constant<int, 0>{}, k0);
     if constexpr (PD > 1)
-      if (k0 + 1 < J0) step(std::integral_constant<int, PD - 1>{}, k0 + 1);
+      if (k0 + 1 < kend) step(std::integral_constant<int, PD - 1>{}, k0 + 1);
   }
   __syncthreads();   // the last products have read the staged operands
 #pragma unroll
@@ -630,10 +639,112 @@ __device__ __forceinline__ void chol_strip(const FactorArgs& a, uint64_t wait_ti
       const int64_t ti = tile_index(I0 + r, J);
       float* dst = Lt + ti * TILE_ELEMS;
       for (int e = tid; e < TILE_ELEMS; e += 256) dst[e] = S[(e & (TILE - 1)) + (e >> 6) * LDT];
-      bf16_copy_to_global((uint16_t*)a.Lbf + ti * TILE_ELEMS, S, tid);
-      publish_tile(&a.tflag[ti], &a.colcnt[J], a.epoch);
+      if (rw) {
+        publish_store(&a.tflag[ti], -a.epoch);
+      } else {
+        bf16_copy_to_global((uint16_t*)a.Lbf + ti * TILE_ELEMS, S, tid);
+        publish_tile(&a.tflag[ti], &a.colcnt[J], a.epoch);
+      }
       __syncthreads();   // S is rewritten by the next tile
     }
+  }
+}
+
+// Row walker of a kept block (bfloat16-update factor).  The tiles (I, J), J < j0, of a new
+// tile row I >= j0 below the kept leading columns K solve X L_KK^T = H_IK, a chain along the
+// row (Sec. 2.1: the factor of the new F-block reuses the kept one).  The strips of these
+// tiles stop ROW_TD terms short and hand over Y_J = (H_IJ - sum_{k<J-TD} X_k L_Jk^T) L_JJ^-T;
+// the walker finishes
+//     X_J = Y_J - sum_{j=1..TD} X_{J-j} C_{J,j}^T,   C_{J,j} = L_JJ^-1 L_{J,J-j},
+// with the forward coupling tiles the previous factor formed for the kept columns (unchanged,
+// as the columns are), on bfloat16 MFMA from its own last TD outputs (an LDS ring), and
+// publishes X_J as a finished tile (float and bfloat16 copy).  A link of the chain is then
+// TD tile products in one workgroup instead of a publish, a poll and a tile load between two.
+__device__ __forceinline__ void row_walker(const FactorArgs& a, uint64_t wait_ticks, int I, char* stage) {
+  typedef MF<float> M;
+  typedef M::acc Acc;
+  constexpr int TD = ROW_TD;
+  const int tid = fresh_tid(), lane = tid & 63, w = tid >> 6;
+  const int j0 = a.j0;
+  float* Lt = (float*)a.Ltiles;
+  uint16_t* Lb = (uint16_t*)a.Lbf;
+  const uint16_t* Mc = (const uint16_t*)a.Mc;    // forward couplings first: (J TD + j - 1) tiles
+  uint16_t* ring = (uint16_t*)stage;              // X_J at slot J % (TD + 1), row-major, stride LDK
+  uint16_t* cst = ring + (TD + 1) * TILE * LDK;   // C_{J,j} at slot j - 1, row-major, stride LDK
+  const int qr = (w & 1) * 32, qc = (w >> 1) * 32, lr = lane & 15, lk = lane >> 4;
+  // a coupling tile's 16 entries of walk thread tid (row tid / 4, columns 16 (tid % 4) ..)
+  // are its 16-byte chunks tid and 256 + tid, staged at row tid / 4, column 16 (tid % 4)
+  const int o16 = (tid >> 2) * LDK + (tid & 3) * 16;
+  u32x4 cr[TD][2];
+  auto fetch_c = [&](int J1) __attribute__((always_inline)) {   // column J1's couplings
+#pragma unroll
+    for (int j = 0; j < TD; ++j) {
+      const u32x4* p = (const u32x4*)(Mc + ((int64_t)J1 * TD + j) * TILE_ELEMS);
+      cr[j][0] = p[tid];
+      cr[j][1] = p[256 + tid];
+    }
+  };
+  fetch_c(0);
+  for (int J = 0; J < j0; ++J) {
+    const int64_t ti = tile_index(I, J);
+    float* Y = Lt + ti * TILE_ELEMS;   // column-major; Y_J in, X_J out
+    spin_until(&a.tflag[ti], -a.epoch, true, a.ctrl, wait_ticks);
+    acquire_agent();
+    Acc acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          acc[bi][bj][v] = Y[(qc + 16 * bj + lr) * TILE + qr + 16 * bi + M::row(lane, v)];
+#pragma unroll
+    for (int j = 0; j < TD; ++j) {
+      ((u32x4*)(cst + j * TILE * LDK + o16))[0] = cr[j][0];
+      ((u32x4*)(cst + j * TILE * LDK + o16))[1] = cr[j][1];
+    }
+    __syncthreads();   // couplings staged; the ring holds X_{J-1} .. X_{J-TD}
+    fetch_c(min(J + 1, j0 - 1));
+#pragma unroll
+    for (int j = 1; j <= TD; ++j) {
+      if (J - j < 0) break;
+      const uint16_t* HA = ring + ((J - j) % (TD + 1)) * TILE * LDK;
+      const uint16_t* HB = cst + (j - 1) * TILE * LDK;
+#pragma unroll
+      for (int kh = 0; kh < TILE; kh += 32) {
+        const int kofs = kh + 8 * lk;
+        u32x4 x0 = *(const u32x4*)(HA + (qr + lr) * LDK + kofs);
+        u32x4 x1 = *(const u32x4*)(HA + (qr + 16 + lr) * LDK + kofs);
+        const u32x4 y0 = *(const u32x4*)(HB + (qc + lr) * LDK + kofs);
+        const u32x4 y1 = *(const u32x4*)(HB + (qc + 16 + lr) * LDK + kofs);
+        const uint32_t neg = 0x80008000u;   // X_J -= X_{J-j} C^T: negate the X operand
+        x0 ^= neg;
+        x1 ^= neg;
+        const bf16x8 a0 = __builtin_bit_cast(bf16x8, x0), a1 = __builtin_bit_cast(bf16x8, x1);
+        const bf16x8 b0 = __builtin_bit_cast(bf16x8, y0), b1 = __builtin_bit_cast(bf16x8, y1);
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+      }
+    }
+    // X_J into the ring (its slot held X_{J-TD-1}, last read at step J-1) and the float tile
+    uint16_t* HX = ring + (J % (TD + 1)) * TILE * LDK;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rr = qr + 16 * bi + M::row(lane, v), cc = qc + 16 * bj + lr;
+          HX[rr * LDK + cc] = __builtin_bit_cast(uint16_t, (__bf16)acc[bi][bj][v]);
+          Y[cc * TILE + rr] = acc[bi][bj][v];
+        }
+    __syncthreads();   // the ring slot is complete
+    u32x4* dst = (u32x4*)(Lb + ti * TILE_ELEMS + (tid >> 2) * TILE + (tid & 3) * 16);   // bfloat16 copy
+    dst[0] = ((const u32x4*)(HX + o16))[0];
+    dst[1] = ((const u32x4*)(HX + o16))[1];
+    publish_tile(&a.tflag[ti], &a.colcnt[J], a.epoch);
   }
 }
 
@@ -875,7 +986,8 @@ template <typename T, bool BF>
 __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wait_ticks) {
   // two staged tiles (the walker's and a single tile's buffers), or a strip's operands
   constexpr size_t TWO = 2 * (size_t)TILE * LDT * sizeof(T);
-  __shared__ __attribute__((aligned(16))) char smem[BF && STRIP_STAGE_BYTES > TWO ? STRIP_STAGE_BYTES : TWO];
+  constexpr size_t BFSTAGE = STRIP_STAGE_BYTES > ROW_STAGE_BYTES ? STRIP_STAGE_BYTES : ROW_STAGE_BYTES;
+  __shared__ __attribute__((aligned(16))) char smem[BF && BFSTAGE > TWO ? BFSTAGE : TWO];
   T* S = (T*)smem;
   T* W = S + TILE * LDT;
   __shared__ double s_part[4][TILE];
@@ -883,12 +995,15 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wa
   __shared__ double s_z[TILE];
   __shared__ double s_tp[TILE];
   __shared__ int s_t, s_kind, s_I, s_J, s_cnt;
-  const UnitPlan plan = {a.nb, a.j0, BF ? CHOL_STRIP : 1, CHOL_PAIR, BF};
+  const bool rw = BF && a.rowwalk;
+  const UnitPlan plan = {a.nb, a.j0, BF ? CHOL_STRIP : 1, CHOL_PAIR, BF, rw};
   const int64_t nunits = unit_total(plan);
+  const int nrw = rw ? a.nb - a.j0 : 0;   // row walkers: tickets 1 .. nrw
   for (;;) {
     const int tid = fresh_tid();
     if (tid == 0) {
-      const int t = atomicAdd(&a.ctrl->chol_ticket, 1) - 1;   // ticket 0 is the walker
+      // ticket 0 is the walker, the next nrw the row walkers, then the units
+      const int t = atomicAdd(&a.ctrl->chol_ticket, 1) - 1 - nrw;
       FactorUnit f = {UNIT_TILE, 0, 0, 1};
       if (t >= 0 && t < nunits) f = unit_at(t, plan);
       s_t = t;
@@ -900,14 +1015,20 @@ __global__ __launch_bounds__(256, 2) void k_chol_tiles(FactorArgs a, uint64_t wa
     __syncthreads();
     const int t = s_t, kind = s_kind, I = s_I, J = s_J, cnt = s_cnt;
     __syncthreads();   // every thread has its ticket before thread 0 may take the next
-    if (t < 0) {
+    if (t < -nrw) {
       walker<T, BF>(a, wait_ticks, S, W, s_part, s_rhs, s_z, s_tp);
       return;
+    }
+    if constexpr (BF) {
+      if (t < 0) {
+        row_walker(a, wait_ticks, a.j0 + nrw + t, smem);
+        return;
+      }
     }
     if (t >= nunits) return;
     if constexpr (BF) {
       if (kind == UNIT_STRIP) {
-        chol_strip<CHOL_STRIP, 1>(a, wait_ticks, I, cnt, J, smem);
+        chol_strip<CHOL_STRIP, 1>(a, wait_ticks, I, cnt, J, smem, rw && J < a.j0);
         __syncthreads();
         continue;
       }
@@ -936,12 +1057,18 @@ __global__ void k_tiles_to_dense(int n, const T* __restrict__ Lt, double* __rest
 
 }  // namespace
 
-void launch_cholesky(hipStream_t s, const FactorArgs& a, bool fp32) {
-  if (a.nb <= 0 || a.j0 < 0 || a.j0 >= a.nb) return;
+void launch_cholesky(hipStream_t s, const FactorArgs& args, bool fp32) {
+  if (args.nb <= 0 || args.j0 < 0 || args.j0 >= args.nb) return;
+  FactorArgs a = args;
   const bool bf = fp32 && a.Lbf;
-  const UnitPlan plan = {a.nb, a.j0, bf ? CHOL_STRIP : 1, CHOL_PAIR, bf};
-  int64_t grid = unit_total(plan) + 1;   // the units and the walker
-  if (a.max_wgs > 0 && grid > a.max_wgs) grid = a.max_wgs < 2 ? 2 : a.max_wgs;   // walker + >= 1 worker
+  // Row walkers for the rows below a kept block: the bfloat16-update factor, whose previous
+  // launch formed the kept columns' couplings (a kept block implies the same precision and
+  // buffers), with a few rows and a grid that leaves workers beside the walkers.
+  const int nrw = a.nb - a.j0;
+  a.rowwalk = bf && a.Mc && a.j0 >= ROW_TD + 2 && nrw <= 32 && (a.max_wgs == 0 || a.max_wgs >= nrw + 9);
+  const UnitPlan plan = {a.nb, a.j0, bf ? CHOL_STRIP : 1, CHOL_PAIR, bf, a.rowwalk != 0};
+  int64_t grid = unit_total(plan) + 1 + (a.rowwalk ? nrw : 0);   // the units and the walkers
+  if (a.max_wgs > 0 && grid > a.max_wgs) grid = a.max_wgs < 2 ? 2 : a.max_wgs;   // walkers + >= 1 worker
   if (fp32 && a.Lbf)
     hipLaunchKernelGGL((k_chol_tiles<float, true>), dim3((unsigned)grid), dim3(256), 0, s, a, a.wait_ticks);
   else if (fp32)

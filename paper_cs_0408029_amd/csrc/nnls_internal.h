@@ -91,11 +91,12 @@ struct FactorUnit {
 struct UnitPlan {
   int nb, j0, RS, RP;
   bool pairs;
+  bool kept_single = false;   // kept columns in one-column strips (the row walkers' partial tiles)
 };
 __host__ __device__ inline int strips_of(int rows, int R) { return rows > 0 ? (rows + R - 1) / R : 0; }
 __host__ __device__ inline int group_span(int J, const UnitPlan& p) {
   const int end = J < p.j0 ? p.j0 : p.nb;
-  return (p.pairs && J + 1 < end) ? 2 : 1;
+  return (p.pairs && J + 1 < end && !(J < p.j0 && p.kept_single)) ? 2 : 1;
 }
 __host__ __device__ inline int group_units(int J, int C, const UnitPlan& p) {
   if (J < p.j0) return strips_of(p.nb - p.j0, C == 2 ? p.RP : p.RS);
@@ -313,6 +314,8 @@ struct FactorArgs {
                           // nullptr: the updates read the float tiles
   void* Mc;               // optional: the triangular solves' coupling tiles, formed after the
                           // factor (walk_coupling_bytes; nullptr: not formed)
+  int rowwalk;            // set by launch_cholesky: the new tile rows below a kept block are
+                          // finished by row walkers from the previous factor's coupling tiles
 };
 // Newest terms the walker of the triangular solves adds itself each step.  The factor's
 // coupling tiles hold them premultiplied by the inverted diagonal tile, in the factor's

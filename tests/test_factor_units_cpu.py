@@ -1,8 +1,9 @@
 """The tiled factor's unit plan (which tiles each ticket takes, in which order), compiled from
 the library's own header and checked on the host for every block count up to 40, every
-number of kept columns and four strip shapes: each computed tile is taken exactly once, and
-every unit waits only for tiles produced under smaller tickets (the walker's outputs at the
-ticket of the last unit it needs), which is what makes every wait of the persistent grid end.
+number of kept columns and four strip shapes, with and without row walkers for the rows below
+a kept block: each computed tile is taken exactly once, and every unit waits only for tiles
+produced under smaller tickets (the walkers' outputs at the ticket of the last unit they
+need), which is what makes every wait of the persistent grid end.
 CPU only."""
 import os
 import shutil

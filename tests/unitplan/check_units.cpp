@@ -12,8 +12,12 @@
 
 using namespace nnls;
 
-static int check(int nb, int j0, int RS, int RP, bool pairs) {
-  const UnitPlan p = {nb, j0, RS, RP, pairs};
+// kept_single: the kept columns' units are one-column strips that stop TD terms short and
+// hand over partial tiles; the row walker of tile row I finishes (I, J) once the units of
+// (I, 0 .. J) are through (it runs from the start of the launch on tickets of its own).
+static int check(int nb, int j0, int RS, int RP, bool pairs, bool kept_single = false) {
+  const UnitPlan p = {nb, j0, RS, RP, pairs, kept_single};
+  constexpr int TD = WalkTD<float>::value;
   const int64_t total = unit_total(p);
   std::map<std::pair<int, int>, int64_t> producer;   // tile -> unit (the partial unit for walker tiles)
   std::vector<FactorUnit> units;
@@ -32,6 +36,8 @@ static int check(int nb, int j0, int RS, int RP, bool pairs) {
         // strips hold plain off-diagonal tiles only (not the walker's inputs)
         if (f.kind != UNIT_TILE && J >= j0 && I - J <= 1)
           return std::printf("walker tile (%d,%d) in a strip nb=%d j0=%d\n", I, J, nb, j0), 1;
+        if (kept_single && J < j0 && f.kind != UNIT_STRIP)
+          return std::printf("kept tile (%d,%d) not in a one-column strip nb=%d j0=%d\n", I, J, nb, j0), 1;
       }
   }
   int64_t want = 0;
@@ -46,8 +52,15 @@ static int check(int nb, int j0, int RS, int RP, bool pairs) {
     if (J + 1 < nb) w = std::max(w, producer.at({J + 1, J}));
     walker[J] = w;
   }
+  std::map<std::pair<int, int>, int64_t> rowdone;   // kept_single: the row walkers' finished tiles
+  if (kept_single)
+    for (int I = j0; I < nb; ++I) {
+      int64_t w = -1;
+      for (int J = 0; J < j0; ++J) rowdone[{I, J}] = w = std::max(w, producer.at({I, J}));
+    }
   auto ready_at = [&](int I, int K) -> int64_t {   // ticket after which tile (I, K) is final
     if (I < j0 && K < j0) return -1;                // kept from the previous launch
+    if (kept_single && K < j0) return rowdone.at({I, K});
     if (K >= j0 && I - K <= 1) return walker[K];    // the walker's diagonal and sub-diagonal
     return producer.at({I, K});
   };
@@ -66,8 +79,9 @@ static int check(int nb, int j0, int RS, int RP, bool pairs) {
     for (int c = 0; c < C; ++c)
       for (int r = 0; r < f.cnt; ++r) {
         const int I = f.I + r, J = f.J + c;
-        const bool partial = f.kind == UNIT_TILE && J >= j0 && I - J <= 1;
-        const int kend = (f.kind == UNIT_TILE && I == J && J > j0) ? J - 1 : (C == 2 ? f.J : J);
+        const bool partial = (f.kind == UNIT_TILE && J >= j0 && I - J <= 1) || (kept_single && J < j0);
+        int kend = (f.kind == UNIT_TILE && I == J && J > j0) ? J - 1 : (C == 2 ? f.J : J);
+        if (kept_single && J < j0) kend = std::max(J - TD, 0);
         for (int k = 0; k < kend; ++k) {
           if (!need(ready_at(I, k), "L_Ik")) return 1;
           if (!need(ready_at(J, k), "L_Jk")) return 1;
@@ -91,8 +105,14 @@ int main() {
         const bool pairs = shape != 0;
         if (check(nb, j0, RS, RP, pairs)) return 1;
         ++cases;
+        if (pairs && j0 > 0) {   // with row walkers for the rows below the kept block
+          if (check(nb, j0, RS, RP, pairs, true)) return 1;
+          ++cases;
+        }
       }
-  if (check(469, 0, CHOL_STRIP, CHOL_PAIR, true) || check(782, 613, CHOL_STRIP, CHOL_PAIR, true)) return 1;
-  std::printf("ok %d\n", cases + 2);
+  if (check(469, 0, CHOL_STRIP, CHOL_PAIR, true) || check(782, 613, CHOL_STRIP, CHOL_PAIR, true) ||
+      check(199, 185, CHOL_STRIP, CHOL_PAIR, true, true) || check(196, 195, CHOL_STRIP, CHOL_PAIR, true, true))
+    return 1;
+  std::printf("ok %d\n", cases + 4);
   return 0;
 }
