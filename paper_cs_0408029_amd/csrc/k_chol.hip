@@ -69,24 +69,31 @@ __device__ inline void gather_tile(const FactorArgs& a, int tid, int I, int J, T
   } else {
     for (int e = tid; e < TILE_ELEMS; e += 256) S[(e & (TILE - 1)) + (e >> 6) * LDT] = (T)0;
     __syncthreads();
-    if (tid < TILE) {
-      // position q's list holds the rows p >= q in ascending order: find p >= r0
-      const int c = tid, q = c0 + c;
-      if (q < a.nF && r0 < a.nF) {
-        const int64_t s = a.gpos.pptr[a.Flist[q]], e = s + a.gpos.pcnt[q];
-        int64_t L = s, R = e;
-        while (L < R) {
-          const int64_t M = (L + R) >> 1;
-          if (a.gpos.prow[M] < r0) L = M + 1; else R = M;
-        }
-        for (int64_t t = L; t < e; ++t) {
-          const int p = a.gpos.prow[t];
-          if (p >= r0 + TILE) break;
-          S[(p - r0) + c * LDT] = (T)a.gpos.pval[t];
-        }
-      } else if (q >= a.nF && I == J) {
-        S[c + c * LDT] = (T)1;
+    // four lanes a column (a quad of one wave): position q's list holds the rows p >= q in
+    // ascending order.  The quad narrows [L, R) to the first row >= r0 by a five-way search
+    // (each lane probes one of the four interior points, and the count of probes below r0
+    // picks the fifth), then scans the block's entries interleaved, lane k taking every
+    // fourth from L + k.
+    const int c = tid >> 2, k = tid & 3, q = c0 + c;
+    if (q < a.nF && r0 < a.nF) {
+      const int64_t s = a.gpos.pptr[a.Flist[q]], e = s + a.gpos.pcnt[q];
+      int64_t L = s, R = e;
+      while (R - L > 4) {   // the same trip count in the four lanes of the quad
+        const int64_t step = (R - L) / 5;
+        const int below = a.gpos.prow[L + (k + 1) * step] < r0 ? 1 : 0;
+        int cnt = below + __shfl_xor(below, 1);
+        cnt += __shfl_xor(cnt, 2);
+        // the probes below r0 are a prefix (the rows ascend): cnt of them
+        if (cnt < 4) R = L + (cnt + 1) * step;
+        if (cnt > 0) L = L + cnt * step + 1;
       }
+      for (int64_t t = L + k; t < e; t += 4) {
+        const int p = a.gpos.prow[t];
+        if (p >= r0 + TILE) break;
+        if (p >= r0) S[(p - r0) + c * LDT] = (T)a.gpos.pval[t];
+      }
+    } else if (q >= a.nF && I == J && k == 0) {
+      S[c + c * LDT] = (T)1;
     }
   }
   __syncthreads();
