@@ -186,7 +186,9 @@ int nnls_solve_dense(nnls_handle* h, int32_t m, int32_t n, const double* A, int3
  * problem forms A^T b and the Gram matrix (and checks the input), then one workgroup per
  * problem runs the whole pivoting loop of the Sec. 2 algorithm box on the device; a
  * problem's result does not depend on the other problems in the batch.  opts applies to every problem
- * (NNLS_FP32_IR: float32 factor, float64 refinement).  info: host nnls_info[batch] or
+ * (NNLS_FP32_IR: float32 Gram matrix and factor, float64 refinement; NNLS_BF16_IR runs the
+ * same float32 tier, bit for bit: at n <= 256 the batched kernels are bound by the stream of
+ * A and the pivot chain, not by the factor's multiply rate).  info: host nnls_info[batch] or
  * NULL.  Returns NNLS_OK when every problem succeeded, otherwise the first failing status
  * (per-problem statuses are in info; a failed problem does not affect the others).
  * Errors: INVALID_ARG for a bad size or null pointer (nothing runs); per problem
@@ -308,8 +310,10 @@ typedef struct {
 
 /* Start a server on device `device`.  cfg and opts may be NULL (defaults; opts applies to
  * every request, NNLS_FLAG_PROFILE is ignored, and max_workgroups 0 becomes 128 so that
- * concurrent factorisations share the device; results do not depend on it).  Errors: INVALID_ARG (bad config),
- * DEVICE, NO_MEMORY. */
+ * concurrent factorisations share the device; results do not depend on it).  Every
+ * precision is accepted: the sparse lane runs it as nnls_solve_csc does, and the batched
+ * lanes run NNLS_BF16_IR as their float32 tier (as nnls_solve_dense_batched).
+ * Errors: INVALID_ARG (bad config), DEVICE, NO_MEMORY. */
 int nnls_server_create(nnls_server** out, int device, const nnls_server_config* cfg,
                        const nnls_options* opts);
 

@@ -1059,7 +1059,8 @@ int nnls_solve_dense_batched(nnls_handle* h, int32_t batch, const int32_t* m, co
   if (opts) o = *opts;
   if (!h || batch < 0 || (batch > 0 && (!m || !n || !A || !lda || !b || !x || !y)))
     return NNLS_ERR_INVALID_ARG;
-  if (check_options(o) != NNLS_OK || o.precision == NNLS_BF16_IR) return NNLS_ERR_INVALID_ARG;
+  if (check_options(o) != NNLS_OK) return NNLS_ERR_INVALID_ARG;
+  if (o.precision == NNLS_BF16_IR) o.precision = NNLS_FP32_IR;   // the batched path's float32 tier
   if (info)
     for (int i = 0; i < batch; ++i) {
       std::memset(&info[i], 0, sizeof(nnls_info));
@@ -1165,7 +1166,8 @@ int nnls_solve_dense_batched_noalloc(nnls_handle* h, int32_t batch, const int32_
   if (opts) o = *opts;
   if (!h || batch < 0 || (batch > 0 && (!m || !n || !A || !lda || !b || !x || !y)))
     return NNLS_ERR_INVALID_ARG;
-  if (check_options(o) != NNLS_OK || o.precision == NNLS_BF16_IR) return NNLS_ERR_INVALID_ARG;
+  if (check_options(o) != NNLS_OK) return NNLS_ERR_INVALID_ARG;
+  if (o.precision == NNLS_BF16_IR) o.precision = NNLS_FP32_IR;   // the batched path's float32 tier
   if (info)
     for (int i = 0; i < batch; ++i) {
       std::memset(&info[i], 0, sizeof(nnls_info));
@@ -1269,7 +1271,8 @@ int nnls_batch_plan_create(nnls_handle* h, int32_t batch, const int32_t* m, cons
   nnls_default_options(&o);
   if (opts) o = *opts;
   if (!h || batch < 1 || !m || !n || !A || !lda || !b || !x || !y) return NNLS_ERR_INVALID_ARG;
-  if (check_options(o) != NNLS_OK || o.precision == NNLS_BF16_IR) return NNLS_ERR_INVALID_ARG;
+  if (check_options(o) != NNLS_OK) return NNLS_ERR_INVALID_ARG;
+  if (o.precision == NNLS_BF16_IR) o.precision = NNLS_FP32_IR;   // the batched path's float32 tier
   for (int i = 0; i < batch; ++i)
     if (n[i] < 1 || m[i] < n[i] || lda[i] < m[i] || !A[i] || !b[i] || !x[i] || !y[i]) return NNLS_ERR_INVALID_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return NNLS_ERR_DEVICE;

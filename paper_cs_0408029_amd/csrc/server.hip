@@ -444,7 +444,7 @@ void batch_lane(nnls_server* s) {
   ba.tau = s->opts.tau;
   ba.p_max = s->opts.p_max;
   ba.max_iter = s->opts.max_iter;
-  ba.fp32 = s->opts.precision == NNLS_FP32_IR ? 1 : 0;
+  ba.fp32 = s->opts.precision != NNLS_FP64 ? 1 : 0;   // NNLS_BF16_IR: the batched float32 tier
   ba.ir_max_steps = s->opts.ir_max_steps;
   ba.ir_rtol = s->opts.ir_rtol;
   ba.gram_dual = (s->opts.flags & NNLS_FLAG_GRAM_DUAL) != 0 ? 1 : 0;
@@ -680,8 +680,9 @@ int nnls_server_create(nnls_server** out, int device, const nnls_server_config* 
   o.flags &= ~NNLS_FLAG_PROFILE;
   // several factorisations share the device: each takes a persistent grid of its own
   if (o.max_workgroups == 0) o.max_workgroups = 128;
-  if (!(o.tau >= 0.0) || o.p_max < 0 || (o.precision != NNLS_FP64 && o.precision != NNLS_FP32_IR) ||
-      (o.precision == NNLS_FP32_IR && (o.ir_max_steps < 0 || !(o.ir_rtol > 0.0))))
+  if (!(o.tau >= 0.0) || o.p_max < 0 ||
+      (o.precision != NNLS_FP64 && o.precision != NNLS_FP32_IR && o.precision != NNLS_BF16_IR) ||
+      (o.precision != NNLS_FP64 && (o.ir_max_steps < 0 || !(o.ir_rtol > 0.0))))
     return NNLS_ERR_INVALID_ARG;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {

@@ -242,3 +242,15 @@ def test_plan_rejects_bad_batches(h):
     with pytest.raises(RuntimeError):
         N.BatchPlan(h, [A], [torch.zeros(3, dtype=torch.float64, device=DEV)],
                     [torch.zeros(5, dtype=torch.float64, device=DEV)], [torch.zeros(5, dtype=torch.float64, device=DEV)])
+
+
+def test_bf16_request_runs_the_float32_tier(h, batch24):
+    """NNLS_BF16_IR on the batched path runs its float32 tier: the same statuses, iteration
+    counts and bitwise the same x and y as NNLS_FP32_IR."""
+    problems, insts = batch24
+    st32, inf32, x32, y32 = run_batch(h, problems, precision=N.NNLS_FP32_IR)
+    st16, inf16, x16, y16 = run_batch(h, problems, precision=N.NNLS_BF16_IR)
+    assert st32 == st16 == N.NNLS_OK
+    for a, b, xa, xb, ya, yb in zip(inf32, inf16, x32, x16, y32, y16):
+        assert a.status == b.status and a.iterations == b.iterations and a.ir_steps == b.ir_steps
+        assert np.array_equal(xa, xb) and np.array_equal(ya, yb)

@@ -64,8 +64,10 @@ def check_against_oracle(insts, results, refs, tol):
         assert np.all(x >= 0) and np.all(y >= 0) and np.dot(x, y) == 0.0
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-8)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-8), (2, 1e-8)])
 def test_mixed_stream_matches_oracle(stream_small, oracle_small, precision, tol):
+    """precision 2 (NNLS_BF16_IR): bfloat16-update factors on the sparse lane, the float32
+    tier on the batched lanes."""
     with N.Server(0, opts=N.default_options(precision=precision), workers=4, batch_lanes=2,
                   batch_max_n=160) as srv:
         results = run_all(srv, stream_small)
