@@ -476,11 +476,18 @@ def test_bf16_ill_conditioned_climbs_the_ladder(h):
     assert 0 < info.est_rel_err <= 1e-12 and actual <= info.est_rel_err + 4e-16
 
 
-def test_bf16_rejected_where_not_offered(h):
+def test_bf16_on_the_batched_path_is_its_float32_tier(h):
+    """The batched path has no bfloat16 tier: a NNLS_BF16_IR request runs its float32 tier,
+    bit for bit the NNLS_FP32_IR result."""
     A = np.random.default_rng(0).standard_normal((40, 20))
     b = np.ones(40)
-    x = torch.empty(20, dtype=torch.float64, device=DEV)
-    y = torch.empty_like(x)
-    st, _ = N.nnls_solve_dense_batched(h, [colmajor_dev(A)], [t(b)], [x], [y],
-                                       N.default_options(precision=N.NNLS_BF16_IR))
-    assert st == N.NNLS_ERR_INVALID_ARG
+    out = {}
+    for prec in (N.NNLS_FP32_IR, N.NNLS_BF16_IR):
+        x = torch.empty(20, dtype=torch.float64, device=DEV)
+        y = torch.empty_like(x)
+        st, _ = N.nnls_solve_dense_batched(h, [colmajor_dev(A)], [t(b)], [x], [y],
+                                           N.default_options(precision=prec))
+        assert st == N.NNLS_OK
+        out[prec] = (x.cpu().numpy(), y.cpu().numpy())
+    assert np.array_equal(out[N.NNLS_FP32_IR][0], out[N.NNLS_BF16_IR][0])
+    assert np.array_equal(out[N.NNLS_FP32_IR][1], out[N.NNLS_BF16_IR][1])
