@@ -86,23 +86,34 @@ def profiled_traffic(kernel_srcs, summary: str):
     return float(fields["traffic_bytes_per_launch"])
 
 
+CPU_THREADS = 0   # --cpu-threads: BLAS threads of the oracle timing (0: as the host sets them)
+
+
 def cpu_baseline(inst, budget_s: float, max_solves: int = 5, what: str = "whole solve(s) of the benchmark instance"):
     """The oracle as it stands, on this host, over whole solves of the same instance until
-    budget_s of CPU work has been spent (at least one solve, at most max_solves)."""
+    budget_s of CPU work has been spent (at least one solve, at most max_solves); with
+    --cpu-threads K its BLAS runs on K threads (1: the serial baseline)."""
+    import contextlib
     from oracle import bpp_solve
+    limit = contextlib.nullcontext()
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        from threadpoolctl import threadpool_info, threadpool_limits
+        if CPU_THREADS > 0:
+            limit = threadpool_limits(limits=CPU_THREADS)
+            threads = CPU_THREADS
+        else:
+            threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count() or 1
     t0 = time.perf_counter()
     count = 0
-    while True:
-        res = bpp_solve(inst.A, inst.b)
-        count += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or count >= max_solves:
-            break
+    with limit:
+        while True:
+            res = bpp_solve(inst.A, inst.b)
+            count += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s or count >= max_solves:
+                break
     return {"value": count / el, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{count} {what}, {el:.1f} s", "status": res.status,
             "free_set_match": bool(np.array_equal(res.free, inst.active))}
@@ -740,6 +751,8 @@ def main():
                     help="metric: skip the 60000 x 12000 pair")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="BLAS threads of the oracle timing (0: the host's default; 1: serial)")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "fp32ir", "bf16ir"], default="fp64",
                     help="fp64: the plain FP64 path (the metric's reference); fp32ir: float32 factor "
@@ -771,6 +784,8 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+    global CPU_THREADS
+    CPU_THREADS = args.cpu_threads
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
