@@ -141,10 +141,12 @@ def test_rerun_is_bitwise_identical(h):
     assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3]) and a[4] == b[4]
 
 
-@pytest.mark.parametrize("cap,precision", [(1, 0), (7, 0), (64, 0), (7, 1)])
+@pytest.mark.parametrize("cap,precision", [(1, 0), (7, 0), (64, 0), (7, 1), (64, 2)])
 def test_capped_persistent_grid_is_bitwise_identical(h, cap, precision):
     """A capped factor grid (fewer persistent workgroups taking the tile tickets) computes
-    every tile with the same operations in the same order as one workgroup per tile."""
+    every tile with the same operations in the same order as one workgroup per tile.  (The
+    bfloat16-update factor's row walkers below a kept block need a cap of at least the new
+    tile rows + 9; a cap of 64 leaves them on.)"""
     inst = W.sparse_large(1002, m=6000, n=1200)
     a = solve_csc(h, inst.A, inst.b, precision=precision)
     b = solve_csc(h, inst.A, inst.b, precision=precision, max_workgroups=cap)
@@ -152,12 +154,14 @@ def test_capped_persistent_grid_is_bitwise_identical(h, cap, precision):
     assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3]) and a[4] == b[4]
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-10)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-10), (2, 1e-10)])
 @pytest.mark.parametrize("m,n,cap", [(6000, 1200, 0), (60000, 12000, 0), (6000, 1200, 7)])
 def test_kept_factor_tiles_match_full_refactor(h, m, n, cap, precision, tol):
     """The factor keeps the leading tile columns that no exchange touched (F ordered so
     that they come first); against refactoring the whole F-block every iteration it takes
-    the same pivot steps and gives x within rounding, and the later iterations keep tiles."""
+    the same pivot steps and gives x within rounding, and the later iterations keep tiles.
+    With bfloat16 updates (precision 2) the rows below a kept block go through the row
+    walkers and the previous factor's coupling tiles."""
     inst = W.sparse_large(1002, m=m, n=n)
     kw = dict(precision=precision, max_workgroups=cap)
     st1, info1, x1, y1, _ = solve_csc(h, inst.A, inst.b, **kw)
