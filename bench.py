@@ -417,6 +417,7 @@ def bench_serve(args):
                                f"20 N(0,1)/col + band, 30-60% active, margin 1e-3; pool of {len(pool)} "
                                "problems, seed 1004",
                    "workers": args.workers, "batch_lanes": args.batch_lanes,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
                    "batch_max_n": args.batch_max_n, "batch_step_iters": args.batch_step_iters,
                    "max_workgroups": args.max_workgroups,
                    "pool_n_mean": float(ns.mean()), "pool_n_max": int(ns.max())},
@@ -766,7 +767,9 @@ def main():
     ap.add_argument("--duration", type=float, default=10.0, help="serve: timed seconds of arrivals")
     ap.add_argument("--warmup-s", type=float, default=1.0, help="serve: warm-up seconds of arrivals")
     ap.add_argument("--pool", type=int, default=128, help="serve: distinct problems cycled")
-    ap.add_argument("--workers", type=int, default=12, help="serve: concurrent sparse solves")
+    ap.add_argument("--workers", type=int, default=16, help="serve: concurrent sparse solves")
+    ap.add_argument("--hw-queues", type=int, default=24,
+                    help="serve: GPU_MAX_HW_QUEUES for this process (at least workers + batch lanes)")
     ap.add_argument("--batch-lanes", type=int, default=2, help="serve: batched launches in flight")
     ap.add_argument("--batch-max-n", type=int, default=256, help="serve: largest n sent to batched launches")
     ap.add_argument("--max-workgroups", type=int, default=0,
@@ -792,9 +795,11 @@ def main():
         sys.exit(2)
 
     if args.workload == "serve":
-        # one hardware queue per stream of the serving engine (HIP's default is 4), set
-        # before the runtime starts
-        os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+        if not 1 <= args.hw_queues <= 32:
+            ap.error("--hw-queues must be in [1, 32]")
+        # a hardware queue for every stream of the serving engine (HIP's default is 4),
+        # set before the runtime starts; it replaces a value from the environment
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     import torch
     import paper_cs_0408029_amd as N
 

@@ -283,7 +283,10 @@ typedef struct {
   size_t hbm_budget;        /* device bytes admitted requests may hold; 0: 90% of the free
                                memory at create                                          */
   int32_t workers;          /* sparse requests solved at once, each on its own stream;
-                               0: 8                                                      */
+                               0: 16.  Streams beyond the process's hardware queues
+                               (GPU_MAX_HW_QUEUES, 4 unless set before the HIP runtime
+                               starts) share queues and serialise: set it to at least
+                               workers + batch_lanes                                     */
   int32_t batch_lanes;      /* batched launches in flight at once; 0: 2                  */
   int32_t batch_max_n;      /* n <= batch_max_n goes to batched launches; 0: 256; < 0:
                                never                                                     */
@@ -309,7 +312,7 @@ typedef struct {
 } nnls_serving_stats;
 
 /* Start a server on device `device`.  cfg and opts may be NULL (defaults; opts applies to
- * every request, NNLS_FLAG_PROFILE is ignored, and max_workgroups 0 becomes 128 so that
+ * every request, NNLS_FLAG_PROFILE is ignored, and max_workgroups 0 becomes 96 so that
  * concurrent factorisations share the device; results do not depend on it).  Every
  * precision is accepted: the sparse lane runs it as nnls_solve_csc does, and the batched
  * lanes run NNLS_BF16_IR as their float32 tier (as nnls_solve_dense_batched).

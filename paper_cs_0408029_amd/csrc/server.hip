@@ -665,7 +665,7 @@ int nnls_server_create(nnls_server** out, int device, const nnls_server_config* 
   *out = nullptr;
   nnls_server_config c{};
   if (cfg) c = *cfg;
-  if (c.workers == 0) c.workers = 8;
+  if (c.workers == 0) c.workers = 16;
   if (c.batch_lanes == 0) c.batch_lanes = 2;
   if (c.batch_max_n == 0) c.batch_max_n = 256;
   if (c.batch_max_count == 0) c.batch_max_count = 1024;
@@ -678,8 +678,9 @@ int nnls_server_create(nnls_server** out, int device, const nnls_server_config* 
   nnls_default_options(&o);
   if (opts) o = *opts;
   o.flags &= ~NNLS_FLAG_PROFILE;
-  // several factorisations share the device: each takes a persistent grid of its own
-  if (o.max_workgroups == 0) o.max_workgroups = 128;
+  // several factorisations share the device: each takes a persistent grid of its own, and
+  // 16 workers' grids of 96 fill the compute units about three times over
+  if (o.max_workgroups == 0) o.max_workgroups = 96;
   if (!(o.tau >= 0.0) || o.p_max < 0 ||
       (o.precision != NNLS_FP64 && o.precision != NNLS_FP32_IR && o.precision != NNLS_BF16_IR) ||
       (o.precision != NNLS_FP64 && (o.ir_max_steps < 0 || !(o.ir_rtol > 0.0))))
