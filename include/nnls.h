@@ -414,7 +414,10 @@ int nnls_spd_solve(nnls_handle* h, int32_t n, const double* S, int32_t lds, cons
 
 /* Eq. 5 on a given split: r = A x - b (x is used as given: callers pass x_G = 0) and
  * y_i = a_i^T r for i in G (free[i] == 0), y_i = 0 for i in F.  free: uint8[n] device.
- * r may be NULL. */
+ * r may be NULL.  When n (m) exceeds 2^19, the residual (dual) gathers x (r) in slices of
+ * 2^18 elements over a sliced copy of A that the call builds in the handle's workspace
+ * (about 12 nnz + 4 (m + 1) n / 2^18 bytes per copy); each r_i and y_i is then the
+ * sequential sum of its terms in ascending index order. */
 int nnls_dual_csc(nnls_handle* h, int32_t m, int32_t n, int64_t nnz, const int32_t* colptr,
                   const int32_t* rowidx, const double* val, const double* b,
                   const uint8_t* free_flags, const double* x, double* r, double* y);

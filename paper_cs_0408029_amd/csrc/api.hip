@@ -106,6 +106,7 @@ struct nnls_handle {
   DevBuf est, ev, exi;                         // condition estimate: state, probe vector, signs
   DevBuf bprobs, border, binfo, bws;   // batched dense problems
   DevBuf scan;                         // chunk sums of the setup prefix scans
+  DevBuf slc, srp, sri, srv, sdp, sdi, sdv;   // sliced gathers: counts; residual and dual copies
   Ctrl* h_ctrl = nullptr;     // pinned
   int64_t* h_scalar = nullptr;  // pinned scratch for small reads
   int epoch = 0;
@@ -922,7 +923,7 @@ void release_workspace(nnls_handle* h) {
                     &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart, &h->spart,
                     &h->upcnt, &h->prow, &h->pval, &h->pcnt, &h->Fold, &h->zr, &h->est, &h->ev, &h->exi,
                     &h->bprobs, &h->border, &h->binfo, &h->bws, &h->scan, &h->wr, &h->bw, &h->bb, &h->rlo, &h->Lbf,
-                    &h->Mc};
+                    &h->Mc, &h->slc, &h->srp, &h->sri, &h->srv, &h->sdp, &h->sdi, &h->sdv};
   for (DevBuf* b : bufs) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
@@ -1007,7 +1008,7 @@ int nnls_destroy(nnls_handle* h) {
                     &h->Lt, &h->Dinv, &h->colcnt, &h->dflag, &h->tflag, &h->z, &h->xF, &h->Hd, &h->gF, &h->rpart, &h->spart,
                     &h->upcnt, &h->prow, &h->pval, &h->pcnt, &h->Fold, &h->zr, &h->est, &h->ev, &h->exi,
                     &h->bprobs, &h->border, &h->binfo, &h->bws, &h->scan, &h->wr, &h->bw, &h->bb, &h->rlo, &h->Lbf,
-                    &h->Mc};
+                    &h->Mc, &h->slc, &h->srp, &h->sri, &h->srv, &h->sdp, &h->sdi, &h->sdv};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
@@ -1618,12 +1619,45 @@ int nnls_dual_csc(nnls_handle* h, int32_t m, int32_t n, int64_t nnz, const int32
     TRY(ensure(h, h->r, sizeof(double) * (size_t)m));
     rr = (double*)h->r.p;
   }
+  // a gathered vector larger than an XCD's L2 is swept in slices (x for the residual,
+  // r for the dual); the sliced copies of A are built before the products
+  const bool slice_x = n > SLICE_MIN_LEN, slice_r = m > SLICE_MIN_LEN;
+  const int nsx = slice_count(n), nsr = slice_count(m);
+  if (slice_x || slice_r) {
+    const int64_t slots = std::max(slice_x ? (int64_t)nsx * ((int64_t)m + 1) : 0,
+                                   slice_r ? (int64_t)nsr * ((int64_t)n + 1) : 0);
+    TRY(ensure(h, h->slc, sizeof(int32_t) * (size_t)slots));
+    TRY(ensure(h, h->scan, sizeof(int32_t) * ((size_t)slots / 2048 + 1)));
+  }
+  if (slice_x) {
+    TRY(ensure(h, h->srp, sizeof(int32_t) * ((size_t)nsx * ((size_t)m + 1) + 1)));
+    TRY(ensure(h, h->sri, sizeof(int32_t) * (size_t)nnz));
+    TRY(ensure(h, h->srv, sizeof(double) * (size_t)nnz));
+    launch_slice_build(h->stream, m, nnz, (const int32_t*)h->rowptr.p, (const int32_t*)h->colidx.p,
+                       (const double*)h->valr.p, nsx, (int32_t*)h->slc.p, (int32_t*)h->srp.p,
+                       (int32_t*)h->sri.p, (double*)h->srv.p, (int32_t*)h->scan.p);
+  }
+  if (slice_r) {
+    TRY(ensure(h, h->sdp, sizeof(int32_t) * ((size_t)nsr * ((size_t)n + 1) + 1)));
+    TRY(ensure(h, h->sdi, sizeof(int32_t) * (size_t)nnz));
+    TRY(ensure(h, h->sdv, sizeof(double) * (size_t)nnz));
+    launch_slice_build(h->stream, n, nnz, colptr, rowidx, val, nsr, (int32_t*)h->slc.p, (int32_t*)h->sdp.p,
+                       (int32_t*)h->sdi.p, (double*)h->sdv.p, (int32_t*)h->scan.p);
+  }
   int64_t pe = prof_begin(h, NNLS_PROF_RESIDUAL);
-  launch_residual_csr(h->stream, m, nnz, (const int32_t*)h->rowptr.p, (const int32_t*)h->colidx.p,
-                      (const double*)h->valr.p, x, b, rr);
+  if (slice_x)
+    launch_sliced_residual(h->stream, m, nsx, (const int32_t*)h->srp.p, (const int32_t*)h->sri.p,
+                           (const double*)h->srv.p, x, b, rr);
+  else
+    launch_residual_csr(h->stream, m, nnz, (const int32_t*)h->rowptr.p, (const int32_t*)h->colidx.p,
+                        (const double*)h->valr.p, x, b, rr);
   prof_end(h, pe, 12.0 * (double)nnz + 20.0 * m + 8.0 * n);
   pe = prof_begin(h, NNLS_PROF_DUAL);
-  launch_dual_csc(h->stream, n, colptr, rowidx, val, rr, free_flags, y);
+  if (slice_r)
+    launch_sliced_dual(h->stream, n, nsr, (const int32_t*)h->sdp.p, (const int32_t*)h->sdi.p,
+                       (const double*)h->sdv.p, rr, free_flags, y);
+  else
+    launch_dual_csc(h->stream, n, colptr, rowidx, val, rr, free_flags, y);
   prof_end(h, pe, 12.0 * (double)nnz + 8.0 * m + 13.0 * n);
   HIP_TRY(hipStreamSynchronize(h->stream));
   prof_flush(h);

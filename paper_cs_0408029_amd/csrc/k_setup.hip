@@ -608,6 +608,10 @@ static void launch_scan(hipStream_t s, int64_t n, const Tin* count, Tout* out, T
     hipLaunchKernelGGL((k_scan_apply<Tin, Tout>), dim3(nchunk), dim3(256), 0, s, n, count, (const Tout*)sums, out);
 }
 
+void launch_scan_i32(hipStream_t s, int64_t n, const int32_t* count, int32_t* out, int32_t* sums) {
+  launch_scan<int32_t, int32_t>(s, n, count, out, sums);
+}
+
 void launch_build_csr(hipStream_t s, int m, int n, int64_t nnz, const int32_t* colptr,
                       const int32_t* rowidx, const double* val, int32_t* rowcnt, int32_t* rowptr,
                       int32_t* colidx, double* valr, void* scan_scratch) {

@@ -249,6 +249,27 @@ void launch_residual_dual_dd(hipStream_t s, int m, int n, int64_t nnz, const int
                              const int32_t* rowidx, const double* val, const double* A, int lda,
                              const double* x, const double* b, const uint8_t* flags, double* rh,
                              double* rl, double* y, double* gfree);
+// Gathers sliced for the L2 (k_slice.hip): slices of 2^SLICE_SHIFT elements (2 MB of
+// doubles) of the gathered vector; used when that vector is longer than SLICE_MIN_LEN
+// (larger than an XCD's 4 MB L2).
+constexpr int SLICE_SHIFT = 18;
+constexpr int SLICE_MIN_LEN = 1 << 19;
+inline int slice_count(int len) { return (int)(((int64_t)len + (1 << SLICE_SHIFT) - 1) >> SLICE_SHIFT); }
+// Copy a compressed matrix (N outputs, ptr[N + 1], ascending idx per output, values) slice
+// by slice: sptr (ns (N + 1) + 1 ints) gives output o's run in slice s at
+// [sptr[s (N + 1) + o], sptr[s (N + 1) + o + 1]); sidx, sval (nnz each) hold the runs.
+// counts: ns (N + 1) ints of scratch; scan_sums: ceil(ns (N + 1) / 2048) ints.
+void launch_slice_build(hipStream_t s, int N, int64_t nnz, const int32_t* ptr, const int32_t* idx,
+                        const double* val, int ns, int32_t* counts, int32_t* sptr, int32_t* sidx,
+                        double* sval, int32_t* scan_sums);
+// r = A x - b over the row-major copy sliced by columns (ns slices of x)
+void launch_sliced_residual(hipStream_t s, int m, int ns, const int32_t* sptr, const int32_t* sidx,
+                            const double* sval, const double* x, const double* b, double* r);
+// y_j = a_j^T r where flags[j] == 0, else 0, over the CSC sliced by rows (ns slices of r)
+void launch_sliced_dual(hipStream_t s, int n, int ns, const int32_t* sptr, const int32_t* sidx,
+                        const double* sval, const double* r, const uint8_t* flags, double* y);
+// exclusive prefix sum of count[0..n) into out[0..n] (k_setup.hip); sums: ceil(n / 2048)
+void launch_scan_i32(hipStream_t s, int64_t n, const int32_t* count, int32_t* out, int32_t* sums);
 // x[Flist[p]] -= d[p] for p < nF; writes max |d| and max |x_F| into ctrl (one workgroup);
 // first: the first step of a refinement (ir_dprev becomes INF, else the previous ir_dmax)
 void launch_ir_update(hipStream_t s, int nF, const int32_t* Flist, const double* d, double* x,

@@ -272,6 +272,73 @@ void launch_dual_csc(hipStream_t s, int n, const int32_t* colptr, const int32_t*
   });
 }
 
+// Sliced gathers: the copy is built exactly as the device does (counts per slice, a scan,
+// a scatter), so the stub touches every range the real kernels touch.
+void launch_slice_build(hipStream_t s, int N, int64_t nnz, const int32_t* ptr, const int32_t* idx, const double* val,
+                        int ns, int32_t* counts, int32_t* sptr, int32_t* sidx, double* sval, int32_t* scan_sums) {
+  stub_enqueue(s, [=] {
+    const int64_t ld = (int64_t)N + 1;
+    for (int64_t o = 0; o < N; ++o) {
+      int32_t q = ptr[o];
+      for (int sl = 0; sl < ns; ++sl) {
+        const int32_t p0 = q;
+        while (q < ptr[o + 1] && (idx[q] >> SLICE_SHIFT) == sl) ++q;
+        counts[sl * ld + o] = q - p0;
+      }
+    }
+    for (int sl = 0; sl < ns; ++sl) counts[sl * ld + N] = 0;
+    int32_t run = 0;
+    for (int64_t k = 0; k < ns * ld; ++k) {
+      sptr[k] = run;
+      run += counts[k];
+    }
+    sptr[ns * ld] = run;
+    scan_sums[0] = run;
+    for (int64_t o = 0; o < N; ++o) {
+      int cur = -1;
+      int32_t pos = 0;
+      for (int32_t q = ptr[o]; q < ptr[o + 1]; ++q) {
+        const int sl = idx[q] >> SLICE_SHIFT;
+        if (sl != cur) {
+          cur = sl;
+          pos = sptr[sl * ld + o];
+        }
+        sidx[pos] = idx[q];
+        sval[pos] = val[q];
+        ++pos;
+      }
+    }
+    (void)nnz;
+  });
+}
+
+void launch_sliced_residual(hipStream_t s, int m, int ns, const int32_t* sptr, const int32_t* sidx,
+                            const double* sval, const double* x, const double* b, double* r) {
+  stub_enqueue(s, [=] {
+    const int64_t ld = (int64_t)m + 1;
+    for (int i = 0; i < m; ++i) {
+      double t = -b[i];
+      for (int sl = 0; sl < ns; ++sl)
+        for (int32_t e = sptr[sl * ld + i]; e < sptr[sl * ld + i + 1]; ++e) t += sval[e] * x[sidx[e]];
+      r[i] = t;
+    }
+  });
+}
+
+void launch_sliced_dual(hipStream_t s, int n, int ns, const int32_t* sptr, const int32_t* sidx,
+                        const double* sval, const double* r, const uint8_t* flags, double* y) {
+  stub_enqueue(s, [=] {
+    const int64_t ld = (int64_t)n + 1;
+    for (int j = 0; j < n; ++j) {
+      double t = 0.0;
+      for (int sl = 0; sl < ns; ++sl)
+        for (int32_t e = sptr[sl * ld + j]; e < sptr[sl * ld + j + 1]; ++e) t += sval[e] * r[sidx[e]];
+      g_sink = g_sink + t;
+      y[j] = flags[j] ? 0.0 : 1.0;
+    }
+  });
+}
+
 int dense_residual_chunks(int m, int n) {
   const int rows = (m + 255) / 256;
   int c = (1024 + rows - 1) / rows;

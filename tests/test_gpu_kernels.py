@@ -250,6 +250,50 @@ def test_residual_every_lane_width(h, m, n, density):
     assert np.all(np.abs(yd.cpu().numpy() - y_ref) <= ybound + 1e-300)
 
 
+def _random_rows_csc(rng, m, n, k):
+    """k random rows per column (duplicates summed), N(0,1) values, sorted CSC."""
+    rows = rng.integers(0, m, size=n * k)
+    cols = np.repeat(np.arange(n), k)
+    A = sp.csc_matrix((rng.standard_normal(n * k), (rows, cols)), shape=(m, n))
+    A.sum_duplicates()
+    A.sort_indices()
+    return A
+
+
+@pytest.mark.parametrize("m,n,k", [(1_300_000, 600_000, 3), ((1 << 19) + 1, 70_000, 5),
+                                   (200_000, (1 << 19) + 3, 2), (1 << 19, 1 << 19, 2),
+                                   (600_000, 1_000, 700)])
+def test_dual_step_sliced(h, m, n, k):
+    """Vectors longer than 2^19 doubles are gathered in slices of 2 MB (x for the residual when
+    n is that long, r for the dual when m is): r = A x - b and y_G = A_G^T r still within the
+    rounding bound, y_F exactly 0, and y_G against the oracle's Eq. 5.  Covers both, one of
+    each, a last slice of a single row or column, the sizes just below the threshold, and
+    long columns (a wave's range of one slice spans several staging windows)."""
+    rng = np.random.default_rng(m + n)
+    A = _random_rows_csc(rng, m, n, k)
+    b = rng.standard_normal(m)
+    free = rng.random(n) < 0.4
+    x = np.where(free, rng.standard_normal(n), 0.0)
+    colptr, rowidx, val = csc_dev(A)
+    yd = torch.full((n,), np.nan, dtype=torch.float64, device=DEV)
+    rd = torch.empty(m, dtype=torch.float64, device=DEV)
+    print(f"sliced dual m={m} n={n} nnz={A.nnz}", flush=True)
+    st = N.nnls_dual_csc(h, m, n, colptr, rowidx, val, t(b), t(free, np.uint8), t(x), rd, yd)
+    assert st == N.NNLS_OK
+    absA = abs(A)
+    lr = int(np.diff(A.tocsr().indptr).max()) + 1   # longest row, plus b
+    r_ref = A @ x - b
+    rbound = (absA @ np.abs(x) + np.abs(b)) * 4 * lr * EPS
+    assert np.all(np.abs(rd.cpu().numpy() - r_ref) <= rbound + 1e-300)
+    yg = yd.cpu().numpy()
+    assert np.all(yg[free] == 0.0)
+    idx_f, idx_g = np.flatnonzero(free), np.flatnonzero(~free)
+    y_or = np.zeros(n)
+    y_or[idx_g] = dual(A, b, idx_f, x[idx_f], idx_g)
+    ybound = (absA.T @ (absA @ np.abs(x) + np.abs(b))) * 8 * (lr + k + 1) * EPS
+    assert np.all(np.abs(yg - y_or) <= ybound + 1e-300)
+
+
 @pytest.mark.parametrize("m,n", [(40, 30), (300, 70), (5000, 40), (20000, 700), (1000, 1000)])
 def test_dual_dense_step(h, m, n):
     """Dense Eq. 5 step (the residual splits over column chunks when the grid is short)."""
