@@ -64,6 +64,15 @@ def check_against_oracle(insts, results, refs, tol):
         assert np.all(x >= 0) and np.all(y >= 0) and np.dot(x, y) == 0.0
 
 
+def test_default_config_matches_oracle(stream_small, oracle_small):
+    """The engine's defaults (16 sparse workers, each factor capped at 96 workgroups, 2
+    batched lanes for n <= 256): every request of the mixed stream gives the oracle's split
+    and x within 1e-10."""
+    with N.Server(0) as srv:
+        res = run_all(srv, stream_small)
+    check_against_oracle(stream_small, res, oracle_small, 1e-10)
+
+
 @pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-8), (2, 1e-8)])
 def test_mixed_stream_matches_oracle(stream_small, oracle_small, precision, tol):
     """precision 2 (NNLS_BF16_IR): bfloat16-update factors on the sparse lane, the float32
